@@ -1,0 +1,205 @@
+/*
+ * orth.h -- C ABI of the MI355X (gfx950) block-orthogonalisation library.
+ *
+ * The library solves, once per block-Krylov step, the project-and-normalize
+ * (PQR) problem of Dreier & Engwer, "A Hardware-aware and Stable
+ * Orthogonalization Framework" (arXiv 2204.13393), eq. (1.1):
+ *
+ *     [Q W] = [Q U] [[I, H], [0, R]],   Q^T U = 0,  U^T U = I,
+ *
+ * where Q (n x k) is the basis built by earlier steps, W (n x s) the new
+ * block, H = Q^T W (k x s) the projection coefficients ("P" in the paper),
+ * R (s x s) the upper-triangular normaliser with positive diagonal ("N" in
+ * the paper) and U (n x s) the explicit new orthonormal block.  The method
+ * is TreeTSPQR (Sec. 4.1): the rows are split into leaves, every leaf
+ * solves its local PQR problem with BCGS-PIP+ (CholeskyQR2, Sec. 3.1), and
+ * one reduction PQR problem on the stacked leaf coefficient blocks, also
+ * solved with BCGS-PIP+, yields H and R.  The basis is never stored
+ * explicitly: it lives in the caller-provided workspace in the paper's
+ * locally orthogonal form Q = blockdiag(Q_1..Q_p) [T_1; ...; T_p] (Sec. 4.1),
+ * per-leaf local bases Q_i plus per-leaf upper-triangular tree factors T_i.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrices are IEEE FP64, column-major with a leading dimension
+ *    (BLAS convention): element (r, c) of an n x s matrix at ptr[c*ld + r].
+ *    A contiguous torch tensor of shape (s, n) is such a matrix with ld = n.
+ *  - Pointers named d_* are device pointers (HIP device memory of the
+ *    current device).  The caller owns every device buffer, including the
+ *    workspace; the library never allocates or frees device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every compute entry point only enqueues work on that stream and returns
+ *    without synchronising; results are valid once the stream has reached
+ *    that point.
+ *  - Return values: ORTH_OK or one of the error codes below.  Argument and
+ *    capacity errors are detected on the host before any work is enqueued
+ *    and leave the handle's state unchanged.  Numerical breakdown (a
+ *    Cholesky pivot that is not positive and finite, Sec. 3.1: the textbook
+ *    Cholesky is not rank revealing) is detected on the device; it is
+ *    reported by orth_status, after which the handle is poisoned.
+ *  - No C++ exception crosses this boundary.  Functions are not thread-safe
+ *    on the same handle.
+ */
+#ifndef ORTH_H_
+#define ORTH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orth_ctx orth_t;
+
+enum orth_code {
+    ORTH_OK = 0,
+    ORTH_ERR_ARG = 1,        /* invalid argument (size, pointer, ld, alignment) */
+    ORTH_ERR_CAPACITY = 2,   /* k + s would exceed k_max */
+    ORTH_ERR_BREAKDOWN = 3,  /* device reported a non-positive / non-finite pivot */
+    ORTH_ERR_HIP = 4,        /* a HIP runtime call failed (no device, launch error) */
+    ORTH_ERR_POISONED = 5,   /* handle saw a breakdown earlier; only destroy works */
+    ORTH_ERR_WORKSPACE = 6,  /* workspace missing, too small or misaligned */
+    ORTH_ERR_UNSUPPORTED = 7 /* valid request this build does not implement */
+};
+
+enum orth_precision {
+    ORTH_FP64 = 0            /* every product in FP64 */
+};
+
+/* Variant of the leaf and reduction subalgorithm (Sec. 3, Sec. 3.1). */
+enum orth_variant {
+    ORTH_PIP_PLUS = 0,       /* BCGS-PIP+ (CholeskyQR2): the default, O(eps) */
+    ORTH_PIP = 1             /* BCGS-PIP (one CholeskyQR sweep), O(eps kappa^2):
+                                kept to reproduce the paper's unstable column */
+};
+
+/*
+ * orth_workspace_bytes -- device workspace size for orth_create.
+ *   n          rows of the basis (>= 1)
+ *   s          block width, one of 1, 2, 4, 8, 16
+ *   k_max      largest basis width the handle will reach (multiple of s,
+ *              s <= k_max); a step that would pass it fails with CAPACITY
+ *   leaf_rows  TSQR leaf height; 0 picks the default
+ *              max(k_max, min(n, 4096)); leaves are
+ *              p = max(1, n / leaf_rows) row blocks of leaf_rows rows, the
+ *              last one taking the remainder; leaf_rows must be >= k_max so
+ *              every local problem keeps full column rank, and <= n
+ *   precision  ORTH_FP64
+ * Returns 0 for invalid arguments.  Pure host arithmetic, no HIP call.
+ */
+size_t orth_workspace_bytes(int64_t n, int32_t s, int32_t k_max,
+                            int32_t leaf_rows, int32_t precision);
+
+/*
+ * orth_create -- make a handle with an empty basis (k = 0).
+ *   d_workspace      device buffer of >= orth_workspace_bytes(...) bytes,
+ *                    256-byte aligned; owned by the caller, must outlive
+ *                    the handle and must not be touched while it lives
+ *   stream           stream all later calls enqueue on
+ *   out              receives the handle
+ * Enqueues the zero fill of the tree-factor storage on `stream`.
+ * Errors: ARG, WORKSPACE, UNSUPPORTED, HIP.
+ */
+int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
+                int32_t precision, void *d_workspace, size_t workspace_bytes,
+                void *stream, orth_t **out);
+
+/*
+ * orth_set_variant -- choose ORTH_PIP_PLUS (default) or ORTH_PIP for the
+ * following steps.  Host-side only.  Errors: ARG, POISONED.
+ */
+int orth_set_variant(orth_t *h, int32_t variant);
+
+/*
+ * orth_step -- solve the PQR problem eq. (1.1) for the new block W and grow
+ * the basis by s columns (Sec. 4.1, TreeTSPQR; one step of the block
+ * Arnoldi process, Sec. 2).
+ *   d_W, ldw   n x s input block, ldw >= n.  May alias d_U (read before U
+ *              is written in the same step).
+ *   d_H, ldh   k x s output, H = Q^T W; ldh >= max(1, k).  May be NULL when
+ *              k = 0 (the first step is the QR of the start block).
+ *   d_R, ldr   s x s output, upper triangular with positive diagonal, zeros
+ *              written below the diagonal; ldr >= s.
+ *   d_U, ldu   n x s output, the explicit new orthonormal block; ldu >= n.
+ * H and R may point into the caller's block Hessenberg matrix (column block
+ * j: d_H at its top, d_R = d_H + k with ldh = ldr = its leading dimension).
+ * On success the basis width becomes k + s (on the host at once).
+ * Errors: ARG, CAPACITY, POISONED, HIP; BREAKDOWN later via orth_status.
+ */
+int orth_step(orth_t *h, const double *d_W, int64_t ldw,
+              double *d_H, int64_t ldh, double *d_R, int64_t ldr,
+              double *d_U, int64_t ldu);
+
+/*
+ * orth_apply_Q -- Y = Q C with the current basis Q (n x k), C (k x m).
+ * The second-stage product "QC" of Sec. 5.1: one sweep over the tree
+ * factors, then the leaf products Y_i = Q_i C_i.  Used for Ritz vectors and
+ * for the explicit basis (C = I).
+ *   d_C, ldc   k x m, ldc >= k;  m >= 1
+ *   d_Y, ldy   n x m output, ldy >= n; must not overlap the workspace or C.
+ * Errors: ARG (also for k = 0), POISONED, HIP.
+ */
+int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
+                 double *d_Y, int64_t ldy);
+
+/*
+ * orth_status -- synchronise the handle's stream and read the device status.
+ *   status  receives ORTH_OK or ORTH_ERR_BREAKDOWN.  After a breakdown the
+ *           handle is poisoned.
+ *   info    optional (may be NULL): 4 ints {tree level (0 = leaves,
+ *           1 = reduction), leaf index, CholeskyQR sweep (1 or 2), pivot
+ *           column}.
+ * Errors: ARG, HIP.
+ */
+int orth_status(orth_t *h, int32_t *status, int32_t *info);
+
+/* orth_basis_width -- current k (host state, no synchronisation). */
+int orth_basis_width(const orth_t *h, int32_t *k);
+
+/* orth_leaf_count -- number of leaves p and the leaf height in use. */
+int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows);
+
+/*
+ * orth_export_local -- copy the locally orthogonal representation out, for
+ * inspection and tests (Sec. 4.1): the stacked local bases
+ * blockdiag(Q_1..Q_p) flattened to an n x k matrix (leaf i's rows hold Q_i)
+ * into d_Qloc (ldq >= n), and the tree factors T_i (k x k, upper
+ * triangular) stacked into a (p*k) x k matrix d_T (ldt >= p*k).
+ * Either destination may be NULL.  Enqueued on the handle's stream.
+ * Errors: ARG, POISONED, HIP.
+ */
+int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq,
+                      double *d_T, int64_t ldt);
+
+/*
+ * orth_destroy -- release the host state.  The workspace stays owned by the
+ * caller.  Always allowed, also on a poisoned handle; NULL is a no-op.
+ */
+int orth_destroy(orth_t *h);
+
+/*
+ * orth_laplacian_apply -- test operator for Arnoldi drivers (not part of the
+ * method): Y = A X for the Dirichlet finite-difference Laplacian on an
+ * nx x ny (nz = 1: 5-point, diagonal 4) or nx x ny x nz (7-point, diagonal
+ * 6) grid plus `shift` on the diagonal, unknowns ordered i + nx*j + nx*ny*l.
+ * X and Y are n x s (n = nx*ny*nz) column-major, ldx, ldy >= n, must not
+ * overlap.  Errors: ARG, HIP.
+ */
+int orth_laplacian_apply(const double *d_X, int64_t ldx, double *d_Y,
+                         int64_t ldy, int32_t s, int32_t nx, int32_t ny,
+                         int32_t nz, double shift, void *stream);
+
+/*
+ * orth_probe_copy -- measurement probe: dst[i] = src[i] for i < count
+ * doubles.  A plain streaming copy of known size, used to calibrate the
+ * hardware byte counters and the achievable HBM bandwidth.  Errors: ARG, HIP.
+ */
+int orth_probe_copy(const double *d_src, double *d_dst, int64_t count,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORTH_H_ */

@@ -1,0 +1,491 @@
+// C-ABI runtime: argument checks, workspace carving and the per-step launch
+// sequence of TreeTSPQR (Sec. 4.1) with BCGS-PIP+ at the leaves and at the
+// single reduction level (Sec. 3.1; the paper recommends BCGS-PIP+ for the
+// reduction across processes, Sec. 5.2).
+//
+// Workspace carving (all regions 256-byte aligned, column-major FP64):
+//   Qloc  ldq x kmax     stacked local bases; leaf i owns rows of leaf i
+//   T     ldt x kmax     tree factors; leaf i's T_i (kmax x kmax, upper
+//                        triangular) in rows [i*kmax, (i+1)*kmax)
+//   Y     ldt x s        reduction-level X: leaf i's [P_i; N_i] in its rows
+//   U1L   ldq x s        leaf sweep-1 block u1
+//   U1R   ldt x s        reduction sweep-1 block
+//   CA    ldt x 16       apply_Q scratch (per-leaf coefficient blocks)
+//   partL nchunkL x (kmax+s) x s   leaf chunk partial Gram blocks
+//   partR nchunkR x (kmax+s) x s   reduction chunk partials
+//   smallL p x rec       per-leaf P1, N1, N1^{-1}, P2, N2^{-1}
+//   smallR 1 x rec
+//   status               DevStatus
+
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "../../include/orth.h"
+#include "orth_internal.h"
+
+using namespace orth;
+
+namespace {
+
+constexpr int64_t kAlign = 32;        // doubles (256 bytes)
+constexpr int kLeafChunk = 1024;      // rows per workgroup at the leaf level
+constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
+constexpr int kFinalChunk = 2048;     // rows per workgroup in the finalize pass
+constexpr int kApplyMB = 16;
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool valid_s(int32_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16; }
+
+// widest [Q X] a level kernel supports for block width s
+int32_t max_cols(int32_t) { return 256; }
+
+struct Plan {
+    int64_t n;
+    int32_t s, kmax, leaf_rows, p;
+    int64_t ldq, ldt;
+    int32_t nchunkL, nchunkR;
+    // region offsets in doubles
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oSL, oSR, oST, total;
+};
+
+int32_t default_leaf_rows(int64_t n, int32_t kmax) {
+    int64_t lr = n < 4096 ? n : 4096;
+    if (lr < kmax) lr = kmax;
+    return (int32_t)lr;
+}
+
+bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t precision, Plan &pl,
+               int *why) {
+    *why = ORTH_ERR_ARG;
+    if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
+    if (precision != ORTH_FP64) return false;
+    if (kmax + s > max_cols(s)) { *why = ORTH_ERR_UNSUPPORTED; return false; }
+    // finalize stages two (k x s) coefficient blocks in LDS; keep it within 64 KB
+    if ((2 * (int64_t)(kmax - s) * s + 2 * (int64_t)s * s) * 8 > 64 * 1024) {
+        *why = ORTH_ERR_UNSUPPORTED;
+        return false;
+    }
+    if (leaf_rows == 0) leaf_rows = default_leaf_rows(n, kmax);
+    if (leaf_rows < kmax || leaf_rows > n) return false;
+    if (n > ((int64_t)1 << 40)) return false;
+    pl.n = n;
+    pl.s = s;
+    pl.kmax = kmax;
+    pl.leaf_rows = leaf_rows;
+    pl.p = (int32_t)(n / leaf_rows);
+    if (pl.p < 1) pl.p = 1;
+    pl.ldq = round_up(n, kAlign);
+    pl.ldt = round_up((int64_t)pl.p * kmax, kAlign);
+    const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
+    const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
+    pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
+    pl.nchunkR = (int32_t)ceil_div((int64_t)pl.p * kmax, kRootChunk);
+    const int64_t pstride = (int64_t)(kmax + s) * s;
+    int64_t off = 0;
+    auto take = [&](int64_t count) {
+        const int64_t o = off;
+        off = round_up(off + count, kAlign);
+        return o;
+    };
+    pl.oQ = take(pl.ldq * kmax);
+    pl.oT = take(pl.ldt * kmax);
+    pl.oY = take(pl.ldt * s);
+    pl.oU1L = take(pl.ldq * s);
+    pl.oU1R = take(pl.ldt * s);
+    pl.oCA = take(pl.ldt * kApplyMB);
+    pl.oPL = take((int64_t)pl.nchunkL * pstride);
+    pl.oPR = take((int64_t)pl.nchunkR * pstride);
+    pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
+    pl.oSR = take(small_stride(kmax, s));
+    pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
+    pl.total = off;
+    return true;
+}
+
+LevelGeom leaf_geom(const Plan &pl, int chunk) {
+    LevelGeom g{};
+    g.nrows = pl.n;
+    g.leaf_rows = pl.leaf_rows;
+    g.nleaf = pl.p;
+    g.chunk_rows = chunk;
+    const int64_t last = pl.n - (int64_t)(pl.p - 1) * pl.leaf_rows;
+    g.cpl = (int32_t)ceil_div(pl.leaf_rows, chunk);
+    g.cpl_last = (int32_t)ceil_div(last, chunk);
+    g.map = RowMap{0, 0};
+    return g;
+}
+
+// the reduction level: one local problem over all p segments of seg_len rows
+LevelGeom root_geom(const Plan &pl, int64_t seg_len, int chunk) {
+    LevelGeom g{};
+    g.nrows = (int64_t)pl.p * seg_len;
+    g.leaf_rows = g.nrows;
+    g.nleaf = 1;
+    g.chunk_rows = chunk;
+    g.cpl = (int32_t)ceil_div(g.nrows, chunk);
+    g.cpl_last = g.cpl;
+    g.map = RowMap{seg_len, pl.kmax};
+    return g;
+}
+
+}  // namespace
+
+struct orth_ctx {
+    Plan pl;
+    int32_t k = 0;
+    int32_t variant = ORTH_PIP_PLUS;
+    bool poisoned = false;
+    hipStream_t stream = nullptr;
+    double *ws = nullptr;
+
+    double *Q() const { return ws + pl.oQ; }
+    double *T() const { return ws + pl.oT; }
+    double *Y() const { return ws + pl.oY; }
+    double *U1L() const { return ws + pl.oU1L; }
+    double *U1R() const { return ws + pl.oU1R; }
+    double *CA() const { return ws + pl.oCA; }
+    double *PL() const { return ws + pl.oPL; }
+    double *PR() const { return ws + pl.oPR; }
+    double *SL() const { return ws + pl.oSL; }
+    double *SR() const { return ws + pl.oSR; }
+    DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + pl.oST); }
+};
+
+extern "C" {
+
+size_t orth_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
+                            int32_t precision) {
+    Plan pl;
+    int why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why)) return 0;
+    return (size_t)pl.total * sizeof(double);
+}
+
+int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                void *d_workspace, size_t workspace_bytes, void *stream, orth_t **out) {
+    if (!out) return ORTH_ERR_ARG;
+    *out = nullptr;
+    Plan pl;
+    int why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why)) return why;
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
+        workspace_bytes < (size_t)pl.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    orth_ctx *h = new (std::nothrow) orth_ctx();
+    if (!h) return ORTH_ERR_HIP;
+    h->pl = pl;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->ws = static_cast<double *>(d_workspace);
+    // tree factors must start at zero: the reduction level relies on the
+    // zero rows below every T_i's current k x k block
+    hipError_t e = launch_fill(h->T(), pl.ldt * (int64_t)pl.kmax, 0.0, h->stream);
+    if (e == hipSuccess) e = launch_fill(h->Y(), pl.ldt * (int64_t)pl.s, 0.0, h->stream);
+    if (e == hipSuccess)
+        e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
+                            (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, h->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return ORTH_ERR_HIP;
+    }
+    *out = h;
+    return ORTH_OK;
+}
+
+int orth_set_variant(orth_t *h, int32_t variant) {
+    if (!h || (variant != ORTH_PIP_PLUS && variant != ORTH_PIP)) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    h->variant = variant;
+    return ORTH_OK;
+}
+
+int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ldh, double *d_R,
+              int64_t ldr, double *d_U, int64_t ldu) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, k = h->k, kmax = pl.kmax;
+    if (!d_W || !d_R || !d_U) return ORTH_ERR_ARG;
+    if (ldw < pl.n || ldu < pl.n || ldr < s) return ORTH_ERR_ARG;
+    if (k > 0 && (!d_H || ldh < k)) return ORTH_ERR_ARG;
+    if (k + s > kmax) return ORTH_ERR_CAPACITY;
+    const bool two = h->variant == ORTH_PIP_PLUS;
+    const int final_sweep = two ? 2 : 1;
+    hipStream_t st = h->stream;
+    const int64_t pstride = (int64_t)(kmax + s) * s;
+    const int64_t sstride = small_stride(kmax, s);
+    const int ncol = k + s;
+    hipError_t e = hipSuccess;
+
+    // ---- leaves: local PQR [Q_i W_i] = [Q_i U_i][[I, P_i], [0, N_i]]
+    const LevelGeom gL = leaf_geom(pl, kLeafChunk);
+    {
+        GramArgs a{};
+        a.Q = Operand{h->Q(), pl.ldq};
+        a.X = Operand{d_W, ldw};
+        a.k = k;
+        a.tile_rows = gram_tile_rows(ncol, s);
+        a.geom = gL;
+        a.partials = h->PL();
+        a.part_stride = pstride;
+        a.status = h->status();
+        e = launch_gram(s, a, ncol, st);
+        if (e != hipSuccess) goto fail;
+    }
+    {
+        CholArgs c{};
+        c.partials = h->PL();
+        c.part_stride = pstride;
+        c.geom = gL;
+        c.k = k;
+        c.kmax = kmax;
+        c.sweep = 1;
+        c.level = 0;
+        c.final_sweep = final_sweep;
+        c.small = h->SL();
+        c.small_stride = sstride;
+        c.Yout = h->Y();
+        c.ldy = pl.ldt;
+        c.yseg = kmax;
+        c.status = h->status();
+        e = launch_chol(s, c, st);
+        if (e != hipSuccess) goto fail;
+
+        CorrectArgs b{};
+        b.Q = Operand{h->Q(), pl.ldq};
+        b.X = Operand{d_W, ldw};
+        b.U1 = OutOperand{h->U1L(), pl.ldq};
+        b.k = k;
+        b.tile_rows = correct_tile_rows(ncol, s);
+        b.geom = gL;
+        b.small = h->SL();
+        b.small_stride = sstride;
+        b.kmax = kmax;
+        b.partials = h->PL();
+        b.part_stride = pstride;
+        b.write_gram = two ? 1 : 0;
+        b.status = h->status();
+        e = launch_correct(s, b, ncol, st);
+        if (e != hipSuccess) goto fail;
+        if (two) {
+            c.sweep = 2;
+            e = launch_chol(s, c, st);
+            if (e != hipSuccess) goto fail;
+        }
+    }
+    // ---- reduction: PQR on the stacked [[T_i, P_i], [0, N_i]] (segments of k+s rows)
+    {
+        const LevelGeom gR = root_geom(pl, ncol, kRootChunk);
+        GramArgs a{};
+        a.Q = Operand{h->T(), pl.ldt};
+        a.X = Operand{h->Y(), pl.ldt};
+        a.k = k;
+        a.tile_rows = gram_tile_rows(ncol, s);
+        a.geom = gR;
+        a.partials = h->PR();
+        a.part_stride = pstride;
+        a.status = h->status();
+        e = launch_gram(s, a, ncol, st);
+        if (e != hipSuccess) goto fail;
+
+        CholArgs c{};
+        c.partials = h->PR();
+        c.part_stride = pstride;
+        c.geom = gR;
+        c.k = k;
+        c.kmax = kmax;
+        c.sweep = 1;
+        c.level = 1;
+        c.final_sweep = final_sweep;
+        c.small = h->SR();
+        c.small_stride = sstride;
+        c.H = k > 0 ? d_H : nullptr;
+        c.ldh = ldh;
+        c.R = d_R;
+        c.ldr = ldr;
+        c.status = h->status();
+        e = launch_chol(s, c, st);
+        if (e != hipSuccess) goto fail;
+
+        CorrectArgs b{};
+        b.Q = Operand{h->T(), pl.ldt};
+        b.X = Operand{h->Y(), pl.ldt};
+        b.U1 = OutOperand{h->U1R(), pl.ldt};
+        b.k = k;
+        b.tile_rows = correct_tile_rows(ncol, s);
+        b.geom = gR;
+        b.small = h->SR();
+        b.small_stride = sstride;
+        b.kmax = kmax;
+        b.partials = h->PR();
+        b.part_stride = pstride;
+        b.write_gram = two ? 1 : 0;
+        b.status = h->status();
+        e = launch_correct(s, b, ncol, st);
+        if (e != hipSuccess) goto fail;
+        if (two) {
+            c.sweep = 2;
+            e = launch_chol(s, c, st);
+            if (e != hipSuccess) goto fail;
+        }
+        // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s]
+        FinalizeArgs f{};
+        f.Q = Operand{h->T(), pl.ldt};
+        f.Qnew = OutOperand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
+        f.U1 = Operand{h->U1R(), pl.ldt};
+        f.k = k;
+        f.geom = root_geom(pl, ncol, kFinalChunk);
+        f.small = h->SR();
+        f.small_stride = sstride;
+        f.kmax = kmax;
+        f.single_sweep = two ? 0 : 1;
+        f.Cptr = nullptr;
+        f.status = h->status();
+        e = launch_finalize(s, f, st);
+        if (e != hipSuccess) goto fail;
+    }
+    // ---- leaves: U_i appended to Q_i, explicit U|_i = [Q_i U_i] [P~_i; N~_i]
+    {
+        FinalizeArgs f{};
+        f.Q = Operand{h->Q(), pl.ldq};
+        f.Qnew = OutOperand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
+        f.U1 = Operand{h->U1L(), pl.ldq};
+        f.k = k;
+        f.geom = leaf_geom(pl, kFinalChunk);
+        f.small = h->SL();
+        f.small_stride = sstride;
+        f.kmax = kmax;
+        f.single_sweep = two ? 0 : 1;
+        f.Cptr = h->T() + (int64_t)k * pl.ldt;
+        f.ldc = pl.ldt;
+        f.cseg = kmax;
+        f.Uout = OutOperand{d_U, ldu};
+        f.status = h->status();
+        e = launch_finalize(s, f, st);
+        if (e != hipSuccess) goto fail;
+    }
+    h->k = k + s;
+    return ORTH_OK;
+fail:
+    (void)hipGetLastError();
+    return ORTH_ERR_HIP;
+}
+
+int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    const Plan &pl = h->pl;
+    const int32_t k = h->k;
+    if (k < 1 || m < 1 || !d_C || !d_Y || ldc < k || ldy < pl.n) return ORTH_ERR_ARG;
+    hipStream_t st = h->stream;
+    for (int32_t j0 = 0; j0 < m; j0 += kApplyMB) {
+        const int32_t mb = (m - j0) < kApplyMB ? (m - j0) : kApplyMB;
+        // reduction level: C_i = T_i C (rows: p segments of k rows)
+        ApplyArgs r{};
+        r.Q = Operand{h->T(), pl.ldt};
+        r.k = k;
+        r.geom = root_geom(pl, k, kFinalChunk);
+        r.Cptr = d_C + (int64_t)j0 * ldc;
+        r.ldc = ldc;
+        r.cseg = 0;
+        r.m = mb;
+        r.Y = OutOperand{h->CA(), pl.ldt};
+        hipError_t e = launch_apply(r, st);
+        if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+        // leaves: Y_i = Q_i C_i
+        ApplyArgs a{};
+        a.Q = Operand{h->Q(), pl.ldq};
+        a.k = k;
+        a.geom = leaf_geom(pl, kFinalChunk);
+        a.Cptr = h->CA();
+        a.ldc = pl.ldt;
+        a.cseg = pl.kmax;
+        a.m = mb;
+        a.Y = OutOperand{d_Y + (int64_t)j0 * ldy, ldy};
+        e = launch_apply(a, st);
+        if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+    }
+    return ORTH_OK;
+}
+
+int orth_status(orth_t *h, int32_t *status, int32_t *info) {
+    if (!h || !status) return ORTH_ERR_ARG;
+    DevStatus ds{};
+    if (hipStreamSynchronize(h->stream) != hipSuccess ||
+        hipMemcpy(&ds, h->status(), sizeof(ds), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    *status = ds.code == 0 ? ORTH_OK : ORTH_ERR_BREAKDOWN;
+    if (ds.code != 0) h->poisoned = true;
+    if (info) {
+        info[0] = ds.level;
+        info[1] = ds.leaf;
+        info[2] = ds.sweep;
+        info[3] = ds.column;
+    }
+    return ORTH_OK;
+}
+
+int orth_basis_width(const orth_t *h, int32_t *k) {
+    if (!h || !k) return ORTH_ERR_ARG;
+    *k = h->k;
+    return ORTH_OK;
+}
+
+int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows) {
+    if (!h) return ORTH_ERR_ARG;
+    if (p) *p = h->pl.p;
+    if (leaf_rows) *leaf_rows = h->pl.leaf_rows;
+    return ORTH_OK;
+}
+
+int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64_t ldt) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    const Plan &pl = h->pl;
+    const int32_t k = h->k;
+    if (k < 1) return ORTH_ERR_ARG;
+    if (d_Qloc && ldq < pl.n) return ORTH_ERR_ARG;
+    if (d_T && ldt < (int64_t)pl.p * k) return ORTH_ERR_ARG;
+    hipError_t e = hipSuccess;
+    if (d_Qloc) e = launch_copy_cols(h->Q(), pl.ldq, RowMap{0, 0}, d_Qloc, ldq, pl.n, k, h->stream);
+    if (e == hipSuccess && d_T)
+        e = launch_copy_cols(h->T(), pl.ldt, RowMap{k, pl.kmax}, d_T, ldt, (int64_t)pl.p * k, k,
+                             h->stream);
+    if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+    return ORTH_OK;
+}
+
+int orth_destroy(orth_t *h) {
+    delete h;
+    return ORTH_OK;
+}
+
+int orth_laplacian_apply(const double *d_X, int64_t ldx, double *d_Y, int64_t ldy, int32_t s,
+                         int32_t nx, int32_t ny, int32_t nz, double shift, void *stream) {
+    if (!d_X || !d_Y || s < 1 || nx < 1 || ny < 1 || nz < 1) return ORTH_ERR_ARG;
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (ldx < n || ldy < n) return ORTH_ERR_ARG;
+    if (launch_laplacian(d_X, ldx, d_Y, ldy, s, nx, ny, nz, shift,
+                         static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    return ORTH_OK;
+}
+
+int orth_probe_copy(const double *d_src, double *d_dst, int64_t count, void *stream) {
+    if (!d_src || !d_dst || count < 0 || ((uintptr_t)d_src % 16) || ((uintptr_t)d_dst % 16))
+        return ORTH_ERR_ARG;
+    if (launch_copy(d_src, d_dst, count, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    return ORTH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Internal declarations shared by the kernels and the C-ABI runtime.
+//
+// Row addressing.  Every kernel sees its operands as column-major matrices
+// whose *logical* rows map to physical rows through a RowMap.  The leaf
+// level uses the identity.  The reduction level (Sec. 4.1, the PQR problem
+// on the stacked leaf coefficient blocks [[T_i, P_i], [0, N_i]]) stores leaf
+// i's block in rows [i*seg_stride, i*seg_stride + seg_len) of the tree-factor
+// matrix, so logical row r maps to (r / seg_len) * seg_stride + r % seg_len.
+//
+// Level geometry.  A level solves `nleaf` independent local PQR problems on
+// consecutive row ranges of `leaf_rows` logical rows (the last one takes the
+// remainder).  Each leaf is cut into chunks of `chunk_rows` rows, one
+// workgroup per chunk; per-chunk partial Gram blocks are summed per leaf in
+// chunk order, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orth {
+
+struct RowMap {
+    int64_t seg_len;     // 0 = identity
+    int64_t seg_stride;
+    __host__ __device__ __forceinline__ int64_t phys(int64_t r) const {
+        if (seg_len == 0) return r;
+        const int64_t q = r / seg_len;
+        return q * seg_stride + (r - q * seg_len);
+    }
+};
+
+struct LevelGeom {
+    int64_t nrows;       // logical rows of the level
+    int64_t leaf_rows;   // logical rows of every leaf but the last
+    int32_t nleaf;
+    int32_t chunk_rows;
+    int32_t cpl;         // chunks of a full leaf
+    int32_t cpl_last;    // chunks of the last leaf
+    RowMap map;
+
+    __host__ __device__ int32_t nchunks() const { return (nleaf - 1) * cpl + cpl_last; }
+    __host__ __device__ int32_t first_chunk(int32_t leaf) const { return leaf * cpl; }
+    __host__ __device__ int32_t chunks_of(int32_t leaf) const {
+        return leaf == nleaf - 1 ? cpl_last : cpl;
+    }
+    __host__ __device__ int64_t leaf_begin(int32_t leaf) const { return (int64_t)leaf * leaf_rows; }
+    __host__ __device__ int64_t leaf_end(int32_t leaf) const {
+        return leaf == nleaf - 1 ? nrows : (int64_t)(leaf + 1) * leaf_rows;
+    }
+    // chunk g -> (leaf, logical row range)
+    __host__ __device__ void chunk(int32_t g, int32_t &leaf, int64_t &r0, int64_t &r1) const {
+        const int32_t full = (nleaf - 1) * cpl;
+        int32_t c;
+        if (g < full) { leaf = g / cpl; c = g - leaf * cpl; }
+        else { leaf = nleaf - 1; c = g - full; }
+        r0 = leaf_begin(leaf) + (int64_t)c * chunk_rows;
+        const int64_t e = leaf_end(leaf);
+        r1 = r0 + chunk_rows < e ? r0 + chunk_rows : e;
+    }
+};
+
+// Device status record (first failure wins).
+struct DevStatus {
+    int32_t code;        // 0 ok, 3 breakdown
+    int32_t level;       // 0 leaves, 1 reduction
+    int32_t leaf;
+    int32_t sweep;       // CholeskyQR sweep 1 or 2
+    int32_t column;      // pivot column
+    int32_t pad[3];
+};
+
+// Per-leaf small-matrix record, in doubles:
+//   P1 [kmax][s] | N1 [s][s] | N1inv [s][s] | P2 [kmax][s] | N2inv [s][s]
+// All stored row-major ([row][col]).
+__host__ __device__ inline int64_t small_stride(int32_t kmax, int32_t s) {
+    return 2 * (int64_t)kmax * s + 3 * (int64_t)s * s;
+}
+
+struct Operand {          // column-major matrix under a level's RowMap
+    const double *ptr;
+    int64_t ld;
+};
+struct OutOperand {
+    double *ptr;
+    int64_t ld;
+};
+
+// ---- kernel launch descriptors (filled by the runtime) ----
+
+// pass A: partial [Q X]^T X per chunk
+struct GramArgs {
+    Operand Q;            // k columns
+    Operand X;            // s columns
+    int32_t k;
+    int32_t tile_rows;
+    LevelGeom geom;
+    double *partials;     // [chunk][kmax + s][s]
+    int64_t part_stride;  // doubles per chunk slot
+    const DevStatus *status;
+};
+
+// pass B: u1 = (x - q P1) N1^{-1}, store u1, partial [Q U1]^T U1 per chunk
+struct CorrectArgs {
+    Operand Q;
+    Operand X;
+    OutOperand U1;
+    int32_t k;
+    int32_t tile_rows;
+    LevelGeom geom;
+    const double *small;  // per-leaf records
+    int64_t small_stride;
+    int32_t kmax;
+    double *partials;
+    int64_t part_stride;
+    int32_t write_gram;   // 0: only u1 (single-sweep variant)
+    const DevStatus *status;
+};
+
+// per-leaf Cholesky of one sweep (and the combination after sweep 2)
+struct CholArgs {
+    const double *partials;
+    int64_t part_stride;
+    LevelGeom geom;
+    int32_t k;
+    int32_t kmax;
+    int32_t sweep;        // 1 or 2
+    int32_t level;        // for the status record
+    int32_t final_sweep;  // sweep that produces [P; N]
+    double *small;
+    int64_t small_stride;
+    // output of the final sweep: either the next level's stacked X (segmented)
+    // or, at the root, H (k x s) and R (s x s)
+    double *Yout;         // next-level X, column-major, ld = ldy, leaf i at row i*yseg
+    int64_t ldy;
+    int64_t yseg;
+    double *H;
+    int64_t ldh;
+    double *R;
+    int64_t ldr;
+    DevStatus *status;
+};
+
+// pass C: u = (u1 - q P2) N2^{-1} -> new basis columns; optional Uout = [q u] C_leaf
+struct FinalizeArgs {
+    Operand Q;            // k columns (read)
+    OutOperand Qnew;      // s new columns (write), same RowMap
+    Operand U1;
+    int32_t k;
+    LevelGeom geom;
+    const double *small;
+    int64_t small_stride;
+    int32_t kmax;
+    int32_t single_sweep; // 1: u = u1 (BCGS-PIP variant)
+    // per-leaf coefficient block C_i ((k+s) x s): element (c, j) at
+    // Cptr[j*ldc + leaf*cseg + c]; Cptr == nullptr -> no explicit output
+    const double *Cptr;
+    int64_t ldc;
+    int64_t cseg;
+    OutOperand Uout;      // explicit output (identity RowMap, leaf level)
+    const DevStatus *status;
+};
+
+// Y = Q C_leaf for a column block of C
+struct ApplyArgs {
+    Operand Q;
+    int32_t k;
+    LevelGeom geom;
+    const double *Cptr;   // element (c, j) at Cptr[j*ldc + leaf*cseg + c]
+    int64_t ldc;
+    int64_t cseg;         // 0: same C for all leaves
+    int32_t m;            // columns of this block
+    OutOperand Y;         // under geom.map
+};
+
+// launchers (orth_kernels.hip)
+hipError_t launch_gram(int s, const GramArgs &a, int ncol_alloc, hipStream_t st);
+hipError_t launch_correct(int s, const CorrectArgs &a, int ncol_alloc, hipStream_t st);
+hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st);
+hipError_t launch_finalize(int s, const FinalizeArgs &a, hipStream_t st);
+hipError_t launch_apply(const ApplyArgs &a, hipStream_t st);
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+hipError_t launch_copy_cols(const double *src, int64_t lds, RowMap smap, double *dst,
+                            int64_t ldd, int64_t rows, int32_t cols, hipStream_t st);
+hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
+                            int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
+hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);
+
+int gram_tile_rows(int ncol, int s);
+size_t gram_lds_bytes(int ncol, int s, int tile_rows);
+size_t correct_lds_bytes(int ncol, int s, int kmax, int tile_rows);
+int correct_tile_rows(int ncol, int s);
+
+}  // namespace orth

@@ -1,0 +1,245 @@
+"""Thin Python binding of liborth.so (the C ABI declared in include/orth.h).
+
+Every function here only marshals arguments: each step of the method runs
+in the library's HIP kernels.  There is no fallback: if the shared library is
+missing or cannot be loaded, ``load()`` raises and nothing runs.
+
+Raw calls keep the C names and argument order (pointers are ints, streams are
+ints holding a hipStream_t).  ``Orthogonalizer`` is a convenience wrapper that
+owns a torch-allocated workspace and takes torch device tensors; a
+column-major n x s matrix is a contiguous torch tensor of shape (s, n).
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborth.so")
+
+ORTH_OK = 0
+ORTH_ERR_ARG = 1
+ORTH_ERR_CAPACITY = 2
+ORTH_ERR_BREAKDOWN = 3
+ORTH_ERR_HIP = 4
+ORTH_ERR_POISONED = 5
+ORTH_ERR_WORKSPACE = 6
+ORTH_ERR_UNSUPPORTED = 7
+ORTH_FP64 = 0
+ORTH_PIP_PLUS = 0
+ORTH_PIP = 1
+
+CODE_NAMES = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "BREAKDOWN", 4: "HIP", 5: "POISONED",
+              6: "WORKSPACE", 7: "UNSUPPORTED"}
+
+# (name, restype, argtypes) for every symbol in include/orth.h
+_i32, _i64, _sz, _vp, _dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
+SIGNATURES = [
+    ("orth_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32]),
+    ("orth_create", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
+    ("orth_step", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64]),
+    ("orth_apply_Q", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
+    ("orth_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_basis_width", ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
+    ("orth_leaf_count", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_export_local", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64]),
+    ("orth_destroy", ctypes.c_int, [_vp]),
+    ("orth_laplacian_apply", ctypes.c_int, [_dp, _i64, _dp, _i64, _i32, _i32, _i32, _i32,
+                                            ctypes.c_double, _vp]),
+    ("orth_probe_copy", ctypes.c_int, [_dp, _dp, _i64, _vp]),
+]
+
+_lib = None
+
+
+class OrthError(RuntimeError):
+    def __init__(self, func, code):
+        super().__init__(f"{func} failed: ORTH_ERR_{CODE_NAMES.get(code, code)} ({code})")
+        self.code = code
+
+
+def load(path=LIB_PATH):
+    """Load liborth.so once; raises if it is not built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2204_13393_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(func, code):
+    if code != ORTH_OK:
+        raise OrthError(func, code)
+
+
+# ---- raw calls (same names as the C ABI) --------------------------------
+
+def orth_workspace_bytes(n, s, k_max, leaf_rows=0, precision=ORTH_FP64):
+    return load().orth_workspace_bytes(n, s, k_max, leaf_rows, precision)
+
+
+def orth_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes, stream):
+    h = ctypes.c_void_p()
+    code = load().orth_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes,
+                              stream, ctypes.byref(h))
+    return code, h
+
+
+def orth_set_variant(h, variant):
+    return load().orth_set_variant(h, variant)
+
+
+def orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu):
+    return load().orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu)
+
+
+def orth_apply_Q(h, d_C, ldc, m, d_Y, ldy):
+    return load().orth_apply_Q(h, d_C, ldc, m, d_Y, ldy)
+
+
+def orth_status(h):
+    st = ctypes.c_int32()
+    info = (ctypes.c_int32 * 4)()
+    code = load().orth_status(h, ctypes.byref(st), info)
+    return code, st.value, list(info)
+
+
+def orth_basis_width(h):
+    k = ctypes.c_int32()
+    code = load().orth_basis_width(h, ctypes.byref(k))
+    return code, k.value
+
+
+def orth_leaf_count(h):
+    p, lr = ctypes.c_int32(), ctypes.c_int32()
+    code = load().orth_leaf_count(h, ctypes.byref(p), ctypes.byref(lr))
+    return code, p.value, lr.value
+
+
+def orth_export_local(h, d_Qloc, ldq, d_T, ldt):
+    return load().orth_export_local(h, d_Qloc, ldq, d_T, ldt)
+
+
+def orth_destroy(h):
+    return load().orth_destroy(h)
+
+
+def orth_laplacian_apply(d_X, ldx, d_Y, ldy, s, nx, ny, nz, shift, stream):
+    return load().orth_laplacian_apply(d_X, ldx, d_Y, ldy, s, nx, ny, nz, shift, stream)
+
+
+def orth_probe_copy(d_src, d_dst, count, stream):
+    return load().orth_probe_copy(d_src, d_dst, count, stream)
+
+
+# ---- torch convenience wrapper ------------------------------------------
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Orthogonalizer:
+    """One TreeTSPQR basis on one GPU, with a torch-owned workspace.
+
+    Tensors are column-major: an n x s matrix is a contiguous float64 tensor
+    of shape (s, n) on the device.
+    """
+
+    def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS):
+        import torch
+        load()
+        self.n, self.s, self.k_max = int(n), int(s), int(k_max)
+        self.device = torch.device(device)
+        nbytes = orth_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64)
+        if nbytes == 0:
+            raise OrthError("orth_workspace_bytes", ORTH_ERR_ARG)
+        self.stream = stream
+        self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        code, h = orth_create(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64, aligned, nbytes,
+                              _stream_ptr(stream))
+        _check("orth_create", code)
+        self.h = h
+        _check("orth_set_variant", orth_set_variant(self.h, variant))
+        _, self.p, self.leaf_rows = orth_leaf_count(self.h)
+
+    @property
+    def k(self):
+        return orth_basis_width(self.h)[1]
+
+    def step(self, W, H=None, R=None, U=None):
+        """Solve eq. (1.1) for W ((s, n) tensor); returns (H (s,k), R (s,s), U (s,n))."""
+        import torch
+        k, s, n = self.k, self.s, self.n
+        assert W.dtype == torch.float64 and W.is_contiguous() and W.shape == (s, n)
+        if H is None:
+            H = torch.empty((s, max(k, 1)), dtype=torch.float64, device=self.device)
+        if R is None:
+            R = torch.empty((s, s), dtype=torch.float64, device=self.device)
+        if U is None:
+            U = torch.empty((s, n), dtype=torch.float64, device=self.device)
+        code = orth_step(self.h, W.data_ptr(), n, H.data_ptr(), max(k, 1), R.data_ptr(), s,
+                         U.data_ptr(), n)
+        _check("orth_step", code)
+        return H[:, :k], R, U
+
+    def apply_Q(self, C, Y=None):
+        """Y = Q C for C ((m, k) tensor, column-major k x m); returns (m, n)."""
+        import torch
+        m, k = C.shape
+        assert k == self.k and C.is_contiguous()
+        if Y is None:
+            Y = torch.empty((m, self.n), dtype=torch.float64, device=self.device)
+        _check("orth_apply_Q", orth_apply_Q(self.h, C.data_ptr(), k, m, Y.data_ptr(), self.n))
+        return Y
+
+    def status(self):
+        code, st, info = orth_status(self.h)
+        _check("orth_status", code)
+        return st, info
+
+    def export_local(self):
+        """(Qloc (k, n) column-major n x k, T (k, p*k) column-major (p k) x k)."""
+        import torch
+        k = self.k
+        Qloc = torch.empty((k, self.n), dtype=torch.float64, device=self.device)
+        T = torch.empty((k, self.p * k), dtype=torch.float64, device=self.device)
+        _check("orth_export_local",
+               orth_export_local(self.h, Qloc.data_ptr(), self.n, T.data_ptr(), self.p * k))
+        return Qloc, T
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            orth_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def laplacian_apply(X, grid, shift=0.0, Y=None, stream=None):
+    """Y = A X with the library's test Laplacian; X is (s, n) float64 on the device."""
+    import torch
+    s, n = X.shape
+    nx, ny = grid[0], grid[1]
+    nz = grid[2] if len(grid) > 2 else 1
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check("orth_laplacian_apply", orth_laplacian_apply(X.data_ptr(), n, Y.data_ptr(), n, s, nx, ny,
+                                                        nz, float(shift), _stream_ptr(stream)))
+    return Y
