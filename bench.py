@@ -1,0 +1,309 @@
+#!/usr/bin/env python3
+"""Benchmark of the block-Arnoldi orthogonalisation hot path on one MI355X.
+
+Workload (one "step" of this benchmark): orthogonalise every block of a
+30-step block-Arnoldi run on the 2D Dirichlet 5-point Laplacian on a
+4096 x 4096 grid (n = 2^24 rows), block width s = 8, TSQR leaf height 4096
+(4096 leaves), basis kept in locally orthogonal form: orth_create on the
+workspace, then 31 orth_step calls (the start block, k = 0, and 30 Krylov
+blocks, k = 8 .. 240).  The 31 input blocks (the seeded N(0,1) start block
+and the A U_j blocks of the Arnoldi run) are generated on the GPU before
+timing and stay resident in HBM; the operator is not part of the timed work.
+
+Reported value: algorithmic HBM throughput of the whole sequence (GB/s,
+higher is better): sum over the 31 calls of
+    B(k) = 16 n (k + 2s) + 8 p (2 k^2 + 3 s (k + s))
+bytes (two reads of the basis and the block, writes of U_i and U, and the
+tree-factor traffic), divided by the measured time.  ``ms_per_step`` is the
+time of one whole 31-call sequence.  The roofline object refers to the
+dominant kernel class, timed live with HIP events on the handle's stream.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "block-Arnoldi orth step time + HBM GB/s, mixed vs FP64 at \u2016I\u2212Q\u1d40Q\u2016\u22641e-10"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(name="lap2d-4096x4096-s8", nx=4096, ny=4096, s=8, steps=30, leaf_rows=4096, seed=0)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2204_13393_amd", "csrc", "orth_kernels.hip")
+
+
+def step_bytes(n, s, p, k):
+    """Algorithmic bytes of one orth_step at basis width k."""
+    return 16.0 * n * (k + 2 * s) + 8.0 * p * (2.0 * k * k + 3.0 * s * (k + s))
+
+
+def kernel_bytes(cls, n, s, p, k):
+    """Algorithmic bytes one launch of a kernel class must move at width k."""
+    if cls == "leaf_gram":
+        return 8.0 * n * (k + s)                      # read Q_i, W_i
+    if cls == "leaf_correct":
+        return 8.0 * n * (k + s) + 8.0 * n * s        # read Q_i, W_i; write u1
+    if cls == "leaf_finalize":
+        return 8.0 * n * (k + s) + 16.0 * n * s       # read Q_i, u1; write U_i, U
+    tri = k * (k + 1) / 2.0
+    if cls == "root_gram":
+        return 8.0 * p * (tri + (k + s) * s)
+    if cls == "root_correct":
+        return 8.0 * p * (tri + 2.0 * (k + s) * s)
+    if cls == "root_finalize":
+        return 8.0 * p * (tri + 2.0 * (k + s) * s)
+    return 0.0
+
+
+def source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(kernel_cls):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except Exception:
+        return None
+    if t.get("kernel_source_sha256") != source_sha():
+        return None
+    ent = t.get("kernels", {}).get(kernel_cls)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(rows_nx=4096, rows_ny=128, s=8, steps=30):
+    """The oracle, untuned, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import block_arnoldi, pqr_reference
+    from oracle import operators as ops
+    from synth import normal_block
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    n = rows_nx * rows_ny
+    spent = [0.0]
+    widths = []
+
+    def timed(Q, X):
+        widths.append(Q.shape[1] if Q is not None else 0)
+        t0 = time.perf_counter()
+        r = pqr_reference(Q, X)
+        spent[0] += time.perf_counter() - t0
+        return r
+
+    R0 = normal_block(n, s, 0)
+    block_arnoldi(lambda X: ops.laplacian_2d_apply(X, rows_nx, rows_ny, 0.0), R0, steps, timed)
+    p = max(1, n // 4096)
+    total = sum(step_bytes(n, s, p, k) for k in widths)
+    return {
+        "value": total / spent[0] / 1e9,
+        "unit": "GB/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "seconds": spent[0],
+        "sample": (f"2D {rows_nx}x{rows_ny} Laplacian (n = {n}, 1/{(4096 * 4096) // n} of the rows), "
+                   f"s = {s}, start block + {steps} block-Arnoldi steps through the oracle's "
+                   "unique-PQR reference (BCGS2 + Householder, numpy FP64); operator time "
+                   "excluded; same algorithmic-byte formula as the GPU value"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (one MI355X); "
+              "multi-GPU sharding is design-only, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2204_13393_amd import orth, laplacian_apply
+    from synth import normal_block
+
+    orth.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W = WORKLOAD
+    nx, ny, s, steps, leaf = W["nx"], W["ny"], W["s"], W["steps"], W["leaf_rows"]
+    n = nx * ny
+    kmax = (steps + 1) * s
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+
+    print(f"[bench] generating inputs: n={n} s={s} steps={steps}", file=sys.stderr, flush=True)
+    # --- inputs: start block + 30 Krylov blocks, resident in HBM
+    R0 = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, W["seed"]).T)).to(dev)
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64)
+    ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    Xs = [R0]
+    V = torch.empty((kmax, n), dtype=torch.float64, device=dev)          # explicit U blocks
+    Hm = torch.zeros((steps * s, kmax), dtype=torch.float64, device=dev)  # column-major K x 30s
+    R0out = torch.empty((s, s), dtype=torch.float64, device=dev)
+
+    def run_sequence(blocks, h):
+        for j, X in enumerate(blocks):
+            k = j * s
+            U = V[k:k + s]
+            if j == 0:
+                code = orth.orth_step(h, X.data_ptr(), n, 0, 1, R0out.data_ptr(), s, U.data_ptr(), n)
+            else:
+                col = Hm[(j - 1) * s:j * s]
+                code = orth.orth_step(h, X.data_ptr(), n, col.data_ptr(), kmax,
+                                      col[:, k:].data_ptr(), kmax, U.data_ptr(), n)
+            if code:
+                raise orth.OrthError("orth_step", code)
+
+    def make_handle():
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sptr)
+        if code:
+            raise orth.OrthError("orth_create", code)
+        return h
+
+    # closed-loop Arnoldi once, to produce the Krylov blocks (not timed)
+    h = make_handle()
+    for j in range(steps + 1):
+        k = j * s
+        U = V[k:k + s]
+        if j == 0:
+            code = orth.orth_step(h, Xs[0].data_ptr(), n, 0, 1, R0out.data_ptr(), s, U.data_ptr(), n)
+        else:
+            col = Hm[(j - 1) * s:j * s]
+            code = orth.orth_step(h, Xs[j].data_ptr(), n, col.data_ptr(), kmax,
+                                  col[:, k:].data_ptr(), kmax, U.data_ptr(), n)
+        if code:
+            raise orth.OrthError("orth_step", code)
+        if j < steps:
+            Xs.append(laplacian_apply(U, (nx, ny), 0.0))
+    code, st, info = orth.orth_status(h)
+    if code or st:
+        raise RuntimeError(f"Arnoldi input generation failed: status {st} info {info}")
+    orth.orth_destroy(h)
+    torch.cuda.synchronize()
+    print("[bench] inputs ready", file=sys.stderr, flush=True)
+
+    # --- warmup
+    for _ in range(args.warmup):
+        h = make_handle()
+        run_sequence(Xs, h)
+        orth.orth_destroy(h)
+    torch.cuda.synchronize()
+
+    # --- timed region
+    handles = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    prof = {}
+    for _ in range(args.steps):
+        h = make_handle()
+        if not args.no_profile:
+            orth.orth_profile_enable(h, 1)
+        run_sequence(Xs, h)
+        handles.append(h)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
+    for h in handles:
+        code, st, info = orth.orth_status(h)
+        if code or st:
+            raise RuntimeError(f"orth_step breakdown: {info}")
+        if not args.no_profile:
+            code, p = orth.orth_profile_read(h)
+            for name, (ms, cnt) in p.items():
+                a = prof.setdefault(name, [0.0, 0])
+                a[0] += ms
+                a[1] += cnt
+        orth.orth_destroy(h)
+    ms_per_step = max(wall_ms, gpu_ms)
+    print(f"[bench] timed {args.steps} sequences: {ms_per_step:.2f} ms each", file=sys.stderr, flush=True)
+
+    # --- accuracy gate: e_perp of the explicit basis (torch GEMM, independent of the kernels)
+    G = torch.mm(V, V.t())
+    G -= torch.eye(kmax, dtype=torch.float64, device=dev)
+    e_perp = float(torch.linalg.matrix_norm(G, "fro"))
+    del G
+
+    p = max(1, n // leaf)
+    widths = [j * s for j in range(steps + 1)]
+    total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
+    value = total_bytes / (ms_per_step / 1e3) / 1e9
+
+    roofline = None
+    kernels = {}
+    if prof:
+        for name, (ms, cnt) in prof.items():
+            if cnt == 0:
+                continue
+            byts = sum(kernel_bytes(name, n, s, p, k) for k in widths) * args.steps
+            kernels[name] = {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3,
+                             "gbs": (byts / (ms / 1e3) / 1e9) if byts else None}
+        dom = max((k for k in kernels if kernel_bytes(k, n, s, p, 8) > 0),
+                  key=lambda k: kernels[k]["ms_total"])
+        d = kernels[dom]
+        byts_per_launch = sum(kernel_bytes(dom, n, s, p, k) for k in widths) / len(widths)
+        achieved = byts_per_launch / (d["avg_us"] / 1e6) / 1e9
+        traffic = load_traffic(dom)
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                    "avg_launch_us": d["avg_us"], "alg_bytes_per_launch": byts_per_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "ms_per_orth_call": ms_per_step / len(widths),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: N(0,1) start block (seed 0) and the A U_j Krylov blocks of a block-Arnoldi "
+                "run on the 2D Dirichlet Laplacian, generated on the GPU before timing",
+        "config": {"workload": W["name"], "n": n, "s": s, "arnoldi_steps": steps,
+                   "orth_calls_per_step": len(widths), "leaf_rows": leaf, "leaves": p,
+                   "k_max": kmax, "precision": "fp64", "variant": "BCGS-PIP+ leaves and reduction"},
+        "e_perp": e_perp,
+        "e_perp_gate_1e-10": e_perp <= 1e-10,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

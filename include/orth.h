@@ -172,6 +172,41 @@ int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows);
 int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq,
                       double *d_T, int64_t ldt);
 
+/* Kernel classes timed by the profiler (one class per launch site). */
+enum orth_kernel_class {
+    ORTH_K_LEAF_GRAM = 0,      /* leaves, sweep-1 Gram [Q_i W_i]^T W_i          */
+    ORTH_K_LEAF_CHOL = 1,      /* leaves, per-leaf Cholesky (both sweeps)       */
+    ORTH_K_LEAF_CORRECT = 2,   /* leaves, u1 = (w - q P1) N1^-1 + sweep-2 Gram  */
+    ORTH_K_ROOT_GRAM = 3,      /* reduction level, sweep-1 Gram                 */
+    ORTH_K_ROOT_CHOL = 4,      /* reduction level Cholesky (both sweeps)        */
+    ORTH_K_ROOT_CORRECT = 5,   /* reduction level correction + sweep-2 Gram     */
+    ORTH_K_ROOT_FINALIZE = 6,  /* reduction level new columns [P~_i; N~_i]      */
+    ORTH_K_LEAF_FINALIZE = 7,  /* leaves: U_i appended, explicit U assembled    */
+    ORTH_K_APPLY = 8,          /* orth_apply_Q launches                         */
+    ORTH_K_COUNT = 9
+};
+
+/*
+ * orth_profile_enable -- on != 0: every later launch of the handle is
+ * bracketed by a pair of HIP events recorded on the handle's stream; on = 0
+ * stops recording.  Events are host-side objects (no device allocation).
+ * Errors: ARG, HIP.
+ */
+int orth_profile_enable(orth_t *h, int32_t on);
+
+/*
+ * orth_profile_read -- synchronise the stream, then add the elapsed time of
+ * every recorded event pair to per-class totals and clear the record.
+ *   total_ms   array of ORTH_K_COUNT doubles: milliseconds per class
+ *   launches   array of ORTH_K_COUNT int64: launches per class
+ * Totals accumulate across reads until orth_profile_reset.
+ * Errors: ARG, HIP.
+ */
+int orth_profile_read(orth_t *h, double *total_ms, int64_t *launches);
+
+/* orth_profile_reset -- drop pending events and zero the totals. */
+int orth_profile_reset(orth_t *h);
+
 /*
  * orth_destroy -- release the host state.  The workspace stays owned by the
  * caller.  Always allowed, also on a poisoned handle; NULL is a no-op.

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/orth.h"
 #include "orth_internal.h"
@@ -140,6 +141,39 @@ struct orth_ctx {
     bool poisoned = false;
     hipStream_t stream = nullptr;
     double *ws = nullptr;
+    // profiler: event pairs recorded around launches
+    bool prof_on = false;
+    struct Mark { int cls; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
+    double prof_ms[ORTH_K_COUNT] = {};
+    int64_t prof_n[ORTH_K_COUNT] = {};
+
+    hipEvent_t get_event() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // bracket one launch; returns the mark index or -1
+    int begin(int cls) {
+        if (!prof_on) return -1;
+        Mark m{cls, get_event(), get_event()};
+        if (!m.a || !m.b || hipEventRecord(m.a, stream) != hipSuccess) return -1;
+        marks.push_back(m);
+        return (int)marks.size() - 1;
+    }
+    void end(int idx) {
+        if (idx >= 0) (void)hipEventRecord(marks[idx].b, stream);
+    }
+    ~orth_ctx() {
+        for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+        for (auto e : spare) (void)hipEventDestroy(e);
+    }
 
     double *Q() const { return ws + pl.oQ; }
     double *T() const { return ws + pl.oT; }
@@ -232,7 +266,9 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         a.partials = h->PL();
         a.part_stride = pstride;
         a.status = h->status();
+        const int pm = h->begin(ORTH_K_LEAF_GRAM);
         e = launch_gram(s, a, ncol, st);
+        h->end(pm);
         if (e != hipSuccess) goto fail;
     }
     {
@@ -251,7 +287,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         c.ldy = pl.ldt;
         c.yseg = kmax;
         c.status = h->status();
-        e = launch_chol(s, c, st);
+        { const int pm = h->begin(ORTH_K_LEAF_CHOL); e = launch_chol(s, c, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
 
         CorrectArgs b{};
@@ -268,11 +304,11 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         b.part_stride = pstride;
         b.write_gram = two ? 1 : 0;
         b.status = h->status();
-        e = launch_correct(s, b, ncol, st);
+        { const int pm = h->begin(ORTH_K_LEAF_CORRECT); e = launch_correct(s, b, ncol, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
         if (two) {
             c.sweep = 2;
-            e = launch_chol(s, c, st);
+            { const int pm = h->begin(ORTH_K_LEAF_CHOL); e = launch_chol(s, c, st); h->end(pm); }
             if (e != hipSuccess) goto fail;
         }
     }
@@ -288,7 +324,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         a.partials = h->PR();
         a.part_stride = pstride;
         a.status = h->status();
-        e = launch_gram(s, a, ncol, st);
+        { const int pm = h->begin(ORTH_K_ROOT_GRAM); e = launch_gram(s, a, ncol, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
 
         CholArgs c{};
@@ -307,7 +343,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         c.R = d_R;
         c.ldr = ldr;
         c.status = h->status();
-        e = launch_chol(s, c, st);
+        { const int pm = h->begin(ORTH_K_ROOT_CHOL); e = launch_chol(s, c, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
 
         CorrectArgs b{};
@@ -324,11 +360,11 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         b.part_stride = pstride;
         b.write_gram = two ? 1 : 0;
         b.status = h->status();
-        e = launch_correct(s, b, ncol, st);
+        { const int pm = h->begin(ORTH_K_ROOT_CORRECT); e = launch_correct(s, b, ncol, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
         if (two) {
             c.sweep = 2;
-            e = launch_chol(s, c, st);
+            { const int pm = h->begin(ORTH_K_ROOT_CHOL); e = launch_chol(s, c, st); h->end(pm); }
             if (e != hipSuccess) goto fail;
         }
         // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s]
@@ -344,7 +380,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.single_sweep = two ? 0 : 1;
         f.Cptr = nullptr;
         f.status = h->status();
-        e = launch_finalize(s, f, st);
+        { const int pm = h->begin(ORTH_K_ROOT_FINALIZE); e = launch_finalize(s, f, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
     }
     // ---- leaves: U_i appended to Q_i, explicit U|_i = [Q_i U_i] [P~_i; N~_i]
@@ -364,7 +400,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.cseg = kmax;
         f.Uout = OutOperand{d_U, ldu};
         f.status = h->status();
-        e = launch_finalize(s, f, st);
+        { const int pm = h->begin(ORTH_K_LEAF_FINALIZE); e = launch_finalize(s, f, st); h->end(pm); }
         if (e != hipSuccess) goto fail;
     }
     h->k = k + s;
@@ -393,7 +429,9 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         r.cseg = 0;
         r.m = mb;
         r.Y = OutOperand{h->CA(), pl.ldt};
+        const int pm0 = h->begin(ORTH_K_APPLY);
         hipError_t e = launch_apply(r, st);
+        h->end(pm0);
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         // leaves: Y_i = Q_i C_i
         ApplyArgs a{};
@@ -405,7 +443,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         a.cseg = pl.kmax;
         a.m = mb;
         a.Y = OutOperand{d_Y + (int64_t)j0 * ldy, ldy};
-        e = launch_apply(a, st);
+        { const int pm = h->begin(ORTH_K_APPLY); e = launch_apply(a, st); h->end(pm); }
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
     }
     return ORTH_OK;
@@ -457,6 +495,55 @@ int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64
         e = launch_copy_cols(h->T(), pl.ldt, RowMap{k, pl.kmax}, d_T, ldt, (int64_t)pl.p * k, k,
                              h->stream);
     if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+    return ORTH_OK;
+}
+
+int orth_profile_enable(orth_t *h, int32_t on) {
+    if (!h) return ORTH_ERR_ARG;
+    h->prof_on = on != 0;
+    return ORTH_OK;
+}
+
+int orth_profile_read(orth_t *h, double *total_ms, int64_t *launches) {
+    if (!h || !total_ms || !launches) return ORTH_ERR_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    for (auto &m : h->marks) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            h->prof_ms[m.cls] += ms;
+            h->prof_n[m.cls] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        h->spare.push_back(m.a);
+        h->spare.push_back(m.b);
+    }
+    h->marks.clear();
+    for (int c = 0; c < ORTH_K_COUNT; ++c) {
+        total_ms[c] = h->prof_ms[c];
+        launches[c] = h->prof_n[c];
+    }
+    return ORTH_OK;
+}
+
+int orth_profile_reset(orth_t *h) {
+    if (!h) return ORTH_ERR_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    for (auto &m : h->marks) {
+        h->spare.push_back(m.a);
+        h->spare.push_back(m.b);
+    }
+    h->marks.clear();
+    for (int c = 0; c < ORTH_K_COUNT; ++c) {
+        h->prof_ms[c] = 0.0;
+        h->prof_n[c] = 0;
+    }
     return ORTH_OK;
 }
 

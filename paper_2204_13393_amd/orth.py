@@ -43,6 +43,9 @@ SIGNATURES = [
     ("orth_basis_width", ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     ("orth_leaf_count", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_export_local", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64]),
+    ("orth_profile_enable", ctypes.c_int, [_vp, _i32]),
+    ("orth_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
+    ("orth_profile_reset", ctypes.c_int, [_vp]),
     ("orth_destroy", ctypes.c_int, [_vp]),
     ("orth_laplacian_apply", ctypes.c_int, [_dp, _i64, _dp, _i64, _i32, _i32, _i32, _i32,
                                             ctypes.c_double, _vp]),
@@ -126,6 +129,26 @@ def orth_leaf_count(h):
 
 def orth_export_local(h, d_Qloc, ldq, d_T, ldt):
     return load().orth_export_local(h, d_Qloc, ldq, d_T, ldt)
+
+
+KERNEL_CLASSES = ["leaf_gram", "leaf_chol", "leaf_correct", "root_gram", "root_chol",
+                  "root_correct", "root_finalize", "leaf_finalize", "apply"]
+
+
+def orth_profile_enable(h, on):
+    return load().orth_profile_enable(h, int(on))
+
+
+def orth_profile_read(h):
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    code = load().orth_profile_read(h, ms, cnt)
+    return code, {KERNEL_CLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def orth_profile_reset(h):
+    return load().orth_profile_reset(h)
 
 
 def orth_destroy(h):
