@@ -46,14 +46,14 @@ def step_bytes(n, s, p, k):
 
 def kernel_bytes(cls, n, s, p, k):
     """Algorithmic bytes one launch of a kernel class must move at width k."""
-    if cls == "leaf_gram":
-        return 8.0 * n * (k + s)                      # read Q_i, W_i
+    if cls in ("leaf_gram", "leaf_gram2"):
+        return 8.0 * n * (k + s)                      # read Q_i and W_i (or u1)
     if cls == "leaf_correct":
         return 8.0 * n * (k + s) + 8.0 * n * s        # read Q_i, W_i; write u1
     if cls == "leaf_finalize":
         return 8.0 * n * (k + s) + 16.0 * n * s       # read Q_i, u1; write U_i, U
     tri = k * (k + 1) / 2.0
-    if cls == "root_gram":
+    if cls in ("root_gram", "root_gram2"):
         return 8.0 * p * (tri + (k + s) * s)
     if cls == "root_correct":
         return 8.0 * p * (tri + 2.0 * (k + s) * s)

@@ -176,14 +176,16 @@ int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq,
 enum orth_kernel_class {
     ORTH_K_LEAF_GRAM = 0,      /* leaves, sweep-1 Gram [Q_i W_i]^T W_i          */
     ORTH_K_LEAF_CHOL = 1,      /* leaves, per-leaf Cholesky (both sweeps)       */
-    ORTH_K_LEAF_CORRECT = 2,   /* leaves, u1 = (w - q P1) N1^-1 + sweep-2 Gram  */
+    ORTH_K_LEAF_CORRECT = 2,   /* leaves, u1 = (w - q P1) N1^-1                 */
     ORTH_K_ROOT_GRAM = 3,      /* reduction level, sweep-1 Gram                 */
-    ORTH_K_ROOT_CHOL = 4,      /* reduction level Cholesky (both sweeps)        */
-    ORTH_K_ROOT_CORRECT = 5,   /* reduction level correction + sweep-2 Gram     */
+    ORTH_K_ROOT_CHOL = 4,      /* reduction level Cholesky and pre-sums         */
+    ORTH_K_ROOT_CORRECT = 5,   /* reduction level correction                    */
     ORTH_K_ROOT_FINALIZE = 6,  /* reduction level new columns [P~_i; N~_i]      */
     ORTH_K_LEAF_FINALIZE = 7,  /* leaves: U_i appended, explicit U assembled    */
     ORTH_K_APPLY = 8,          /* orth_apply_Q launches                         */
-    ORTH_K_COUNT = 9
+    ORTH_K_LEAF_GRAM2 = 9,     /* leaves, sweep-2 Gram [Q_i U1_i]^T U1_i        */
+    ORTH_K_ROOT_GRAM2 = 10,    /* reduction level, sweep-2 Gram                 */
+    ORTH_K_COUNT = 11
 };
 
 /*

@@ -30,10 +30,13 @@ using namespace orth;
 namespace {
 
 constexpr int64_t kAlign = 32;        // doubles (256 bytes)
-constexpr int kLeafChunk = 1024;      // rows per workgroup at the leaf level
+constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
 constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
 constexpr int kFinalChunk = 2048;     // rows per workgroup in the finalize pass
 constexpr int kApplyMB = 16;
+constexpr int kMaxRowGroups = 4;      // partial slots per chunk in the sweep-1 Gram
+constexpr int kReduceGroup = 16;      // slots pre-summed per group at the reduction level
+constexpr size_t kLdsLimit = 64 * 1024;
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -49,7 +52,7 @@ struct Plan {
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oSL, oSR, oST, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, total;
 };
 
 int32_t default_leaf_rows(int64_t n, int32_t kmax) {
@@ -64,8 +67,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
     if (precision != ORTH_FP64) return false;
     if (kmax + s > max_cols(s)) { *why = ORTH_ERR_UNSUPPORTED; return false; }
-    // finalize stages two (k x s) coefficient blocks in LDS; keep it within 64 KB
-    if ((2 * (int64_t)(kmax - s) * s + 2 * (int64_t)s * s) * 8 > 64 * 1024) {
+    // the widest step (k = kmax - s) must fit the LDS staging of the kernels
+    if (finalize_lds_bytes(kmax - s, s) > kLdsLimit) {
         *why = ORTH_ERR_UNSUPPORTED;
         return false;
     }
@@ -97,8 +100,9 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oU1L = take(pl.ldq * s);
     pl.oU1R = take(pl.ldt * s);
     pl.oCA = take(pl.ldt * kApplyMB);
-    pl.oPL = take((int64_t)pl.nchunkL * pstride);
-    pl.oPR = take((int64_t)pl.nchunkR * pstride);
+    pl.oPL = take((int64_t)pl.nchunkL * kMaxRowGroups * pstride);
+    pl.oPR = take((int64_t)pl.nchunkR * kMaxRowGroups * pstride);
+    pl.oPR2 = take(ceil_div((int64_t)pl.nchunkR * kMaxRowGroups, kReduceGroup) * pstride);
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
@@ -183,6 +187,7 @@ struct orth_ctx {
     double *CA() const { return ws + pl.oCA; }
     double *PL() const { return ws + pl.oPL; }
     double *PR() const { return ws + pl.oPR; }
+    double *PR2() const { return ws + pl.oPR2; }
     double *SL() const { return ws + pl.oSL; }
     double *SR() const { return ws + pl.oSR; }
     DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + pl.oST); }
@@ -236,6 +241,137 @@ int orth_set_variant(orth_t *h, int32_t variant) {
     return ORTH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One level of the tree: sweep-1 Gram, Cholesky, correction + sweep-2 Gram,
+// Cholesky (the final one writes [P; N] to the next level's X, or H and R at
+// the root).  Partial Gram slots are pre-summed in groups when a level has
+// more than kReduceGroup of them per leaf.
+struct LevelRun {
+    Operand Q, X;
+    OutOperand U1;
+    LevelGeom geom;
+    double *part, *part2;
+    double *small;
+    int level;
+    // final outputs
+    double *Yout;
+    int64_t ldy, yseg;
+    double *H;
+    int64_t ldh;
+    double *R;
+    int64_t ldr;
+};
+
+int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
+    hipStream_t st = h->stream;
+    const int64_t pstride = (int64_t)(kmax + s) * s;
+    const int cls0 = L.level == 0 ? 0 : 3;          // LEAF_* or ROOT_* classes
+    hipError_t e;
+
+    GramArgs ga{};
+    ga.Q = L.Q;
+    ga.X = L.X;
+    ga.k = k;
+    ga.tile_groups = gram_tile_groups(ncol);
+    ga.geom = L.geom;
+    ga.partials = L.part;
+    ga.part_stride = pstride;
+    ga.status = h->status();
+    {
+        const int pm = h->begin(cls0 + 0);
+        e = launch_gram(s, ga, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
+    CholArgs c{};
+    c.part_stride = pstride;
+    c.nleaf = L.geom.nleaf;
+    c.k = k;
+    c.kmax = kmax;
+    c.level = L.level;
+    c.final_sweep = two ? 2 : 1;
+    c.small = L.small;
+    c.small_stride = small_stride(kmax, s);
+    c.Yout = L.Yout;
+    c.ldy = L.ldy;
+    c.yseg = L.yseg;
+    c.H = L.H;
+    c.ldh = L.ldh;
+    c.R = L.R;
+    c.ldr = L.ldr;
+    c.status = h->status();
+
+    // sum the slots of each leaf; pre-reduce when a single leaf owns many
+    auto chol = [&](int sweep, int ppc) -> int {
+        c.sweep = sweep;
+        c.partials = L.part;
+        c.slots_per_leaf = L.geom.cpl * ppc;
+        c.slots_last = L.geom.cpl_last * ppc;
+        if (L.geom.nleaf == 1 && c.slots_last > kReduceGroup) {
+            ReduceArgs r{};
+            r.in = L.part;
+            r.stride = pstride;
+            r.nslots = c.slots_last;
+            r.group = kReduceGroup;
+            r.nentries = ncol * s;
+            r.out = L.part2;
+            r.status = h->status();
+            const int pm = h->begin(cls0 + 1);
+            e = launch_reduce(r, st);
+            h->end(pm);
+            if (e != hipSuccess) return ORTH_ERR_HIP;
+            c.partials = L.part2;
+            c.slots_per_leaf = c.slots_last = (int32_t)ceil_div(r.nslots, kReduceGroup);
+        }
+        const int pm = h->begin(cls0 + 1);
+        e = launch_chol(s, c, st);
+        h->end(pm);
+        return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
+    };
+    if (int rc = chol(1, gram_row_groups(ncol))) return rc;
+
+    // correction u1 = (x - q P1) N1^{-1}, stored to the level's U1 scratch
+    FinalizeArgs f{};
+    f.Q = L.Q;
+    f.Qnew = L.U1;
+    f.U1 = L.X;
+    f.sweep = 1;
+    f.k = k;
+    f.geom = L.geom;
+    f.small = L.small;
+    f.small_stride = small_stride(kmax, s);
+    f.kmax = kmax;
+    f.single_sweep = 0;
+    f.Cptr = nullptr;
+    f.status = h->status();
+    {
+        const int pm = h->begin(cls0 + 2);
+        e = launch_finalize(s, f, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
+    if (!two) return ORTH_OK;
+    // sweep-2 Gram [Q U1]^T U1
+    GramArgs g2 = ga;
+    g2.X = Operand{L.U1.ptr, L.U1.ld};
+    {
+        const int pm = h->begin(L.level == 0 ? ORTH_K_LEAF_GRAM2 : ORTH_K_ROOT_GRAM2);
+        e = launch_gram(s, g2, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
+    return chol(2, gram_row_groups(ncol));
+}
+
+}  // namespace
+
+extern "C" {
+
 int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ldh, double *d_R,
               int64_t ldr, double *d_U, int64_t ldu) {
     if (!h) return ORTH_ERR_ARG;
@@ -247,141 +383,60 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     if (k > 0 && (!d_H || ldh < k)) return ORTH_ERR_ARG;
     if (k + s > kmax) return ORTH_ERR_CAPACITY;
     const bool two = h->variant == ORTH_PIP_PLUS;
-    const int final_sweep = two ? 2 : 1;
     hipStream_t st = h->stream;
-    const int64_t pstride = (int64_t)(kmax + s) * s;
-    const int64_t sstride = small_stride(kmax, s);
     const int ncol = k + s;
-    hipError_t e = hipSuccess;
+    int rc;
 
     // ---- leaves: local PQR [Q_i W_i] = [Q_i U_i][[I, P_i], [0, N_i]]
-    const LevelGeom gL = leaf_geom(pl, kLeafChunk);
     {
-        GramArgs a{};
-        a.Q = Operand{h->Q(), pl.ldq};
-        a.X = Operand{d_W, ldw};
-        a.k = k;
-        a.tile_rows = gram_tile_rows(ncol, s);
-        a.geom = gL;
-        a.partials = h->PL();
-        a.part_stride = pstride;
-        a.status = h->status();
-        const int pm = h->begin(ORTH_K_LEAF_GRAM);
-        e = launch_gram(s, a, ncol, st);
-        h->end(pm);
-        if (e != hipSuccess) goto fail;
-    }
-    {
-        CholArgs c{};
-        c.partials = h->PL();
-        c.part_stride = pstride;
-        c.geom = gL;
-        c.k = k;
-        c.kmax = kmax;
-        c.sweep = 1;
-        c.level = 0;
-        c.final_sweep = final_sweep;
-        c.small = h->SL();
-        c.small_stride = sstride;
-        c.Yout = h->Y();
-        c.ldy = pl.ldt;
-        c.yseg = kmax;
-        c.status = h->status();
-        { const int pm = h->begin(ORTH_K_LEAF_CHOL); e = launch_chol(s, c, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
-
-        CorrectArgs b{};
-        b.Q = Operand{h->Q(), pl.ldq};
-        b.X = Operand{d_W, ldw};
-        b.U1 = OutOperand{h->U1L(), pl.ldq};
-        b.k = k;
-        b.tile_rows = correct_tile_rows(ncol, s);
-        b.geom = gL;
-        b.small = h->SL();
-        b.small_stride = sstride;
-        b.kmax = kmax;
-        b.partials = h->PL();
-        b.part_stride = pstride;
-        b.write_gram = two ? 1 : 0;
-        b.status = h->status();
-        { const int pm = h->begin(ORTH_K_LEAF_CORRECT); e = launch_correct(s, b, ncol, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
-        if (two) {
-            c.sweep = 2;
-            { const int pm = h->begin(ORTH_K_LEAF_CHOL); e = launch_chol(s, c, st); h->end(pm); }
-            if (e != hipSuccess) goto fail;
-        }
+        LevelRun L{};
+        L.Q = Operand{h->Q(), pl.ldq};
+        L.X = Operand{d_W, ldw};
+        L.U1 = OutOperand{h->U1L(), pl.ldq};
+        L.geom = leaf_geom(pl, kLeafChunk);
+        L.part = h->PL();
+        L.small = h->SL();
+        L.level = 0;
+        L.Yout = h->Y();
+        L.ldy = pl.ldt;
+        L.yseg = kmax;
+        if ((rc = run_level(h, L, k, two))) goto fail;
     }
     // ---- reduction: PQR on the stacked [[T_i, P_i], [0, N_i]] (segments of k+s rows)
     {
-        const LevelGeom gR = root_geom(pl, ncol, kRootChunk);
-        GramArgs a{};
-        a.Q = Operand{h->T(), pl.ldt};
-        a.X = Operand{h->Y(), pl.ldt};
-        a.k = k;
-        a.tile_rows = gram_tile_rows(ncol, s);
-        a.geom = gR;
-        a.partials = h->PR();
-        a.part_stride = pstride;
-        a.status = h->status();
-        { const int pm = h->begin(ORTH_K_ROOT_GRAM); e = launch_gram(s, a, ncol, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
+        LevelRun L{};
+        L.Q = Operand{h->T(), pl.ldt};
+        L.X = Operand{h->Y(), pl.ldt};
+        L.U1 = OutOperand{h->U1R(), pl.ldt};
+        L.geom = root_geom(pl, ncol, kRootChunk);
+        L.part = h->PR();
+        L.part2 = h->PR2();
+        L.small = h->SR();
+        L.level = 1;
+        L.H = k > 0 ? d_H : nullptr;
+        L.ldh = ldh;
+        L.R = d_R;
+        L.ldr = ldr;
+        if ((rc = run_level(h, L, k, two))) goto fail;
 
-        CholArgs c{};
-        c.partials = h->PR();
-        c.part_stride = pstride;
-        c.geom = gR;
-        c.k = k;
-        c.kmax = kmax;
-        c.sweep = 1;
-        c.level = 1;
-        c.final_sweep = final_sweep;
-        c.small = h->SR();
-        c.small_stride = sstride;
-        c.H = k > 0 ? d_H : nullptr;
-        c.ldh = ldh;
-        c.R = d_R;
-        c.ldr = ldr;
-        c.status = h->status();
-        { const int pm = h->begin(ORTH_K_ROOT_CHOL); e = launch_chol(s, c, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
-
-        CorrectArgs b{};
-        b.Q = Operand{h->T(), pl.ldt};
-        b.X = Operand{h->Y(), pl.ldt};
-        b.U1 = OutOperand{h->U1R(), pl.ldt};
-        b.k = k;
-        b.tile_rows = correct_tile_rows(ncol, s);
-        b.geom = gR;
-        b.small = h->SR();
-        b.small_stride = sstride;
-        b.kmax = kmax;
-        b.partials = h->PR();
-        b.part_stride = pstride;
-        b.write_gram = two ? 1 : 0;
-        b.status = h->status();
-        { const int pm = h->begin(ORTH_K_ROOT_CORRECT); e = launch_correct(s, b, ncol, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
-        if (two) {
-            c.sweep = 2;
-            { const int pm = h->begin(ORTH_K_ROOT_CHOL); e = launch_chol(s, c, st); h->end(pm); }
-            if (e != hipSuccess) goto fail;
-        }
         // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s]
         FinalizeArgs f{};
         f.Q = Operand{h->T(), pl.ldt};
         f.Qnew = OutOperand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
         f.U1 = Operand{h->U1R(), pl.ldt};
+        f.sweep = 2;
         f.k = k;
         f.geom = root_geom(pl, ncol, kFinalChunk);
         f.small = h->SR();
-        f.small_stride = sstride;
+        f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
         f.single_sweep = two ? 0 : 1;
         f.Cptr = nullptr;
         f.status = h->status();
-        { const int pm = h->begin(ORTH_K_ROOT_FINALIZE); e = launch_finalize(s, f, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
+        const int pm = h->begin(ORTH_K_ROOT_FINALIZE);
+        const hipError_t e = launch_finalize(s, f, st);
+        h->end(pm);
+        if (e != hipSuccess) { rc = ORTH_ERR_HIP; goto fail; }
     }
     // ---- leaves: U_i appended to Q_i, explicit U|_i = [Q_i U_i] [P~_i; N~_i]
     {
@@ -389,10 +444,11 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.Q = Operand{h->Q(), pl.ldq};
         f.Qnew = OutOperand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
         f.U1 = Operand{h->U1L(), pl.ldq};
+        f.sweep = 2;
         f.k = k;
         f.geom = leaf_geom(pl, kFinalChunk);
         f.small = h->SL();
-        f.small_stride = sstride;
+        f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
         f.single_sweep = two ? 0 : 1;
         f.Cptr = h->T() + (int64_t)k * pl.ldt;
@@ -400,14 +456,16 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.cseg = kmax;
         f.Uout = OutOperand{d_U, ldu};
         f.status = h->status();
-        { const int pm = h->begin(ORTH_K_LEAF_FINALIZE); e = launch_finalize(s, f, st); h->end(pm); }
-        if (e != hipSuccess) goto fail;
+        const int pm = h->begin(ORTH_K_LEAF_FINALIZE);
+        const hipError_t e = launch_finalize(s, f, st);
+        h->end(pm);
+        if (e != hipSuccess) { rc = ORTH_ERR_HIP; goto fail; }
     }
     h->k = k + s;
     return ORTH_OK;
 fail:
     (void)hipGetLastError();
-    return ORTH_ERR_HIP;
+    return rc;
 }
 
 int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {

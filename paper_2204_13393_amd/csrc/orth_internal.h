@@ -87,40 +87,37 @@ struct OutOperand {
 
 // ---- kernel launch descriptors (filled by the runtime) ----
 
-// pass A: partial [Q X]^T X per chunk
+// pass A: partial [Q X]^T X per chunk (and per row group of the chunk)
 struct GramArgs {
     Operand Q;            // k columns
     Operand X;            // s columns
     int32_t k;
-    int32_t tile_rows;
+    int32_t tile_groups;  // waves of a workgroup sharing the rows: 1, 2 or 4
     LevelGeom geom;
-    double *partials;     // [chunk][kmax + s][s]
-    int64_t part_stride;  // doubles per chunk slot
+    double *partials;     // slot (chunk * row_groups + rg): [k + s][s]
+    int64_t part_stride;  // doubles per slot
     const DevStatus *status;
 };
 
-// pass B: u1 = (x - q P1) N1^{-1}, store u1, partial [Q U1]^T U1 per chunk
-struct CorrectArgs {
-    Operand Q;
-    Operand X;
-    OutOperand U1;
-    int32_t k;
-    int32_t tile_rows;
-    LevelGeom geom;
-    const double *small;  // per-leaf records
-    int64_t small_stride;
-    int32_t kmax;
-    double *partials;
-    int64_t part_stride;
-    int32_t write_gram;   // 0: only u1 (single-sweep variant)
+// fixed-order pre-reduction of many partial slots of one leaf:
+// out[grp][e] = sum over slots [grp*group, min((grp+1)*group, nslots)) of in[slot][e]
+struct ReduceArgs {
+    const double *in;
+    int64_t stride;       // doubles per slot (in and out)
+    int32_t nslots;
+    int32_t group;
+    int32_t nentries;
+    double *out;
     const DevStatus *status;
 };
 
 // per-leaf Cholesky of one sweep (and the combination after sweep 2)
 struct CholArgs {
-    const double *partials;
+    const double *partials;   // slot (leaf * slots_per_leaf + i)
     int64_t part_stride;
-    LevelGeom geom;
+    int32_t nleaf;
+    int32_t slots_per_leaf;   // every leaf but the last
+    int32_t slots_last;       // the last leaf
     int32_t k;
     int32_t kmax;
     int32_t sweep;        // 1 or 2
@@ -140,11 +137,14 @@ struct CholArgs {
     DevStatus *status;
 };
 
-// pass C: u = (u1 - q P2) N2^{-1} -> new basis columns; optional Uout = [q u] C_leaf
+// row update: sweep 1: u1 = (x - q P1) N1^{-1} (U1 = x in, Qnew = u1 out);
+// sweep 2: u = (u1 - q P2) N2^{-1} -> new basis columns, optional explicit
+// Uout = [q u] C_leaf
 struct FinalizeArgs {
     Operand Q;            // k columns (read)
-    OutOperand Qnew;      // s new columns (write), same RowMap
-    Operand U1;
+    OutOperand Qnew;      // s output columns, same RowMap
+    Operand U1;           // s input columns (x for sweep 1, u1 for sweep 2)
+    int32_t sweep;        // which coefficients of the leaf record: 1 (P1, N1^-1) or 2 (P2, N2^-1)
     int32_t k;
     LevelGeom geom;
     const double *small;
@@ -173,8 +173,8 @@ struct ApplyArgs {
 };
 
 // launchers (orth_kernels.hip)
-hipError_t launch_gram(int s, const GramArgs &a, int ncol_alloc, hipStream_t st);
-hipError_t launch_correct(int s, const CorrectArgs &a, int ncol_alloc, hipStream_t st);
+hipError_t launch_gram(int s, const GramArgs &a, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st);
 hipError_t launch_finalize(int s, const FinalizeArgs &a, hipStream_t st);
 hipError_t launch_apply(const ApplyArgs &a, hipStream_t st);
@@ -186,9 +186,10 @@ hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy
                             int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);
 
-int gram_tile_rows(int ncol, int s);
-size_t gram_lds_bytes(int ncol, int s, int tile_rows);
-size_t correct_lds_bytes(int ncol, int s, int kmax, int tile_rows);
-int correct_tile_rows(int ncol, int s);
+// layout helpers shared with the runtime's planning
+int gram_tile_groups(int ncol);                 // waves per row group (1, 2, 4)
+int gram_col_groups(int ncol);                  // workgroups across the columns
+int gram_row_groups(int ncol);                  // partial slots per chunk
+size_t finalize_lds_bytes(int k, int s);        // dynamic LDS of k_finalize
 
 }  // namespace orth

@@ -10,11 +10,11 @@
 //   k_chol      per leaf: fixed-order sum of the chunk partials, the s x s
 //               Cholesky factor N of G - P^T P and its inverse; after the
 //               second sweep also the combination P = P1 + P2 N1, N = N2 N1.
-//   k_correct   sweep 2 (BCGS-PIP+, lines 3-4): u1 = (x - q P1) N1^{-1} row
-//               by row, stored, and the partial [Q U1]^T U1 of the same rows
-//               while the row tile is still in LDS.
-//   k_finalize  per row: u = (u1 - q P2) N2^{-1} appended to the level's
-//               local basis, and at the leaf level the explicit new block
+//   k_rowupdate per row: the correction u1 = (x - q P1) N1^{-1} of
+//               BCGS-PIP+ (its third line), whose sweep-2 Gram [Q U1]^T U1 is
+//               then k_gram again; and the finalize u = (u1 - q P2) N2^{-1}
+//               appended to the level's local basis, at the leaf level
+//               together with the explicit new block
 //               U|_i = [Q_i U_i] [P~_i; N~_i] (Sec. 4.1, assembly of U).
 //
 // Layout: every operand is column-major; rows are streamed in tiles with
@@ -32,187 +32,148 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-__device__ __forceinline__ bool failed(const DevStatus *st) {
-    return __builtin_nontemporal_load(&st->code) != 0;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bool failed(const DevStatus *st) { return st->code != 0; }
+
+// One 16x16x4 FP64 matrix-core product D += A B.  Lane roles (gfx950):
+// A[i][kk] is held by lane i + 16 kk, B[kk][j] by lane j + 16 kk, and
+// D[i][j] by lane j + 16 (i % 4) in accumulator register i / 4.
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__host__ __device__ __forceinline__ int odd_ld(int ncol) { return ncol | 1; }
+__device__ __forceinline__ dbl4 zero4() { return dbl4{0.0, 0.0, 0.0, 0.0}; }
 
-// Cross-wave fixed-order reduction of acc[CPT][S] (lanes = columns) and store
-// of the chunk's partial Gram block.  `red` needs kWaves*64*S doubles.
-template <int S, int CPT>
-__device__ __forceinline__ void store_partial(double (&acc)[CPT][S], double *red, int ncol,
-                                              double *out) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// 8 consecutive doubles starting at p (vector loads when 16-byte aligned)
+__device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        const double2 *q = reinterpret_cast<const double2 *>(p);
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < S; ++j) red[(wave * 64 + lane) * S + j] = acc[q][j];
-        __syncthreads();
-        for (int e = tid; e < 64 * S; e += kThreads) {
-            const int c = e / S + 64 * q;
-            if (c < ncol) {
-                double v = red[e];
-#pragma unroll
-                for (int w = 1; w < kWaves; ++w) v += red[w * 64 * S + e];
-                out[64 * q * S + e] = v;
-            }
+        for (int u = 0; u < 4; ++u) {
+            const double2 w = q[u];
+            v[2 * u] = w.x;
+            v[2 * u + 1] = w.y;
         }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[u];
     }
 }
 
-// Load rows [rt, rt+nr) of [A B] (ka columns of A then S of B) into a row-major
-// LDS tile tile[r*ldt + c]; rows >= nr are zero.
-template <int S>
-__device__ __forceinline__ void load_tile(const Operand &A, const Operand &B, int ka, int64_t rt,
-                                          int nr, int TR, const RowMap &map, double *tile,
-                                          int ldt, double *bt) {
-    const int tid = threadIdx.x;
-    const int rr = tid % TR;
-    const int cstep = kThreads / TR;
-    const bool rok = rr < nr;
-    const int64_t prow = map.phys(rt + (rok ? rr : 0));
-    const int ncol = ka + S;
-    for (int c = tid / TR; c < ncol; c += cstep) {
-        double v = 0.0;
-        if (rok) v = (c < ka) ? A.ptr[(int64_t)c * A.ld + prow] : B.ptr[(int64_t)(c - ka) * B.ld + prow];
-        tile[rr * ldt + c] = v;
-        if (c >= ka) bt[rr * S + (c - ka)] = v;
-    }
-}
+constexpr int kGramTPW = 4;   // 16-column tiles per wave in k_gram
 
 }  // namespace
 
 // ---------------------------------------------------------------- sweep 1
-template <int S, int CPT>
+// Partial [Q X]^T X of one row chunk on the matrix cores.  The columns of
+// Z = [Q X] are cut into 16-column tiles; a wave owns up to kGramTPW tiles
+// and one N tile per 16 columns of X.  The contraction runs over rows: in a
+// macro-step of 32 rows, lane group kk = lane/16 feeds rows r + 8 kk + t to
+// the t-th of 8 back-to-back products, so every lane streams 8 consecutive
+// rows (64 contiguous bytes) of one column straight from HBM; no LDS.
+// When the tiles do not fill all waves, the spare waves take other
+// macro-steps of the chunk (row groups) and write their own partial slots.
+template <int S>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     if (failed(a.status)) return;
-    extern __shared__ double lds[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k = a.k, ncol = k + S, TR = a.tile_rows, LDT = odd_ld(ncol);
-    double *tile = lds;
-    double *xt = lds + TR * LDT;
+    constexpr int NT = (S + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int il = lane & 15, g = lane >> 4;
+    const int k = a.k, ncol = k + S;
+    const int nmt = (ncol + 15) >> 4;
+    const int TG = a.tile_groups, RG = kWaves / TG;
+    const int tg = blockIdx.y * TG + wave % TG;
+    const int rg = wave / TG;
+    const int tile0 = tg * kGramTPW;
+    if (tile0 >= nmt) return;  // no columns for this wave (no barrier in this kernel)
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(blockIdx.x, leaf, r0, r1);
 
-    double acc[CPT][S];
+    const double *colp[kGramTPW];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q)
+    for (int t = 0; t < kGramTPW; ++t) {
+        const int c = (tile0 + t) * 16 + il;
+        colp[t] = c < k ? a.Q.ptr + (int64_t)c * a.Q.ld
+                        : (c < ncol ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr);
+    }
+    const double *xcol[NT];
 #pragma unroll
-        for (int j = 0; j < S; ++j) acc[q][j] = 0.0;
+    for (int nt = 0; nt < NT; ++nt) {
+        const int j = 16 * nt + il;
+        xcol[nt] = j < S ? a.X.ptr + (int64_t)j * a.X.ld : nullptr;
+    }
+    dbl4 acc[kGramTPW][NT];
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
 
-    for (int64_t rt = r0; rt < r1; rt += TR) {
-        const int nr = (int)((r1 - rt) < TR ? (r1 - rt) : TR);
-        __syncthreads();
-        load_tile<S>(a.Q, a.X, k, rt, nr, TR, a.geom.map, tile, LDT, xt);
-        __syncthreads();
-        for (int r = wave; r < nr; r += kWaves) {
-            double xv[S];
+    const bool ident = a.geom.map.seg_len == 0;
+    for (int64_t rm = r0 + 32 * rg; rm < r1; rm += 32 * RG) {
+        double av[kGramTPW][8], bv[NT][8];
+        const int64_t rb = rm + 8 * g;
+        if (ident && rm + 32 <= r1) {
 #pragma unroll
-            for (int j = 0; j < S; ++j) xv[j] = xt[r * S + j];
+            for (int t = 0; t < kGramTPW; ++t) {
+                if (colp[t]) load8(colp[t] + rb, av[t]);
+                else
 #pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                const int c = lane + 64 * q;
-                const double v = (c < ncol) ? tile[r * LDT + c] : 0.0;
+                    for (int u = 0; u < 8; ++u) av[t][u] = 0.0;
+            }
 #pragma unroll
-                for (int j = 0; j < S; ++j) acc[q][j] = fma(v, xv[j], acc[q][j]);
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) bv[nt][u] = xcol[nt] ? xcol[nt][rb + u] : 0.0;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t row = rb + u;
+                const bool ok = row < r1;
+                const int64_t prow = a.geom.map.phys(ok ? row : r0);
+#pragma unroll
+                for (int t = 0; t < kGramTPW; ++t) av[t][u] = (ok && colp[t]) ? colp[t][prow] : 0.0;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? xcol[nt][prow] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int t = 0; t < kGramTPW; ++t)
+                if (tile0 + t < nmt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = mfma16(av[t][u], bv[nt][u], acc[t][nt]);
+    }
+    double *out = a.partials + ((int64_t)blockIdx.x * RG + rg) * a.part_stride;
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t) {
+        if (tile0 + t >= nmt) break;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int j = 16 * nt + il;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = (tile0 + t) * 16 + 4 * v + g;
+                if (c < ncol && j < S) out[(int64_t)c * S + j] = acc[t][nt][v];
             }
         }
     }
-    store_partial<S, CPT>(acc, lds, ncol, a.partials + (int64_t)blockIdx.x * a.part_stride);
 }
 
-// ---------------------------------------------------------------- sweep 2
-// Projection lane layout: G = 256/TR lanes share one tile row and split the k
-// columns (c = g, g+G, ...); their partial sums meet in a butterfly over the
-// G lanes, which sit in the same wave (64/G rows per wave).
-template <int S, int CPT>
-__global__ __launch_bounds__(kThreads) void k_correct(CorrectArgs a) {
+// ---------------------------------------------------------------- reduce
+// Fixed-order pre-sum of groups of partial slots (one thread per entry).
+__global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
     if (failed(a.status)) return;
-    extern __shared__ double lds[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k = a.k, ncol = k + S, TR = a.tile_rows, LDT = odd_ld(ncol);
-    const int G = kThreads / TR;
-    double *tile = lds;                       // TR x LDT
-    double *xt = tile + TR * LDT;             // TR x S
-    double *ut = xt + TR * S;                 // TR x S
-    double *p1 = ut + TR * S;                 // k x S
-    double *n1i = p1 + (int64_t)k * S;        // S x S
-    int leaf;
-    int64_t r0, r1;
-    a.geom.chunk(blockIdx.x, leaf, r0, r1);
-    const double *rec = a.small + (int64_t)leaf * a.small_stride;
-    for (int e = tid; e < k * S; e += kThreads) p1[e] = rec[e];
-    for (int e = tid; e < S * S; e += kThreads) n1i[e] = rec[(int64_t)a.kmax * S + S * S + e];
-
-    double acc[CPT][S];
-#pragma unroll
-    for (int q = 0; q < CPT; ++q)
-#pragma unroll
-        for (int j = 0; j < S; ++j) acc[q][j] = 0.0;
-
-    // projection role of this thread: tile row pr, column phase g
-    const int g = lane % G;
-    const int pr = wave * (64 / G) + lane / G;
-
-    for (int64_t rt = r0; rt < r1; rt += TR) {
-        const int nr = (int)((r1 - rt) < TR ? (r1 - rt) : TR);
-        __syncthreads();
-        load_tile<S>(a.Q, a.X, k, rt, nr, TR, a.geom.map, tile, LDT, xt);
-        __syncthreads();
-        // y = x - q P1 (partial over this lane's columns, then butterfly)
-        double y[S];
-#pragma unroll
-        for (int j = 0; j < S; ++j) y[j] = 0.0;
-        for (int c = g; c < k; c += G) {
-            const double v = tile[pr * LDT + c];
-#pragma unroll
-            for (int j = 0; j < S; ++j) y[j] = fma(v, p1[c * S + j], y[j]);
-        }
-        for (int off = 1; off < G; off <<= 1) {
-#pragma unroll
-            for (int j = 0; j < S; ++j) y[j] += __shfl_xor(y[j], off, 64);
-        }
-        if (g == 0) {
-            double t[S];
-#pragma unroll
-            for (int j = 0; j < S; ++j) t[j] = xt[pr * S + j] - y[j];
-            // u1 = t N1^{-1} (upper triangular)
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                double u = 0.0;
-#pragma unroll
-                for (int i = 0; i <= j; ++i) u = fma(t[i], n1i[i * S + j], u);
-                ut[pr * S + j] = u;
-            }
-            if (pr < nr) {
-                const int64_t prow = a.geom.map.phys(rt + pr);
-#pragma unroll
-                for (int j = 0; j < S; ++j) a.U1.ptr[(int64_t)j * a.U1.ld + prow] = ut[pr * S + j];
-            }
-        }
-        __syncthreads();
-        if (a.write_gram) {
-            for (int r = wave; r < nr; r += kWaves) {
-                double uv[S];
-#pragma unroll
-                for (int j = 0; j < S; ++j) uv[j] = ut[r * S + j];
-#pragma unroll
-                for (int q = 0; q < CPT; ++q) {
-                    const int c = lane + 64 * q;
-                    double v = 0.0;
-                    if (c < k) v = tile[r * LDT + c];
-                    else if (c < ncol) v = ut[r * S + (c - k)];
-#pragma unroll
-                    for (int j = 0; j < S; ++j) acc[q][j] = fma(v, uv[j], acc[q][j]);
-                }
-            }
-        }
-    }
-    if (a.write_gram)
-        store_partial<S, CPT>(acc, lds, ncol, a.partials + (int64_t)blockIdx.x * a.part_stride);
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= a.nentries) return;
+    const int grp = blockIdx.y;
+    const int s0 = grp * a.group;
+    const int s1 = s0 + a.group < a.nslots ? s0 + a.group : a.nslots;
+    double v = 0.0;
+    for (int sl = s0; sl < s1; ++sl) v += a.in[(int64_t)sl * a.stride + e];
+    a.out[(int64_t)grp * a.stride + e] = v;
 }
 
 // ---------------------------------------------------------------- Cholesky
@@ -230,7 +191,8 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
     __shared__ int bad;
     if (tid == 0) bad = 0;
 
-    const int first = a.geom.first_chunk(leaf), cnt = a.geom.chunks_of(leaf);
+    const int first = leaf * a.slots_per_leaf;
+    const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < ncol * S; e += kThreads) {
         double v = 0.0;
         for (int p = 0; p < cnt; ++p) v += a.partials[(int64_t)(first + p) * a.part_stride + e];
@@ -329,35 +291,43 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- finalize
-template <int S, int RPT>
-__global__ __launch_bounds__(kThreads) void k_finalize(FinalizeArgs a) {
+// ---------------------------------------------------------------- row update
+// One thread per row (RPT rows per thread), the row's basis entries streamed
+// column by column with coalesced loads, the k x s coefficient blocks read as
+// LDS broadcasts.  Two uses:
+//   sweep 1 (correction):  u1 = (x - q P1) N1^{-1}            -> U1 scratch
+//   sweep 2 (finalize):    u  = (u1 - q P2) N2^{-1}           -> new basis columns
+//                          and, with EXPL, the explicit block
+//                          U|_i = q P~_i + u N~_i  (C = [P~_i; N~_i]).
+template <int S, int RPT, bool EXPL>
+__global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
     if (failed(a.status)) return;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int k = a.k;
-    double *p2 = lds;                         // k x S
-    double *cq = p2 + (int64_t)k * S;         // k x S   (C rows 0..k-1)
-    double *cn = cq + (int64_t)k * S;         // S x S   (C rows k..k+S-1)
-    double *n2i = cn + S * S;                 // S x S
+    double *pc = lds;                         // k x S   projection coefficients
+    double *cq = pc + (int64_t)k * S;         // k x S   C rows 0..k-1      (EXPL)
+    double *cn = cq + (EXPL ? (int64_t)k * S : 0);  // S x S   C rows k..k+S-1 (EXPL)
+    double *ni = cn + (EXPL ? S * S : 0);     // S x S   triangular inverse
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(blockIdx.x, leaf, r0, r1);
     const double *rec = a.small + (int64_t)leaf * a.small_stride;
-    const double *recP2 = rec + (int64_t)a.kmax * S + 2 * S * S;
-    const double *recN2i = recP2 + (int64_t)a.kmax * S;
-    const bool explicit_out = a.Cptr != nullptr;
+    // record: P1 [kmax][S] | N1 | N1^{-1} | P2 [kmax][S] | N2^{-1}
+    const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
+    const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
+    const bool ident_only = a.single_sweep != 0;   // u = u1 (one-sweep variant)
     for (int e = tid; e < k * S; e += kThreads) {
-        p2[e] = a.single_sweep ? 0.0 : recP2[e];
-        if (explicit_out) {
+        pc[e] = ident_only ? 0.0 : recP[e];
+        if (EXPL) {
             const int c = e / S, j = e % S;
             cq[e] = a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + c];
         }
     }
     for (int e = tid; e < S * S; e += kThreads) {
         const int i = e / S, j = e % S;
-        n2i[e] = a.single_sweep ? (i == j ? 1.0 : 0.0) : recN2i[e];
-        if (explicit_out) cn[e] = a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + k + i];
+        ni[e] = ident_only ? (i == j ? 1.0 : 0.0) : recNi[e];
+        if (EXPL) cn[e] = a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + k + i];
     }
     __syncthreads();
 
@@ -370,24 +340,30 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinalizeArgs a) {
             ok[i] = r < r1;
             prow[i] = a.geom.map.phys(ok[i] ? r : r0);
         }
-        double pa[RPT][S], pb[RPT][S];
+        double pa[RPT][S], pb[EXPL ? RPT : 1][S];
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
-            for (int j = 0; j < S; ++j) { pa[i][j] = 0.0; pb[i][j] = 0.0; }
-#pragma unroll 2
+            for (int j = 0; j < S; ++j) pa[i][j] = 0.0;
+        if (EXPL)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int j = 0; j < S; ++j) pb[EXPL ? i : 0][j] = 0.0;
+#pragma unroll 4
         for (int c = 0; c < k; ++c) {
             double q[RPT];
 #pragma unroll
             for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)c * a.Q.ld + prow[i]];
 #pragma unroll
             for (int j = 0; j < S; ++j) {
-                const double vp = p2[c * S + j];
-                const double vc = cq[c * S + j];
+                const double vp = pc[c * S + j];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    pa[i][j] = fma(q[i], vp, pa[i][j]);
-                    pb[i][j] = fma(q[i], vc, pb[i][j]);
+                for (int i = 0; i < RPT; ++i) pa[i][j] = fma(q[i], vp, pa[i][j]);
+                if (EXPL) {
+                    const double vc = cq[c * S + j];
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) pb[EXPL ? i : 0][j] = fma(q[i], vc, pb[EXPL ? i : 0][j]);
                 }
             }
         }
@@ -401,15 +377,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinalizeArgs a) {
             for (int j = 0; j < S; ++j) {
                 double v = 0.0;
 #pragma unroll
-                for (int l = 0; l <= j; ++l) v = fma(t[l], n2i[l * S + j], v);
+                for (int l = 0; l <= j; ++l) v = fma(t[l], ni[l * S + j], v);
                 u[j] = v;
                 a.Qnew.ptr[(int64_t)j * a.Qnew.ld + prow[i]] = v;
             }
-            if (explicit_out) {
+            if (EXPL) {
                 const int64_t r = base + tid + (int64_t)kThreads * i;
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
-                    double v = pb[i][j];
+                    double v = pb[EXPL ? i : 0][j];
 #pragma unroll
                     for (int l = 0; l <= j; ++l) v = fma(u[l], cn[l * S + j], v);
                     a.Uout.ptr[(int64_t)j * a.Uout.ld + r] = v;
@@ -536,73 +512,31 @@ static int grid_for(int64_t count, int threads) {
     return (int)b;
 }
 
-int gram_tile_rows(int ncol, int s) {
-    const int ldt = odd_ld(ncol);
-    const int budget = 40 * 1024;
-    for (int tr = 64; tr >= 8; tr >>= 1)
-        if ((size_t)tr * (ldt + 2 * s) * 8 <= (size_t)budget) return tr;
-    return 8;
+int gram_tile_groups(int ncol) {
+    const int nmt = (ncol + 15) / 16;
+    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
+    return groups <= 1 ? 1 : (groups <= 2 ? 2 : 4);
 }
 
-size_t gram_lds_bytes(int ncol, int s, int tr) {
-    const size_t tile = (size_t)tr * (odd_ld(ncol) + s) * 8;
-    const size_t red = (size_t)kWaves * 64 * s * 8;
-    return tile > red ? tile : red;
+int gram_col_groups(int ncol) {
+    const int nmt = (ncol + 15) / 16;
+    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
+    return groups <= 4 ? 1 : (groups + 3) / 4;
 }
 
-size_t correct_lds_bytes(int ncol, int s, int kmax, int tr) {
-    (void)kmax;
-    const int k = ncol - s;
-    const size_t tile = ((size_t)tr * (odd_ld(ncol) + 2 * s) + (size_t)k * s + (size_t)s * s) * 8;
-    const size_t red = (size_t)kWaves * 64 * s * 8;
-    return tile > red ? tile : red;
-}
+int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 
-int correct_tile_rows(int ncol, int s) {
-    for (int tr = 16; tr >= 8; tr >>= 1)
-        if (correct_lds_bytes(ncol, s, 0, tr) <= 60 * 1024) return tr;
-    return 8;
-}
-
-static int cpt_for(int ncol) {
-    const int c = (ncol + 63) / 64;
-    if (c <= 1) return 1;
-    if (c <= 2) return 2;
-    if (c <= 4) return 4;
-    return 8;
-}
-
-#define ORTH_DISPATCH_CPT(KERNEL, S, CPT, ARGS, LDS, GRID, ST)                                  \
-    switch (CPT) {                                                                              \
-        case 1: hipLaunchKernelGGL((KERNEL<S, 1>), GRID, dim3(kThreads), LDS, ST, ARGS); break; \
-        case 2: hipLaunchKernelGGL((KERNEL<S, 2>), GRID, dim3(kThreads), LDS, ST, ARGS); break; \
-        case 4: hipLaunchKernelGGL((KERNEL<S, 4>), GRID, dim3(kThreads), LDS, ST, ARGS); break; \
-        default:                                                                                \
-            if (8 * S > 64) return hipErrorInvalidValue;                                        \
-            hipLaunchKernelGGL((KERNEL<S, (8 * S > 64 ? 1 : 8)>), GRID, dim3(kThreads), LDS, ST, \
-                               ARGS);                                                           \
-            break;                                                                              \
-    }
+size_t finalize_lds_bytes(int k, int s) { return ((size_t)2 * k * s + 2 * (size_t)s * s) * 8; }
 
 template <int S>
 static hipError_t gram_s(const GramArgs &a, hipStream_t st) {
     const int ncol = a.k + S;
-    const size_t lds = gram_lds_bytes(ncol, S, a.tile_rows);
-    const dim3 grid(a.geom.nchunks());
-    ORTH_DISPATCH_CPT(k_gram, S, cpt_for(ncol), a, lds, grid, st);
+    const dim3 grid(a.geom.nchunks(), gram_col_groups(ncol));
+    hipLaunchKernelGGL((k_gram<S>), grid, dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 
-template <int S>
-static hipError_t correct_s(const CorrectArgs &a, hipStream_t st) {
-    const int ncol = a.k + S;
-    const size_t lds = correct_lds_bytes(ncol, S, a.kmax, a.tile_rows);
-    const dim3 grid(a.geom.nchunks());
-    ORTH_DISPATCH_CPT(k_correct, S, cpt_for(ncol), a, lds, grid, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_gram(int s, const GramArgs &a, int, hipStream_t st) {
+hipError_t launch_gram(int s, const GramArgs &a, hipStream_t st) {
     switch (s) {
         case 1: return gram_s<1>(a, st);
         case 2: return gram_s<2>(a, st);
@@ -613,21 +547,17 @@ hipError_t launch_gram(int s, const GramArgs &a, int, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_correct(int s, const CorrectArgs &a, int, hipStream_t st) {
-    switch (s) {
-        case 1: return correct_s<1>(a, st);
-        case 2: return correct_s<2>(a, st);
-        case 4: return correct_s<4>(a, st);
-        case 8: return correct_s<8>(a, st);
-        case 16: return correct_s<16>(a, st);
-    }
-    return hipErrorInvalidValue;
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st) {
+    const int ngrp = (a.nslots + a.group - 1) / a.group;
+    const dim3 grid((a.nentries + kThreads - 1) / kThreads, ngrp);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(kThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 template <int S>
 static hipError_t chol_s(const CholArgs &a, hipStream_t st) {
     const size_t lds = ((size_t)(a.k + S) * S + 3 * S * S) * 8;
-    hipLaunchKernelGGL((k_chol<S>), dim3(a.geom.nleaf), dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -643,20 +573,24 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
 }
 
 template <int S>
-static hipError_t finalize_s(const FinalizeArgs &a, hipStream_t st) {
-    const size_t lds = ((size_t)2 * a.k * S + 2 * S * S) * 8;
+static hipError_t rowupdate_s(const FinalizeArgs &a, hipStream_t st) {
     constexpr int RPT = S >= 16 ? 1 : 2;
-    hipLaunchKernelGGL((k_finalize<S, RPT>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
+    const bool expl = a.Cptr != nullptr;
+    const size_t lds = finalize_lds_bytes(a.k, S) - (expl ? 0 : ((size_t)a.k * S + S * S) * 8);
+    if (expl)
+        hipLaunchKernelGGL((k_rowupdate<S, RPT, true>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_rowupdate<S, RPT, false>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(int s, const FinalizeArgs &a, hipStream_t st) {
     switch (s) {
-        case 1: return finalize_s<1>(a, st);
-        case 2: return finalize_s<2>(a, st);
-        case 4: return finalize_s<4>(a, st);
-        case 8: return finalize_s<8>(a, st);
-        case 16: return finalize_s<16>(a, st);
+        case 1: return rowupdate_s<1>(a, st);
+        case 2: return rowupdate_s<2>(a, st);
+        case 4: return rowupdate_s<4>(a, st);
+        case 8: return rowupdate_s<8>(a, st);
+        case 16: return rowupdate_s<16>(a, st);
     }
     return hipErrorInvalidValue;
 }

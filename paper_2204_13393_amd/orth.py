@@ -132,7 +132,8 @@ def orth_export_local(h, d_Qloc, ldq, d_T, ldt):
 
 
 KERNEL_CLASSES = ["leaf_gram", "leaf_chol", "leaf_correct", "root_gram", "root_chol",
-                  "root_correct", "root_finalize", "leaf_finalize", "apply"]
+                  "root_correct", "root_finalize", "leaf_finalize", "apply", "leaf_gram2",
+                  "root_gram2"]
 
 
 def orth_profile_enable(h, on):
