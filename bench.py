@@ -129,11 +129,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="after timing, run one plain copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (one MI355X); "
-              "multi-GPU sharding is design-only, see DESIGN.md", file=sys.stderr)
+              "sharding across GPUs is not part of it", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -272,6 +274,16 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                     "avg_launch_us": d["avg_us"], "alg_bytes_per_launch": byts_per_launch}
+
+    if args.copy_probe_gib > 0:
+        cnt = int(args.copy_probe_gib * (1 << 30)) // 8
+        src = torch.ones(cnt, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        if orth.orth_probe_copy(src.data_ptr(), dst.data_ptr(), cnt, sptr):
+            raise RuntimeError("copy probe failed")
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -284,7 +284,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     ga.status = h->status();
     {
         const int pm = h->begin(cls0 + 0);
-        e = launch_gram(s, ga, st);
+        e = launch_gram(s, ga, cls0 + 0, st);
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
@@ -351,7 +351,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     f.status = h->status();
     {
         const int pm = h->begin(cls0 + 2);
-        e = launch_finalize(s, f, st);
+        e = launch_finalize(s, f, cls0 + 2, st);
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
@@ -360,8 +360,9 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     GramArgs g2 = ga;
     g2.X = Operand{L.U1.ptr, L.U1.ld};
     {
-        const int pm = h->begin(L.level == 0 ? ORTH_K_LEAF_GRAM2 : ORTH_K_ROOT_GRAM2);
-        e = launch_gram(s, g2, st);
+        const int cls2 = L.level == 0 ? ORTH_K_LEAF_GRAM2 : ORTH_K_ROOT_GRAM2;
+        const int pm = h->begin(cls2);
+        e = launch_gram(s, g2, cls2, st);
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
@@ -434,7 +435,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.Cptr = nullptr;
         f.status = h->status();
         const int pm = h->begin(ORTH_K_ROOT_FINALIZE);
-        const hipError_t e = launch_finalize(s, f, st);
+        const hipError_t e = launch_finalize(s, f, ORTH_K_ROOT_FINALIZE, st);
         h->end(pm);
         if (e != hipSuccess) { rc = ORTH_ERR_HIP; goto fail; }
     }
@@ -457,7 +458,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.Uout = OutOperand{d_U, ldu};
         f.status = h->status();
         const int pm = h->begin(ORTH_K_LEAF_FINALIZE);
-        const hipError_t e = launch_finalize(s, f, st);
+        const hipError_t e = launch_finalize(s, f, ORTH_K_LEAF_FINALIZE, st);
         h->end(pm);
         if (e != hipSuccess) { rc = ORTH_ERR_HIP; goto fail; }
     }

@@ -74,7 +74,9 @@ constexpr int kGramTPW = 4;   // 16-column tiles per wave in k_gram
 // rows (64 contiguous bytes) of one column straight from HBM; no LDS.
 // When the tiles do not fill all waves, the spare waves take other
 // macro-steps of the chunk (row groups) and write their own partial slots.
-template <int S>
+// CLS (the launch site's profiler class) only names the instantiation, so a
+// kernel trace attributes every dispatch to its role.
+template <int S, int CLS>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
 //   sweep 2 (finalize):    u  = (u1 - q P2) N2^{-1}           -> new basis columns
 //                          and, with EXPL, the explicit block
 //                          U|_i = q P~_i + u N~_i  (C = [P~_i; N~_i]).
-template <int S, int RPT, bool EXPL>
+template <int S, int RPT, bool EXPL, int CLS>
 __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
     if (failed(a.status)) return;
     extern __shared__ double lds[];
@@ -529,20 +531,25 @@ int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 size_t finalize_lds_bytes(int k, int s) { return ((size_t)2 * k * s + 2 * (size_t)s * s) * 8; }
 
 template <int S>
-static hipError_t gram_s(const GramArgs &a, hipStream_t st) {
+static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
     const int ncol = a.k + S;
     const dim3 grid(a.geom.nchunks(), gram_col_groups(ncol));
-    hipLaunchKernelGGL((k_gram<S>), grid, dim3(kThreads), 0, st, a);
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((k_gram<S, 0>), grid, dim3(kThreads), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_gram<S, 3>), grid, dim3(kThreads), 0, st, a); break;
+        case 9: hipLaunchKernelGGL((k_gram<S, 9>), grid, dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_gram<S, 10>), grid, dim3(kThreads), 0, st, a); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_gram(int s, const GramArgs &a, hipStream_t st) {
+hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st) {
     switch (s) {
-        case 1: return gram_s<1>(a, st);
-        case 2: return gram_s<2>(a, st);
-        case 4: return gram_s<4>(a, st);
-        case 8: return gram_s<8>(a, st);
-        case 16: return gram_s<16>(a, st);
+        case 1: return gram_s<1>(a, cls, st);
+        case 2: return gram_s<2>(a, cls, st);
+        case 4: return gram_s<4>(a, cls, st);
+        case 8: return gram_s<8>(a, cls, st);
+        case 16: return gram_s<16>(a, cls, st);
     }
     return hipErrorInvalidValue;
 }
@@ -573,24 +580,30 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
 }
 
 template <int S>
-static hipError_t rowupdate_s(const FinalizeArgs &a, hipStream_t st) {
-    constexpr int RPT = S >= 16 ? 1 : 2;
+static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
+    constexpr int RPT = S >= 16 ? 2 : 4;
     const bool expl = a.Cptr != nullptr;
     const size_t lds = finalize_lds_bytes(a.k, S) - (expl ? 0 : ((size_t)a.k * S + S * S) * 8);
-    if (expl)
-        hipLaunchKernelGGL((k_rowupdate<S, RPT, true>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
-    else
-        hipLaunchKernelGGL((k_rowupdate<S, RPT, false>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
+    const dim3 grid(a.geom.nchunks());
+    if (expl) {
+        hipLaunchKernelGGL((k_rowupdate<S, RPT, true, 7>), grid, dim3(kThreads), lds, st, a);
+    } else {
+        switch (cls) {
+            case 2: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 2>), grid, dim3(kThreads), lds, st, a); break;
+            case 5: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 5>), grid, dim3(kThreads), lds, st, a); break;
+            default: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 6>), grid, dim3(kThreads), lds, st, a); break;
+        }
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int s, const FinalizeArgs &a, hipStream_t st) {
+hipError_t launch_finalize(int s, const FinalizeArgs &a, int cls, hipStream_t st) {
     switch (s) {
-        case 1: return rowupdate_s<1>(a, st);
-        case 2: return rowupdate_s<2>(a, st);
-        case 4: return rowupdate_s<4>(a, st);
-        case 8: return rowupdate_s<8>(a, st);
-        case 16: return rowupdate_s<16>(a, st);
+        case 1: return rowupdate_s<1>(a, cls, st);
+        case 2: return rowupdate_s<2>(a, cls, st);
+        case 4: return rowupdate_s<4>(a, cls, st);
+        case 8: return rowupdate_s<8>(a, cls, st);
+        case 16: return rowupdate_s<16>(a, cls, st);
     }
     return hipErrorInvalidValue;
 }
