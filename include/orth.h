@@ -77,9 +77,10 @@ enum orth_variant {
 /*
  * orth_workspace_bytes -- device workspace size for orth_create.
  *   n          rows of the basis (>= 1)
- *   s          block width, one of 1, 2, 4, 8, 16
+ *   s          block width, one of 1, 2, 4, 8, 16, 32
  *   k_max      largest basis width the handle will reach (multiple of s,
- *              s <= k_max); a step that would pass it fails with CAPACITY
+ *              s <= k_max, k_max + s <= 2048); a step that would pass it
+ *              fails with CAPACITY
  *   leaf_rows  TSQR leaf height; 0 picks the default
  *              max(k_max, min(n, 4096)); leaves are
  *              p = max(1, n / leaf_rows) row blocks of leaf_rows rows, the

@@ -19,6 +19,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -34,17 +35,15 @@ constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
 constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
 constexpr int kFinalChunk = 2048;     // rows per workgroup in the finalize pass
 constexpr int kApplyMB = 16;
-constexpr int kMaxRowGroups = 4;      // partial slots per chunk in the sweep-1 Gram
 constexpr int kReduceGroup = 16;      // slots pre-summed per group at the reduction level
-constexpr size_t kLdsLimit = 64 * 1024;
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-bool valid_s(int32_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16; }
+bool valid_s(int32_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16 || s == 32; }
 
-// widest [Q X] a level kernel supports for block width s
-int32_t max_cols(int32_t) { return 256; }
+// widest basis (k_max + s) the planner accepts
+int32_t max_cols(int32_t) { return 2048; }
 
 struct Plan {
     int64_t n;
@@ -67,11 +66,6 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
     if (precision != ORTH_FP64) return false;
     if (kmax + s > max_cols(s)) { *why = ORTH_ERR_UNSUPPORTED; return false; }
-    // the widest step (k = kmax - s) must fit the LDS staging of the kernels
-    if (finalize_lds_bytes(kmax - s, s) > kLdsLimit) {
-        *why = ORTH_ERR_UNSUPPORTED;
-        return false;
-    }
     if (leaf_rows == 0) leaf_rows = default_leaf_rows(n, kmax);
     if (leaf_rows < kmax || leaf_rows > n) return false;
     if (n > ((int64_t)1 << 40)) return false;
@@ -87,7 +81,6 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
     pl.nchunkR = (int32_t)ceil_div((int64_t)pl.p * kmax, kRootChunk);
-    const int64_t pstride = (int64_t)(kmax + s) * s;
     int64_t off = 0;
     auto take = [&](int64_t count) {
         const int64_t o = off;
@@ -100,9 +93,19 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oU1L = take(pl.ldq * s);
     pl.oU1R = take(pl.ldt * s);
     pl.oCA = take(pl.ldt * kApplyMB);
-    pl.oPL = take((int64_t)pl.nchunkL * kMaxRowGroups * pstride);
-    pl.oPR = take((int64_t)pl.nchunkR * kMaxRowGroups * pstride);
-    pl.oPR2 = take(ceil_div((int64_t)pl.nchunkR * kMaxRowGroups, kReduceGroup) * pstride);
+    // partial Gram slots are packed per step: chunk c, row group g at
+    // (c * RG + g) * (k + s) * s; size for the largest step
+    int64_t slot_max = 0, red_max = 0;
+    for (int32_t k = 0; k + s <= kmax; k += s) {
+        const int32_t ncol = k + s;
+        const int64_t per = (int64_t)gram_row_groups(ncol) * ncol * s;
+        const int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
+        slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
+        red_max = std::max(red_max, ceil_div(nR * gram_row_groups(ncol), kReduceGroup) * ncol * s);
+    }
+    pl.oPL = take(slot_max);
+    pl.oPR = take(slot_max);
+    pl.oPR2 = take(red_max);
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
@@ -269,7 +272,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     const Plan &pl = h->pl;
     const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
     hipStream_t st = h->stream;
-    const int64_t pstride = (int64_t)(kmax + s) * s;
+    const int64_t pstride = (int64_t)ncol * s;    // packed slot stride of this step
     const int cls0 = L.level == 0 ? 0 : 3;          // LEAF_* or ROOT_* classes
     hipError_t e;
 

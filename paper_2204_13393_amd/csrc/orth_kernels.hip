@@ -179,38 +179,73 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
 }
 
 // ---------------------------------------------------------------- Cholesky
+// Per leaf: sum the leaf's partial Gram slots in slot order, store P to the
+// leaf record, form G - P^T P in row chunks staged through LDS, factor it
+// (right-looking upper Cholesky, lane j owns column j), invert the factor by
+// back substitution, and after the final sweep combine the sweeps and write
+// [P; N] to the next level (or H and R at the root).
+constexpr int kCholCB = 64;   // P rows per LDS chunk
+
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
     if (failed(a.status)) return;
-    extern __shared__ double lds[];
+    constexpr int EPT = (S * S + kThreads - 1) / kThreads;   // S x S entries per thread
+    __shared__ double gs[S * S], sm[S * S], nm[S * S], ni[S * S], n1[S * S];
+    __shared__ double pc[kCholCB * S];
+    __shared__ int bad;
     const int tid = threadIdx.x;
     const int leaf = blockIdx.x;
     const int k = a.k, ncol = k + S;
-    double *pg = lds;                         // ncol x S : [P; G]
-    double *sm = pg + (int64_t)ncol * S;      // S x S work (G - P^T P, then updated)
-    double *nm = sm + S * S;                  // N
-    double *ni = nm + S * S;                  // N^{-1}
-    __shared__ int bad;
     if (tid == 0) bad = 0;
+    double *rec = a.small + (int64_t)leaf * a.small_stride;
+    double *recP1 = rec;
+    double *recN1 = rec + (int64_t)a.kmax * S;
+    double *recN1i = recN1 + S * S;
+    double *recP2 = recN1i + S * S;
+    double *recN2i = recP2 + (int64_t)a.kmax * S;
+    double *recP = a.sweep == 1 ? recP1 : recP2;
 
+    // 1. fixed-order slot sum: P -> leaf record, G -> LDS
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < ncol * S; e += kThreads) {
         double v = 0.0;
-        for (int p = 0; p < cnt; ++p) v += a.partials[(int64_t)(first + p) * a.part_stride + e];
-        pg[e] = v;
+        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        if (e < k * S) recP[e] = v;
+        else gs[e - k * S] = v;
+    }
+    if (a.sweep == 2 && a.final_sweep == 2)
+        for (int e = tid; e < S * S; e += kThreads) n1[e] = recN1[e];
+    __syncthreads();
+    // 2. sm = G - P^T P, P streamed through LDS in row chunks
+    double d[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) d[m] = 0.0;
+    for (int c0 = 0; c0 < k; c0 += kCholCB) {
+        const int cb = (k - c0) < kCholCB ? (k - c0) : kCholCB;
+        for (int e = tid; e < cb * S; e += kThreads) pc[e] = recP[(int64_t)c0 * S + e];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EPT; ++m) {
+            const int e = tid + kThreads * m;
+            if (e < S * S) {
+                const int i = e / S, j = e % S;
+                for (int c = 0; c < cb; ++c) d[m] = fma(pc[c * S + i], pc[c * S + j], d[m]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+        const int e = tid + kThreads * m;
+        if (e < S * S) {
+            sm[e] = gs[e] - d[m];
+            nm[e] = 0.0;
+            ni[e] = 0.0;
+        }
     }
     __syncthreads();
-    for (int e = tid; e < S * S; e += kThreads) {
-        const int i = e / S, j = e % S;
-        double d = 0.0;
-        for (int c = 0; c < k; ++c) d = fma(pg[c * S + i], pg[c * S + j], d);
-        sm[e] = pg[(k + i) * S + j] - d;
-        nm[e] = 0.0;
-        ni[e] = 0.0;
-    }
-    __syncthreads();
-    // right-looking upper Cholesky: N^T N = sm, lane j owns column j
+    // 3. right-looking upper Cholesky: N^T N = sm
     for (int kk = 0; kk < S; ++kk) {
         if (tid == kk) {
             const double piv = sm[kk * S + kk];
@@ -237,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
         }
         return;
     }
-    // N^{-1}, lane j owns column j (back substitution)
+    // 4. N^{-1}, lane j owns column j
     if (tid < S) {
         const int j = tid;
         ni[j * S + j] = 1.0 / nm[j * S + j];
@@ -248,40 +283,29 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
         }
     }
     __syncthreads();
-    double *rec = a.small + (int64_t)leaf * a.small_stride;
-    double *recP1 = rec;
-    double *recN1 = rec + (int64_t)a.kmax * S;
-    double *recN1i = recN1 + S * S;
-    double *recP2 = recN1i + S * S;
-    double *recN2i = recP2 + (int64_t)a.kmax * S;
     if (a.sweep == 1) {
-        for (int e = tid; e < k * S; e += kThreads) recP1[e] = pg[e];
         for (int e = tid; e < S * S; e += kThreads) { recN1[e] = nm[e]; recN1i[e] = ni[e]; }
     } else {
-        for (int e = tid; e < k * S; e += kThreads) recP2[e] = pg[e];
         for (int e = tid; e < S * S; e += kThreads) recN2i[e] = ni[e];
     }
     if (a.sweep != a.final_sweep) return;
-    // [P; N] of this leaf:  sweep 1 only -> (P1, N1);  two sweeps ->
-    // P = P1 + P2 N1, N = N2 N1 (the reiteration combination).
+    // 5. [P; N] of this leaf: one sweep -> (P1, N1); two sweeps ->
+    //    P = P1 + P2 N1, N = N2 N1 (the reiteration combination)
     const int64_t ybase = (int64_t)leaf * a.yseg;
     for (int e = tid; e < ncol * S; e += kThreads) {
         const int c = e / S, j = e % S;
         double v;
         if (c < k) {
-            if (a.sweep == 1) {
-                v = pg[e];
-            } else {
-                v = recP1[e];
-                for (int i = 0; i <= j; ++i) v = fma(pg[c * S + i], recN1[i * S + j], v);
-            }
+            v = recP1[e];
+            if (a.sweep == 2)
+                for (int i = 0; i <= j; ++i) v = fma(recP2[c * S + i], n1[i * S + j], v);
         } else {
             const int i = c - k;
             if (a.sweep == 1) {
                 v = nm[i * S + j];
             } else {
                 v = 0.0;
-                for (int l = i; l <= j; ++l) v = fma(nm[i * S + l], recN1[l * S + j], v);
+                for (int l = i; l <= j; ++l) v = fma(nm[i * S + l], n1[l * S + j], v);
             }
         }
         if (a.Yout) a.Yout[(int64_t)j * a.ldy + ybase + c] = v;
@@ -295,22 +319,24 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
 
 // ---------------------------------------------------------------- row update
 // One thread per row (RPT rows per thread), the row's basis entries streamed
-// column by column with coalesced loads, the k x s coefficient blocks read as
-// LDS broadcasts.  Two uses:
+// column by column with coalesced loads, the k x s coefficient blocks staged
+// through LDS in blocks of kRowCB columns and read as broadcasts.  Two uses:
 //   sweep 1 (correction):  u1 = (x - q P1) N1^{-1}            -> U1 scratch
 //   sweep 2 (finalize):    u  = (u1 - q P2) N2^{-1}           -> new basis columns
 //                          and, with EXPL, the explicit block
 //                          U|_i = q P~_i + u N~_i  (C = [P~_i; N~_i]).
+constexpr int kRowCB = 64;
+
 template <int S, int RPT, bool EXPL, int CLS>
 __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
     if (failed(a.status)) return;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int k = a.k;
-    double *pc = lds;                         // k x S   projection coefficients
-    double *cq = pc + (int64_t)k * S;         // k x S   C rows 0..k-1      (EXPL)
-    double *cn = cq + (EXPL ? (int64_t)k * S : 0);  // S x S   C rows k..k+S-1 (EXPL)
-    double *ni = cn + (EXPL ? S * S : 0);     // S x S   triangular inverse
+    double *pc = lds;                                   // kRowCB x S  projection block
+    double *cq = pc + kRowCB * S;                       // kRowCB x S  C rows (EXPL)
+    double *ni = cq + (EXPL ? kRowCB * S : 0);          // S x S       triangular inverse
+    double *cn = ni + S * S;                            // S x S       C rows k..k+S-1 (EXPL)
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(blockIdx.x, leaf, r0, r1);
@@ -318,20 +344,13 @@ __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
     // record: P1 [kmax][S] | N1 | N1^{-1} | P2 [kmax][S] | N2^{-1}
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
     const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
-    const bool ident_only = a.single_sweep != 0;   // u = u1 (one-sweep variant)
-    for (int e = tid; e < k * S; e += kThreads) {
-        pc[e] = ident_only ? 0.0 : recP[e];
-        if (EXPL) {
-            const int c = e / S, j = e % S;
-            cq[e] = a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + c];
-        }
-    }
+    const bool ident_only = a.single_sweep != 0;        // u = u1 (one-sweep variant)
+    const double *cbase = EXPL ? a.Cptr + (int64_t)leaf * a.cseg : nullptr;
     for (int e = tid; e < S * S; e += kThreads) {
         const int i = e / S, j = e % S;
         ni[e] = ident_only ? (i == j ? 1.0 : 0.0) : recNi[e];
-        if (EXPL) cn[e] = a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + k + i];
+        if (EXPL) cn[e] = cbase[(int64_t)j * a.ldc + k + i];
     }
-    __syncthreads();
 
     for (int64_t base = r0; base < r1; base += (int64_t)kThreads * RPT) {
         int64_t prow[RPT];
@@ -352,23 +371,36 @@ __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
                 for (int j = 0; j < S; ++j) pb[EXPL ? i : 0][j] = 0.0;
-#pragma unroll 4
-        for (int c = 0; c < k; ++c) {
-            double q[RPT];
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)c * a.Q.ld + prow[i]];
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const double vp = pc[c * S + j];
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) pa[i][j] = fma(q[i], vp, pa[i][j]);
+        for (int c0 = 0; c0 < k; c0 += kRowCB) {
+            const int cb = (k - c0) < kRowCB ? (k - c0) : kRowCB;
+            __syncthreads();
+            for (int e = tid; e < cb * S; e += kThreads) {
+                pc[e] = ident_only ? 0.0 : recP[(int64_t)c0 * S + e];
                 if (EXPL) {
-                    const double vc = cq[c * S + j];
+                    const int c = e / S, j = e % S;
+                    cq[e] = cbase[(int64_t)j * a.ldc + c0 + c];
+                }
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int c = 0; c < cb; ++c) {
+                double q[RPT];
 #pragma unroll
-                    for (int i = 0; i < RPT; ++i) pb[EXPL ? i : 0][j] = fma(q[i], vc, pb[EXPL ? i : 0][j]);
+                for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)(c0 + c) * a.Q.ld + prow[i]];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    const double vp = pc[c * S + j];
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) pa[i][j] = fma(q[i], vp, pa[i][j]);
+                    if (EXPL) {
+                        const double vc = cq[c * S + j];
+#pragma unroll
+                        for (int i = 0; i < RPT; ++i) pb[EXPL ? i : 0][j] = fma(q[i], vc, pb[EXPL ? i : 0][j]);
+                    }
                 }
             }
         }
+        __syncthreads();   // ni / cn visible even when k = 0
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             if (!ok[i]) continue;
@@ -404,15 +436,11 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs a) {
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int k = a.k, m = a.m;
-    double *cl = lds;  // k x kApplyMB
+    double *cl = lds;  // kRowCB x kApplyMB
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(blockIdx.x, leaf, r0, r1);
-    for (int e = tid; e < k * kApplyMB; e += kThreads) {
-        const int c = e / kApplyMB, j = e % kApplyMB;
-        cl[e] = j < m ? a.Cptr[(int64_t)j * a.ldc + (int64_t)leaf * a.cseg + c] : 0.0;
-    }
-    __syncthreads();
+    const double *cbase = a.Cptr + (int64_t)leaf * a.cseg;
     for (int64_t base = r0; base < r1; base += (int64_t)kThreads * RPT) {
         int64_t prow[RPT];
         bool ok[RPT];
@@ -427,15 +455,24 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs a) {
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int j = 0; j < kApplyMB; ++j) acc[i][j] = 0.0;
-        for (int c = 0; c < k; ++c) {
-            double q[RPT];
+        for (int c0 = 0; c0 < k; c0 += kRowCB) {
+            const int cb = (k - c0) < kRowCB ? (k - c0) : kRowCB;
+            __syncthreads();
+            for (int e = tid; e < cb * kApplyMB; e += kThreads) {
+                const int c = e / kApplyMB, j = e % kApplyMB;
+                cl[e] = j < m ? cbase[(int64_t)j * a.ldc + c0 + c] : 0.0;
+            }
+            __syncthreads();
+            for (int c = 0; c < cb; ++c) {
+                double q[RPT];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)c * a.Q.ld + prow[i]];
+                for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)(c0 + c) * a.Q.ld + prow[i]];
 #pragma unroll
-            for (int j = 0; j < kApplyMB; ++j) {
-                const double w = cl[c * kApplyMB + j];
+                for (int j = 0; j < kApplyMB; ++j) {
+                    const double w = cl[c * kApplyMB + j];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) acc[i][j] = fma(q[i], w, acc[i][j]);
+                    for (int i = 0; i < RPT; ++i) acc[i][j] = fma(q[i], w, acc[i][j]);
+                }
             }
         }
 #pragma unroll
@@ -528,7 +565,10 @@ int gram_col_groups(int ncol) {
 
 int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 
-size_t finalize_lds_bytes(int k, int s) { return ((size_t)2 * k * s + 2 * (size_t)s * s) * 8; }
+size_t finalize_lds_bytes(int k, int s) {
+    (void)k;
+    return ((size_t)2 * kRowCB * s + 2 * (size_t)s * s) * 8;
+}
 
 template <int S>
 static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
@@ -550,6 +590,7 @@ hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st) {
         case 4: return gram_s<4>(a, cls, st);
         case 8: return gram_s<8>(a, cls, st);
         case 16: return gram_s<16>(a, cls, st);
+        case 32: return gram_s<32>(a, cls, st);
     }
     return hipErrorInvalidValue;
 }
@@ -563,8 +604,7 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st) {
 
 template <int S>
 static hipError_t chol_s(const CholArgs &a, hipStream_t st) {
-    const size_t lds = ((size_t)(a.k + S) * S + 3 * S * S) * 8;
-    hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -575,15 +615,16 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
         case 4: return chol_s<4>(a, st);
         case 8: return chol_s<8>(a, st);
         case 16: return chol_s<16>(a, st);
+        case 32: return chol_s<32>(a, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <int S>
 static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
-    constexpr int RPT = S >= 16 ? 2 : 4;
+    constexpr int RPT = S >= 32 ? 1 : (S >= 16 ? 2 : 4);
     const bool expl = a.Cptr != nullptr;
-    const size_t lds = finalize_lds_bytes(a.k, S) - (expl ? 0 : ((size_t)a.k * S + S * S) * 8);
+    const size_t lds = expl ? finalize_lds_bytes(a.k, S) : ((size_t)kRowCB * S + 2 * (size_t)S * S) * 8;
     const dim3 grid(a.geom.nchunks());
     if (expl) {
         hipLaunchKernelGGL((k_rowupdate<S, RPT, true, 7>), grid, dim3(kThreads), lds, st, a);
@@ -604,13 +645,14 @@ hipError_t launch_finalize(int s, const FinalizeArgs &a, int cls, hipStream_t st
         case 4: return rowupdate_s<4>(a, cls, st);
         case 8: return rowupdate_s<8>(a, cls, st);
         case 16: return rowupdate_s<16>(a, cls, st);
+        case 32: return rowupdate_s<32>(a, cls, st);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply(const ApplyArgs &a, hipStream_t st) {
     if (a.m < 1 || a.m > kApplyMB) return hipErrorInvalidValue;
-    const size_t lds = (size_t)a.k * kApplyMB * 8;
+    const size_t lds = (size_t)kRowCB * kApplyMB * 8;
     hipLaunchKernelGGL((k_apply<1>), dim3(a.geom.nchunks()), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }

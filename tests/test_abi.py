@@ -41,16 +41,22 @@ def test_workspace_bytes_arithmetic():
 
 @pytest.mark.parametrize("args", [
     (0, 4, 44, 0, 0),        # n < 1
-    (1000, 3, 12, 0, 0),     # s not in {1,2,4,8,16}
+    (1000, 3, 12, 0, 0),     # s not in {1,2,4,8,16,32}
     (1000, 4, 2, 0, 0),      # k_max < s
     (1000, 4, 10, 0, 0),     # k_max not a multiple of s
     (1000, 4, 40, 20, 0),    # leaf_rows < k_max
     (1000, 4, 40, 2000, 0),  # leaf_rows > n
     (1000, 4, 40, 0, 1),     # unknown precision
-    (100000, 16, 256, 0, 0), # wider than the kernels support
+    (100000, 16, 2048, 0, 0),  # wider than the planner accepts (k_max + s > 2048)
 ])
 def test_workspace_rejects_bad_arguments(args):
     assert orth.orth_workspace_bytes(*args) == 0
+
+
+def test_wide_blocks_are_planned():
+    # s = 32 and bases wider than 256 columns (the 3D large-block workload)
+    assert orth.orth_workspace_bytes(2 ** 24, 32, 544, 4096, 0) > 2 ** 24 * 544 * 8
+    assert orth.orth_workspace_bytes(4096, 32, 128, 0, 0) > 0
 
 
 def test_create_validates_before_any_device_call():
@@ -63,7 +69,7 @@ def test_create_validates_before_any_device_call():
     need = orth.orth_workspace_bytes(10000, 4, 44, 1000, 0)
     code, h = orth.orth_create(10000, 4, 44, 1000, 0, 4096, need - 8, 0)
     assert code == orth.ORTH_ERR_WORKSPACE          # too small
-    code, h = orth.orth_create(100000, 16, 256, 0, 0, 4096, 1 << 40, 0)
+    code, h = orth.orth_create(100000, 16, 2048, 0, 0, 4096, 1 << 40, 0)
     assert code == orth.ORTH_ERR_UNSUPPORTED
 
 

@@ -57,6 +57,9 @@ CASES = [
     (4096, 16, 96, 1024),     # s = 16
     (777, 1, 12, 100),        # s = 1 (CGS2 on vectors), ragged
     (5000, 8, 248, 2500),     # widest basis of the headline shape (k + s = 256)
+    (6000, 32, 160, 2000),    # s = 32, two N tiles in the Gram products
+    (5000, 16, 256, 2500),    # k + s = 272: two column groups in the Gram kernel
+    (9000, 8, 504, 4500),     # k + s = 512, coefficient blocks of 64 columns
 ]
 
 
