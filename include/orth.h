@@ -216,6 +216,73 @@ int orth_profile_reset(orth_t *h);
  */
 int orth_destroy(orth_t *h);
 
+/* ------------------------------------------------------------------------
+ * Batched form: `count` independent bases (uneven n, s, k_max) advance one
+ * orth_step together.  Each step is a fixed sequence of grouped launches,
+ * one per phase over all instances (TreeTSPQR's local problems and
+ * reductions are independent across instances, Sec. 4.1), with no host
+ * synchronisation and no allocation, so whole runs can be captured in a
+ * hipGraph.  Every instance works at k = step * s_i.
+ * ------------------------------------------------------------------------ */
+typedef struct orth_batch_ctx orth_batch_t;
+
+/*
+ * orth_batch_workspace_bytes -- workspace for orth_batch_create.  Host arrays
+ * of `count` entries: n[i], s[i], k_max[i] as for orth_workspace_bytes;
+ * leaf_rows may be NULL (default height for every instance) or hold 0 for
+ * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  Returns 0 for
+ * invalid arguments.
+ */
+size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t *s,
+                                  const int32_t *k_max, const int32_t *leaf_rows,
+                                  int32_t precision);
+
+/*
+ * orth_batch_create -- empty bases for every instance.  Copies the instance
+ * descriptors and launch tables into the workspace and zero-fills the tree
+ * factors on `stream`, then synchronises that stream (creation only).
+ * Errors: ARG, WORKSPACE, UNSUPPORTED, HIP.
+ */
+int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const int32_t *k_max,
+                      const int32_t *leaf_rows, int32_t precision, void *d_workspace,
+                      size_t workspace_bytes, void *stream, orth_batch_t **out);
+
+/* orth_batch_set_variant -- ORTH_PIP_PLUS (default) or ORTH_PIP for all instances. */
+int orth_batch_set_variant(orth_batch_t *b, int32_t variant);
+
+/*
+ * orth_batch_step -- one PQR step (eq. (1.1)) for every instance.
+ *   d_W     DEVICE array of `count` device pointers: instance i's new block,
+ *           n_i x s_i, column-major, ld = n_i (may alias the matching d_U[i])
+ *   d_U     DEVICE array: explicit new blocks, n_i x s_i, ld = n_i
+ *   d_Hess  DEVICE array: instance i's K_i x K_i column-major buffer
+ *           (K_i = k_max[i], ld = K_i); call j writes [H; R] (rows
+ *           0 .. (j+1) s_i - 1) into its column block j (columns
+ *           j s_i .. (j+1) s_i - 1), R with zeros below its diagonal
+ * The pointer arrays are read by the kernels when they run, so a captured
+ * graph replays with whatever they hold then.
+ * Errors: ARG, CAPACITY (all steps done), POISONED, HIP; breakdown via
+ * orth_batch_status.
+ */
+int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_U,
+                    double *const *d_Hess);
+
+/*
+ * orth_batch_status -- synchronise and read the batch status word.  info (may
+ * be NULL): 5 ints {instance, level, leaf, sweep, column} of the first
+ * breakdown.  After a breakdown the batch is poisoned.  Errors: ARG, HIP.
+ */
+int orth_batch_status(orth_batch_t *b, int32_t *status, int32_t *info);
+
+/* orth_batch_progress -- steps taken and the number of steps the batch allows. */
+int orth_batch_progress(const orth_batch_t *b, int32_t *steps_done, int32_t *steps_max);
+
+/* orth_batch_leaf_rows -- the leaf height chosen for every instance (count ints). */
+int orth_batch_leaf_rows(const orth_batch_t *b, int32_t *leaf_rows);
+
+/* orth_batch_destroy -- release the host state (NULL is a no-op). */
+int orth_batch_destroy(orth_batch_t *b);
+
 /*
  * orth_laplacian_apply -- test operator for Arnoldi drivers (not part of the
  * method): Y = A X for the Dirichlet finite-difference Laplacian on an

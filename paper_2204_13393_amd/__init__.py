@@ -6,6 +6,6 @@ include/orth.h); ``orth`` is its ctypes binding.  Build the library with
 """
 
 from . import orth  # noqa: F401
-from .orth import Orthogonalizer, OrthError, laplacian_apply, load  # noqa: F401
+from .orth import BatchOrthogonalizer, Orthogonalizer, OrthError, laplacian_apply, load  # noqa: F401
 
-__all__ = ["orth", "Orthogonalizer", "OrthError", "laplacian_apply", "load"]
+__all__ = ["orth", "Orthogonalizer", "BatchOrthogonalizer", "OrthError", "laplacian_apply", "load"]

@@ -31,11 +31,7 @@ using namespace orth;
 namespace {
 
 constexpr int64_t kAlign = 32;        // doubles (256 bytes)
-constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
-constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
-constexpr int kFinalChunk = 2048;     // rows per workgroup in the finalize pass
 constexpr int kApplyMB = 16;
-constexpr int kReduceGroup = 16;      // slots pre-summed per group at the reduction level
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -113,30 +109,10 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     return true;
 }
 
-LevelGeom leaf_geom(const Plan &pl, int chunk) {
-    LevelGeom g{};
-    g.nrows = pl.n;
-    g.leaf_rows = pl.leaf_rows;
-    g.nleaf = pl.p;
-    g.chunk_rows = chunk;
-    const int64_t last = pl.n - (int64_t)(pl.p - 1) * pl.leaf_rows;
-    g.cpl = (int32_t)ceil_div(pl.leaf_rows, chunk);
-    g.cpl_last = (int32_t)ceil_div(last, chunk);
-    g.map = RowMap{0, 0};
-    return g;
-}
+LevelGeom leaf_geom(const Plan &pl, int chunk) { return make_leaf_geom(pl.n, pl.leaf_rows, pl.p, chunk); }
 
-// the reduction level: one local problem over all p segments of seg_len rows
 LevelGeom root_geom(const Plan &pl, int64_t seg_len, int chunk) {
-    LevelGeom g{};
-    g.nrows = (int64_t)pl.p * seg_len;
-    g.leaf_rows = g.nrows;
-    g.nleaf = 1;
-    g.chunk_rows = chunk;
-    g.cpl = (int32_t)ceil_div(g.nrows, chunk);
-    g.cpl_last = g.cpl;
-    g.map = RowMap{seg_len, pl.kmax};
-    return g;
+    return make_root_geom(pl.p, pl.kmax, seg_len, chunk);
 }
 
 }  // namespace
@@ -307,6 +283,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     c.ldh = L.ldh;
     c.R = L.R;
     c.ldr = L.ldr;
+    c.instance = -1;
     c.status = h->status();
 
     // sum the slots of each leaf; pre-reduce when a single leaf owns many
@@ -634,6 +611,230 @@ int orth_probe_copy(const double *d_src, double *d_dst, int64_t count, void *str
         (void)hipGetLastError();
         return ORTH_ERR_HIP;
     }
+    return ORTH_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ batched form
+// Many independent instances (uneven n and s) advance one orth_step together:
+// every phase is one grouped launch over all instances (BatchPhase order), so
+// a batch step is a fixed sequence of at most BP_COUNT launches, with no host
+// synchronisation or allocation: a caller can capture whole runs in a graph.
+//
+// Workspace: [descriptors][block prefix tables][status][instance regions...],
+// each instance region carved exactly like a single handle's workspace.
+
+namespace {
+
+struct BatchLayout {
+    int32_t count = 0, steps_max = 0;
+    std::vector<Plan> plans;
+    std::vector<int64_t> inst_off;      // doubles, per instance region
+    int64_t o_desc = 0, o_prefix = 0, o_status = 0, total = 0;   // doubles
+};
+
+bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const int32_t *k_max,
+                       const int32_t *leaf_rows, int32_t precision, BatchLayout &L, int *why) {
+    *why = ORTH_ERR_ARG;
+    if (count < 1 || count > (1 << 20) || !n || !s || !k_max) return false;
+    L.count = count;
+    L.plans.resize(count);
+    L.inst_off.resize(count);
+    L.steps_max = 1 << 30;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!make_plan(n[i], s[i], k_max[i], leaf_rows ? leaf_rows[i] : 0, precision, L.plans[i], why))
+            return false;
+        L.steps_max = std::min(L.steps_max, k_max[i] / s[i]);
+    }
+    int64_t off = 0;
+    auto take = [&](int64_t doubles) {
+        const int64_t o = off;
+        off = round_up(off + doubles, kAlign);
+        return o;
+    };
+    L.o_desc = take(ceil_div((int64_t)count * sizeof(BatchInst), 8));
+    L.o_prefix = take(ceil_div((int64_t)L.steps_max * BP_COUNT * (count + 1) * 4, 8));
+    L.o_status = take(ceil_div(sizeof(DevStatus), 8));
+    for (int32_t i = 0; i < count; ++i) L.inst_off[i] = take(L.plans[i].total);
+    L.total = off;
+    return true;
+}
+
+}  // namespace
+
+struct orth_batch_ctx {
+    BatchLayout L;
+    int32_t step = 0;
+    int32_t variant = ORTH_PIP_PLUS;
+    bool poisoned = false;
+    hipStream_t stream = nullptr;
+    double *ws = nullptr;
+    std::vector<BatchInst> desc;
+    std::vector<int32_t> prefix;          // steps_max x BP_COUNT x (count + 1)
+    size_t lds[BP_COUNT] = {};
+    DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + L.o_status); }
+};
+
+extern "C" {
+
+size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t *s, const int32_t *k_max,
+                                  const int32_t *leaf_rows, int32_t precision) {
+    BatchLayout L;
+    int why;
+    if (!make_batch_layout(count, n, s, k_max, leaf_rows, precision, L, &why)) return 0;
+    return (size_t)L.total * sizeof(double);
+}
+
+int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const int32_t *k_max,
+                      const int32_t *leaf_rows, int32_t precision, void *d_workspace,
+                      size_t workspace_bytes, void *stream, orth_batch_t **out) {
+    if (!out) return ORTH_ERR_ARG;
+    *out = nullptr;
+    BatchLayout L;
+    int why;
+    if (!make_batch_layout(count, n, s, k_max, leaf_rows, precision, L, &why)) return why;
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
+        workspace_bytes < (size_t)L.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    orth_batch_ctx *b = new (std::nothrow) orth_batch_ctx();
+    if (!b) return ORTH_ERR_HIP;
+    b->L = L;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->ws = static_cast<double *>(d_workspace);
+    b->desc.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        const Plan &pl = L.plans[i];
+        double *base = b->ws + L.inst_off[i];
+        BatchInst &d = b->desc[i];
+        d.n = pl.n;
+        d.ldq = pl.ldq;
+        d.ldt = pl.ldt;
+        d.s = pl.s;
+        d.kmax = pl.kmax;
+        d.leaf_rows = pl.leaf_rows;
+        d.p = pl.p;
+        d.Q = base + pl.oQ;
+        d.T = base + pl.oT;
+        d.Y = base + pl.oY;
+        d.U1L = base + pl.oU1L;
+        d.U1R = base + pl.oU1R;
+        d.PL = base + pl.oPL;
+        d.PR = base + pl.oPR;
+        d.PR2 = base + pl.oPR2;
+        d.SL = base + pl.oSL;
+        d.SR = base + pl.oSR;
+    }
+    // block prefix tables of every (step, phase)
+    const int64_t stride = count + 1;
+    b->prefix.assign((size_t)L.steps_max * BP_COUNT * stride, 0);
+    for (int32_t st = 0; st < L.steps_max; ++st)
+        for (int ph = 0; ph < BP_COUNT; ++ph) {
+            int32_t *row = &b->prefix[((size_t)st * BP_COUNT + ph) * stride];
+            for (int32_t i = 0; i < count; ++i) row[i + 1] = row[i] + batch_phase_blocks(b->desc[i], ph, st, 1);
+        }
+    for (int ph = 0; ph < BP_COUNT; ++ph)
+        for (int32_t i = 0; i < count; ++i) b->lds[ph] = std::max(b->lds[ph], batch_phase_lds(ph, b->desc[i].s));
+    hipError_t e = hipMemcpyAsync(b->ws + L.o_desc, b->desc.data(), count * sizeof(BatchInst),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.o_prefix, b->prefix.data(), b->prefix.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, b->stream);
+    for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
+        const Plan &pl = L.plans[i];
+        e = launch_fill(b->desc[i].T, pl.ldt * (int64_t)pl.kmax, 0.0, b->stream);
+        if (e == hipSuccess) e = launch_fill(b->desc[i].Y, pl.ldt * (int64_t)pl.s, 0.0, b->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_fill_i32(reinterpret_cast<int32_t *>(b->status()),
+                            (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, b->stream);
+    // the host copies above read b->desc / b->prefix; finish before returning
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return ORTH_ERR_HIP;
+    }
+    *out = b;
+    return ORTH_OK;
+}
+
+int orth_batch_set_variant(orth_batch_t *b, int32_t variant) {
+    if (!b || (variant != ORTH_PIP_PLUS && variant != ORTH_PIP)) return ORTH_ERR_ARG;
+    if (b->poisoned) return ORTH_ERR_POISONED;
+    b->variant = variant;
+    return ORTH_OK;
+}
+
+int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_U, double *const *d_Hess) {
+    if (!b) return ORTH_ERR_ARG;
+    if (b->poisoned) return ORTH_ERR_POISONED;
+    if (!d_W || !d_U || !d_Hess) return ORTH_ERR_ARG;
+    if (b->step >= b->L.steps_max) return ORTH_ERR_CAPACITY;
+    const int32_t count = b->L.count;
+    BatchArgs a{};
+    a.inst = reinterpret_cast<const BatchInst *>(b->ws + b->L.o_desc);
+    a.count = count;
+    a.step = b->step;
+    a.two = b->variant == ORTH_PIP_PLUS ? 1 : 0;
+    a.W = d_W;
+    a.U = d_U;
+    a.Hess = d_Hess;
+    a.status = b->status();
+    const int32_t *dprefix = reinterpret_cast<const int32_t *>(b->ws + b->L.o_prefix);
+    for (int ph = 0; ph < BP_COUNT; ++ph) {
+        const size_t row = ((size_t)b->step * BP_COUNT + ph) * (count + 1);
+        const bool second = ph == BP_LGRAM2 || ph == BP_LCHOL2 || ph == BP_RGRAM2 || ph == BP_RRED2 ||
+                            ph == BP_RCHOL2;
+        if (second && !a.two) continue;
+        const int32_t blocks = b->prefix[row + count];
+        if (blocks == 0) continue;
+        a.phase = ph;
+        a.prefix = dprefix + row;
+        if (launch_batch_phase(a, blocks, b->lds[ph], b->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return ORTH_ERR_HIP;
+        }
+    }
+    b->step += 1;
+    return ORTH_OK;
+}
+
+int orth_batch_status(orth_batch_t *b, int32_t *status, int32_t *info) {
+    if (!b || !status) return ORTH_ERR_ARG;
+    DevStatus ds{};
+    if (hipStreamSynchronize(b->stream) != hipSuccess ||
+        hipMemcpy(&ds, b->status(), sizeof(ds), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    *status = ds.code == 0 ? ORTH_OK : ORTH_ERR_BREAKDOWN;
+    if (ds.code != 0) b->poisoned = true;
+    if (info) {
+        info[0] = ds.instance;
+        info[1] = ds.level;
+        info[2] = ds.leaf;
+        info[3] = ds.sweep;
+        info[4] = ds.column;
+    }
+    return ORTH_OK;
+}
+
+int orth_batch_progress(const orth_batch_t *b, int32_t *steps_done, int32_t *steps_max) {
+    if (!b) return ORTH_ERR_ARG;
+    if (steps_done) *steps_done = b->step;
+    if (steps_max) *steps_max = b->L.steps_max;
+    return ORTH_OK;
+}
+
+int orth_batch_leaf_rows(const orth_batch_t *b, int32_t *leaf_rows) {
+    if (!b || !leaf_rows) return ORTH_ERR_ARG;
+    for (int32_t i = 0; i < b->L.count; ++i) leaf_rows[i] = b->L.plans[i].leaf_rows;
+    return ORTH_OK;
+}
+
+int orth_batch_destroy(orth_batch_t *b) {
+    delete b;
     return ORTH_OK;
 }
 

@@ -59,6 +59,59 @@ struct LevelGeom {
     }
 };
 
+// ---- level planning shared by the runtime and the batched kernels ----
+constexpr int kThreads = 256;         // threads per workgroup of every kernel
+constexpr int kWaves = kThreads / 64;
+constexpr int kGramTPW = 4;           // 16-column tiles per wave in the Gram kernel
+
+// waves of a Gram workgroup that share rows (1, 2, 4), workgroups across the
+// columns, and partial slots per chunk (row groups)
+__host__ __device__ inline int gram_tile_groups(int ncol) {
+    const int nmt = (ncol + 15) / 16;
+    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
+    return groups <= 1 ? 1 : (groups <= 2 ? 2 : 4);
+}
+__host__ __device__ inline int gram_col_groups(int ncol) {
+    const int nmt = (ncol + 15) / 16;
+    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
+    return groups <= 4 ? 1 : (groups + 3) / 4;
+}
+__host__ __device__ inline int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
+constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
+constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
+constexpr int kFinalChunk = 2048;     // rows per workgroup in the row updates
+constexpr int kReduceGroup = 16;      // slots pre-summed per group at a single-leaf level
+
+__host__ __device__ inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// leaves of leaf_rows rows (the last takes the remainder), identity rows
+__host__ __device__ inline LevelGeom make_leaf_geom(int64_t n, int32_t leaf_rows, int32_t p, int chunk) {
+    LevelGeom g{};
+    g.nrows = n;
+    g.leaf_rows = leaf_rows;
+    g.nleaf = p;
+    g.chunk_rows = chunk;
+    const int64_t last = n - (int64_t)(p - 1) * leaf_rows;
+    g.cpl = (int32_t)ceil_div64(leaf_rows, chunk);
+    g.cpl_last = (int32_t)ceil_div64(last, chunk);
+    g.map = RowMap{0, 0};
+    return g;
+}
+
+// the reduction level: one local problem over p segments of seg_len rows,
+// segment i stored at rows [i*kmax, i*kmax + seg_len)
+__host__ __device__ inline LevelGeom make_root_geom(int32_t p, int32_t kmax, int64_t seg_len, int chunk) {
+    LevelGeom g{};
+    g.nrows = (int64_t)p * seg_len;
+    g.leaf_rows = g.nrows;
+    g.nleaf = 1;
+    g.chunk_rows = chunk;
+    g.cpl = (int32_t)ceil_div64(g.nrows, chunk);
+    g.cpl_last = g.cpl;
+    g.map = RowMap{seg_len, kmax};
+    return g;
+}
+
 // Device status record (first failure wins).
 struct DevStatus {
     int32_t code;        // 0 ok, 3 breakdown
@@ -66,7 +119,8 @@ struct DevStatus {
     int32_t leaf;
     int32_t sweep;       // CholeskyQR sweep 1 or 2
     int32_t column;      // pivot column
-    int32_t pad[3];
+    int32_t instance;    // batch instance (-1 for a single handle)
+    int32_t pad[2];
 };
 
 // Per-leaf small-matrix record, in doubles:
@@ -134,6 +188,7 @@ struct CholArgs {
     int64_t ldh;
     double *R;
     int64_t ldr;
+    int32_t instance;         // for the status record (-1: single handle)
     DevStatus *status;
 };
 
@@ -172,6 +227,69 @@ struct ApplyArgs {
     OutOperand Y;         // under geom.map
 };
 
+// ---- batched form: many independent instances, one grouped launch per phase ----
+// Per-instance descriptor (device memory); regions carved like a single handle.
+struct BatchInst {
+    int64_t n, ldq, ldt;
+    int32_t s, kmax, leaf_rows, p;
+    double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR;
+};
+
+// phases of one orth_batch_step, in stream order
+enum BatchPhase {
+    BP_LGRAM = 0, BP_LCHOL1, BP_LCORR, BP_LGRAM2, BP_LCHOL2,
+    BP_RGRAM, BP_RRED1, BP_RCHOL1, BP_RCORR, BP_RGRAM2, BP_RRED2, BP_RCHOL2,
+    BP_RFIN, BP_LFIN, BP_COUNT
+};
+
+struct BatchArgs {
+    const BatchInst *inst;
+    const int32_t *prefix;    // exclusive block prefix over instances, count + 1 entries
+    int32_t count;
+    int32_t step;             // call index: instance i works at k = step * s_i
+    int32_t phase;
+    int32_t two;              // 1: BCGS-PIP+ (two sweeps), 0: BCGS-PIP
+    const double *const *W;   // device array: instance i's W (n_i x s_i, ld n_i)
+    double *const *U;         // device array: explicit new blocks
+    double *const *Hess;      // device array: K_i x K_i column-major, block `step` gets [H; R]
+    DevStatus *status;
+};
+
+// workgroups instance d needs in a phase of a given step (0: phase skipped)
+__host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int phase, int step, int two) {
+    const int32_t k = step * d.s, ncol = k + d.s;
+    const bool second = phase == BP_LGRAM2 || phase == BP_LCHOL2 || phase == BP_RGRAM2 ||
+                        phase == BP_RRED2 || phase == BP_RCHOL2;
+    if (second && !two) return 0;
+    switch (phase) {
+        case BP_LGRAM:
+        case BP_LGRAM2:
+            return make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk).nchunks() * gram_col_groups(ncol);
+        case BP_LCHOL1:
+        case BP_LCHOL2:
+            return d.p;
+        case BP_LCORR:
+        case BP_LFIN:
+            return make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk).nchunks();
+        case BP_RGRAM:
+        case BP_RGRAM2:
+            return make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_col_groups(ncol);
+        case BP_RRED1:
+        case BP_RRED2: {
+            const int32_t slots = make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_row_groups(ncol);
+            if (slots <= kReduceGroup) return 0;
+            return (int32_t)(ceil_div64((int64_t)ncol * d.s, kThreads) * ceil_div64(slots, kReduceGroup));
+        }
+        case BP_RCHOL1:
+        case BP_RCHOL2:
+            return 1;
+        case BP_RCORR:
+        case BP_RFIN:
+            return make_root_geom(d.p, d.kmax, ncol, kFinalChunk).nchunks();
+    }
+    return 0;
+}
+
 // launchers (orth_kernels.hip)
 hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
@@ -185,11 +303,10 @@ hipError_t launch_copy_cols(const double *src, int64_t lds, RowMap smap, double 
 hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
                             int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);
+hipError_t launch_batch_phase(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st);
+size_t batch_phase_lds(int phase, int s);     // dynamic LDS one instance of width s needs
 
 // layout helpers shared with the runtime's planning
-int gram_tile_groups(int ncol);                 // waves per row group (1, 2, 4)
-int gram_col_groups(int ncol);                  // workgroups across the columns
-int gram_row_groups(int ncol);                  // partial slots per chunk
 size_t finalize_lds_bytes(int k, int s);        // dynamic LDS of k_finalize
 
 }  // namespace orth

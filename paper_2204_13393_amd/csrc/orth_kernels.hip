@@ -29,8 +29,6 @@ namespace orth {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -61,7 +59,6 @@ __device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
     }
 }
 
-constexpr int kGramTPW = 4;   // 16-column tiles per wave in k_gram
 
 }  // namespace
 
@@ -76,8 +73,8 @@ constexpr int kGramTPW = 4;   // 16-column tiles per wave in k_gram
 // macro-steps of the chunk (row groups) and write their own partial slots.
 // CLS (the launch site's profiler class) only names the instantiation, so a
 // kernel trace attributes every dispatch to its role.
-template <int S, int CLS>
-__global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
+template <int S>
+__device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -85,13 +82,13 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     const int k = a.k, ncol = k + S;
     const int nmt = (ncol + 15) >> 4;
     const int TG = a.tile_groups, RG = kWaves / TG;
-    const int tg = blockIdx.y * TG + wave % TG;
+    const int tg = by * TG + wave % TG;
     const int rg = wave / TG;
     const int tile0 = tg * kGramTPW;
     if (tile0 >= nmt) return;  // no columns for this wave (no barrier in this kernel)
     int leaf;
     int64_t r0, r1;
-    a.geom.chunk(blockIdx.x, leaf, r0, r1);
+    a.geom.chunk(bx, leaf, r0, r1);
 
     const double *colp[kGramTPW];
 #pragma unroll
@@ -148,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[t][nt] = mfma16(av[t][u], bv[nt][u], acc[t][nt]);
     }
-    double *out = a.partials + ((int64_t)blockIdx.x * RG + rg) * a.part_stride;
+    double *out = a.partials + ((int64_t)bx * RG + rg) * a.part_stride;
 #pragma unroll
     for (int t = 0; t < kGramTPW; ++t) {
         if (tile0 + t >= nmt) break;
@@ -164,19 +161,26 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     }
 }
 
+template <int S, int CLS>
+__global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
+    gram_body<S>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------- reduce
 // Fixed-order pre-sum of groups of partial slots (one thread per entry).
-__global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
+__device__ __forceinline__ void reduce_body(const ReduceArgs &a, int bx, int by) {
     if (failed(a.status)) return;
-    const int e = blockIdx.x * kThreads + threadIdx.x;
+    const int e = bx * kThreads + threadIdx.x;
     if (e >= a.nentries) return;
-    const int grp = blockIdx.y;
+    const int grp = by;
     const int s0 = grp * a.group;
     const int s1 = s0 + a.group < a.nslots ? s0 + a.group : a.nslots;
     double v = 0.0;
     for (int sl = s0; sl < s1; ++sl) v += a.in[(int64_t)sl * a.stride + e];
     a.out[(int64_t)grp * a.stride + e] = v;
 }
+
+__global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x, blockIdx.y); }
 
 // ---------------------------------------------------------------- Cholesky
 // Per leaf: sum the leaf's partial Gram slots in slot order, store P to the
@@ -187,14 +191,20 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
 constexpr int kCholCB = 64;   // P rows per LDS chunk
 
 template <int S>
-__global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
+__host__ __device__ constexpr size_t chol_lds_bytes() {
+    return ((size_t)5 * S * S + (size_t)kCholCB * S) * 8 + 16;
+}
+
+template <int S>
+__device__ __forceinline__ void chol_body(const CholArgs &a, int bx) {
     if (failed(a.status)) return;
     constexpr int EPT = (S * S + kThreads - 1) / kThreads;   // S x S entries per thread
-    __shared__ double gs[S * S], sm[S * S], nm[S * S], ni[S * S], n1[S * S];
-    __shared__ double pc[kCholCB * S];
-    __shared__ int bad;
+    extern __shared__ double lds[];
+    double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
+    double *pc = n1 + S * S;                                  // kCholCB x S
+    int &bad = *reinterpret_cast<int *>(pc + kCholCB * S);
     const int tid = threadIdx.x;
-    const int leaf = blockIdx.x;
+    const int leaf = bx;
     const int k = a.k, ncol = k + S;
     if (tid == 0) bad = 0;
     double *rec = a.small + (int64_t)leaf * a.small_stride;
@@ -269,6 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
             a.status->leaf = leaf;
             a.status->sweep = a.sweep;
             a.status->column = bad - 1;
+            a.status->instance = a.instance;
         }
         return;
     }
@@ -317,6 +328,9 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) { chol_body<S>(a, blockIdx.x); }
+
 // ---------------------------------------------------------------- row update
 // One thread per row (RPT rows per thread), the row's basis entries streamed
 // column by column with coalesced loads, the k x s coefficient blocks staged
@@ -327,8 +341,8 @@ __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) {
 //                          U|_i = q P~_i + u N~_i  (C = [P~_i; N~_i]).
 constexpr int kRowCB = 64;
 
-template <int S, int RPT, bool EXPL, int CLS>
-__global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
+template <int S, int RPT, bool EXPL>
+__device__ __forceinline__ void rowupdate_body(const FinalizeArgs &a, int bx) {
     if (failed(a.status)) return;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -339,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
     double *cn = ni + S * S;                            // S x S       C rows k..k+S-1 (EXPL)
     int leaf;
     int64_t r0, r1;
-    a.geom.chunk(blockIdx.x, leaf, r0, r1);
+    a.geom.chunk(bx, leaf, r0, r1);
     const double *rec = a.small + (int64_t)leaf * a.small_stride;
     // record: P1 [kmax][S] | N1 | N1^{-1} | P2 [kmax][S] | N2^{-1}
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
@@ -427,6 +441,11 @@ __global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
             }
         }
     }
+}
+
+template <int S, int RPT, bool EXPL, int CLS>
+__global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
+    rowupdate_body<S, RPT, EXPL>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- apply Q C
@@ -543,6 +562,203 @@ __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, do
     if (blockIdx.x == 0 && threadIdx.x == 0 && (count & 1)) dst[count - 1] = src[count - 1];
 }
 
+// ---------------------------------------------------------------- batched form
+// One grouped launch per phase covers every instance of a batch: workgroup b
+// belongs to the instance whose block range [prefix[i], prefix[i+1]) holds b.
+// The per-instance work is the same device code as the single-handle
+// kernels, selected by the instance's block width.
+__device__ __forceinline__ void batch_locate(const BatchArgs &a, int &inst, int &local) {
+    __shared__ int32_t found[2];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    for (int i = tid; i < a.count; i += kThreads)
+        if (a.prefix[i] <= b && b < a.prefix[i + 1]) {
+            found[0] = i;
+            found[1] = b - a.prefix[i];
+        }
+    __syncthreads();
+    inst = found[0];
+    local = found[1];
+}
+
+__device__ __forceinline__ int64_t hess_offset(const BatchInst &d, int step) {
+    return (int64_t)step * d.s * d.kmax;      // column block `step` of the K x K buffer
+}
+
+template <int S>
+__device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int local) {
+    const int k = a.step * S, ncol = k + S;
+    const bool leaf = a.phase == BP_LGRAM || a.phase == BP_LGRAM2;
+    GramArgs g{};
+    g.k = k;
+    g.tile_groups = gram_tile_groups(ncol);
+    g.part_stride = (int64_t)ncol * S;
+    g.status = a.status;
+    if (leaf) {
+        g.Q = Operand{d.Q, d.ldq};
+        g.X = a.phase == BP_LGRAM ? Operand{a.W[inst], d.n} : Operand{d.U1L, d.ldq};
+        g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk);
+        g.partials = d.PL;
+    } else {
+        g.Q = Operand{d.T, d.ldt};
+        g.X = a.phase == BP_RGRAM ? Operand{d.Y, d.ldt} : Operand{d.U1R, d.ldt};
+        g.geom = make_root_geom(d.p, d.kmax, ncol, kRootChunk);
+        g.partials = d.PR;
+    }
+    const int cg = gram_col_groups(ncol);
+    gram_body<S>(g, local / cg, local % cg);
+}
+
+template <int S>
+__device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int local) {
+    const int k = a.step * S, ncol = k + S;
+    const bool leaf = a.phase == BP_LCHOL1 || a.phase == BP_LCHOL2;
+    const int sweep = (a.phase == BP_LCHOL1 || a.phase == BP_RCHOL1) ? 1 : 2;
+    CholArgs c{};
+    c.part_stride = (int64_t)ncol * S;
+    c.k = k;
+    c.kmax = d.kmax;
+    c.sweep = sweep;
+    c.level = leaf ? 0 : 1;
+    c.final_sweep = a.two ? 2 : 1;
+    c.small_stride = small_stride(d.kmax, S);
+    c.instance = inst;
+    c.status = a.status;
+    const int rg = gram_row_groups(ncol);
+    if (leaf) {
+        const LevelGeom gl = make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk);
+        c.partials = d.PL;
+        c.nleaf = d.p;
+        c.slots_per_leaf = gl.cpl * rg;
+        c.slots_last = gl.cpl_last * rg;
+        c.small = d.SL;
+        c.Yout = d.Y;
+        c.ldy = d.ldt;
+        c.yseg = d.kmax;
+    } else {
+        const LevelGeom gr = make_root_geom(d.p, d.kmax, ncol, kRootChunk);
+        const int slots = gr.nchunks() * rg;
+        c.partials = slots > kReduceGroup ? d.PR2 : d.PR;
+        c.nleaf = 1;
+        c.slots_per_leaf = c.slots_last = slots > kReduceGroup ? (int32_t)ceil_div64(slots, kReduceGroup) : slots;
+        c.small = d.SR;
+        double *col = a.Hess[inst] + hess_offset(d, a.step);
+        c.H = k > 0 ? col : nullptr;
+        c.ldh = d.kmax;
+        c.R = col + k;
+        c.ldr = d.kmax;
+    }
+    chol_body<S>(c, local);
+}
+
+__device__ void batch_reduce(const BatchArgs &a, const BatchInst &d, int local) {
+    const int k = a.step * d.s, ncol = k + d.s;
+    const int slots = make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_row_groups(ncol);
+    ReduceArgs r{};
+    r.in = d.PR;
+    r.stride = (int64_t)ncol * d.s;
+    r.nslots = slots;
+    r.group = kReduceGroup;
+    r.nentries = ncol * d.s;
+    r.out = d.PR2;
+    r.status = a.status;
+    const int eb = (int)ceil_div64(r.nentries, kThreads);
+    reduce_body(r, local % eb, local / eb);
+}
+
+template <int S>
+__device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst, int local) {
+    constexpr int RPT = S >= 32 ? 1 : (S >= 16 ? 2 : 4);
+    const int k = a.step * S, ncol = k + S;
+    FinalizeArgs f{};
+    f.k = k;
+    f.kmax = d.kmax;
+    f.small_stride = small_stride(d.kmax, S);
+    f.status = a.status;
+    switch (a.phase) {
+        case BP_LCORR:
+            f.Q = Operand{d.Q, d.ldq};
+            f.Qnew = OutOperand{d.U1L, d.ldq};
+            f.U1 = Operand{a.W[inst], d.n};
+            f.sweep = 1;
+            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
+            f.small = d.SL;
+            rowupdate_body<S, RPT, false>(f, local);
+            return;
+        case BP_RCORR:
+            f.Q = Operand{d.T, d.ldt};
+            f.Qnew = OutOperand{d.U1R, d.ldt};
+            f.U1 = Operand{d.Y, d.ldt};
+            f.sweep = 1;
+            f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
+            f.small = d.SR;
+            rowupdate_body<S, RPT, false>(f, local);
+            return;
+        case BP_RFIN:
+            f.Q = Operand{d.T, d.ldt};
+            f.Qnew = OutOperand{d.T + (int64_t)k * d.ldt, d.ldt};
+            f.U1 = Operand{d.U1R, d.ldt};
+            f.sweep = 2;
+            f.single_sweep = a.two ? 0 : 1;
+            f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
+            f.small = d.SR;
+            rowupdate_body<S, RPT, false>(f, local);
+            return;
+        default:   // BP_LFIN
+            f.Q = Operand{d.Q, d.ldq};
+            f.Qnew = OutOperand{d.Q + (int64_t)k * d.ldq, d.ldq};
+            f.U1 = Operand{d.U1L, d.ldq};
+            f.sweep = 2;
+            f.single_sweep = a.two ? 0 : 1;
+            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
+            f.small = d.SL;
+            f.Cptr = d.T + (int64_t)k * d.ldt;
+            f.ldc = d.ldt;
+            f.cseg = d.kmax;
+            f.Uout = OutOperand{a.U[inst], d.n};
+            rowupdate_body<S, RPT, true>(f, local);
+            return;
+    }
+}
+
+#define ORTH_BATCH_SWITCH(FN, ...)            \
+    switch (d.s) {                           \
+        case 1: FN<1>(__VA_ARGS__); break;   \
+        case 2: FN<2>(__VA_ARGS__); break;   \
+        case 4: FN<4>(__VA_ARGS__); break;   \
+        case 8: FN<8>(__VA_ARGS__); break;   \
+        case 16: FN<16>(__VA_ARGS__); break; \
+        default: FN<32>(__VA_ARGS__); break; \
+    }
+
+__global__ __launch_bounds__(kThreads) void kb_gram(BatchArgs a) {
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    ORTH_BATCH_SWITCH(batch_gram, a, d, inst, local)
+}
+
+__global__ __launch_bounds__(kThreads) void kb_chol(BatchArgs a) {
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    ORTH_BATCH_SWITCH(batch_chol, a, d, inst, local)
+}
+
+__global__ __launch_bounds__(kThreads) void kb_reduce(BatchArgs a) {
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    batch_reduce(a, d, local);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_rowupdate(BatchArgs a) {
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    ORTH_BATCH_SWITCH(batch_rowupdate, a, d, inst, local)
+}
+
 // ---------------------------------------------------------------- launchers
 static int grid_for(int64_t count, int threads) {
     int64_t b = (count + threads - 1) / threads;
@@ -550,20 +766,6 @@ static int grid_for(int64_t count, int threads) {
     if (b < 1) b = 1;
     return (int)b;
 }
-
-int gram_tile_groups(int ncol) {
-    const int nmt = (ncol + 15) / 16;
-    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
-    return groups <= 1 ? 1 : (groups <= 2 ? 2 : 4);
-}
-
-int gram_col_groups(int ncol) {
-    const int nmt = (ncol + 15) / 16;
-    const int groups = (nmt + kGramTPW - 1) / kGramTPW;
-    return groups <= 4 ? 1 : (groups + 3) / 4;
-}
-
-int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 
 size_t finalize_lds_bytes(int k, int s) {
     (void)k;
@@ -604,7 +806,7 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st) {
 
 template <int S>
 static hipError_t chol_s(const CholArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), chol_lds_bytes<S>(), st, a);
     return hipGetLastError();
 }
 
@@ -688,6 +890,42 @@ hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3(grid_for(count / 2 + 1, 256)), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
+}  // namespace orth
+
+namespace orth {
+
+size_t batch_phase_lds(int phase, int s) {
+    auto chol = [](int s) -> size_t {
+        return ((size_t)5 * s * s + (size_t)kCholCB * s) * 8 + 16;
+    };
+    switch (phase) {
+        case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
+            return chol(s);
+        case BP_LCORR: case BP_RCORR: case BP_RFIN: case BP_LFIN:
+            return finalize_lds_bytes(0, s);
+    }
+    return 0;
+}
+
+hipError_t launch_batch_phase(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    switch (a.phase) {
+        case BP_LGRAM: case BP_LGRAM2: case BP_RGRAM: case BP_RGRAM2:
+            hipLaunchKernelGGL(kb_gram, dim3(blocks), dim3(kThreads), lds, st, a);
+            break;
+        case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
+            hipLaunchKernelGGL(kb_chol, dim3(blocks), dim3(kThreads), lds, st, a);
+            break;
+        case BP_RRED1: case BP_RRED2:
+            hipLaunchKernelGGL(kb_reduce, dim3(blocks), dim3(kThreads), lds, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL(kb_rowupdate, dim3(blocks), dim3(kThreads), lds, st, a);
+            break;
+    }
     return hipGetLastError();
 }
 

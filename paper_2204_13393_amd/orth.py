@@ -47,6 +47,15 @@ SIGNATURES = [
     ("orth_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     ("orth_profile_reset", ctypes.c_int, [_vp]),
     ("orth_destroy", ctypes.c_int, [_vp]),
+    ("orth_batch_workspace_bytes", _sz, [_i32, _vp, _vp, _vp, _vp, _i32]),
+    ("orth_batch_create", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp,
+                                         ctypes.POINTER(_vp)]),
+    ("orth_batch_set_variant", ctypes.c_int, [_vp, _i32]),
+    ("orth_batch_step", ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    ("orth_batch_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_batch_progress", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_batch_leaf_rows", ctypes.c_int, [_vp, _vp]),
+    ("orth_batch_destroy", ctypes.c_int, [_vp]),
     ("orth_laplacian_apply", ctypes.c_int, [_dp, _i64, _dp, _i64, _i32, _i32, _i32, _i32,
                                             ctypes.c_double, _vp]),
     ("orth_probe_copy", ctypes.c_int, [_dp, _dp, _i64, _vp]),
@@ -164,6 +173,62 @@ def orth_probe_copy(d_src, d_dst, count, stream):
     return load().orth_probe_copy(d_src, d_dst, count, stream)
 
 
+def _arr(ctype, values):
+    if values is None:
+        return None
+    return (ctype * len(values))(*values)
+
+
+def orth_batch_workspace_bytes(n, s, k_max, leaf_rows=None, precision=ORTH_FP64):
+    count = len(n)
+    return load().orth_batch_workspace_bytes(
+        count, ctypes.cast(_arr(ctypes.c_int64, n), _vp), ctypes.cast(_arr(_i32, s), _vp),
+        ctypes.cast(_arr(_i32, k_max), _vp),
+        ctypes.cast(_arr(_i32, leaf_rows), _vp) if leaf_rows is not None else None, precision)
+
+
+def orth_batch_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes, stream):
+    h = ctypes.c_void_p()
+    count = len(n)
+    code = load().orth_batch_create(
+        count, ctypes.cast(_arr(ctypes.c_int64, n), _vp), ctypes.cast(_arr(_i32, s), _vp),
+        ctypes.cast(_arr(_i32, k_max), _vp),
+        ctypes.cast(_arr(_i32, leaf_rows), _vp) if leaf_rows is not None else None,
+        precision, d_workspace, workspace_bytes, stream, ctypes.byref(h))
+    return code, h
+
+
+def orth_batch_set_variant(b, variant):
+    return load().orth_batch_set_variant(b, variant)
+
+
+def orth_batch_step(b, d_W, d_U, d_Hess):
+    return load().orth_batch_step(b, d_W, d_U, d_Hess)
+
+
+def orth_batch_status(b):
+    st = ctypes.c_int32()
+    info = (ctypes.c_int32 * 5)()
+    code = load().orth_batch_status(b, ctypes.byref(st), info)
+    return code, st.value, list(info)
+
+
+def orth_batch_progress(b):
+    done, mx = ctypes.c_int32(), ctypes.c_int32()
+    code = load().orth_batch_progress(b, ctypes.byref(done), ctypes.byref(mx))
+    return code, done.value, mx.value
+
+
+def orth_batch_leaf_rows(b, count):
+    out = (_i32 * count)()
+    code = load().orth_batch_leaf_rows(b, ctypes.cast(out, _vp))
+    return code, list(out)
+
+
+def orth_batch_destroy(b):
+    return load().orth_batch_destroy(b)
+
+
 # ---- torch convenience wrapper ------------------------------------------
 
 def _stream_ptr(stream):
@@ -267,3 +332,69 @@ def laplacian_apply(X, grid, shift=0.0, Y=None, stream=None):
     _check("orth_laplacian_apply", orth_laplacian_apply(X.data_ptr(), n, Y.data_ptr(), n, s, nx, ny,
                                                         nz, float(shift), _stream_ptr(stream)))
     return Y
+
+
+class BatchOrthogonalizer:
+    """Many independent TreeTSPQR bases advancing one step per call.
+
+    n, s, k_max, leaf_rows: per-instance lists (leaf_rows None or 0 entries:
+    default height).  Tensors are column-major as in ``Orthogonalizer``:
+    instance i's block is a (s_i, n_i) float64 tensor, its Hessenberg buffer a
+    (K_i, K_i) tensor (column j of the K_i x K_i matrix is row j of the tensor).
+    """
+
+    def __init__(self, n, s, k_max, leaf_rows=None, device="cuda", stream=None, variant=ORTH_PIP_PLUS):
+        import torch
+        load()
+        self.n, self.s, self.k_max = list(map(int, n)), list(map(int, s)), list(map(int, k_max))
+        self.count = len(self.n)
+        self.device = torch.device(device)
+        nbytes = orth_batch_workspace_bytes(self.n, self.s, self.k_max, leaf_rows)
+        if nbytes == 0:
+            raise OrthError("orth_batch_workspace_bytes", ORTH_ERR_ARG)
+        self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream
+        code, h = orth_batch_create(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64, aligned, nbytes,
+                                    _stream_ptr(stream))
+        _check("orth_batch_create", code)
+        self.h = h
+        _check("orth_batch_set_variant", orth_batch_set_variant(self.h, variant))
+        self.leaf_rows = orth_batch_leaf_rows(self.h, self.count)[1]
+        self._ptrs = {}
+
+    def pointer_array(self, tensors):
+        """Device int64 array of the tensors' data pointers (cached by identity)."""
+        import torch
+        key = tuple(t.data_ptr() for t in tensors)
+        arr = self._ptrs.get(key)
+        if arr is None:
+            arr = torch.tensor(list(key), dtype=torch.int64, device=self.device)
+            self._ptrs[key] = arr
+        return arr
+
+    def step(self, W, U, Hess):
+        """One step for every instance; W, U, Hess are lists of tensors (or device pointer arrays)."""
+        pw = W if not isinstance(W, (list, tuple)) else self.pointer_array(W)
+        pu = U if not isinstance(U, (list, tuple)) else self.pointer_array(U)
+        ph = Hess if not isinstance(Hess, (list, tuple)) else self.pointer_array(Hess)
+        _check("orth_batch_step", orth_batch_step(self.h, pw.data_ptr(), pu.data_ptr(), ph.data_ptr()))
+
+    def progress(self):
+        return orth_batch_progress(self.h)[1:]
+
+    def status(self):
+        code, st, info = orth_batch_status(self.h)
+        _check("orth_batch_status", code)
+        return st, info
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            orth_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
