@@ -122,6 +122,175 @@ def cpu_baseline(rows_nx=4096, rows_ny=128, s=8, steps=30):
     }
 
 
+def batched_workload(count=512, seed=4):
+    """Instances of the batched workload: n log-uniform in [2^14, 2^20] as a
+    near-square 2D grid, s uniform in {1, 2, 4, 8, 16}, start block + 20 steps."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    e = rng.uniform(14, 20, count)
+    nx = np.round(2 ** (e / 2)).astype(int)
+    ny = np.round(2 ** e / nx).astype(int)
+    s = rng.choice([1, 2, 4, 8, 16], count)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(nx, ny, s)]
+
+
+def bench_batched(args):
+    """Batched form: all instances advance together, one grouped launch per
+    phase; closed-loop Arnoldi with the stencil between steps.  Reports the
+    orthogonalisation time (HIP events around every batch step, stencils
+    excluded), the same run replayed from one captured hipGraph, and the
+    same instances run one after another through single handles."""
+    import torch
+    from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, orth
+    inst = batched_workload()
+    steps = 20
+    ns = [nx * ny for nx, ny, _ in inst]
+    ss = [s for _, _, s in inst]
+    ks = [(steps + 1) * s for s in ss]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    gen = torch.Generator(device="cuda")
+    R0 = []
+    for i, (n, s) in enumerate(zip(ns, ss)):
+        gen.manual_seed(1000 + i)
+        R0.append(torch.randn((s, n), dtype=torch.float64, device=dev, generator=gen))
+    W = [torch.empty_like(r) for r in R0]
+    U = [torch.empty_like(r) for r in R0]
+    H = [torch.zeros((k, k), dtype=torch.float64, device=dev) for k in ks]
+    print(f"[bench] batched: {len(inst)} instances, sum n = {sum(ns)}", file=sys.stderr, flush=True)
+
+    def stencils():
+        for i, (nx, ny, s) in enumerate(inst):
+            if orth.orth_laplacian_apply(U[i].data_ptr(), ns[i], W[i].data_ptr(), ns[i], s, nx, ny, 1, 0.0, sp):
+                raise RuntimeError("stencil failed")
+
+    def one_run(b, timed):
+        evs = []
+        for j in range(steps + 1):
+            if j == 0:
+                for i in range(len(ns)):
+                    W[i].copy_(R0[i])
+            else:
+                stencils()
+            if timed:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            b.step(*ptrs)
+            if timed:
+                e1.record(stream)
+                evs.append((e0, e1))
+        return evs
+
+    with torch.cuda.stream(stream):
+        b = BatchOrthogonalizer(ns, ss, ks, None, stream=stream)
+        ptrs = (b.pointer_array(W), b.pointer_array(U), b.pointer_array(H))
+        ws_ptr, ws_bytes = (b.workspace.data_ptr() + 255) // 256 * 256, b.workspace.numel() * 8 - 256
+        b.close()
+        runs = []
+        for rep in range(args.warmup + args.steps):
+            code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
+            if code:
+                raise orth.OrthError("orth_batch_create", code)
+            b.h = h
+            evs = one_run(b, rep >= args.warmup)
+            stream.synchronize()
+            st, info = b.status()
+            if st:
+                raise RuntimeError(f"batched breakdown {info}")
+            if evs:
+                runs.append(sum(e0.elapsed_time(e1) for e0, e1 in evs))
+            orth.orth_batch_destroy(h)
+            b.h = None
+        # one hipGraph holding the whole run (stencils + batch steps), and one of the stencils alone
+        code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
+        b.h = h
+        stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        one_run(b, False)
+    gs = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gs, stream=stream):
+        for j in range(steps):
+            stencils()
+    graph_ms = []
+    for rep in range(2):
+        orth.orth_batch_destroy(b.h)
+        code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
+        b.h = h
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):          # replay on the timed stream
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        t_all = e0.elapsed_time(e1)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            gs.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms.append(t_all - e0.elapsed_time(e1))
+    st, info = b.status()
+    if st:
+        raise RuntimeError(f"graph replay breakdown {info}")
+    orth.orth_batch_destroy(b.h)
+    b.h = None
+    leaf = b.leaf_rows
+    del b, g, gs
+    torch.cuda.empty_cache()
+
+    # the same instances through single handles, one after another
+    print("[bench] single handles, sequential", file=sys.stderr, flush=True)
+    single = []
+    torch.cuda.synchronize()
+    t_single = 0.0
+    for i, (nx, ny, s) in enumerate(inst):
+        with torch.cuda.stream(stream):
+            o = Orthogonalizer(ns[i], s, ks[i], stream=stream)
+            Wi, Ui = W[i], U[i]
+            Wi.copy_(R0[i])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            tot = 0.0
+            for j in range(steps + 1):
+                if j:
+                    orth.orth_laplacian_apply(Ui.data_ptr(), ns[i], Wi.data_ptr(), ns[i], s, nx, ny, 1, 0.0, sp)
+                e0.record(stream)
+                o.step(Wi, U=Ui)
+                e1.record(stream)
+                stream.synchronize()
+                tot += e0.elapsed_time(e1)
+            t_single += tot
+            o.close()
+            del o
+    p_of = lambda n, lr: max(1, n // lr)
+    total_bytes = 0.0
+    for (n, s, lr) in zip(ns, ss, leaf):
+        for j in range(steps + 1):
+            total_bytes += step_bytes(n, s, p_of(n, lr), j * s)
+    best = min(runs)
+    out = {
+        "metric": METRIC,
+        "workload": "batched-512-lap2d",
+        "value": total_bytes / (best / 1e3) / 1e9,
+        "unit": "GB/s",
+        "ms_per_run_batched": best,
+        "ms_per_run_graph": min(graph_ms),
+        "graph_note": "one hipGraph of the whole run minus a graph of its stencils alone",
+        "ms_per_run_single_sequential": t_single,
+        "speedup_vs_single": t_single / best,
+        "instances": len(inst),
+        "steps": steps,
+        "sum_n": sum(ns),
+        "alg_bytes_per_run": total_bytes,
+        "dtype": "f64",
+        "data": "synthetic: per-instance seeded N(0,1) start blocks on the GPU, 2D Dirichlet Laplacians",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,12 +300,18 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
+    ap.add_argument("--workload", default="lap2d-4096x4096-s8",
+                    choices=["lap2d-4096x4096-s8", "batched"],
+                    help="the default single-basis run, or the batched form (512 instances)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (one MI355X); "
               "sharding across GPUs is not part of it", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import numpy as np
     import torch
