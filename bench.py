@@ -291,6 +291,112 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lap3d(args):
+    """Large block: 3D 7-point Laplacian on 256^3 (n = 2^24), s = 32, start
+    block + 16 block-Arnoldi steps (k up to 512), leaf height 4096, FP64.
+    Closed loop; HIP events around every orth_step (stencils excluded).
+    A second, short run starts from a block with singular values log-spaced
+    from 1 to 1e-8 and reports whether CholeskyQR2 breaks down on it
+    (eps kappa^2 > 1/2 there)."""
+    import numpy as np
+    import torch
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    from synth import normal_block
+    nx = ny = nz = 256
+    n, s, steps, leaf = nx * ny * nz, 32, 16, 4096
+    kmax = (steps + 1) * s
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    print("[bench] lap3d: generating the start block", file=sys.stderr, flush=True)
+    R0 = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, 5).T)).to(dev)
+    V = torch.empty((kmax, n), dtype=torch.float64, device=dev)
+    W = torch.empty((s, n), dtype=torch.float64, device=dev)
+    H = torch.zeros((kmax, kmax), dtype=torch.float64, device=dev)
+    o = Orthogonalizer(n, s, kmax, leaf)
+    ws_ptr = (o.workspace.data_ptr() + 255) // 256 * 256
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf)
+    o.close()
+
+    def run(timed):
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sp)
+        if code:
+            raise orth.OrthError("orth_create", code)
+        if timed:
+            orth.orth_profile_enable(h, 1)
+        ms = 0.0
+        for j in range(steps + 1):
+            k = j * s
+            if j == 0:
+                W.copy_(R0)
+            elif orth.orth_laplacian_apply(V[k - s:k].data_ptr(), n, W.data_ptr(), n, s, nx, ny, nz, 0.0, sp):
+                raise RuntimeError("stencil failed")
+            col = H[j * s:(j + 1) * s]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            code = orth.orth_step(h, W.data_ptr(), n, col.data_ptr(), kmax, col[:, k:].data_ptr(), kmax,
+                                  V[k:k + s].data_ptr(), n)
+            e1.record(stream)
+            if code:
+                raise orth.OrthError("orth_step", code)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+        code, st, info = orth.orth_status(h)
+        prof = orth.orth_profile_read(h)[1] if timed else None
+        orth.orth_destroy(h)
+        if st:
+            raise RuntimeError(f"breakdown {info}")
+        return ms, prof
+
+    for _ in range(args.warmup):
+        run(False)
+    times = []
+    prof = None
+    for _ in range(args.steps):
+        ms, prof = run(True)
+        times.append(ms)
+    best = min(times)
+    G = torch.mm(V, V.t())
+    G -= torch.eye(kmax, dtype=torch.float64, device=dev)
+    e_perp = float(torch.linalg.matrix_norm(G, "fro"))
+    del G
+    p = n // leaf
+    widths = [j * s for j in range(steps + 1)]
+    total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
+    total_flops = sum((10.0 * s * k + 14.0 * s * s) * n for k in widths)
+    kernels = {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
+               for name, (ms, cnt) in prof.items() if cnt}
+    # ill-conditioned start block: sigma_j = 10^(-8 j / 31)
+    rng = np.random.default_rng(5)
+    Gm = rng.standard_normal((n, s))
+    Rg = np.linalg.cholesky(Gm.T @ Gm).T
+    Vh = np.linalg.qr(np.random.default_rng(6).standard_normal((s, s)))[0]
+    sig = 10.0 ** (-8.0 * np.arange(s) / (s - 1))
+    M = np.linalg.solve(Rg, np.diag(sig) @ Vh.T)
+    W.copy_(torch.from_numpy(np.ascontiguousarray((Gm @ M).T)))
+    del Gm
+    code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sp)
+    orth.orth_step(h, W.data_ptr(), n, 0, 1, H.data_ptr(), kmax, V[:s].data_ptr(), n)
+    code, st, info = orth.orth_status(h)
+    orth.orth_destroy(h)
+    out = {
+        "metric": METRIC,
+        "workload": "lap3d-256-s32",
+        "value": total_bytes / (best / 1e3) / 1e9,
+        "unit": "GB/s",
+        "ms_per_sequence": best,
+        "tflops_paper_count": total_flops / (best / 1e3) / 1e12,
+        "orth_calls": len(widths),
+        "e_perp": e_perp,
+        "kernels": kernels,
+        "ill_conditioned_start_block": {"kappa": 1e8, "status": "breakdown" if st else "ok", "info": info},
+        "dtype": "f64",
+        "data": "synthetic: N(0,1) start block (seed 5), 3D Dirichlet Laplacian 256^3",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,8 +407,9 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
-                    choices=["lap2d-4096x4096-s8", "batched"],
-                    help="the default single-basis run, or the batched form (512 instances)")
+                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32"],
+                    help="the default single-basis run, the batched form (512 instances), "
+                         "or the large-block 3D run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -312,6 +419,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "lap3d-256-s32":
+        return bench_lap3d(args)
 
     import numpy as np
     import torch
