@@ -36,6 +36,16 @@ constexpr int kApplyMB = 16;
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Leading dimension of a stored basis: an odd multiple of 256 bytes.  With a
+// power-of-two column stride every column of a wide operand starts at the
+// same offset modulo the memory interleave, and the Gram products (which
+// read 64 columns per wave at once) measured about 14% slower at n = 2^24.
+int64_t basis_ld(int64_t rows) {
+    int64_t ld = round_up(rows, kAlign);
+    if ((ld / kAlign) % 2 == 0) ld += kAlign;
+    return ld;
+}
+
 bool valid_s(int32_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16 || s == 32; }
 
 // widest basis (k_max + s) the planner accepts
@@ -71,8 +81,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.leaf_rows = leaf_rows;
     pl.p = (int32_t)(n / leaf_rows);
     if (pl.p < 1) pl.p = 1;
-    pl.ldq = round_up(n, kAlign);
-    pl.ldt = round_up((int64_t)pl.p * kmax, kAlign);
+    pl.ldq = basis_ld(n);
+    pl.ldt = basis_ld((int64_t)pl.p * kmax);
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
     const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);

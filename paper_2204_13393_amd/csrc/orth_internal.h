@@ -306,7 +306,5 @@ hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_
 hipError_t launch_batch_phase(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st);
 size_t batch_phase_lds(int phase, int s);     // dynamic LDS one instance of width s needs
 
-// layout helpers shared with the runtime's planning
-size_t finalize_lds_bytes(int k, int s);        // dynamic LDS of k_finalize
 
 }  // namespace orth

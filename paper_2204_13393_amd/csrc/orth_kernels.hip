@@ -10,17 +10,17 @@
 //   k_chol      per leaf: fixed-order sum of the chunk partials, the s x s
 //               Cholesky factor N of G - P^T P and its inverse; after the
 //               second sweep also the combination P = P1 + P2 N1, N = N2 N1.
-//   k_rowupdate per row: the correction u1 = (x - q P1) N1^{-1} of
+//   k_rowmfma   per row: the correction u1 = (x - q P1) N1^{-1} of
 //               BCGS-PIP+ (its third line), whose sweep-2 Gram [Q U1]^T U1 is
 //               then k_gram again; and the finalize u = (u1 - q P2) N2^{-1}
 //               appended to the level's local basis, at the leaf level
 //               together with the explicit new block
 //               U|_i = [Q_i U_i] [P~_i; N~_i] (Sec. 4.1, assembly of U).
 //
-// Layout: every operand is column-major; rows are streamed in tiles with
-// coalesced column reads (consecutive lanes = consecutive rows) and staged
-// in LDS as row-major tiles so the Gram products can give each lane whole
-// columns while the s coefficients of a row are LDS broadcasts.
+// Layout: every operand is column-major; rows are streamed with coalesced
+// column reads straight into the matrix-core operands (the Gram products
+// take rows as the contraction index, the row updates take them as the
+// output index of a transposed product), so no basis tile passes through LDS.
 // No floating-point atomics: every sum has a fixed order.
 
 #include "orth_internal.h"
@@ -332,25 +332,84 @@ template <int S>
 __global__ __launch_bounds__(kThreads) void k_chol(CholArgs a) { chol_body<S>(a, blockIdx.x); }
 
 // ---------------------------------------------------------------- row update
-// One thread per row (RPT rows per thread), the row's basis entries streamed
-// column by column with coalesced loads, the k x s coefficient blocks staged
-// through LDS in blocks of kRowCB columns and read as broadcasts.  Two uses:
+// Two uses of one kernel:
 //   sweep 1 (correction):  u1 = (x - q P1) N1^{-1}            -> U1 scratch
 //   sweep 2 (finalize):    u  = (u1 - q P2) N2^{-1}           -> new basis columns
 //                          and, with EXPL, the explicit block
 //                          U|_i = q P~_i + u N~_i  (C = [P~_i; N~_i]).
-constexpr int kRowCB = 64;
+constexpr int kRowCB = 64;   // coefficient rows per LDS block of k_apply
 
-template <int S, int RPT, bool EXPL>
-__device__ __forceinline__ void rowupdate_body(const FinalizeArgs &a, int bx) {
+// On the matrix cores.  A wave owns blocks of 16 TR rows; lane
+// (il = lane % 16, g = lane / 16) streams TR rows (lane_row) of basis column
+// c0 + g, the B operand of TR transposed products Y^T += Coef^T Q^T over 4
+// columns at a time.  Output column m of the coefficient block
+// [P | C_top] is the row index of each product, so a lane's accumulators
+// hold one row (lane_row(rb, il, t)) and the
+// columns m = 16 T + 4 v + g (tile T, register v).  That is exactly the
+// B-operand layout of a further product over m: the per-row triangular
+// factor u = (x - q P) N^{-1} and the explicit block's u C_bot term
+// also run on the matrix cores, with no exchange of data between lanes
+// and no LDS.  The coefficients are read through the cache (they are the
+// same for every row of a leaf).
+// A lane's TR rows of a block: pairs 2 il, 2 il + 1 in each 32-row slice,
+// so one 16-byte access per lane covers 256 contiguous bytes per column.
+__device__ __forceinline__ int64_t lane_row(int64_t rb, int il, int t) {
+    return rb + 32 * (t >> 1) + 2 * il + (t & 1);
+}
+
+template <int TR>
+__device__ __forceinline__ void load_rows(const double *p, double (&v)[TR]) {   // p: row rb + 2 il
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < TR / 2; ++u) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + 32 * u);
+            v[2 * u] = w.x;
+            v[2 * u + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < TR / 2; ++u) {
+            v[2 * u] = p[32 * u];
+            v[2 * u + 1] = p[32 * u + 1];
+        }
+    }
+}
+
+template <int TR>
+__device__ __forceinline__ void store_rows(double *p, const double (&v)[TR]) {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < TR / 2; ++u) *reinterpret_cast<double2 *>(p + 32 * u) = double2{v[2 * u], v[2 * u + 1]};
+    } else {
+#pragma unroll
+        for (int u = 0; u < TR / 2; ++u) {
+            p[32 * u] = v[2 * u];
+            p[32 * u + 1] = v[2 * u + 1];
+        }
+    }
+}
+
+// rows per lane of a block: eight for narrow blocks (64 bytes of a column
+// per lane in flight), fewer where the accumulators of wide blocks would
+// not leave room for two waves per SIMD
+template <int S, bool EXPL>
+__host__ __device__ constexpr int rowmfma_tr() { return S <= 8 ? 8 : ((S >= 32 && EXPL) ? 2 : 4); }
+// 4-column steps whose loads are issued ahead of the products
+template <int S, bool EXPL>
+__host__ __device__ constexpr int rowmfma_pf() { return 1; }
+
+template <int S, bool EXPL, int TR, int PF>
+__device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
     if (failed(a.status)) return;
-    extern __shared__ double lds[];
-    const int tid = threadIdx.x;
+    constexpr int RB = 16 * TR;              // rows per wave block
+    constexpr int M = EXPL ? 2 * S : S;      // coefficient columns [P | C_top]
+    constexpr int NTM = (M + 15) / 16;       // 16-column output tiles
+    constexpr int NTS = (S + 15) / 16;       // tiles of the new block
+    constexpr int NV = S < 4 ? 1 : 4;        // accumulator registers holding block columns
+    constexpr int KS = (S + 3) / 4;          // 4-deep steps over the block
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int il = lane & 15, g = lane >> 4;
     const int k = a.k;
-    double *pc = lds;                                   // kRowCB x S  projection block
-    double *cq = pc + kRowCB * S;                       // kRowCB x S  C rows (EXPL)
-    double *ni = cq + (EXPL ? kRowCB * S : 0);          // S x S       triangular inverse
-    double *cn = ni + S * S;                            // S x S       C rows k..k+S-1 (EXPL)
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(bx, leaf, r0, r1);
@@ -358,94 +417,170 @@ __device__ __forceinline__ void rowupdate_body(const FinalizeArgs &a, int bx) {
     // record: P1 [kmax][S] | N1 | N1^{-1} | P2 [kmax][S] | N2^{-1}
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
     const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
-    const bool ident_only = a.single_sweep != 0;        // u = u1 (one-sweep variant)
+    const bool ident_only = a.single_sweep != 0;   // u = u1 (one-sweep variant)
     const double *cbase = EXPL ? a.Cptr + (int64_t)leaf * a.cseg : nullptr;
-    for (int e = tid; e < S * S; e += kThreads) {
-        const int i = e / S, j = e % S;
-        ni[e] = ident_only ? (i == j ? 1.0 : 0.0) : recNi[e];
-        if (EXPL) cn[e] = cbase[(int64_t)j * a.ldc + k + i];
-    }
+    const bool ident = a.geom.map.seg_len == 0;
 
-    for (int64_t base = r0; base < r1; base += (int64_t)kThreads * RPT) {
-        int64_t prow[RPT];
-        bool ok[RPT];
+    for (int64_t rb = r0 + RB * wave; rb < r1; rb += RB * kWaves) {
+        const int64_t rl = rb + 2 * il;              // this lane's first row
+        int64_t prow[TR];
+        bool ok[TR];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int64_t r = base + tid + (int64_t)kThreads * i;
-            ok[i] = r < r1;
-            prow[i] = a.geom.map.phys(ok[i] ? r : r0);
+        for (int t = 0; t < TR; ++t) {
+            const int64_t r = lane_row(rb, il, t);
+            ok[t] = r < r1;
+            prow[t] = a.geom.map.phys(ok[t] ? r : r0);
         }
-        double pa[RPT][S], pb[EXPL ? RPT : 1][S];
+        const bool fast = ident && rb + RB <= r1;   // the lane's rows are contiguous and present
+        dbl4 acc[TR][NTM];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
+        for (int t = 0; t < TR; ++t)
 #pragma unroll
-            for (int j = 0; j < S; ++j) pa[i][j] = 0.0;
-        if (EXPL)
+            for (int T = 0; T < NTM; ++T) acc[t][T] = zero4();
+
+        // operands of the 4-column step at c0: the lane's TR rows of column
+        // c0 + g and the coefficients of output columns 16 T + il (zero past k)
+        auto fetch = [&](int c0, double (&q)[TR], double (&cf)[NTM]) {
+            const int c = c0 + g;
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
+            for (int t = 0; t < TR; ++t) q[t] = 0.0;
 #pragma unroll
-                for (int j = 0; j < S; ++j) pb[EXPL ? i : 0][j] = 0.0;
-        for (int c0 = 0; c0 < k; c0 += kRowCB) {
-            const int cb = (k - c0) < kRowCB ? (k - c0) : kRowCB;
-            __syncthreads();
-            for (int e = tid; e < cb * S; e += kThreads) {
-                pc[e] = ident_only ? 0.0 : recP[(int64_t)c0 * S + e];
-                if (EXPL) {
-                    const int c = e / S, j = e % S;
-                    cq[e] = cbase[(int64_t)j * a.ldc + c0 + c];
+            for (int T = 0; T < NTM; ++T) cf[T] = 0.0;
+            if (c < k) {
+                const double *col = a.Q.ptr + (int64_t)c * a.Q.ld;
+                if (fast) {
+                    load_rows<TR>(col + rl, q);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TR; ++t) q[t] = ok[t] ? col[prow[t]] : 0.0;
+                }
+#pragma unroll
+                for (int T = 0; T < NTM; ++T) {
+                    const int m = 16 * T + il;
+                    if (m < S) cf[T] = ident_only ? 0.0 : recP[(int64_t)c * S + m];
+                    else if (EXPL && m < 2 * S) cf[T] = cbase[(int64_t)(m - S) * a.ldc + c];
                 }
             }
-            __syncthreads();
-#pragma unroll 4
-            for (int c = 0; c < cb; ++c) {
-                double q[RPT];
+        };
+        // PF steps of prefetch: the loads of the next PF steps are in
+        // flight while the matrix cores work on this one
+        double qs[PF + 1][TR], cs[PF + 1][NTM];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)(c0 + c) * a.Q.ld + prow[i]];
+        for (int p = 0; p < PF; ++p) fetch(4 * p, qs[p], cs[p]);
+        for (int c0 = 0; c0 < k; c0 += 4) {
+            fetch(c0 + 4 * PF, qs[PF], cs[PF]);
 #pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    const double vp = pc[c * S + j];
+            for (int t = 0; t < TR; ++t)
 #pragma unroll
-                    for (int i = 0; i < RPT; ++i) pa[i][j] = fma(q[i], vp, pa[i][j]);
-                    if (EXPL) {
-                        const double vc = cq[c * S + j];
+                for (int T = 0; T < NTM; ++T) acc[t][T] = mfma16(cs[0][T], qs[0][t], acc[t][T]);
 #pragma unroll
-                        for (int i = 0; i < RPT; ++i) pb[EXPL ? i : 0][j] = fma(q[i], vc, pb[EXPL ? i : 0][j]);
+            for (int p = 0; p < PF; ++p) {
+#pragma unroll
+                for (int t = 0; t < TR; ++t) qs[p][t] = qs[p + 1][t];
+#pragma unroll
+                for (int T = 0; T < NTM; ++T) cs[p][T] = cs[p + 1][T];
+            }
+        }
+
+        // x - q P for the block's columns j = 16 T + 4 v + g < S, the lane's
+        // TR rows of column j read (and later written) as 16-byte pairs
+        double tv[TR][NTS][4];
+#pragma unroll
+        for (int T = 0; T < NTS; ++T)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * T + 4 * v + g;
+                double x[TR];
+#pragma unroll
+                for (int t = 0; t < TR; ++t) x[t] = 0.0;
+                if (v < NV && j < S) {
+                    const double *col = a.U1.ptr + (int64_t)j * a.U1.ld;
+                    if (fast) {
+                        load_rows<TR>(col + rl, x);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < TR; ++t) x[t] = ok[t] ? col[prow[t]] : 0.0;
                     }
                 }
+#pragma unroll
+                for (int t = 0; t < TR; ++t) tv[t][T][v] = (v < NV && j < S) ? x[t] - acc[t][T][v] : 0.0;
+            }
+        // u = (x - q P) N^{-1}: products over l = 4 ks + g (N^{-1} upper triangular)
+        dbl4 uv[TR][NTS];
+#pragma unroll
+        for (int T = 0; T < NTS; ++T) {
+            double an[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int l = 4 * ks + g, jo = 16 * T + il;
+                an[ks] = 0.0;
+                if (l < S && jo < S && l <= jo) an[ks] = ident_only ? (l == jo ? 1.0 : 0.0) : recNi[l * S + jo];
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                uv[t][T] = zero4();
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    if (4 * ks <= 16 * T + 15) uv[t][T] = mfma16(an[ks], tv[t][ks / 4][ks % 4], uv[t][T]);
             }
         }
-        __syncthreads();   // ni / cn visible even when k = 0
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            if (!ok[i]) continue;
-            double t[S], u[S];
+        for (int T = 0; T < NTS; ++T)
 #pragma unroll
-            for (int j = 0; j < S; ++j) t[j] = a.U1.ptr[(int64_t)j * a.U1.ld + prow[i]] - pa[i][j];
+            for (int v = 0; v < NV; ++v) {
+                const int j = 16 * T + 4 * v + g;
+                if (j >= S) continue;
+                double y[TR];
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                double v = 0.0;
+                for (int t = 0; t < TR; ++t) y[t] = uv[t][T][v];
+                double *col = a.Qnew.ptr + (int64_t)j * a.Qnew.ld;
+                if (fast) {
+                    store_rows<TR>(col + rl, y);
+                } else {
 #pragma unroll
-                for (int l = 0; l <= j; ++l) v = fma(t[l], ni[l * S + j], v);
-                u[j] = v;
-                a.Qnew.ptr[(int64_t)j * a.Qnew.ld + prow[i]] = v;
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) col[prow[t]] = y[t];
+                }
             }
-            if (EXPL) {
-                const int64_t r = base + tid + (int64_t)kThreads * i;
+        if (EXPL) {
+            // U| = q C_top + u C_bot, C_bot = C rows k..k+S-1; rows are logical
 #pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    double v = pb[EXPL ? i : 0][j];
+            for (int T = 0; T < NTM; ++T) {
+                if (16 * T + 15 < S) continue;        // tile without C columns
+                double ac[KS];
 #pragma unroll
-                    for (int l = 0; l <= j; ++l) v = fma(u[l], cn[l * S + j], v);
-                    a.Uout.ptr[(int64_t)j * a.Uout.ld + r] = v;
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int l = 4 * ks + g, m = 16 * T + il;
+                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(m - S) * a.ldc + k + l] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) acc[t][T] = mfma16(ac[ks], uv[t][ks / 4][ks % 4], acc[t][T]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * T + 4 * v + g;
+                    if (m < S || m >= 2 * S) continue;
+                    double y[TR];
+#pragma unroll
+                    for (int t = 0; t < TR; ++t) y[t] = acc[t][T][v];
+                    double *col = a.Uout.ptr + (int64_t)(m - S) * a.Uout.ld;
+                    if (fast) {
+                        store_rows<TR>(col + rl, y);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < TR; ++t)
+                            if (ok[t]) col[lane_row(rb, il, t)] = y[t];
+                    }
                 }
             }
         }
     }
 }
 
-template <int S, int RPT, bool EXPL, int CLS>
-__global__ __launch_bounds__(kThreads) void k_rowupdate(FinalizeArgs a) {
-    rowupdate_body<S, RPT, EXPL>(a, blockIdx.x);
+template <int S, bool EXPL, int CLS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rowmfma(FinalizeArgs a) {
+    rowmfma_body<S, EXPL, rowmfma_tr<S, EXPL>(), rowmfma_pf<S, EXPL>()>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- apply Q C
@@ -668,7 +803,9 @@ __device__ void batch_reduce(const BatchArgs &a, const BatchInst &d, int local) 
 
 template <int S>
 __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst, int local) {
-    constexpr int RPT = S >= 32 ? 1 : (S >= 16 ? 2 : 4);
+    // one kernel holds every block width: rows per lane kept low so the
+    // widest variant fits two waves per SIMD without spilling
+    constexpr int kBatchTR = S >= 16 ? 2 : 4;
     const int k = a.step * S, ncol = k + S;
     FinalizeArgs f{};
     f.k = k;
@@ -683,7 +820,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.sweep = 1;
             f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
             f.small = d.SL;
-            rowupdate_body<S, RPT, false>(f, local);
+            rowmfma_body<S, false, kBatchTR, 1>(f, local);
             return;
         case BP_RCORR:
             f.Q = Operand{d.T, d.ldt};
@@ -692,7 +829,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.sweep = 1;
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
-            rowupdate_body<S, RPT, false>(f, local);
+            rowmfma_body<S, false, kBatchTR, 1>(f, local);
             return;
         case BP_RFIN:
             f.Q = Operand{d.T, d.ldt};
@@ -702,7 +839,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.single_sweep = a.two ? 0 : 1;
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
-            rowupdate_body<S, RPT, false>(f, local);
+            rowmfma_body<S, false, kBatchTR, 1>(f, local);
             return;
         default:   // BP_LFIN
             f.Q = Operand{d.Q, d.ldq};
@@ -716,7 +853,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.ldc = d.ldt;
             f.cseg = d.kmax;
             f.Uout = OutOperand{a.U[inst], d.n};
-            rowupdate_body<S, RPT, true>(f, local);
+            rowmfma_body<S, true, kBatchTR, 1>(f, local);
             return;
     }
 }
@@ -752,7 +889,7 @@ __global__ __launch_bounds__(kThreads) void kb_reduce(BatchArgs a) {
     batch_reduce(a, d, local);
 }
 
-__global__ __launch_bounds__(kThreads) void kb_rowupdate(BatchArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_rowupdate(BatchArgs a) {
     int inst, local;
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
@@ -765,11 +902,6 @@ static int grid_for(int64_t count, int threads) {
     if (b > 65536) b = 65536;
     if (b < 1) b = 1;
     return (int)b;
-}
-
-size_t finalize_lds_bytes(int k, int s) {
-    (void)k;
-    return ((size_t)2 * kRowCB * s + 2 * (size_t)s * s) * 8;
 }
 
 template <int S>
@@ -824,17 +956,14 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
 
 template <int S>
 static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
-    constexpr int RPT = S >= 32 ? 1 : (S >= 16 ? 2 : 4);
-    const bool expl = a.Cptr != nullptr;
-    const size_t lds = expl ? finalize_lds_bytes(a.k, S) : ((size_t)kRowCB * S + 2 * (size_t)S * S) * 8;
     const dim3 grid(a.geom.nchunks());
-    if (expl) {
-        hipLaunchKernelGGL((k_rowupdate<S, RPT, true, 7>), grid, dim3(kThreads), lds, st, a);
+    if (a.Cptr != nullptr) {
+        hipLaunchKernelGGL((k_rowmfma<S, true, 7>), grid, dim3(kThreads), 0, st, a);
     } else {
         switch (cls) {
-            case 2: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 2>), grid, dim3(kThreads), lds, st, a); break;
-            case 5: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 5>), grid, dim3(kThreads), lds, st, a); break;
-            default: hipLaunchKernelGGL((k_rowupdate<S, RPT, false, 6>), grid, dim3(kThreads), lds, st, a); break;
+            case 2: hipLaunchKernelGGL((k_rowmfma<S, false, 2>), grid, dim3(kThreads), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_rowmfma<S, false, 5>), grid, dim3(kThreads), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_rowmfma<S, false, 6>), grid, dim3(kThreads), 0, st, a); break;
         }
     }
     return hipGetLastError();
@@ -904,8 +1033,6 @@ size_t batch_phase_lds(int phase, int s) {
     switch (phase) {
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
             return chol(s);
-        case BP_LCORR: case BP_RCORR: case BP_RFIN: case BP_LFIN:
-            return finalize_lds_bytes(0, s);
     }
     return 0;
 }

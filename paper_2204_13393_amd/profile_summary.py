@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for this library's kernels.
 
 Kernel instantiations carry their launch site's profiler class as the last
-template argument (k_gram<S, CLS>, k_rowupdate<S, RPT, EXPL, CLS>), so every
+template argument (k_gram<S, CLS>, k_rowmfma<S, EXPL, CLS>), so every
 dispatch in a kernel trace maps to one class of orth_kernel_class.
 
     python -m paper_2204_13393_amd.profile_summary trace  <kernel_trace.csv>
@@ -29,9 +29,9 @@ def classify(name):
     m = re.search(r"k_gram<(\d+), (\d+)>", name)
     if m:
         return GRAM.get(int(m.group(2)), "gram?")
-    m = re.search(r"k_rowupdate<(\d+), (\d+), (?:true|false), (\d+)>", name)
+    m = re.search(r"k_rowmfma<(\d+), (?:true|false), (\d+)>", name)
     if m:
-        return ROWUPD.get(int(m.group(3)), "rowupdate?")
+        return ROWUPD.get(int(m.group(2)), "rowupdate?")
     for key, cls in (("k_chol", "chol"), ("k_reduce", "reduce"), ("k_apply", "apply"),
                      ("k_copy(", "copy_probe"), ("k_laplacian", "operator"), ("k_fill", "fill"),
                      ("k_copy_cols", "export")):
