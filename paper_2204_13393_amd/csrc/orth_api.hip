@@ -628,17 +628,21 @@ int orth_probe_copy(const double *d_src, double *d_dst, int64_t count, void *str
 
 // ============================================================ batched form
 // Many independent instances (uneven n and s) advance one orth_step together:
-// every phase is one grouped launch over all instances (BatchPhase order), so
-// a batch step is a fixed sequence of at most BP_COUNT launches, with no host
-// synchronisation or allocation: a caller can capture whole runs in a graph.
+// every phase is one grouped launch per block width present (BatchPhase
+// order), so a batch step is a fixed sequence of at most BP_COUNT x widths
+// launches, with no host synchronisation or allocation: a caller can capture
+// whole runs in a graph.
 //
 // Workspace: [descriptors][block prefix tables][status][instance regions...],
-// each instance region carved exactly like a single handle's workspace.
+// each instance region carved exactly like a single handle's workspace.  The
+// prefix table of (step, phase, width) gives instances of other widths no
+// blocks.
 
 namespace {
 
 struct BatchLayout {
     int32_t count = 0, steps_max = 0;
+    std::vector<int32_t> widths;        // distinct block widths, ascending
     std::vector<Plan> plans;
     std::vector<int64_t> inst_off;      // doubles, per instance region
     int64_t o_desc = 0, o_prefix = 0, o_status = 0, total = 0;   // doubles
@@ -656,7 +660,9 @@ bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const 
         if (!make_plan(n[i], s[i], k_max[i], leaf_rows ? leaf_rows[i] : 0, precision, L.plans[i], why))
             return false;
         L.steps_max = std::min(L.steps_max, k_max[i] / s[i]);
+        if (std::find(L.widths.begin(), L.widths.end(), s[i]) == L.widths.end()) L.widths.push_back(s[i]);
     }
+    std::sort(L.widths.begin(), L.widths.end());
     int64_t off = 0;
     auto take = [&](int64_t doubles) {
         const int64_t o = off;
@@ -664,7 +670,7 @@ bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const 
         return o;
     };
     L.o_desc = take(ceil_div((int64_t)count * sizeof(BatchInst), 8));
-    L.o_prefix = take(ceil_div((int64_t)L.steps_max * BP_COUNT * (count + 1) * 4, 8));
+    L.o_prefix = take(ceil_div((int64_t)L.steps_max * BP_COUNT * (int64_t)L.widths.size() * (count + 1) * 4, 8));
     L.o_status = take(ceil_div(sizeof(DevStatus), 8));
     for (int32_t i = 0; i < count; ++i) L.inst_off[i] = take(L.plans[i].total);
     L.total = off;
@@ -681,8 +687,11 @@ struct orth_batch_ctx {
     hipStream_t stream = nullptr;
     double *ws = nullptr;
     std::vector<BatchInst> desc;
-    std::vector<int32_t> prefix;          // steps_max x BP_COUNT x (count + 1)
-    size_t lds[BP_COUNT] = {};
+    std::vector<int32_t> prefix;          // steps_max x BP_COUNT x widths x (count + 1)
+    std::vector<size_t> lds;              // BP_COUNT x widths
+    size_t row(int32_t step, int ph, size_t w) const {
+        return (((size_t)step * BP_COUNT + ph) * L.widths.size() + w) * (L.count + 1);
+    }
     DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + L.o_status); }
 };
 
@@ -735,16 +744,19 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         d.SL = base + pl.oSL;
         d.SR = base + pl.oSR;
     }
-    // block prefix tables of every (step, phase)
-    const int64_t stride = count + 1;
-    b->prefix.assign((size_t)L.steps_max * BP_COUNT * stride, 0);
+    // block prefix tables of every (step, phase, width)
+    const size_t nw = L.widths.size();
+    b->prefix.assign(b->row(L.steps_max, 0, 0), 0);
     for (int32_t st = 0; st < L.steps_max; ++st)
-        for (int ph = 0; ph < BP_COUNT; ++ph) {
-            int32_t *row = &b->prefix[((size_t)st * BP_COUNT + ph) * stride];
-            for (int32_t i = 0; i < count; ++i) row[i + 1] = row[i] + batch_phase_blocks(b->desc[i], ph, st, 1);
-        }
+        for (int ph = 0; ph < BP_COUNT; ++ph)
+            for (size_t w = 0; w < nw; ++w) {
+                int32_t *row = &b->prefix[b->row(st, ph, w)];
+                for (int32_t i = 0; i < count; ++i)
+                    row[i + 1] = row[i] + (b->desc[i].s == L.widths[w] ? batch_phase_blocks(b->desc[i], ph, st, 1) : 0);
+            }
+    b->lds.assign((size_t)BP_COUNT * nw, 0);
     for (int ph = 0; ph < BP_COUNT; ++ph)
-        for (int32_t i = 0; i < count; ++i) b->lds[ph] = std::max(b->lds[ph], batch_phase_lds(ph, b->desc[i].s));
+        for (size_t w = 0; w < nw; ++w) b->lds[ph * nw + w] = batch_phase_lds(ph, L.widths[w]);
     hipError_t e = hipMemcpyAsync(b->ws + L.o_desc, b->desc.data(), count * sizeof(BatchInst),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -792,18 +804,21 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
     a.Hess = d_Hess;
     a.status = b->status();
     const int32_t *dprefix = reinterpret_cast<const int32_t *>(b->ws + b->L.o_prefix);
+    const size_t nw = b->L.widths.size();
     for (int ph = 0; ph < BP_COUNT; ++ph) {
-        const size_t row = ((size_t)b->step * BP_COUNT + ph) * (count + 1);
         const bool second = ph == BP_LGRAM2 || ph == BP_LCHOL2 || ph == BP_RGRAM2 || ph == BP_RRED2 ||
                             ph == BP_RCHOL2;
         if (second && !a.two) continue;
-        const int32_t blocks = b->prefix[row + count];
-        if (blocks == 0) continue;
         a.phase = ph;
-        a.prefix = dprefix + row;
-        if (launch_batch_phase(a, blocks, b->lds[ph], b->stream) != hipSuccess) {
-            (void)hipGetLastError();
-            return ORTH_ERR_HIP;
+        for (size_t w = 0; w < nw; ++w) {
+            const size_t row = b->row(b->step, ph, w);
+            const int32_t blocks = b->prefix[row + count];
+            if (blocks == 0) continue;
+            a.prefix = dprefix + row;
+            if (launch_batch_phase(a, b->L.widths[w], blocks, b->lds[ph * nw + w], b->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return ORTH_ERR_HIP;
+            }
         }
     }
     b->step += 1;

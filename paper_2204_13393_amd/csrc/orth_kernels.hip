@@ -803,9 +803,6 @@ __device__ void batch_reduce(const BatchArgs &a, const BatchInst &d, int local) 
 
 template <int S>
 __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst, int local) {
-    // one kernel holds every block width: rows per lane kept low so the
-    // widest variant fits two waves per SIMD without spilling
-    constexpr int kBatchTR = S >= 16 ? 2 : 4;
     const int k = a.step * S, ncol = k + S;
     FinalizeArgs f{};
     f.k = k;
@@ -820,7 +817,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.sweep = 1;
             f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
             f.small = d.SL;
-            rowmfma_body<S, false, kBatchTR, 1>(f, local);
+            rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
         case BP_RCORR:
             f.Q = Operand{d.T, d.ldt};
@@ -829,7 +826,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.sweep = 1;
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
-            rowmfma_body<S, false, kBatchTR, 1>(f, local);
+            rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
         case BP_RFIN:
             f.Q = Operand{d.T, d.ldt};
@@ -839,7 +836,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.single_sweep = a.two ? 0 : 1;
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
-            rowmfma_body<S, false, kBatchTR, 1>(f, local);
+            rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
         default:   // BP_LFIN
             f.Q = Operand{d.Q, d.ldq};
@@ -853,33 +850,29 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.ldc = d.ldt;
             f.cseg = d.kmax;
             f.Uout = OutOperand{a.U[inst], d.n};
-            rowmfma_body<S, true, kBatchTR, 1>(f, local);
+            rowmfma_body<S, true, rowmfma_tr<S, true>(), rowmfma_pf<S, true>()>(f, local);
             return;
     }
 }
 
-#define ORTH_BATCH_SWITCH(FN, ...)            \
-    switch (d.s) {                           \
-        case 1: FN<1>(__VA_ARGS__); break;   \
-        case 2: FN<2>(__VA_ARGS__); break;   \
-        case 4: FN<4>(__VA_ARGS__); break;   \
-        case 8: FN<8>(__VA_ARGS__); break;   \
-        case 16: FN<16>(__VA_ARGS__); break; \
-        default: FN<32>(__VA_ARGS__); break; \
-    }
-
+// One kernel per block width: the host launches a phase once for every
+// width present in the batch, with a block prefix table that gives the
+// other widths' instances no blocks, so each width keeps its own register
+// allocation.
+template <int S>
 __global__ __launch_bounds__(kThreads) void kb_gram(BatchArgs a) {
     int inst, local;
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
-    ORTH_BATCH_SWITCH(batch_gram, a, d, inst, local)
+    batch_gram<S>(a, d, inst, local);
 }
 
+template <int S>
 __global__ __launch_bounds__(kThreads) void kb_chol(BatchArgs a) {
     int inst, local;
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
-    ORTH_BATCH_SWITCH(batch_chol, a, d, inst, local)
+    batch_chol<S>(a, d, inst, local);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_reduce(BatchArgs a) {
@@ -889,11 +882,12 @@ __global__ __launch_bounds__(kThreads) void kb_reduce(BatchArgs a) {
     batch_reduce(a, d, local);
 }
 
+template <int S>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_rowupdate(BatchArgs a) {
     int inst, local;
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
-    ORTH_BATCH_SWITCH(batch_rowupdate, a, d, inst, local)
+    batch_rowupdate<S>(a, d, inst, local);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1037,23 +1031,36 @@ size_t batch_phase_lds(int phase, int s) {
     return 0;
 }
 
-hipError_t launch_batch_phase(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st) {
-    if (blocks <= 0) return hipSuccess;
+template <int S>
+static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st) {
     switch (a.phase) {
         case BP_LGRAM: case BP_LGRAM2: case BP_RGRAM: case BP_RGRAM2:
-            hipLaunchKernelGGL(kb_gram, dim3(blocks), dim3(kThreads), lds, st, a);
+            hipLaunchKernelGGL((kb_gram<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
-            hipLaunchKernelGGL(kb_chol, dim3(blocks), dim3(kThreads), lds, st, a);
+            hipLaunchKernelGGL((kb_chol<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_RRED1: case BP_RRED2:
             hipLaunchKernelGGL(kb_reduce, dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         default:
-            hipLaunchKernelGGL(kb_rowupdate, dim3(blocks), dim3(kThreads), lds, st, a);
+            hipLaunchKernelGGL((kb_rowupdate<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(const BatchArgs &a, int s, int32_t blocks, size_t lds, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    switch (s) {
+        case 1: return batch_phase_s<1>(a, blocks, lds, st);
+        case 2: return batch_phase_s<2>(a, blocks, lds, st);
+        case 4: return batch_phase_s<4>(a, blocks, lds, st);
+        case 8: return batch_phase_s<8>(a, blocks, lds, st);
+        case 16: return batch_phase_s<16>(a, blocks, lds, st);
+        case 32: return batch_phase_s<32>(a, blocks, lds, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace orth
