@@ -141,7 +141,7 @@ def bench_batched(args):
     excluded), the same run replayed from one captured hipGraph, and the
     same instances run one after another through single handles."""
     import torch
-    from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, orth
+    from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, autotune, orth
     inst = batched_workload()
     steps = 20
     ns = [nx * ny for nx, ny, _ in inst]
@@ -149,6 +149,14 @@ def bench_batched(args):
     ks = [(steps + 1) * s for s in ss]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # leaf heights from the autotuner (one measurement per (s, k_max, n rounded
+    # to a power of two) bucket), and the library default for comparison
+    t0 = time.perf_counter()
+    tuned = autotune.tune_batch(ns, ss, ks)
+    tune_s = time.perf_counter() - t0
+    buckets = len({autotune.bucket_of(n, s, k) for n, s, k in zip(ns, ss, ks)})
+    print(f"[bench] batched: autotuned leaf heights in {tune_s:.1f} s ({buckets} buckets)",
+          file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
     gen = torch.Generator(device="cuda")
@@ -166,7 +174,7 @@ def bench_batched(args):
             if orth.orth_laplacian_apply(U[i].data_ptr(), ns[i], W[i].data_ptr(), ns[i], s, nx, ny, 1, 0.0, sp):
                 raise RuntimeError("stencil failed")
 
-    def one_run(b, timed):
+    def one_run(b, timed, ptrs):
         evs = []
         for j in range(steps + 1):
             if j == 0:
@@ -183,33 +191,42 @@ def bench_batched(args):
                 evs.append((e0, e1))
         return evs
 
+    def eager_runs(leaf_rows):
+        with torch.cuda.stream(stream):
+            bb = BatchOrthogonalizer(ns, ss, ks, leaf_rows, stream=stream)
+            bptrs = (bb.pointer_array(W), bb.pointer_array(U), bb.pointer_array(H))
+            base, nbytes = (bb.workspace.data_ptr() + 255) // 256 * 256, bb.workspace.numel() * 8 - 256
+            bb.close()
+            times = []
+            for rep in range(args.warmup + args.steps):
+                code, h = orth.orth_batch_create(ns, ss, ks, leaf_rows, orth.ORTH_FP64, base, nbytes, sp)
+                if code:
+                    raise orth.OrthError("orth_batch_create", code)
+                bb.h = h
+                evs = one_run(bb, rep >= args.warmup, bptrs)
+                stream.synchronize()
+                st, info = bb.status()
+                if st:
+                    raise RuntimeError(f"batched breakdown {info}")
+                if evs:
+                    times.append(sum(e0.elapsed_time(e1) for e0, e1 in evs))
+                orth.orth_batch_destroy(h)
+                bb.h = None
+        return bb, bptrs, base, nbytes, times
+
+    b, _, _, _, default_runs = eager_runs(None)
+    default_leaf = b.leaf_rows
+    del b
+    torch.cuda.empty_cache()
     with torch.cuda.stream(stream):
-        b = BatchOrthogonalizer(ns, ss, ks, None, stream=stream)
-        ptrs = (b.pointer_array(W), b.pointer_array(U), b.pointer_array(H))
-        ws_ptr, ws_bytes = (b.workspace.data_ptr() + 255) // 256 * 256, b.workspace.numel() * 8 - 256
-        b.close()
-        runs = []
-        for rep in range(args.warmup + args.steps):
-            code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
-            if code:
-                raise orth.OrthError("orth_batch_create", code)
-            b.h = h
-            evs = one_run(b, rep >= args.warmup)
-            stream.synchronize()
-            st, info = b.status()
-            if st:
-                raise RuntimeError(f"batched breakdown {info}")
-            if evs:
-                runs.append(sum(e0.elapsed_time(e1) for e0, e1 in evs))
-            orth.orth_batch_destroy(h)
-            b.h = None
+        b, ptrs, ws_ptr, ws_bytes, runs = eager_runs(tuned)
         # one hipGraph holding the whole run (stencils + batch steps), and one of the stencils alone
-        code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
+        code, h = orth.orth_batch_create(ns, ss, ks, tuned, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
         b.h = h
         stream.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
-        one_run(b, False)
+        one_run(b, False, ptrs)
     gs = torch.cuda.CUDAGraph()
     with torch.cuda.graph(gs, stream=stream):
         for j in range(steps):
@@ -217,7 +234,7 @@ def bench_batched(args):
     graph_ms = []
     for rep in range(2):
         orth.orth_batch_destroy(b.h)
-        code, h = orth.orth_batch_create(ns, ss, ks, None, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
+        code, h = orth.orth_batch_create(ns, ss, ks, tuned, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
         b.h = h
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -249,7 +266,7 @@ def bench_batched(args):
     t_single = 0.0
     for i, (nx, ny, s) in enumerate(inst):
         with torch.cuda.stream(stream):
-            o = Orthogonalizer(ns[i], s, ks[i], stream=stream)
+            o = Orthogonalizer(ns[i], s, ks[i], tuned[i], stream=stream)
             Wi, Ui = W[i], U[i]
             Wi.copy_(R0[i])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -271,12 +288,18 @@ def bench_batched(args):
         for j in range(steps + 1):
             total_bytes += step_bytes(n, s, p_of(n, lr), j * s)
     best = min(runs)
+    hist = {}
+    for lr in leaf:
+        hist[str(lr)] = hist.get(str(lr), 0) + 1
     out = {
         "metric": METRIC,
         "workload": "batched-512-lap2d",
         "value": total_bytes / (best / 1e3) / 1e9,
         "unit": "GB/s",
         "ms_per_run_batched": best,
+        "ms_per_run_batched_default_leaf": min(default_runs),
+        "leaf_rows": {"source": "autotuned", "tuning_s": tune_s, "buckets": buckets, "histogram": hist,
+                      "default_histogram": {str(v): default_leaf.count(v) for v in sorted(set(default_leaf))}},
         "ms_per_run_graph": min(graph_ms),
         "graph_note": "one hipGraph of the whole run minus a graph of its stencils alone",
         "ms_per_run_single_sequential": t_single,

@@ -283,6 +283,44 @@ int orth_batch_leaf_rows(const orth_batch_t *b, int32_t *leaf_rows);
 /* orth_batch_destroy -- release the host state (NULL is a no-op). */
 int orth_batch_destroy(orth_batch_t *b);
 
+/* ---- leaf-height autotuner -------------------------------------------------
+ *
+ * The local problem size is the free parameter of TreeTSPQR (Sec. 4.1): the
+ * leaves stream n x k bytes whatever their height, while the reduction level
+ * grows with the number of leaves p = n / leaf_rows (it holds p (k+s) rows).
+ * Its best value depends on the machine and is found by measurement (the
+ * local problem size study of Sec. 6.2; Sec. 5.1 ties it to the memory
+ * hierarchy).
+ *
+ * orth_tune_leaf_rows times `steps` calls (k = 0, s, 2s, ...) on synthetic
+ * blocks (uniform in [-1, 1), a fixed hash of the call index, row and column)
+ * for every candidate leaf height
+ *     {256, 512, ..., 16384} restricted to [k_max, n], and n itself if n <= 16384,
+ * through one handle (copies = 1, orth_step) or through a batch of `copies`
+ * identical instances (orth_batch_step; this saturates the GPU as a large
+ * batch does).  Among candidates within 2% of the fastest the tallest is
+ * written to *best_leaf_rows.  Synchronous: it waits for `stream` after
+ * every call.
+ *   copies        1 .. 4096
+ *   d_workspace   device memory, 256-byte aligned, of at least
+ *                 orth_tune_workspace_bytes(n, s, k_max, copies) bytes, owned
+ *                 by the caller; its contents are overwritten.
+ *   steps         calls per candidate, 1 <= steps <= k_max / s.
+ *   cand_rows, cand_ms (may be NULL when max_cand = 0): arrays of max_cand
+ *                 entries receiving every candidate and its time in ms for
+ *                 the `steps` calls (a negative time marks a candidate whose
+ *                 run broke down); *ncand (may be NULL) receives the
+ *                 candidate count.
+ * Errors: ARG (sizes as for orth_create, steps or copies out of range, no
+ * candidate), WORKSPACE, HIP, BREAKDOWN (every candidate broke down).
+ * orth_tune_workspace_bytes returns 0 for invalid sizes.
+ */
+size_t orth_tune_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t copies);
+int orth_tune_leaf_rows(int64_t n, int32_t s, int32_t k_max, int32_t steps,
+                        int32_t copies, void *d_workspace, size_t workspace_bytes,
+                        void *stream, int32_t *best_leaf_rows, int32_t *cand_rows,
+                        double *cand_ms, int32_t max_cand, int32_t *ncand);
+
 /*
  * orth_laplacian_apply -- test operator for Arnoldi drivers (not part of the
  * method): Y = A X for the Dirichlet finite-difference Laplacian on an

@@ -5,7 +5,7 @@ include/orth.h); ``orth`` is its ctypes binding.  Build the library with
 ``python -m paper_2204_13393_amd.build``.
 """
 
-from . import orth  # noqa: F401
+from . import autotune, orth  # noqa: F401
 from .orth import BatchOrthogonalizer, Orthogonalizer, OrthError, laplacian_apply, load  # noqa: F401
 
-__all__ = ["orth", "Orthogonalizer", "BatchOrthogonalizer", "OrthError", "laplacian_apply", "load"]
+__all__ = ["autotune", "orth", "Orthogonalizer", "BatchOrthogonalizer", "OrthError", "laplacian_apply", "load"]

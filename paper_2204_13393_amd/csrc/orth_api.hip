@@ -58,6 +58,7 @@ struct Plan {
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, total;
+    int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
 int32_t default_leaf_rows(int64_t n, int32_t kmax) {
@@ -107,11 +108,16 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         const int64_t per = (int64_t)gram_row_groups(ncol) * ncol * s;
         const int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
         slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
-        red_max = std::max(red_max, ceil_div(nR * gram_row_groups(ncol), kReduceGroup) * ncol * s);
+        // pre-summed slot groups of a level with a single local problem: the
+        // reduction level, and the leaf level when there is one leaf
+        const int64_t single = pl.p == 1 ? std::max((int64_t)pl.nchunkL, nR) : nR;
+        red_max = std::max(red_max, ceil_div(single * gram_row_groups(ncol), kReduceGroup) * ncol * s);
     }
     pl.oPL = take(slot_max);
     pl.oPR = take(slot_max);
     pl.oPR2 = take(red_max);
+    pl.slot_cap = slot_max;
+    pl.red_cap = red_max;
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
@@ -243,6 +249,7 @@ struct LevelRun {
     OutOperand U1;
     LevelGeom geom;
     double *part, *part2;
+    int64_t part_cap, part2_cap;   // doubles available at part and part2
     double *small;
     int level;
     // final outputs
@@ -262,6 +269,8 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     const int cls0 = L.level == 0 ? 0 : 3;          // LEAF_* or ROOT_* classes
     hipError_t e;
 
+    // host check of the Gram grid against the partial-slot region it writes
+    if ((int64_t)L.geom.nchunks() * gram_row_groups(ncol) * pstride > L.part_cap) return ORTH_ERR_HIP;
     GramArgs ga{};
     ga.Q = L.Q;
     ga.X = L.X;
@@ -303,6 +312,8 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
         c.slots_per_leaf = L.geom.cpl * ppc;
         c.slots_last = L.geom.cpl_last * ppc;
         if (L.geom.nleaf == 1 && c.slots_last > kReduceGroup) {
+            // host check of the grid against the buffer it writes
+            if (!L.part2 || ceil_div(c.slots_last, kReduceGroup) * pstride > L.part2_cap) return ORTH_ERR_HIP;
             ReduceArgs r{};
             r.in = L.part;
             r.stride = pstride;
@@ -386,6 +397,9 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.U1 = OutOperand{h->U1L(), pl.ldq};
         L.geom = leaf_geom(pl, kLeafChunk);
         L.part = h->PL();
+        L.part2 = h->PR2();          // pre-sums when a single leaf holds many slots
+        L.part_cap = pl.slot_cap;
+        L.part2_cap = pl.red_cap;
         L.small = h->SL();
         L.level = 0;
         L.Yout = h->Y();
@@ -402,6 +416,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.geom = root_geom(pl, ncol, kRootChunk);
         L.part = h->PR();
         L.part2 = h->PR2();
+        L.part_cap = pl.slot_cap;
+        L.part2_cap = pl.red_cap;
         L.small = h->SR();
         L.level = 1;
         L.H = k > 0 ? d_H : nullptr;
@@ -860,6 +876,183 @@ int orth_batch_leaf_rows(const orth_batch_t *b, int32_t *leaf_rows) {
 
 int orth_batch_destroy(orth_batch_t *b) {
     delete b;
+    return ORTH_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ leaf-height autotuner
+// Times whole orth_step sequences on synthetic blocks for every candidate
+// leaf height: through one handle (copies = 1) or through a batch of
+// `copies` identical instances, which keeps the GPU saturated as it is in a
+// large batch.  Among candidates within 2% of the fastest the tallest wins:
+// fewer leaves mean a smaller reduction level.
+
+namespace {
+
+std::vector<int32_t> tune_candidates(int64_t n, int32_t kmax) {
+    std::vector<int32_t> c;
+    for (int64_t lr = 256; lr <= 16384; lr *= 2)
+        if (lr >= kmax && lr <= n) c.push_back((int32_t)lr);
+    if (n <= 16384 && n >= kmax && (c.empty() || c.back() != n)) c.push_back((int32_t)n);
+    return c;
+}
+
+// single:  [plan][W n x s][U n x s][H k_max x s][R s x s]
+// batch:   [batch][W n x s][U copies x n x s][Hess copies x k_max x k_max][3 x copies pointers]
+// (doubles; every region 256-byte aligned)
+struct TuneLayout {
+    int64_t head = 0, oW = 0, oU = 0, oH = 0, oR = 0, oP = 0, total = 0;
+};
+
+bool tune_layout(int64_t n, int32_t s, int32_t kmax, int32_t copies, TuneLayout &L) {
+    if (copies < 1 || copies > 4096) return false;
+    const std::vector<int32_t> cand = tune_candidates(n, kmax);
+    if (cand.empty()) return false;
+    for (int32_t lr : cand) {
+        int why;
+        if (copies == 1) {
+            Plan pl;
+            if (!make_plan(n, s, kmax, lr, ORTH_FP64, pl, &why)) return false;
+            L.head = std::max(L.head, round_up(pl.total, kAlign));
+        } else {
+            std::vector<int64_t> nn(copies, n);
+            std::vector<int32_t> ss(copies, s), kk(copies, kmax), ll(copies, lr);
+            BatchLayout B;
+            if (!make_batch_layout(copies, nn.data(), ss.data(), kk.data(), ll.data(), ORTH_FP64, B, &why))
+                return false;
+            L.head = std::max(L.head, round_up(B.total, kAlign));
+        }
+    }
+    L.oW = L.head;
+    L.oU = L.oW + round_up(n * s, kAlign);
+    if (copies == 1) {
+        L.oH = L.oU + round_up(n * s, kAlign);
+        L.oR = L.oH + round_up((int64_t)kmax * s, kAlign);
+        L.total = L.oR + round_up((int64_t)s * s, kAlign);
+    } else {
+        L.oH = L.oU + round_up(n * s, kAlign) * copies;
+        L.oP = L.oH + round_up((int64_t)kmax * kmax, kAlign) * copies;
+        L.total = L.oP + round_up(3 * (int64_t)copies, kAlign);
+    }
+    return true;
+}
+
+// time of `steps` calls for one candidate; ORTH_ERR_BREAKDOWN if it broke down
+int tune_one(int64_t n, int32_t s, int32_t kmax, int32_t lr, int32_t steps, int32_t copies,
+             const TuneLayout &L, double *ws, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double *ms_out) {
+    double *W = ws + L.oW;
+    double ms_total = 0.0;
+    auto timed = [&](auto &&call) -> int {
+        float ms = 0.0f;
+        if (hipEventRecord(e0, st) != hipSuccess) return ORTH_ERR_HIP;
+        const int rc = call();
+        if (rc != ORTH_OK) return rc;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return ORTH_ERR_HIP;
+        ms_total += ms;
+        return ORTH_OK;
+    };
+    int rc = ORTH_OK;
+    int32_t status = ORTH_OK;
+    if (copies == 1) {
+        orth_t *h = nullptr;
+        rc = orth_create(n, s, kmax, lr, ORTH_FP64, ws, (size_t)L.head * sizeof(double), st, &h);
+        if (rc != ORTH_OK) return rc;
+        double *U = ws + L.oU, *H = ws + L.oH, *R = ws + L.oR;
+        for (int32_t j = 0; j < steps && rc == ORTH_OK; ++j) {
+            if (launch_synth(W, n, n, s, (uint64_t)j + 1, st) != hipSuccess) { rc = ORTH_ERR_HIP; break; }
+            rc = timed([&] { return orth_step(h, W, n, H, kmax, R, s, U, n); });
+        }
+        if (rc == ORTH_OK) rc = orth_status(h, &status, nullptr);
+        (void)orth_destroy(h);
+    } else {
+        std::vector<int64_t> nn(copies, n);
+        std::vector<int32_t> ss(copies, s), kk(copies, kmax), ll(copies, lr);
+        orth_batch_t *b = nullptr;
+        rc = orth_batch_create(copies, nn.data(), ss.data(), kk.data(), ll.data(), ORTH_FP64, ws,
+                               (size_t)L.head * sizeof(double), st, &b);
+        if (rc != ORTH_OK) return rc;
+        // device pointer arrays: every copy reads the same W and writes its own U and Hess
+        std::vector<double *> ptrs(3 * (size_t)copies);
+        for (int32_t i = 0; i < copies; ++i) {
+            ptrs[i] = W;
+            ptrs[copies + i] = ws + L.oU + round_up(n * s, kAlign) * i;
+            ptrs[2 * copies + i] = ws + L.oH + round_up((int64_t)kmax * kmax, kAlign) * i;
+        }
+        double **dptr = reinterpret_cast<double **>(ws + L.oP);
+        if (hipMemcpyAsync(dptr, ptrs.data(), ptrs.size() * sizeof(double *), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = ORTH_ERR_HIP;
+        for (int32_t j = 0; j < steps && rc == ORTH_OK; ++j) {
+            if (launch_synth(W, n, n, s, (uint64_t)j + 1, st) != hipSuccess) { rc = ORTH_ERR_HIP; break; }
+            rc = timed([&] { return orth_batch_step(b, dptr, dptr + copies, dptr + 2 * copies); });
+        }
+        if (rc == ORTH_OK) rc = orth_batch_status(b, &status, nullptr);
+        (void)orth_batch_destroy(b);
+    }
+    if (rc != ORTH_OK) return rc;
+    *ms_out = ms_total;
+    return status == ORTH_OK ? ORTH_OK : ORTH_ERR_BREAKDOWN;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t orth_tune_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t copies) {
+    TuneLayout L;
+    if (!tune_layout(n, s, k_max, copies, L)) return 0;
+    return (size_t)L.total * sizeof(double);
+}
+
+int orth_tune_leaf_rows(int64_t n, int32_t s, int32_t k_max, int32_t steps, int32_t copies,
+                        void *d_workspace, size_t workspace_bytes, void *stream, int32_t *best_leaf_rows,
+                        int32_t *cand_rows, double *cand_ms, int32_t max_cand, int32_t *ncand) {
+    if (!best_leaf_rows || (max_cand > 0 && (!cand_rows || !cand_ms))) return ORTH_ERR_ARG;
+    TuneLayout L;
+    if (!tune_layout(n, s, k_max, copies, L)) return ORTH_ERR_ARG;
+    if (steps < 1 || steps > k_max / s) return ORTH_ERR_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 || workspace_bytes < (size_t)L.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *ws = static_cast<double *>(d_workspace);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    const std::vector<int32_t> cand = tune_candidates(n, k_max);
+    std::vector<double> times(cand.size(), -1.0);
+    int rc = ORTH_OK;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        double ms = 0.0;
+        const int r = tune_one(n, s, k_max, cand[c], steps, copies, L, ws, st, e0, e1, &ms);
+        if (r == ORTH_OK) times[c] = ms;
+        else if (r != ORTH_ERR_BREAKDOWN) { rc = r; break; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ORTH_OK) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    double fastest = -1.0;
+    for (double t : times)
+        if (t >= 0.0 && (fastest < 0.0 || t < fastest)) fastest = t;
+    if (fastest < 0.0) return ORTH_ERR_BREAKDOWN;
+    int32_t best = 0;
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (times[c] >= 0.0 && times[c] <= 1.02 * fastest) best = std::max(best, cand[c]);
+    *best_leaf_rows = best;
+    for (size_t c = 0; c < cand.size() && (int32_t)c < max_cand; ++c) {
+        cand_rows[c] = cand[c];
+        cand_ms[c] = times[c];
+    }
+    if (ncand) *ncand = (int32_t)cand.size();
     return ORTH_OK;
 }
 

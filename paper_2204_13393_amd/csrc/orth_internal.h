@@ -303,6 +303,7 @@ hipError_t launch_copy_cols(const double *src, int64_t lds, RowMap smap, double 
 hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
                             int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);
+hipError_t launch_synth(double *W, int64_t ld, int64_t n, int32_t s, uint64_t seed, hipStream_t st);
 // one phase for the instances of block width s (prefix table restricted to them)
 hipError_t launch_batch_phase(const BatchArgs &a, int s, int32_t blocks, size_t lds, hipStream_t st);
 size_t batch_phase_lds(int phase, int s);     // dynamic LDS one instance of width s needs

@@ -686,6 +686,25 @@ __global__ void k_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy
     }
 }
 
+// Synthetic blocks for timing runs: entry (r, c) of block `seed` is a
+// splitmix64 hash of (seed, c, r) mapped to a uniform value in [-1, 1).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ void k_synth(double *W, int64_t ld, int64_t n, int32_t s, uint64_t seed) {
+    const int64_t total = n * s;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, r = e - c * n;
+        const uint64_t h = splitmix64(splitmix64(seed * 0x100000001B3ull + (uint64_t)c) ^ (uint64_t)r);
+        W[c * ld + r] = (double)(h >> 11) * 0x1.0p-52 - 1.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, double *__restrict__ dst,
                                               int64_t count) {
     const int64_t n2 = count / 2;
@@ -1007,6 +1026,12 @@ hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy
     const int64_t total = (int64_t)nx * ny * nz * s;
     hipLaunchKernelGGL(k_laplacian, dim3(grid_for(total, 256)), dim3(256), 0, st, X, ldx, Y, ldy, s,
                        nx, ny, nz, shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_synth(double *W, int64_t ld, int64_t n, int32_t s, uint64_t seed, hipStream_t st) {
+    if (n <= 0 || s <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_synth, dim3(grid_for(n * s, 256)), dim3(256), 0, st, W, ld, n, s, seed);
     return hipGetLastError();
 }
 

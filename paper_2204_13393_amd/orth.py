@@ -59,6 +59,9 @@ SIGNATURES = [
     ("orth_laplacian_apply", ctypes.c_int, [_dp, _i64, _dp, _i64, _i32, _i32, _i32, _i32,
                                             ctypes.c_double, _vp]),
     ("orth_probe_copy", ctypes.c_int, [_dp, _dp, _i64, _vp]),
+    ("orth_tune_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_tune_leaf_rows", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp,
+                                           ctypes.POINTER(_i32), _vp, _vp, _i32, ctypes.POINTER(_i32)]),
 ]
 
 _lib = None
@@ -171,6 +174,22 @@ def orth_laplacian_apply(d_X, ldx, d_Y, ldy, s, nx, ny, nz, shift, stream):
 
 def orth_probe_copy(d_src, d_dst, count, stream):
     return load().orth_probe_copy(d_src, d_dst, count, stream)
+
+
+def orth_tune_workspace_bytes(n, s, k_max, copies=1):
+    return load().orth_tune_workspace_bytes(n, s, k_max, copies)
+
+
+def orth_tune_leaf_rows(n, s, k_max, steps, copies, d_workspace, workspace_bytes, stream, max_cand=16):
+    """Returns (code, best leaf height, [(candidate, ms), ...])."""
+    best, count = ctypes.c_int32(), ctypes.c_int32()
+    rows = (_i32 * max_cand)()
+    ms = (ctypes.c_double * max_cand)()
+    code = load().orth_tune_leaf_rows(n, s, k_max, steps, copies, d_workspace, workspace_bytes, stream,
+                                      ctypes.byref(best), ctypes.cast(rows, _vp), ctypes.cast(ms, _vp),
+                                      max_cand, ctypes.byref(count))
+    cand = [(rows[i], ms[i]) for i in range(min(count.value, max_cand))] if code == ORTH_OK else []
+    return code, best.value, cand
 
 
 def _arr(ctype, values):

@@ -90,3 +90,49 @@ def test_product_path_has_no_oracle_import():
             if f.endswith(".py"):
                 src = open(os.path.join(root, f)).read()
                 assert "oracle" not in re.findall(r"^\s*(?:from|import)\s+(\w+)", src, flags=re.M), f
+
+
+def test_tune_workspace_and_argument_checks():
+    # the tuner's workspace holds the largest candidate plan plus W, U, H, R
+    n, s, k = 20000, 4, 32
+    need = orth.orth_tune_workspace_bytes(n, s, k, 1)
+    assert need % 256 == 0
+    heights = (256, 512, 1024, 2048, 4096, 8192, 16384)
+    plan_max = max(orth.orth_workspace_bytes(n, s, k, lr, 0) for lr in heights)
+    assert need >= plan_max + 2 * n * s * 8 + k * s * 8
+    # batches of copies: the largest batch workspace plus per-copy U and Hess
+    need4 = orth.orth_tune_workspace_bytes(n, s, k, 4)
+    batch_max = max(orth.orth_batch_workspace_bytes([n] * 4, [s] * 4, [k] * 4, [lr] * 4) for lr in heights)
+    assert need4 >= batch_max + n * s * 8 + 4 * (n * s * 8 + k * k * 8)
+    assert orth.orth_tune_workspace_bytes(0, 4, 32, 1) == 0
+    assert orth.orth_tune_workspace_bytes(100, 4, 200, 1) == 0       # k_max > n: no candidate
+    assert orth.orth_tune_workspace_bytes(n, s, k, 0) == 0           # copies out of range
+    # rejected before any device call
+    code, best, cand = orth.orth_tune_leaf_rows(n, s, k, 0, 1, 4096, need, None)
+    assert code == orth.ORTH_ERR_ARG                                  # steps < 1
+    code, best, cand = orth.orth_tune_leaf_rows(n, s, k, k // s + 1, 1, 4096, need, None)
+    assert code == orth.ORTH_ERR_ARG                                  # steps > k_max / s
+    code, best, cand = orth.orth_tune_leaf_rows(n, s, k, 2, 1, 4096, need - 8, None)
+    assert code == orth.ORTH_ERR_WORKSPACE
+    code, best, cand = orth.orth_tune_leaf_rows(n, s, k, 2, 1, 4096 + 8, need, None)
+    assert code == orth.ORTH_ERR_WORKSPACE                            # misaligned
+    code, best, cand = orth.orth_tune_leaf_rows(n, s, k, 2, 4, 4096, need4 - 8, None)
+    assert code == orth.ORTH_ERR_WORKSPACE
+
+
+def test_autotune_batch_buckets(monkeypatch, tmp_path):
+    from paper_2204_13393_amd import autotune
+    calls = []
+
+    def fake(n, s, k_max, steps=None, copies=1, cache=None, stream=None):
+        calls.append((n, s, k_max, copies))
+        return 8192
+    monkeypatch.setattr(autotune, "tune_leaf_rows", fake)
+    ns = [20000, 17000, 1 << 20, 3000, 5000]
+    ss = [4, 4, 8, 2, 2]
+    ks = [84, 84, 168, 42, 42]
+    rows = autotune.tune_batch(ns, ss, ks)
+    # 20000 and 17000 share the 2^14 bucket; 3000 rounds to 2^12 and 5000 to 2^12
+    assert calls == [(16384, 4, 84, 64), (1 << 20, 8, 168, 8), (4096, 2, 42, 64)]
+    # results are clipped to each instance's [k_max, n]
+    assert rows == [8192, 8192, 8192, 3000, 5000]

@@ -1,0 +1,84 @@
+"""GPU tests of the leaf-height autotuner (orth_tune_leaf_rows and its cache).
+
+* every admissible candidate {256, ..., 16384} within [k_max, n] (and n itself
+  when n <= 16384) is timed, through one handle and through batches of
+  identical copies, with a positive time (no breakdown on the synthetic
+  blocks), and the reported best is the tallest within 2% of the fastest;
+* the Python cache returns the measured value without measuring again;
+* a handle built with the tuned height reproduces the oracle's unique PQR.
+"""
+
+import json
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pqr_reference
+from synth import normal_block
+
+from gpu_util import kappa_after_projection, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    return torch
+
+
+@pytest.mark.parametrize("n,s,k_max,copies", [(20000, 4, 32, 1), (3000, 8, 64, 1), (9000, 2, 300, 1),
+                                              (20000, 4, 32, 3), (3000, 16, 64, 8)])
+def test_tuner_times_every_candidate(torch_cuda, n, s, k_max, copies):
+    from paper_2204_13393_amd import autotune
+    _say("tune", n, s, k_max, copies)
+    best, cand = autotune.measure_leaf_rows(n, s, k_max, steps=min(4, k_max // s), copies=copies)
+    expect = [lr for lr in (256, 512, 1024, 2048, 4096, 8192, 16384) if k_max <= lr <= n]
+    if n <= 16384 and n not in expect:
+        expect.append(n)
+    assert [r for r, _ in cand] == expect
+    assert all(ms > 0 for _, ms in cand)
+    fastest = min(ms for _, ms in cand)
+    # the tallest candidate within 2% of the fastest
+    assert best == max(r for r, ms in cand if ms <= 1.02 * fastest)
+
+
+def test_tuner_cache_and_tuned_handle(torch_cuda, tmp_path):
+    from paper_2204_13393_amd import Orthogonalizer, autotune
+    _say("tune cache")
+    path = str(tmp_path / "leaf_rows.json")
+    n, s, k_max = 12000, 4, 40
+    lr = autotune.tune_leaf_rows(n, s, k_max, steps=3, cache=path)
+    table = json.load(open(path))
+    assert len(table) == 1 and list(table.values())[0]["leaf_rows"] == lr
+    # a second call is served from the cache (a planted value proves it)
+    key = list(table)[0]
+    table[key]["leaf_rows"] = 1000
+    json.dump(table, open(path, "w"))
+    assert autotune.tune_leaf_rows(n, s, k_max, steps=3, cache=path) == 1000
+    # the tuned height gives the oracle's unique P, N, U
+    g = Orthogonalizer(n, s, k_max, lr)
+    Q = np.zeros((n, 0))
+    for j in range(k_max // s):
+        X = normal_block(n, s, 70 + j) * np.geomspace(1.0, 0.25, s)
+        H, R, U = g.step(to_dev(X))
+        P, N, Ur = pqr_reference(Q, X)
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if j:
+            assert np.linalg.norm(to_host(H) - P) / xn <= 1e-12
+        assert np.linalg.norm(to_host(R) - N) / xn <= 1e-12 * kap
+        assert np.max(np.abs(to_host(U) - Ur)) <= 1e-12 * kap
+        Q = np.hstack([Q, Ur])
+    assert g.status()[0] == 0
+    g.close()

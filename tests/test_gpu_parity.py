@@ -60,6 +60,7 @@ CASES = [
     (6000, 32, 160, 2000),    # s = 32, two N tiles in the Gram products
     (5000, 16, 256, 2500),    # k + s = 272: two column groups in the Gram kernel
     (9000, 8, 504, 4500),     # k + s = 512, coefficient blocks of 64 columns
+    (20000, 4, 32, 16384),    # one leaf of 10 chunks: its 40 Gram slots are pre-summed
 ]
 
 
