@@ -463,7 +463,8 @@ def main():
     print(f"[bench] generating inputs: n={n} s={s} steps={steps}", file=sys.stderr, flush=True)
     # --- inputs: start block + 30 Krylov blocks, resident in HBM
     R0 = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, W["seed"]).T)).to(dev)
-    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64)
+    # one workspace for both forms (the mixed form's is the larger: it adds the FP32 copy)
+    nbytes = max(orth.orth_workspace_bytes(n, s, kmax, leaf, p_) for p_ in (orth.ORTH_FP64, orth.ORTH_MIXED_SPLIT32))
     ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
     ws_ptr = (ws.data_ptr() + 255) // 256 * 256
     Xs = [R0]
@@ -484,8 +485,8 @@ def main():
             if code:
                 raise orth.OrthError("orth_step", code)
 
-    def make_handle():
-        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sptr)
+    def make_handle(precision=orth.ORTH_FP64):
+        code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sptr)
         if code:
             raise orth.OrthError("orth_create", code)
         return h
@@ -512,66 +513,76 @@ def main():
     torch.cuda.synchronize()
     print("[bench] inputs ready", file=sys.stderr, flush=True)
 
-    # --- warmup
-    for _ in range(args.warmup):
-        h = make_handle()
-        run_sequence(Xs, h)
-        orth.orth_destroy(h)
-    torch.cuda.synchronize()
+    def timed_runs(precision):
+        """Warmup, then args.steps timed sequences over the resident inputs;
+        returns (ms per sequence, per-class profile, e_perp of the explicit basis)."""
+        for _ in range(args.warmup):
+            h = make_handle(precision)
+            run_sequence(Xs, h)
+            orth.orth_destroy(h)
+        torch.cuda.synchronize()
+        handles = []
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        prof = {}
+        for _ in range(args.steps):
+            h = make_handle(precision)
+            if not args.no_profile:
+                orth.orth_profile_enable(h, 1)
+            run_sequence(Xs, h)
+            handles.append(h)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        wall_ms = (t1 - t0) * 1e3 / args.steps
+        gpu_ms = ev0.elapsed_time(ev1) / args.steps
+        for h in handles:
+            code, st, info = orth.orth_status(h)
+            if code or st:
+                raise RuntimeError(f"orth_step breakdown: {info}")
+            if not args.no_profile:
+                code, pr = orth.orth_profile_read(h)
+                for name, (ms, cnt) in pr.items():
+                    a = prof.setdefault(name, [0.0, 0])
+                    a[0] += ms
+                    a[1] += cnt
+            orth.orth_destroy(h)
+        # accuracy gate: e_perp of the explicit basis (torch GEMM, independent of the kernels)
+        G = torch.mm(V, V.t())
+        G -= torch.eye(kmax, dtype=torch.float64, device=dev)
+        ep = float(torch.linalg.matrix_norm(G, "fro"))
+        del G
+        return max(wall_ms, gpu_ms), prof, ep
 
-    # --- timed region
-    handles = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    prof = {}
-    for _ in range(args.steps):
-        h = make_handle()
-        if not args.no_profile:
-            orth.orth_profile_enable(h, 1)
-        run_sequence(Xs, h)
-        handles.append(h)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall_ms = (t1 - t0) * 1e3 / args.steps
-    gpu_ms = ev0.elapsed_time(ev1) / args.steps
-    for h in handles:
-        code, st, info = orth.orth_status(h)
-        if code or st:
-            raise RuntimeError(f"orth_step breakdown: {info}")
-        if not args.no_profile:
-            code, p = orth.orth_profile_read(h)
-            for name, (ms, cnt) in p.items():
-                a = prof.setdefault(name, [0.0, 0])
-                a[0] += ms
-                a[1] += cnt
-        orth.orth_destroy(h)
-    ms_per_step = max(wall_ms, gpu_ms)
+    ms_per_step, prof, e_perp = timed_runs(orth.ORTH_FP64)
     print(f"[bench] timed {args.steps} sequences: {ms_per_step:.2f} ms each", file=sys.stderr, flush=True)
-
-    # --- accuracy gate: e_perp of the explicit basis (torch GEMM, independent of the kernels)
-    G = torch.mm(V, V.t())
-    G -= torch.eye(kmax, dtype=torch.float64, device=dev)
-    e_perp = float(torch.linalg.matrix_norm(G, "fro"))
-    del G
+    # the mixed form (leaf bases stored FP32 hi + lo, sweep-1 Gram on hi) on the same inputs
+    ms_mixed, prof_mixed, e_perp_mixed = timed_runs(orth.ORTH_MIXED_SPLIT32)
+    print(f"[bench] mixed form: {ms_mixed:.2f} ms per sequence, e_perp {e_perp_mixed:.2e}",
+          file=sys.stderr, flush=True)
 
     p = max(1, n // leaf)
     widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
     value = total_bytes / (ms_per_step / 1e3) / 1e9
 
-    roofline = None
-    kernels = {}
-    if prof:
-        for name, (ms, cnt) in prof.items():
+    def per_class(pr):
+        out = {}
+        for name, (ms, cnt) in pr.items():
             if cnt == 0:
                 continue
             byts = sum(kernel_bytes(name, n, s, p, k) for k in widths) * args.steps
-            kernels[name] = {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3,
-                             "gbs": (byts / (ms / 1e3) / 1e9) if byts else None}
+            out[name] = {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3,
+                         "gbs": (byts / (ms / 1e3) / 1e9) if byts else None}
+        return out
+
+    roofline = None
+    kernels = {}
+    if prof:
+        kernels = per_class(prof)
         dom = max((k for k in kernels if kernel_bytes(k, n, s, p, 8) > 0),
                   key=lambda k: kernels[k]["ms_total"])
         d = kernels[dom]
@@ -617,6 +628,16 @@ def main():
                    "k_max": kmax, "precision": "fp64", "variant": "BCGS-PIP+ leaves and reduction"},
         "e_perp": e_perp,
         "e_perp_gate_1e-10": e_perp <= 1e-10,
+        "mixed": {
+            "precision": "mixed_split32: leaf bases FP32 hi + lo, sweep-1 Gram on hi, FP64 arithmetic",
+            "ms_per_step": ms_mixed,
+            "value_effective": total_bytes / (ms_mixed / 1e3) / 1e9,
+            "unit": "GB/s (FP64 algorithmic bytes)",
+            "speedup_vs_fp64": ms_per_step / ms_mixed,
+            "e_perp": e_perp_mixed,
+            "e_perp_gate_1e-10": e_perp_mixed <= 1e-10,
+            "kernels": per_class(prof_mixed) if prof_mixed else {},
+        },
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

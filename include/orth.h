@@ -21,8 +21,9 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - All matrices are IEEE FP64, column-major with a leading dimension
- *    (BLAS convention): element (r, c) of an n x s matrix at ptr[c*ld + r].
+ *  - All matrices the caller passes are IEEE FP64, column-major with a
+ *    leading dimension (BLAS convention): element (r, c) of an n x s matrix
+ *    at ptr[c*ld + r].
  *    A contiguous torch tensor of shape (s, n) is such a matrix with ld = n.
  *  - Pointers named d_* are device pointers (HIP device memory of the
  *    current device).  The caller owns every device buffer, including the
@@ -63,8 +64,31 @@ enum orth_code {
     ORTH_ERR_UNSUPPORTED = 7 /* valid request this build does not implement */
 };
 
+/*
+ * Precision form.  Arithmetic is FP64 on the matrix cores in both forms;
+ * the bases, tree factors, s x s Cholesky factors and H, R, U are FP64.
+ *   ORTH_FP64           every pass reads the FP64 leaf bases.
+ *   ORTH_MIXED_SPLIT32  the leaf bases are also kept as an FP32 copy
+ *                       (rounded to nearest), and the first CholeskyQR
+ *                       sweep's Gram product (Sec. 3.1) reads that copy: 4
+ *                       instead of 8 bytes per basis entry, P1 and N1
+ *                       accurate to about 6e-8 relative.  The correction
+ *                       u1 = (w - q P1) N1^{-1}, the second sweep and the
+ *                       assembly of U read the FP64 bases, so w = q P1 +
+ *                       u1 N1 holds in the stored basis and the reiteration
+ *                       wins the accuracy back (Sec. 3.1): results match the
+ *                       FP64 form to rounding.  Leaf bytes per step drop
+ *                       from 32 to 28 per basis entry (plus 4 bytes per new
+ *                       entry written); the workspace grows by 4 bytes per
+ *                       leaf basis entry.  The first sweep stays stable
+ *                       while 6e-8 kappa^2 << 1/2 (kappa the condition
+ *                       number of the projected block); beyond it a pivot
+ *                       may fail (BREAKDOWN).  Single handles only:
+ *                       orth_batch_create returns UNSUPPORTED.
+ */
 enum orth_precision {
-    ORTH_FP64 = 0            /* every product in FP64 */
+    ORTH_FP64 = 0,
+    ORTH_MIXED_SPLIT32 = 1
 };
 
 /* Variant of the leaf and reduction subalgorithm (Sec. 3, Sec. 3.1). */
@@ -86,7 +110,7 @@ enum orth_variant {
  *              p = max(1, n / leaf_rows) row blocks of leaf_rows rows, the
  *              last one taking the remainder; leaf_rows must be >= k_max so
  *              every local problem keeps full column rank, and <= n
- *   precision  ORTH_FP64
+ *   precision  ORTH_FP64 or ORTH_MIXED_SPLIT32
  * Returns 0 for invalid arguments.  Pure host arithmetic, no HIP call.
  */
 size_t orth_workspace_bytes(int64_t n, int32_t s, int32_t k_max,
@@ -222,7 +246,8 @@ int orth_destroy(orth_t *h);
  * one per phase over all instances (TreeTSPQR's local problems and
  * reductions are independent across instances, Sec. 4.1), with no host
  * synchronisation and no allocation, so whole runs can be captured in a
- * hipGraph.  Every instance works at k = step * s_i.
+ * hipGraph.  Every instance works at k = step * s_i.  Phases are launched
+ * once per block width present in the batch.
  * ------------------------------------------------------------------------ */
 typedef struct orth_batch_ctx orth_batch_t;
 
@@ -230,8 +255,8 @@ typedef struct orth_batch_ctx orth_batch_t;
  * orth_batch_workspace_bytes -- workspace for orth_batch_create.  Host arrays
  * of `count` entries: n[i], s[i], k_max[i] as for orth_workspace_bytes;
  * leaf_rows may be NULL (default height for every instance) or hold 0 for
- * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  Returns 0 for
- * invalid arguments.
+ * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  precision
+ * must be ORTH_FP64.  Returns 0 for invalid arguments.
  */
 size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t *s,
                                   const int32_t *k_max, const int32_t *leaf_rows,

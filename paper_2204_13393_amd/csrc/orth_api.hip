@@ -54,10 +54,11 @@ int32_t max_cols(int32_t) { return 2048; }
 struct Plan {
     int64_t n;
     int32_t s, kmax, leaf_rows, p;
+    int32_t precision;           // ORTH_FP64, or ORTH_MIXED_SPLIT32 (adds the FP32 copy of the leaf bases)
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, total;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -71,7 +72,7 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
                int *why) {
     *why = ORTH_ERR_ARG;
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
-    if (precision != ORTH_FP64) return false;
+    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32) return false;
     if (kmax + s > max_cols(s)) { *why = ORTH_ERR_UNSUPPORTED; return false; }
     if (leaf_rows == 0) leaf_rows = default_leaf_rows(n, kmax);
     if (leaf_rows < kmax || leaf_rows > n) return false;
@@ -79,6 +80,7 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.n = n;
     pl.s = s;
     pl.kmax = kmax;
+    pl.precision = precision;
     pl.leaf_rows = leaf_rows;
     pl.p = (int32_t)(n / leaf_rows);
     if (pl.p < 1) pl.p = 1;
@@ -121,6 +123,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
+    // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
+    pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
     pl.total = off;
     return true;
 }
@@ -181,6 +185,9 @@ struct orth_ctx {
     double *U1R() const { return ws + pl.oU1R; }
     double *CA() const { return ws + pl.oCA; }
     double *PL() const { return ws + pl.oPL; }
+    float *Qhi() const {
+        return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
+    }
     double *PR() const { return ws + pl.oPR; }
     double *PR2() const { return ws + pl.oPR2; }
     double *SL() const { return ws + pl.oSL; }
@@ -246,6 +253,7 @@ namespace {
 // more than kReduceGroup of them per leaf.
 struct LevelRun {
     Operand Q, X;
+    const float *Qhi;              // mixed form, leaves: FP32 copy read by the sweep-1 Gram
     OutOperand U1;
     LevelGeom geom;
     double *part, *part2;
@@ -273,6 +281,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     if ((int64_t)L.geom.nchunks() * gram_row_groups(ncol) * pstride > L.part_cap) return ORTH_ERR_HIP;
     GramArgs ga{};
     ga.Q = L.Q;
+    ga.Qhi = L.Qhi;
     ga.X = L.X;
     ga.k = k;
     ga.tile_groups = gram_tile_groups(ncol);
@@ -359,6 +368,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     if (!two) return ORTH_OK;
     // sweep-2 Gram [Q U1]^T U1
     GramArgs g2 = ga;
+    g2.Qhi = nullptr;             // the second sweep reads the FP64 basis
     g2.X = Operand{L.U1.ptr, L.U1.ld};
     {
         const int cls2 = L.level == 0 ? ORTH_K_LEAF_GRAM2 : ORTH_K_ROOT_GRAM2;
@@ -396,6 +406,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.X = Operand{d_W, ldw};
         L.U1 = OutOperand{h->U1L(), pl.ldq};
         L.geom = leaf_geom(pl, kLeafChunk);
+        L.Qhi = h->Qhi();
         L.part = h->PL();
         L.part2 = h->PR2();          // pre-sums when a single leaf holds many slots
         L.part_cap = pl.slot_cap;
@@ -450,6 +461,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         FinalizeArgs f{};
         f.Q = Operand{h->Q(), pl.ldq};
         f.Qnew = OutOperand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
+        f.Qnew_hi = h->Qhi() ? h->Qhi() + (int64_t)k * pl.ldq : nullptr;
         f.U1 = Operand{h->U1L(), pl.ldq};
         f.sweep = 2;
         f.k = k;
@@ -668,6 +680,10 @@ bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const 
                        const int32_t *leaf_rows, int32_t precision, BatchLayout &L, int *why) {
     *why = ORTH_ERR_ARG;
     if (count < 1 || count > (1 << 20) || !n || !s || !k_max) return false;
+    if (precision != ORTH_FP64) {
+        *why = ORTH_ERR_UNSUPPORTED;   // the batched kernels keep FP64 bases only
+        return false;
+    }
     L.count = count;
     L.plans.resize(count);
     L.inst_off.resize(count);

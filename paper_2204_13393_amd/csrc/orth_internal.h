@@ -144,6 +144,7 @@ struct OutOperand {
 // pass A: partial [Q X]^T X per chunk (and per row group of the chunk)
 struct GramArgs {
     Operand Q;            // k columns
+    const float *Qhi;     // mixed form, sweep 1: read the FP32 copy of Q (same ld) instead
     Operand X;            // s columns
     int32_t k;
     int32_t tile_groups;  // waves of a workgroup sharing the rows: 1, 2 or 4
@@ -198,6 +199,7 @@ struct CholArgs {
 struct FinalizeArgs {
     Operand Q;            // k columns (read)
     OutOperand Qnew;      // s output columns, same RowMap
+    float *Qnew_hi;       // mixed form: also store fl32 of the new columns here (ld of Qnew)
     Operand U1;           // s input columns (x for sweep 1, u1 for sweep 2)
     int32_t sweep;        // which coefficients of the leaf record: 1 (P1, N1^-1) or 2 (P2, N2^-1)
     int32_t k;

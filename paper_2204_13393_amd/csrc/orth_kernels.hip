@@ -60,6 +60,40 @@ __device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
 }
 
 
+// R consecutive doubles / floats (as FP64) starting at p, vector loads when
+// 16-byte aligned
+template <int R>
+__device__ __forceinline__ void load_run(const double *p, double (&v)[R]) {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < R / 2; ++u) {
+            const double2 w = reinterpret_cast<const double2 *>(p)[u];
+            v[2 * u] = w.x;
+            v[2 * u + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < R; ++u) v[u] = p[u];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void load_run(const float *p, double (&v)[R]) {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < R / 4; ++u) {
+            const float4 w = reinterpret_cast<const float4 *>(p)[u];
+            v[4 * u] = w.x;
+            v[4 * u + 1] = w.y;
+            v[4 * u + 2] = w.z;
+            v[4 * u + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < R; ++u) v[u] = p[u];
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- sweep 1
@@ -164,6 +198,117 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
 template <int S, int CLS>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     gram_body<S>(a, blockIdx.x, blockIdx.y);
+}
+
+// The mixed form's sweep-1 Gram: the basis columns come from the FP32 copy
+// (4 bytes per entry, converted exactly to FP64), X stays FP64.  Same tiles,
+// slots and products as gram_body; each lane takes RPL consecutive rows per
+// column (16 for narrow blocks) so a wave keeps as many bytes in flight as
+// the FP64 kernel.
+template <int S>
+__device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) {
+    if (failed(a.status)) return;
+    constexpr int NT = (S + 15) / 16;
+    constexpr int RPL = S >= 16 ? 8 : 16;
+    constexpr int MS = 4 * RPL;                 // rows per macro-step
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int il = lane & 15, g = lane >> 4;
+    const int k = a.k, ncol = k + S;
+    const int nmt = (ncol + 15) >> 4;
+    const int TG = a.tile_groups, RG = kWaves / TG;
+    const int tg = by * TG + wave % TG;
+    const int rg = wave / TG;
+    const int tile0 = tg * kGramTPW;
+    if (tile0 >= nmt) return;
+    int leaf;
+    int64_t r0, r1;
+    a.geom.chunk(bx, leaf, r0, r1);
+
+    const float *colh[kGramTPW];
+    const double *colp[kGramTPW];
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t) {
+        const int c = (tile0 + t) * 16 + il;
+        colh[t] = c < k ? a.Qhi + (int64_t)c * a.Q.ld : nullptr;
+        colp[t] = (c >= k && c < ncol) ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr;
+    }
+    const double *xcol[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int j = 16 * nt + il;
+        xcol[nt] = j < S ? a.X.ptr + (int64_t)j * a.X.ld : nullptr;
+    }
+    dbl4 acc[kGramTPW][NT];
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
+
+    const bool ident = a.geom.map.seg_len == 0;
+    for (int64_t rm = r0 + MS * rg; rm < r1; rm += MS * RG) {
+        double av[kGramTPW][RPL], bv[NT][RPL];
+        const int64_t rb = rm + RPL * g;
+        if (ident && rm + MS <= r1) {
+#pragma unroll
+            for (int t = 0; t < kGramTPW; ++t) {
+                if (colh[t]) {
+                    load_run<RPL>(colh[t] + rb, av[t]);
+                } else if (colp[t]) {
+                    load_run<RPL>(colp[t] + rb, av[t]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RPL; ++u) av[t][u] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if (xcol[nt]) {
+                    load_run<RPL>(xcol[nt] + rb, bv[nt]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RPL; ++u) bv[nt][u] = 0.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+                const int64_t row = rb + u;
+                const bool ok = row < r1;
+                const int64_t prow = a.geom.map.phys(ok ? row : r0);
+#pragma unroll
+                for (int t = 0; t < kGramTPW; ++t)
+                    av[t][u] = !ok ? 0.0 : (colh[t] ? (double)colh[t][prow] : (colp[t] ? colp[t][prow] : 0.0));
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? xcol[nt][prow] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RPL; ++u)
+#pragma unroll
+            for (int t = 0; t < kGramTPW; ++t)
+                if (tile0 + t < nmt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = mfma16(av[t][u], bv[nt][u], acc[t][nt]);
+    }
+    double *out = a.partials + ((int64_t)bx * RG + rg) * a.part_stride;
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t) {
+        if (tile0 + t >= nmt) break;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int j = 16 * nt + il;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = (tile0 + t) * 16 + 4 * v + g;
+                if (c < ncol && j < S) out[(int64_t)c * S + j] = acc[t][nt][v];
+            }
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_gram_hi(GramArgs a) {
+    gram_hi_body<S>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- reduce
@@ -540,6 +685,12 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
 #pragma unroll
                     for (int t = 0; t < TR; ++t)
                         if (ok[t]) col[prow[t]] = y[t];
+                }
+                if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
+                    float *ch = a.Qnew_hi + (int64_t)j * a.Qnew.ld;
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) ch[prow[t]] = (float)y[t];
                 }
             }
         if (EXPL) {
@@ -930,7 +1081,26 @@ static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int S>
+static hipError_t gram_hi_s(const GramArgs &a, hipStream_t st) {
+    const dim3 grid(a.geom.nchunks(), gram_col_groups(a.k + S));
+    hipLaunchKernelGGL((k_gram_hi<S>), grid, dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st) {
+    if (a.Qhi) {                      // mixed form, leaf sweep-1 Gram
+        if (cls != 0) return hipErrorInvalidValue;
+        switch (s) {
+            case 1: return gram_hi_s<1>(a, st);
+            case 2: return gram_hi_s<2>(a, st);
+            case 4: return gram_hi_s<4>(a, st);
+            case 8: return gram_hi_s<8>(a, st);
+            case 16: return gram_hi_s<16>(a, st);
+            case 32: return gram_hi_s<32>(a, st);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (s) {
         case 1: return gram_s<1>(a, cls, st);
         case 2: return gram_s<2>(a, cls, st);

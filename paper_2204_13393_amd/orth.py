@@ -25,6 +25,7 @@ ORTH_ERR_POISONED = 5
 ORTH_ERR_WORKSPACE = 6
 ORTH_ERR_UNSUPPORTED = 7
 ORTH_FP64 = 0
+ORTH_MIXED_SPLIT32 = 1
 ORTH_PIP_PLUS = 0
 ORTH_PIP = 1
 
@@ -264,19 +265,21 @@ class Orthogonalizer:
     of shape (s, n) on the device.
     """
 
-    def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS):
+    def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
+                 precision=ORTH_FP64):
         import torch
         load()
         self.n, self.s, self.k_max = int(n), int(s), int(k_max)
+        self.precision = precision
         self.device = torch.device(device)
-        nbytes = orth_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64)
+        nbytes = orth_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision)
         if nbytes == 0:
             raise OrthError("orth_workspace_bytes", ORTH_ERR_ARG)
         self.stream = stream
         self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        code, h = orth_create(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64, aligned, nbytes,
+        code, h = orth_create(self.n, self.s, self.k_max, leaf_rows, precision, aligned, nbytes,
                               _stream_ptr(stream))
         _check("orth_create", code)
         self.h = h

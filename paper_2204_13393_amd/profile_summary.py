@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for this library's kernels.
 
 Kernel instantiations carry their launch site's profiler class as the last
-template argument (k_gram<S, CLS>, k_rowmfma<S, EXPL, CLS>), so every
+template argument after the block width (k_gram<S, CLS, QM>,
+k_rowmfma<S, EXPL, CLS, QM>), so every
 dispatch in a kernel trace maps to one class of orth_kernel_class.
 
     python -m paper_2204_13393_amd.profile_summary trace  <kernel_trace.csv>
@@ -26,10 +27,10 @@ ROWUPD = {2: "leaf_correct", 5: "root_correct", 6: "root_finalize", 7: "leaf_fin
 
 
 def classify(name):
-    m = re.search(r"k_gram<(\d+), (\d+)>", name)
+    m = re.search(r"k_gram<(\d+), (\d+), (\d+)>", name)
     if m:
         return GRAM.get(int(m.group(2)), "gram?")
-    m = re.search(r"k_rowmfma<(\d+), (?:true|false), (\d+)>", name)
+    m = re.search(r"k_rowmfma<(\d+), (?:true|false), (\d+), (\d+)>", name)
     if m:
         return ROWUPD.get(int(m.group(2)), "rowupdate?")
     for key, cls in (("k_chol", "chol"), ("k_reduce", "reduce"), ("k_apply", "apply"),

@@ -46,11 +46,27 @@ def test_workspace_bytes_arithmetic():
     (1000, 4, 10, 0, 0),     # k_max not a multiple of s
     (1000, 4, 40, 20, 0),    # leaf_rows < k_max
     (1000, 4, 40, 2000, 0),  # leaf_rows > n
-    (1000, 4, 40, 0, 1),     # unknown precision
+    (1000, 4, 40, 0, 2),     # unknown precision
     (100000, 16, 2048, 0, 0),  # wider than the planner accepts (k_max + s > 2048)
 ])
 def test_workspace_rejects_bad_arguments(args):
     assert orth.orth_workspace_bytes(*args) == 0
+
+
+def test_mixed_form_workspace_adds_the_fp32_copy():
+    # the FP32 copy of the leaf bases: 4 bytes per (ld x k_max) entry on top
+    for (n, s, k, lr) in ((10000, 4, 44, 1000), (2 ** 24, 8, 248, 4096), (777, 1, 12, 100)):
+        f64 = orth.orth_workspace_bytes(n, s, k, lr, 0)
+        mixed = orth.orth_workspace_bytes(n, s, k, lr, orth.ORTH_MIXED_SPLIT32)
+        assert f64 > 0 and mixed % 256 == 0
+        assert n * k * 4 <= mixed - f64 <= (n + 64) * k * 4 + 256
+
+
+def test_mixed_form_is_single_handle_only():
+    assert orth.orth_batch_workspace_bytes([5000, 3000], [4, 8], [16, 32], None, orth.ORTH_MIXED_SPLIT32) == 0
+    code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, orth.ORTH_MIXED_SPLIT32,
+                                     4096, 1 << 30, None)
+    assert code == orth.ORTH_ERR_UNSUPPORTED
 
 
 def test_wide_blocks_are_planned():

@@ -1,0 +1,184 @@
+"""GPU tests of the mixed form (ORTH_MIXED_SPLIT32): leaf bases stored as FP32
+hi + lo, the first CholeskyQR sweep on the hi half, the second sweep and the
+assembly of U on hi + lo.
+
+The oracle is the FP64 one (no printed value exists for the mixed form: its
+parity is pinned only against the FP64 oracle).  Tolerances of the mixed
+form, stated per quantity (kappa_j = ||X||_2 ||N^{-1}||_2):
+  ||dP||_F / ||X||_F <= 1e-10,  ||dN||_F / ||X||_F <= 1e-10 kappa_j,
+  max |dU| <= 1e-10 kappa_j,  e_perp of the explicit basis <= 1e-10,
+  residual ||X - Q H - U R||_F / ||X||_F <= 1e-11.
+Outside the first sweep's stability region (6e-8 kappa^2 not small) the
+handle must report BREAKDOWN or still meet the e_perp and residual bounds;
+never a silent loss of orthogonality.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import metrics, pqr_reference
+from oracle import operators as ops
+from synth import normal_block
+
+from gpu_util import kappa_after_projection, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+MIXED = 1
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    assert orth.ORTH_MIXED_SPLIT32 == MIXED
+    return torch
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows", [
+    (10000, 4, 44, 1000),
+    (3000, 8, 64, 700),
+    (1037, 2, 16, 128),
+    (777, 1, 12, 100),
+    (6000, 32, 160, 2000),
+    (5000, 16, 256, 2500),
+])
+def test_mixed_open_loop_parity(torch_cuda, n, s, kmax, leaf_rows):
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("mixed open-loop", n, s, kmax, leaf_rows)
+    rng = np.random.default_rng(n * 7 + s)
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows, precision=MIXED)
+    Q = np.zeros((n, 0))
+    Vg = np.zeros((n, 0))
+    worst = 0.0
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        H, R, U = to_host(Hd), to_host(Rd), to_host(Ud)
+        P, N, Ur = pqr_reference(Q, X)
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if step:
+            worst = max(worst, np.linalg.norm(H - P) / xn)
+            assert np.linalg.norm(H - P) / xn <= 1e-10, step
+        assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0)
+        assert np.linalg.norm(R - N) / xn <= 1e-10 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-10 * kap, step
+        assert metrics.pqr_residual(Vg, X, H, R, U) <= 1e-11
+        Vg = np.hstack([Vg, U])
+        Q = np.hstack([Q, Ur])
+    st, info = gpu.status()
+    assert st == 0, info
+    assert metrics.e_perp(Vg) <= 1e-10
+    # the local bases come back as FP64 (hi + lo), orthonormal per leaf
+    Qloc, T = gpu.export_local()
+    Qloc = to_host(Qloc)
+    for i in range(gpu.p):
+        r0 = i * gpu.leaf_rows
+        r1 = n if i == gpu.p - 1 else r0 + gpu.leaf_rows
+        assert metrics.e_perp(Qloc[r0:r1]) <= 1e-10
+    C = rng.standard_normal((gpu.k, 9))
+    Y = to_host(gpu.apply_Q(to_dev(C)))
+    assert np.max(np.abs(Y - Vg @ C)) <= 1e-10 * np.abs(C).sum(0).max()
+    print("[mixed] worst ||dP||/||X||", worst, "e_perp", metrics.e_perp(Vg), flush=True)
+    gpu.close()
+
+
+def test_mixed_arnoldi_closed_loop(torch_cuda):
+    """2D 100x100 Laplacian + 0.01 I, s = 4, 10 steps, 10 leaves, mixed form."""
+    import torch
+    from paper_2204_13393_amd import Orthogonalizer, laplacian_apply
+    from oracle import block_arnoldi
+    _say("mixed arnoldi lap2d-100x100-s4")
+    nx, ny, shift, s, steps, leaf = 100, 100, 0.01, 4, 10, 1000
+    n = nx * ny
+    R0 = normal_block(n, s, 0)
+    apply_A = lambda X: ops.laplacian_2d_apply(X, nx, ny, shift)
+    Vo, Ho, H0o, _ = block_arnoldi(apply_A, R0, steps)
+    gpu = Orthogonalizer(n, s, (steps + 1) * s, leaf, precision=MIXED)
+    K = (steps + 1) * s
+    Hd = torch.zeros((steps * s, K), dtype=torch.float64, device="cuda")
+    _, H0d, V = gpu.step(to_dev(R0))
+    blocks = [V]
+    for j in range(steps):
+        X = laplacian_apply(blocks[-1], (nx, ny), shift)
+        k = gpu.k
+        Hj, Rj, U = gpu.step(X)
+        Hd[j * s:(j + 1) * s, :k] = Hj
+        Hd[j * s:(j + 1) * s, k:k + s] = Rj
+        blocks.append(U)
+    torch.cuda.synchronize()
+    st, info = gpu.status()
+    assert st == 0, info
+    H = to_host(Hd)
+    Vg = np.hstack([to_host(b) for b in blocks])
+    assert np.max(np.abs(H - Ho)) <= 1e-9
+    assert metrics.e_perp(Vg) <= 1e-10
+    lo, hi = ops.laplacian_extreme_eigs((nx, ny), shift)
+    assert metrics.arnoldi_relation(apply_A, Vg, H, hi) <= 1e-11
+    gpu.close()
+
+
+@pytest.mark.parametrize("sigma_min", [1e-2, 1e-6])
+def test_mixed_stability_boundary(torch_cuda, sigma_min):
+    """Blocks with singular values from 1 to sigma_min: FP64 succeeds; the mixed
+    form either succeeds to its tolerances or reports BREAKDOWN."""
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("mixed boundary", sigma_min)
+    n, s, kmax, leaf = 8000, 8, 48, 2000
+    rng = np.random.default_rng(11)
+    blocks = []
+    for j in range(kmax // s):
+        G = rng.standard_normal((n, s))
+        Ug, _ = np.linalg.qr(G)
+        Vt, _ = np.linalg.qr(rng.standard_normal((s, s)))
+        blocks.append(Ug @ np.diag(np.geomspace(1.0, sigma_min, s)) @ Vt.T)
+    results = {}
+    for prec in (0, MIXED):
+        g = Orthogonalizer(n, s, kmax, leaf, precision=prec)
+        Vg = np.zeros((n, 0))
+        ok_res = True
+        for X in blocks:
+            H, R, U = (to_host(t) for t in g.step(to_dev(X)))
+            ok_res &= bool(metrics.pqr_residual(Vg, X, H, R, U) <= 1e-11)
+            Vg = np.hstack([Vg, U])
+        st, _ = g.status()
+        results[prec] = (st, metrics.e_perp(Vg), ok_res)
+        g.close()
+    st64, ep64, res64 = results[0]
+    assert st64 == 0 and ep64 <= 1e-12 and res64
+    stm, epm, resm = results[MIXED]
+    print("[mixed] sigma_min", sigma_min, "status", stm, "e_perp", epm, flush=True)
+    if sigma_min >= 1e-2:
+        assert stm == 0
+    assert stm == orth.ORTH_ERR_BREAKDOWN or (stm == 0 and epm <= 1e-10 and resm)
+
+
+def test_mixed_determinism(torch_cuda):
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("mixed determinism")
+    n, s, kmax = 9000, 8, 40
+    outs = []
+    for rep in range(2):
+        g = Orthogonalizer(n, s, kmax, 1500, precision=MIXED)
+        res = []
+        for j in range(kmax // s):
+            H, R, U = g.step(to_dev(normal_block(n, s, 300 + j)))
+            res.append((to_host(H), to_host(R), to_host(U)))
+        outs.append(res)
+        g.close()
+    for a, b in zip(*outs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
