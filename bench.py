@@ -337,13 +337,14 @@ def bench_lap3d(args):
     V = torch.empty((kmax, n), dtype=torch.float64, device=dev)
     W = torch.empty((s, n), dtype=torch.float64, device=dev)
     H = torch.zeros((kmax, kmax), dtype=torch.float64, device=dev)
-    o = Orthogonalizer(n, s, kmax, leaf)
+    # one workspace for both forms (the mixed form adds the FP32 copy)
+    o = Orthogonalizer(n, s, kmax, leaf, precision=orth.ORTH_MIXED_SPLIT32)
     ws_ptr = (o.workspace.data_ptr() + 255) // 256 * 256
-    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf)
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_MIXED_SPLIT32)
     o.close()
 
-    def run(timed):
-        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sp)
+    def run(timed, precision=orth.ORTH_FP64):
+        code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sp)
         if code:
             raise orth.OrthError("orth_create", code)
         if timed:
@@ -372,18 +373,22 @@ def bench_lap3d(args):
             raise RuntimeError(f"breakdown {info}")
         return ms, prof
 
-    for _ in range(args.warmup):
-        run(False)
-    times = []
-    prof = None
-    for _ in range(args.steps):
-        ms, prof = run(True)
-        times.append(ms)
-    best = min(times)
-    G = torch.mm(V, V.t())
-    G -= torch.eye(kmax, dtype=torch.float64, device=dev)
-    e_perp = float(torch.linalg.matrix_norm(G, "fro"))
-    del G
+    def timed(precision):
+        for _ in range(args.warmup):
+            run(False, precision)
+        times = []
+        pr = None
+        for _ in range(args.steps):
+            ms, pr = run(True, precision)
+            times.append(ms)
+        G = torch.mm(V, V.t())
+        G -= torch.eye(kmax, dtype=torch.float64, device=dev)
+        ep = float(torch.linalg.matrix_norm(G, "fro"))
+        del G
+        return min(times), pr, ep
+
+    best, prof, e_perp = timed(orth.ORTH_FP64)
+    best_mixed, prof_mixed, e_perp_mixed = timed(orth.ORTH_MIXED_SPLIT32)
     p = n // leaf
     widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
@@ -399,10 +404,13 @@ def bench_lap3d(args):
     M = np.linalg.solve(Rg, np.diag(sig) @ Vh.T)
     W.copy_(torch.from_numpy(np.ascontiguousarray((Gm @ M).T)))
     del Gm
-    code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, ws_ptr, nbytes, sp)
-    orth.orth_step(h, W.data_ptr(), n, 0, 1, H.data_ptr(), kmax, V[:s].data_ptr(), n)
-    code, st, info = orth.orth_status(h)
-    orth.orth_destroy(h)
+    ill = {}
+    for name, prec in (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32)):
+        code, h = orth.orth_create(n, s, kmax, leaf, prec, ws_ptr, nbytes, sp)
+        orth.orth_step(h, W.data_ptr(), n, 0, 1, H.data_ptr(), kmax, V[:s].data_ptr(), n)
+        code, st, info = orth.orth_status(h)
+        orth.orth_destroy(h)
+        ill[name] = {"status": "breakdown" if st else "ok", "info": info}
     out = {
         "metric": METRIC,
         "workload": "lap3d-256-s32",
@@ -413,9 +421,109 @@ def bench_lap3d(args):
         "orth_calls": len(widths),
         "e_perp": e_perp,
         "kernels": kernels,
-        "ill_conditioned_start_block": {"kappa": 1e8, "status": "breakdown" if st else "ok", "info": info},
+        "mixed": {
+            "precision": "mixed_split32: leaf bases FP32 copy for the sweep-1 Gram, FP64 arithmetic",
+            "ms_per_sequence": best_mixed,
+            "value_effective": total_bytes / (best_mixed / 1e3) / 1e9,
+            "speedup_vs_fp64": best / best_mixed,
+            "e_perp": e_perp_mixed,
+            "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
+                        for name, (ms, cnt) in prof_mixed.items() if cnt},
+        },
+        "ill_conditioned_start_block": {"kappa": 1e8, **ill},
         "dtype": "f64",
         "data": "synthetic: N(0,1) start block (seed 5), 3D Dirichlet Laplacian 256^3",
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_stewart(args):
+    """Precision workload: block-column QR (Sec. 2, the block-column QR
+    algorithm) of one n x 240 matrix W = G diag(sigma) V^T with n = 2^24,
+    s = 8 (30 calls), leaf height 4096; sigma log-spaced from 1 to 1e-6 and
+    from 1 to 1e-12 (kappa 1e6 and 1e12); V Haar (QR of a Gaussian), G
+    Gaussian / sqrt(n), orthonormal to about 2 sqrt(240/n) = 0.008 at this n, so
+    the singular values of W are sigma to within 1%.  FP64 and mixed forms.
+    Per form and range: status (and the call after which a breakdown was
+    reported), time of the calls (HIP events around each), e_perp of the
+    explicit Q and ||W - Q R||_F / ||W||_F."""
+    import math
+    import torch
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    n, m, s, leaf = 1 << 24, 240, 8, 4096
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    print("[bench] stewart: generating W (n = 2^24, 240 columns)", file=sys.stderr, flush=True)
+    Gt = torch.randn((m, n), dtype=torch.float64, device=dev, generator=gen)
+    Gt /= math.sqrt(n)
+    Vh, _ = torch.linalg.qr(torch.randn((m, m), dtype=torch.float64, device=dev, generator=gen))
+    Qt = torch.empty((m, n), dtype=torch.float64, device=dev)          # explicit Q, column-major n x m
+    Rt = torch.zeros((m, m), dtype=torch.float64, device=dev)          # R, column-major m x m
+    o = Orthogonalizer(n, s, m, leaf, precision=orth.ORTH_MIXED_SPLIT32)
+    ws_ptr = (o.workspace.data_ptr() + 255) // 256 * 256
+    nbytes = orth.orth_workspace_bytes(n, s, m, leaf, orth.ORTH_MIXED_SPLIT32)
+    o.close()
+    results = []
+    for smin in (1e-6, 1e-12):
+        sig = torch.logspace(0.0, math.log10(smin), m, dtype=torch.float64, device=dev)
+        Wt = torch.mm(Vh * sig, Gt)            # W^T = V diag(sigma) G^T
+        wnorm = float(torch.linalg.norm(Wt))
+        for name, prec in (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32)):
+            for rep in range(args.warmup + 1):
+                Rt.zero_()
+                code, h = orth.orth_create(n, s, m, leaf, prec, ws_ptr, nbytes, sp)
+                if code:
+                    raise orth.OrthError("orth_create", code)
+                ms, failed = 0.0, None
+                for j in range(m // s):
+                    k = j * s
+                    col = Rt[k:k + s]
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    code = orth.orth_step(h, Wt[k:k + s].data_ptr(), n, col.data_ptr(), m,
+                                          col[:, k:].data_ptr(), m, Qt[k:k + s].data_ptr(), n)
+                    e1.record(stream)
+                    if code:
+                        raise orth.OrthError("orth_step", code)
+                    code, st, info = orth.orth_status(h)
+                    if st:
+                        failed = {"call": j, "info": info}
+                        break
+                    ms += e0.elapsed_time(e1)
+                orth.orth_destroy(h)
+            row = {"form": name, "sigma_min": smin, "status": "breakdown" if failed else "ok",
+                   "breakdown": failed}
+            if not failed:
+                Gq = torch.mm(Qt, Qt.t())
+                Gq -= torch.eye(m, dtype=torch.float64, device=dev)
+                row["e_perp"] = float(torch.linalg.matrix_norm(Gq, "fro"))
+                del Gq
+                res2 = 0.0
+                for c0 in range(0, n, 1 << 21):       # ||W^T - R^T Q^T|| in column chunks
+                    D = Wt[:, c0:c0 + (1 << 21)] - torch.mm(Rt, Qt[:, c0:c0 + (1 << 21)])
+                    res2 += float(torch.sum(D * D))
+                    del D
+                row["residual"] = math.sqrt(res2) / wnorm
+                row["ms_30_calls"] = ms
+                row["e_perp_gate_1e-10"] = row["e_perp"] <= 1e-10
+            print(f"[bench] stewart {name} sigma_min {smin}: {row['status']}", file=sys.stderr, flush=True)
+            results.append(row)
+        del Wt
+    fp = {r["sigma_min"]: r for r in results if r["form"] == "fp64"}
+    mx = {r["sigma_min"]: r for r in results if r["form"] == "mixed"}
+    speed = {str(k): fp[k]["ms_30_calls"] / mx[k]["ms_30_calls"]
+             for k in fp if fp[k]["status"] == "ok" and mx[k]["status"] == "ok"}
+    out = {
+        "metric": METRIC,
+        "workload": "stewart-2^24x240-s8",
+        "results": results,
+        "mixed_speedup_vs_fp64": speed,
+        "dtype": "f64",
+        "data": "synthetic: W = G diag(sigma) V^T, G Gaussian/sqrt(n), V Haar (torch, seed 7)",
     }
     print(json.dumps(out), flush=True)
 
@@ -430,9 +538,9 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
-                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32"],
+                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart"],
                     help="the default single-basis run, the batched form (512 instances), "
-                         "or the large-block 3D run")
+                         "the large-block 3D run, or the precision workload (Stewart matrices)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -444,6 +552,8 @@ def main():
         return bench_batched(args)
     if args.workload == "lap3d-256-s32":
         return bench_lap3d(args)
+    if args.workload == "stewart":
+        return bench_stewart(args)
 
     import numpy as np
     import torch
