@@ -147,10 +147,19 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     for (int64_t rm = r0 + 32 * rg; rm < r1; rm += 32 * RG) {
         double av[kGramTPW][8], bv[NT][8];
         const int64_t rb = rm + 8 * g;
-        if (ident && rm + 32 <= r1) {
+        // this lane's 8 rows are contiguous in memory: always at the leaf
+        // level, and at the reduction level when they sit in one segment
+        bool contig = rm + 32 <= r1;
+        int64_t pb = rb;
+        if (!ident) {
+            const int64_t q0 = rb / a.geom.map.seg_len;
+            contig = contig && (rb + 7) / a.geom.map.seg_len == q0;
+            pb = q0 * a.geom.map.seg_stride + (rb - q0 * a.geom.map.seg_len);
+        }
+        if (contig) {
 #pragma unroll
             for (int t = 0; t < kGramTPW; ++t) {
-                if (colp[t]) load8(colp[t] + rb, av[t]);
+                if (colp[t]) load8(colp[t] + pb, av[t]);
                 else
 #pragma unroll
                     for (int u = 0; u < 8; ++u) av[t][u] = 0.0;
@@ -158,7 +167,7 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) bv[nt][u] = xcol[nt] ? xcol[nt][rb + u] : 0.0;
+                for (int u = 0; u < 8; ++u) bv[nt][u] = xcol[nt] ? xcol[nt][pb + u] : 0.0;
         } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
