@@ -43,23 +43,6 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
 
 __device__ __forceinline__ dbl4 zero4() { return dbl4{0.0, 0.0, 0.0, 0.0}; }
 
-// 8 consecutive doubles starting at p (vector loads when 16-byte aligned)
-__device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
-    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-        const double2 *q = reinterpret_cast<const double2 *>(p);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double2 w = q[u];
-            v[2 * u] = w.x;
-            v[2 * u + 1] = w.y;
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[u];
-    }
-}
-
-
 // R consecutive doubles / floats (as FP64) starting at p, vector loads when
 // 16-byte aligned
 template <int R>
@@ -107,10 +90,18 @@ __device__ __forceinline__ void load_run(const float *p, double (&v)[R]) {
 // macro-steps of the chunk (row groups) and write their own partial slots.
 // CLS (the launch site's profiler class) only names the instantiation, so a
 // kernel trace attributes every dispatch to its role.
+// rows per lane and column in one macro-step of the Gram kernel: RPL
+// consecutive rows per lane give each column a contiguous run of 32 RPL bytes
+// per wave
+template <int S>
+__host__ __device__ constexpr int gram_rpl() { return 8; }
+
 template <int S>
 __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
+    constexpr int RPL = gram_rpl<S>();
+    constexpr int MS = 4 * RPL;                 // rows per macro-step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
     const int k = a.k, ncol = k + S;
@@ -144,33 +135,40 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
         for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
 
     const bool ident = a.geom.map.seg_len == 0;
-    for (int64_t rm = r0 + 32 * rg; rm < r1; rm += 32 * RG) {
-        double av[kGramTPW][8], bv[NT][8];
-        const int64_t rb = rm + 8 * g;
-        // this lane's 8 rows are contiguous in memory: always at the leaf
+    for (int64_t rm = r0 + MS * rg; rm < r1; rm += MS * RG) {
+        double av[kGramTPW][RPL], bv[NT][RPL];
+        const int64_t rb = rm + RPL * g;
+        // this lane's RPL rows are contiguous in memory: always at the leaf
         // level, and at the reduction level when they sit in one segment
-        bool contig = rm + 32 <= r1;
+        bool contig = rm + MS <= r1;
         int64_t pb = rb;
         if (!ident) {
             const int64_t q0 = rb / a.geom.map.seg_len;
-            contig = contig && (rb + 7) / a.geom.map.seg_len == q0;
+            contig = contig && (rb + RPL - 1) / a.geom.map.seg_len == q0;
             pb = q0 * a.geom.map.seg_stride + (rb - q0 * a.geom.map.seg_len);
         }
         if (contig) {
 #pragma unroll
             for (int t = 0; t < kGramTPW; ++t) {
-                if (colp[t]) load8(colp[t] + pb, av[t]);
-                else
+                if (colp[t]) {
+                    load_run<RPL>(colp[t] + pb, av[t]);
+                } else {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) av[t][u] = 0.0;
+                    for (int u = 0; u < RPL; ++u) av[t][u] = 0.0;
+                }
             }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int nt = 0; nt < NT; ++nt) {
+                if (xcol[nt]) {
+                    load_run<RPL>(xcol[nt] + pb, bv[nt]);
+                } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) bv[nt][u] = xcol[nt] ? xcol[nt][pb + u] : 0.0;
+                    for (int u = 0; u < RPL; ++u) bv[nt][u] = 0.0;
+                }
+            }
         } else {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < RPL; ++u) {
                 const int64_t row = rb + u;
                 const bool ok = row < r1;
                 const int64_t prow = a.geom.map.phys(ok ? row : r0);
@@ -181,7 +179,7 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < RPL; ++u)
 #pragma unroll
             for (int t = 0; t < kGramTPW; ++t)
                 if (tile0 + t < nmt)
