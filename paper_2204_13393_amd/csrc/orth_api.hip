@@ -58,7 +58,7 @@ struct Plan {
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, total;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -123,6 +123,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
+    // per-leaf coefficient blocks C_i, row-major ((k+s) x s within k_max x s)
+    pl.oCL = take((int64_t)pl.p * kmax * s);
     // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
     pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
     pl.total = off;
@@ -185,6 +187,7 @@ struct orth_ctx {
     double *U1R() const { return ws + pl.oU1R; }
     double *CA() const { return ws + pl.oCA; }
     double *PL() const { return ws + pl.oPL; }
+    double *CL() const { return ws + pl.oCL; }
     float *Qhi() const {
         return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
     }
@@ -437,7 +440,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.ldr = ldr;
         if ((rc = run_level(h, L, k, two))) goto fail;
 
-        // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s]
+        // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s], and
+        // row-major per leaf (C_i) for the leaf finalize
         FinalizeArgs f{};
         f.Q = Operand{h->T(), pl.ldt};
         f.Qnew = OutOperand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
@@ -450,6 +454,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.kmax = kmax;
         f.single_sweep = two ? 0 : 1;
         f.Cptr = nullptr;
+        f.Crow = h->CL();
+        f.crow_seg = (int64_t)kmax * s;
         f.status = h->status();
         const int pm = h->begin(ORTH_K_ROOT_FINALIZE);
         const hipError_t e = launch_finalize(s, f, ORTH_K_ROOT_FINALIZE, st);
@@ -470,9 +476,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
         f.single_sweep = two ? 0 : 1;
-        f.Cptr = h->T() + (int64_t)k * pl.ldt;
-        f.ldc = pl.ldt;
-        f.cseg = kmax;
+        f.Cptr = h->CL();
+        f.cseg = (int64_t)kmax * s;
         f.Uout = OutOperand{d_U, ldu};
         f.status = h->status();
         const int pm = h->begin(ORTH_K_LEAF_FINALIZE);
@@ -775,6 +780,7 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         d.PR2 = base + pl.oPR2;
         d.SL = base + pl.oSL;
         d.SR = base + pl.oSR;
+        d.CL = base + pl.oCL;
     }
     // block prefix tables of every (step, phase, width)
     const size_t nw = L.widths.size();

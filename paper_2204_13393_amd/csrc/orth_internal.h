@@ -208,11 +208,15 @@ struct FinalizeArgs {
     int64_t small_stride;
     int32_t kmax;
     int32_t single_sweep; // 1: u = u1 (BCGS-PIP variant)
-    // per-leaf coefficient block C_i ((k+s) x s): element (c, j) at
-    // Cptr[j*ldc + leaf*cseg + c]; Cptr == nullptr -> no explicit output
+    // per-leaf coefficient block C_i ((k+s) x s), row-major per leaf: element
+    // (c, j) at Cptr[leaf*cseg + c*s + j]; Cptr == nullptr -> no explicit output
     const double *Cptr;
-    int64_t ldc;
     int64_t cseg;
+    // reduction-level finalize: also store the new columns row-major per leaf
+    // segment (logical row r = leaf*(k+s) + c -> Crow[leaf*crow_seg + c*s + j]),
+    // the layout the leaf finalize reads C_i in
+    double *Crow;
+    int64_t crow_seg;
     OutOperand Uout;      // explicit output (identity RowMap, leaf level)
     const DevStatus *status;
 };
@@ -234,7 +238,7 @@ struct ApplyArgs {
 struct BatchInst {
     int64_t n, ldq, ldt;
     int32_t s, kmax, leaf_rows, p;
-    double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR;
+    double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR, *CL;
 };
 
 // phases of one orth_batch_step, in stream order

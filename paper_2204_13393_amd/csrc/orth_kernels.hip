@@ -610,7 +610,7 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
                 for (int T = 0; T < NTM; ++T) {
                     const int m = 16 * T + il;
                     if (m < S) cf[T] = ident_only ? 0.0 : recP[(int64_t)c * S + m];
-                    else if (EXPL && m < 2 * S) cf[T] = cbase[(int64_t)(m - S) * a.ldc + c];
+                    else if (EXPL && m < 2 * S) cf[T] = cbase[(int64_t)c * S + (m - S)];
                 }
             }
         };
@@ -693,6 +693,16 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
                     for (int t = 0; t < TR; ++t)
                         if (ok[t]) col[prow[t]] = y[t];
                 }
+                if (!EXPL && a.Crow) {            // C_i rows for the leaf finalize
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) {
+                            const int64_t r = lane_row(rb, il, t);
+                            const int64_t lf = r / a.geom.map.seg_len;
+                            const int64_t cc = r - lf * a.geom.map.seg_len;
+                            a.Crow[lf * a.crow_seg + cc * S + j] = y[t];
+                        }
+                }
                 if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
                     float *ch = a.Qnew_hi + (int64_t)j * a.Qnew.ld;
 #pragma unroll
@@ -709,7 +719,7 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const int l = 4 * ks + g, m = 16 * T + il;
-                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(m - S) * a.ldc + k + l] : 0.0;
+                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(k + l) * S + (m - S)] : 0.0;
                 }
 #pragma unroll
                 for (int t = 0; t < TR; ++t)
@@ -1013,6 +1023,8 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.single_sweep = a.two ? 0 : 1;
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
+            f.Crow = d.CL;
+            f.crow_seg = (int64_t)d.kmax * S;
             rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
         default:   // BP_LFIN
@@ -1023,9 +1035,8 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.single_sweep = a.two ? 0 : 1;
             f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
             f.small = d.SL;
-            f.Cptr = d.T + (int64_t)k * d.ldt;
-            f.ldc = d.ldt;
-            f.cseg = d.kmax;
+            f.Cptr = d.CL;
+            f.cseg = (int64_t)d.kmax * S;
             f.Uout = OutOperand{a.U[inst], d.n};
             rowmfma_body<S, true, rowmfma_tr<S, true>(), rowmfma_pf<S, true>()>(f, local);
             return;
