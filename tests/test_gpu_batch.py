@@ -29,6 +29,7 @@ INSTANCES = [  # n, s, k_max, leaf_rows (0: default)
     (777, 1, 6, 100),
     (6000, 16, 96, 2000),
     (4100, 32, 192, 2048),
+    (2600, 32, 192, 0),
     (10000, 2, 12, 0),
     (16384, 8, 48, 4096),
 ]

@@ -63,6 +63,10 @@ CASES = [
     (20000, 4, 32, 16384),    # one leaf of 10 chunks: its 40 Gram slots are pre-summed
 ]
 
+# the widest basis the planner accepts (k_max + s = 2048), s = 32, one leaf,
+# and two leaves with the reduction level at its widest
+WIDE_CASES = [(2100, 32, 2016, 2100), (4200, 32, 2016, 2100)]
+
 
 @pytest.mark.parametrize("n,s,kmax,leaf_rows", CASES)
 def test_open_loop_parity(torch_cuda, n, s, kmax, leaf_rows):
@@ -108,6 +112,39 @@ def test_open_loop_parity(torch_cuda, n, s, kmax, leaf_rows):
     assert metrics.e_perp(T) <= 1e-12
     # Y = Q C through the representation
     C = rng.standard_normal((gpu.k, 21))
+    Y = to_host(gpu.apply_Q(to_dev(C)))
+    assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
+    gpu.close()
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows", WIDE_CASES)
+def test_widest_basis(torch_cuda, n, s, kmax, leaf_rows):
+    """k_max + s = 2048: parity of every step against the oracle, e_perp of the
+    explicit basis, and Y = Q C through the representation."""
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("widest", n, s, kmax, leaf_rows)
+    rng = np.random.default_rng(n + s)
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows)
+    Q = np.zeros((n, 0))
+    Ugpu = []
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        H, R, U = to_host(Hd), to_host(Rd), to_host(Ud)
+        P, N, Ur = pqr_reference(Q, X)
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if step:
+            assert np.linalg.norm(H - P) / xn <= 1e-12, step
+        assert np.linalg.norm(R - N) / xn <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-12 * kap, step
+        Ugpu.append(U)
+        Q = np.hstack([Q, Ur])
+    st, info = gpu.status()
+    assert st == 0, info
+    V = np.hstack(Ugpu)
+    assert metrics.e_perp(V) <= 1e-12
+    C = rng.standard_normal((gpu.k, 5))
     Y = to_host(gpu.apply_Q(to_dev(C)))
     assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
     gpu.close()
