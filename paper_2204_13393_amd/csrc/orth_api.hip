@@ -123,8 +123,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oSL = take((int64_t)pl.p * small_stride(kmax, s));
     pl.oSR = take(small_stride(kmax, s));
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
-    // per-leaf coefficient blocks C_i, row-major ((k+s) x s within k_max x s)
-    pl.oCL = take((int64_t)pl.p * kmax * s);
+    // per-leaf coefficient records [P2 | C_i], row-major (k_max x 2s per leaf)
+    pl.oCL = take((int64_t)pl.p * kmax * 2 * s);
     // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
     pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
     pl.total = off;
@@ -257,6 +257,7 @@ namespace {
 struct LevelRun {
     Operand Q, X;
     const float *Qhi;              // mixed form, leaves: FP32 copy read by the sweep-1 Gram
+    double *pc;                    // leaves: per-leaf [P2 | C] records (P2 half written by the Cholesky)
     OutOperand U1;
     LevelGeom geom;
     double *part, *part2;
@@ -315,6 +316,8 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     c.R = L.R;
     c.ldr = L.ldr;
     c.instance = -1;
+    c.pc = L.pc;
+    c.pc_stride = (int64_t)kmax * 2 * s;
     c.status = h->status();
 
     // sum the slots of each leaf; pre-reduce when a single leaf owns many
@@ -410,6 +413,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.U1 = OutOperand{h->U1L(), pl.ldq};
         L.geom = leaf_geom(pl, kLeafChunk);
         L.Qhi = h->Qhi();
+        L.pc = h->CL();
         L.part = h->PL();
         L.part2 = h->PR2();          // pre-sums when a single leaf holds many slots
         L.part_cap = pl.slot_cap;
@@ -455,7 +459,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.single_sweep = two ? 0 : 1;
         f.Cptr = nullptr;
         f.Crow = h->CL();
-        f.crow_seg = (int64_t)kmax * s;
+        f.crow_seg = (int64_t)kmax * 2 * s;
         f.status = h->status();
         const int pm = h->begin(ORTH_K_ROOT_FINALIZE);
         const hipError_t e = launch_finalize(s, f, ORTH_K_ROOT_FINALIZE, st);
@@ -477,7 +481,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.kmax = kmax;
         f.single_sweep = two ? 0 : 1;
         f.Cptr = h->CL();
-        f.cseg = (int64_t)kmax * s;
+        f.cseg = (int64_t)kmax * 2 * s;
         f.Uout = OutOperand{d_U, ldu};
         f.status = h->status();
         const int pm = h->begin(ORTH_K_LEAF_FINALIZE);

@@ -191,6 +191,10 @@ struct CholArgs {
     int64_t ldr;
     int32_t instance;         // for the status record (-1: single handle)
     DevStatus *status;
+    // leaf level, second sweep: also store P2 row-major in the left half of
+    // the per-leaf coefficient record [c][2s] (nullptr: not needed)
+    double *pc;
+    int64_t pc_stride;        // doubles per leaf record
 };
 
 // row update: sweep 1: u1 = (x - q P1) N1^{-1} (U1 = x in, Qnew = u1 out);
@@ -208,13 +212,15 @@ struct FinalizeArgs {
     int64_t small_stride;
     int32_t kmax;
     int32_t single_sweep; // 1: u = u1 (BCGS-PIP variant)
-    // per-leaf coefficient block C_i ((k+s) x s), row-major per leaf: element
-    // (c, j) at Cptr[leaf*cseg + c*s + j]; Cptr == nullptr -> no explicit output
+    // leaf finalize: the per-leaf coefficient record, row-major [c][2s] with
+    // P2 row c in columns 0..s-1 and C_i row c in columns s..2s-1 (C_i =
+    // [P~_i; N~_i], (k+s) x s), leaf i at Cptr + i*cseg; one load per basis
+    // column fetches both.  Cptr == nullptr -> no explicit output
     const double *Cptr;
     int64_t cseg;
-    // reduction-level finalize: also store the new columns row-major per leaf
-    // segment (logical row r = leaf*(k+s) + c -> Crow[leaf*crow_seg + c*s + j]),
-    // the layout the leaf finalize reads C_i in
+    // reduction-level finalize: also store the new columns as the right half
+    // of those records (logical row r = leaf*(k+s) + c ->
+    // Crow[leaf*crow_seg + c*2s + s + j])
     double *Crow;
     int64_t crow_seg;
     OutOperand Uout;      // explicit output (identity RowMap, leaf level)

@@ -373,7 +373,10 @@ __device__ __forceinline__ void chol_body(const CholArgs &a, int bx) {
     for (int e = tid; e < ncol * S; e += kThreads) {
         double v = 0.0;
         for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
-        if (e < k * S) recP[e] = v;
+        if (e < k * S) {
+            recP[e] = v;
+            if (a.pc && a.sweep == 2) a.pc[(int64_t)leaf * a.pc_stride + (int64_t)(e / S) * 2 * S + e % S] = v;
+        }
         else gs[e - k * S] = v;
     }
     if (a.sweep == 2 && a.final_sweep == 2)
@@ -609,8 +612,12 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
 #pragma unroll
                 for (int T = 0; T < NTM; ++T) {
                     const int m = 16 * T + il;
-                    if (m < S) cf[T] = ident_only ? 0.0 : recP[(int64_t)c * S + m];
-                    else if (EXPL && m < 2 * S) cf[T] = cbase[(int64_t)c * S + (m - S)];
+                    if (EXPL) {
+                        // one load per column: [P2 | C] row c of the leaf's record
+                        if (m < 2 * S) cf[T] = (m < S && ident_only) ? 0.0 : cbase[(int64_t)c * 2 * S + m];
+                    } else if (m < S) {
+                        cf[T] = ident_only ? 0.0 : recP[(int64_t)c * S + m];
+                    }
                 }
             }
         };
@@ -700,7 +707,7 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
                             const int64_t r = lane_row(rb, il, t);
                             const int64_t lf = r / a.geom.map.seg_len;
                             const int64_t cc = r - lf * a.geom.map.seg_len;
-                            a.Crow[lf * a.crow_seg + cc * S + j] = y[t];
+                            a.Crow[lf * a.crow_seg + cc * 2 * S + S + j] = y[t];
                         }
                 }
                 if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
@@ -719,7 +726,7 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const int l = 4 * ks + g, m = 16 * T + il;
-                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(k + l) * S + (m - S)] : 0.0;
+                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(k + l) * 2 * S + m] : 0.0;
                 }
 #pragma unroll
                 for (int t = 0; t < TR; ++t)
@@ -957,6 +964,8 @@ __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int
         c.Yout = d.Y;
         c.ldy = d.ldt;
         c.yseg = d.kmax;
+        c.pc = d.CL;
+        c.pc_stride = (int64_t)d.kmax * 2 * S;
     } else {
         const LevelGeom gr = make_root_geom(d.p, d.kmax, ncol, kRootChunk);
         const int slots = gr.nchunks() * rg;
@@ -1024,7 +1033,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
             f.small = d.SR;
             f.Crow = d.CL;
-            f.crow_seg = (int64_t)d.kmax * S;
+            f.crow_seg = (int64_t)d.kmax * 2 * S;
             rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
         default:   // BP_LFIN
@@ -1036,7 +1045,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
             f.small = d.SL;
             f.Cptr = d.CL;
-            f.cseg = (int64_t)d.kmax * S;
+            f.cseg = (int64_t)d.kmax * 2 * S;
             f.Uout = OutOperand{a.U[inst], d.n};
             rowmfma_body<S, true, rowmfma_tr<S, true>(), rowmfma_pf<S, true>()>(f, local);
             return;
