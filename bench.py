@@ -16,7 +16,10 @@ higher is better): sum over the 31 calls of
 bytes (two reads of the basis and the block, writes of U_i and U, and the
 tree-factor traffic), divided by the measured time.  ``ms_per_step`` is the
 time of one whole 31-call sequence.  The roofline object refers to the
-dominant kernel class, timed live with HIP events on the handle's stream.
+dominant kernel class, timed live in the timed region with HIP events on the
+handle's stream around that class's launches only (each event pair adds a
+gap on the stream); one untimed sequence with every launch bracketed gives
+the per-class breakdown (``kernels``) and picks the class.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -60,6 +63,41 @@ def kernel_bytes(cls, n, s, p, k):
     if cls == "root_finalize":
         return 8.0 * p * (tri + 2.0 * (k + s) * s)
     return 0.0
+
+
+class TimingEvent:
+    """A HIP timing event without the system-scope fence
+    (hipEventDisableSystemFence): the default fence writes back and
+    invalidates caches when the event is recorded, which slows the work
+    around it.  Uses the HIP runtime already loaded in the process."""
+
+    _hip = None
+
+    def __init__(self):
+        import ctypes
+        if TimingEvent._hip is None:
+            TimingEvent._hip = ctypes.CDLL("libamdhip64.so.7")
+        self._c = ctypes
+        self.ev = ctypes.c_void_p()
+        if TimingEvent._hip.hipEventCreateWithFlags(ctypes.byref(self.ev), ctypes.c_uint(0x20000000)):
+            raise RuntimeError("hipEventCreateWithFlags failed")
+
+    def record(self, stream):
+        if TimingEvent._hip.hipEventRecord(self.ev, self._c.c_void_p(stream.cuda_stream)):
+            raise RuntimeError("hipEventRecord failed")
+
+    def elapsed_time(self, end):
+        """Milliseconds from this event to `end`; the stream must have been synchronised."""
+        ms = self._c.c_float()
+        if TimingEvent._hip.hipEventElapsedTime(self._c.byref(ms), self.ev, end.ev):
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def __del__(self):
+        # dropped events are destroyed at once (reference counting); at
+        # interpreter exit the runtime may already be gone, so leave them
+        if TimingEvent._hip is not None and self.ev and not sys.is_finalizing():
+            TimingEvent._hip.hipEventDestroy(self.ev)
 
 
 def source_sha():
@@ -183,7 +221,7 @@ def bench_batched(args):
             else:
                 stencils()
             if timed:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0, e1 = TimingEvent(), TimingEvent()
                 e0.record(stream)
             b.step(*ptrs)
             if timed:
@@ -237,7 +275,7 @@ def bench_batched(args):
         code, h = orth.orth_batch_create(ns, ss, ks, tuned, orth.ORTH_FP64, ws_ptr, ws_bytes, sp)
         b.h = h
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = TimingEvent(), TimingEvent()
         with torch.cuda.stream(stream):          # replay on the timed stream
             e0.record(stream)
             g.replay()
@@ -269,7 +307,7 @@ def bench_batched(args):
             o = Orthogonalizer(ns[i], s, ks[i], tuned[i], stream=stream)
             Wi, Ui = W[i], U[i]
             Wi.copy_(R0[i])
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1 = TimingEvent(), TimingEvent()
             tot = 0.0
             for j in range(steps + 1):
                 if j:
@@ -343,11 +381,11 @@ def bench_lap3d(args):
     nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_MIXED_SPLIT32)
     o.close()
 
-    def run(timed, precision=orth.ORTH_FP64):
+    def run(profiled, precision=orth.ORTH_FP64):
         code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sp)
         if code:
             raise orth.OrthError("orth_create", code)
-        if timed:
+        if profiled:
             orth.orth_profile_enable(h, 1)
         ms = 0.0
         for j in range(steps + 1):
@@ -357,7 +395,7 @@ def bench_lap3d(args):
             elif orth.orth_laplacian_apply(V[k - s:k].data_ptr(), n, W.data_ptr(), n, s, nx, ny, nz, 0.0, sp):
                 raise RuntimeError("stencil failed")
             col = H[j * s:(j + 1) * s]
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1 = TimingEvent(), TimingEvent()
             e0.record(stream)
             code = orth.orth_step(h, W.data_ptr(), n, col.data_ptr(), kmax, col[:, k:].data_ptr(), kmax,
                                   V[k:k + s].data_ptr(), n)
@@ -367,24 +405,26 @@ def bench_lap3d(args):
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
         code, st, info = orth.orth_status(h)
-        prof = orth.orth_profile_read(h)[1] if timed else None
+        prof = orth.orth_profile_read(h)[1] if profiled else None
         orth.orth_destroy(h)
         if st:
             raise RuntimeError(f"breakdown {info}")
         return ms, prof
 
     def timed(precision):
+        """Warmup, args.steps unprofiled runs (the time), then one run with
+        every launch bracketed by events (the per-class breakdown)."""
         for _ in range(args.warmup):
             run(False, precision)
         times = []
-        pr = None
         for _ in range(args.steps):
-            ms, pr = run(True, precision)
+            ms, _ = run(False, precision)
             times.append(ms)
         G = torch.mm(V, V.t())
         G -= torch.eye(kmax, dtype=torch.float64, device=dev)
         ep = float(torch.linalg.matrix_norm(G, "fro"))
         del G
+        _, pr = run(True, precision)
         return min(times), pr, ep
 
     best, prof, e_perp = timed(orth.ORTH_FP64)
@@ -482,7 +522,7 @@ def bench_stewart(args):
                 for j in range(m // s):
                     k = j * s
                     col = Rt[k:k + s]
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0, e1 = TimingEvent(), TimingEvent()
                     e0.record(stream)
                     code = orth.orth_step(h, Wt[k:k + s].data_ptr(), n, col.data_ptr(), m,
                                           col[:, k:].data_ptr(), m, Qt[k:k + s].data_ptr(), n)
@@ -623,24 +663,41 @@ def main():
     torch.cuda.synchronize()
     print("[bench] inputs ready", file=sys.stderr, flush=True)
 
-    def timed_runs(precision):
-        """Warmup, then args.steps timed sequences over the resident inputs;
-        returns (ms per sequence, per-class profile, e_perp of the explicit basis)."""
+    p = max(1, n // leaf)
+    widths = [j * s for j in range(steps + 1)]
+
+    def profiled_sequence(precision):
+        """One untimed sequence with every launch bracketed by events: the
+        per-class breakdown, and the dominant class for the timed region."""
+        h = make_handle(precision)
+        orth.orth_profile_enable(h, 1)
+        run_sequence(Xs, h)
+        code, pr = orth.orth_profile_read(h)
+        orth.orth_destroy(h)
+        if code:
+            raise orth.OrthError("orth_profile_read", code)
+        with_bytes = [c for c, (ms, cnt) in pr.items() if cnt and kernel_bytes(c, n, s, p, 8) > 0]
+        return pr, max(with_bytes, key=lambda c: pr[c][0])
+
+    def timed_runs(precision, dom):
+        """Warmup, then args.steps timed sequences over the resident inputs,
+        events around the launches of class `dom` only; returns (ms per
+        sequence, (ms, launches) of `dom`, e_perp of the explicit basis)."""
         for _ in range(args.warmup):
             h = make_handle(precision)
             run_sequence(Xs, h)
             orth.orth_destroy(h)
         torch.cuda.synchronize()
         handles = []
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0 = TimingEvent()
+        ev1 = TimingEvent()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0.record(stream)
-        prof = {}
         for _ in range(args.steps):
             h = make_handle(precision)
-            if not args.no_profile:
+            if dom is not None:
+                orth.orth_profile_select(h, 1 << orth.KERNEL_CLASSES.index(dom))
                 orth.orth_profile_enable(h, 1)
             run_sequence(Xs, h)
             handles.append(h)
@@ -649,33 +706,32 @@ def main():
         t1 = time.perf_counter()
         wall_ms = (t1 - t0) * 1e3 / args.steps
         gpu_ms = ev0.elapsed_time(ev1) / args.steps
+        dom_ms, dom_n = 0.0, 0
         for h in handles:
             code, st, info = orth.orth_status(h)
             if code or st:
                 raise RuntimeError(f"orth_step breakdown: {info}")
-            if not args.no_profile:
+            if dom is not None:
                 code, pr = orth.orth_profile_read(h)
-                for name, (ms, cnt) in pr.items():
-                    a = prof.setdefault(name, [0.0, 0])
-                    a[0] += ms
-                    a[1] += cnt
+                dom_ms += pr[dom][0]
+                dom_n += pr[dom][1]
             orth.orth_destroy(h)
         # accuracy gate: e_perp of the explicit basis (torch GEMM, independent of the kernels)
         G = torch.mm(V, V.t())
         G -= torch.eye(kmax, dtype=torch.float64, device=dev)
         ep = float(torch.linalg.matrix_norm(G, "fro"))
         del G
-        return max(wall_ms, gpu_ms), prof, ep
+        return max(wall_ms, gpu_ms), (dom_ms, dom_n), ep
 
-    ms_per_step, prof, e_perp = timed_runs(orth.ORTH_FP64)
+    prof, dom = (None, None) if args.no_profile else profiled_sequence(orth.ORTH_FP64)
+    prof_mixed, dom_mixed = (None, None) if args.no_profile else profiled_sequence(orth.ORTH_MIXED_SPLIT32)
+    ms_per_step, dom_timed, e_perp = timed_runs(orth.ORTH_FP64, dom)
     print(f"[bench] timed {args.steps} sequences: {ms_per_step:.2f} ms each", file=sys.stderr, flush=True)
-    # the mixed form (leaf bases stored FP32 hi + lo, sweep-1 Gram on hi) on the same inputs
-    ms_mixed, prof_mixed, e_perp_mixed = timed_runs(orth.ORTH_MIXED_SPLIT32)
+    # the mixed form (FP64 leaf bases plus an FP32 copy read by the sweep-1 Gram) on the same inputs
+    ms_mixed, dom_mixed_timed, e_perp_mixed = timed_runs(orth.ORTH_MIXED_SPLIT32, dom_mixed)
     print(f"[bench] mixed form: {ms_mixed:.2f} ms per sequence, e_perp {e_perp_mixed:.2e}",
           file=sys.stderr, flush=True)
 
-    p = max(1, n // leaf)
-    widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
     value = total_bytes / (ms_per_step / 1e3) / 1e9
 
@@ -684,7 +740,7 @@ def main():
         for name, (ms, cnt) in pr.items():
             if cnt == 0:
                 continue
-            byts = sum(kernel_bytes(name, n, s, p, k) for k in widths) * args.steps
+            byts = sum(kernel_bytes(name, n, s, p, k) for k in widths)
             out[name] = {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3,
                          "gbs": (byts / (ms / 1e3) / 1e9) if byts else None}
         return out
@@ -693,15 +749,15 @@ def main():
     kernels = {}
     if prof:
         kernels = per_class(prof)
-        dom = max((k for k in kernels if kernel_bytes(k, n, s, p, 8) > 0),
-                  key=lambda k: kernels[k]["ms_total"])
-        d = kernels[dom]
+        dom_ms, dom_n = dom_timed
+        avg_us = dom_ms / dom_n * 1e3
         byts_per_launch = sum(kernel_bytes(dom, n, s, p, k) for k in widths) / len(widths)
-        achieved = byts_per_launch / (d["avg_us"] / 1e6) / 1e9
+        achieved = byts_per_launch / (avg_us / 1e6) / 1e9
         traffic = load_traffic(dom)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                    "avg_launch_us": d["avg_us"], "alg_bytes_per_launch": byts_per_launch}
+                    "avg_launch_us": avg_us, "launches_timed": dom_n,
+                    "alg_bytes_per_launch": byts_per_launch}
 
     if args.copy_probe_gib > 0:
         cnt = int(args.copy_probe_gib * (1 << 30)) // 8
@@ -739,7 +795,7 @@ def main():
         "e_perp": e_perp,
         "e_perp_gate_1e-10": e_perp <= 1e-10,
         "mixed": {
-            "precision": "mixed_split32: leaf bases FP32 hi + lo, sweep-1 Gram on hi, FP64 arithmetic",
+            "precision": "mixed_split32: leaf bases FP32 copy for the sweep-1 Gram, FP64 arithmetic",
             "ms_per_step": ms_mixed,
             "value_effective": total_bytes / (ms_mixed / 1e3) / 1e9,
             "unit": "GB/s (FP64 algorithmic bytes)",

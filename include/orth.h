@@ -222,6 +222,15 @@ enum orth_kernel_class {
 int orth_profile_enable(orth_t *h, int32_t on);
 
 /*
+ * orth_profile_select -- restrict the bracketing to the classes whose bit
+ * (1u << class) is set in class_mask; the default is every class.  Each
+ * event pair adds a short gap on the stream, so a timing run that needs one
+ * class's launch durations brackets only that class.
+ * Errors: ARG.
+ */
+int orth_profile_select(orth_t *h, uint32_t class_mask);
+
+/*
  * orth_profile_read -- synchronise the stream, then add the elapsed time of
  * every recorded event pair to per-class totals and clear the record.
  *   total_ms   array of ORTH_K_COUNT doubles: milliseconds per class

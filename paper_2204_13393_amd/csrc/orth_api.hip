@@ -148,6 +148,7 @@ struct orth_ctx {
     double *ws = nullptr;
     // profiler: event pairs recorded around launches
     bool prof_on = false;
+    uint32_t prof_mask = ~0u;
     struct Mark { int cls; hipEvent_t a, b; };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> spare;
@@ -160,13 +161,16 @@ struct orth_ctx {
             spare.pop_back();
             return e;
         }
+        // timing-only events: no system-scope fence (its cache writeback
+        // and invalidation would slow the bracketed work); the read
+        // synchronises the stream before taking the times
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     // bracket one launch; returns the mark index or -1
     int begin(int cls) {
-        if (!prof_on) return -1;
+        if (!prof_on || !((prof_mask >> cls) & 1u)) return -1;
         Mark m{cls, get_event(), get_event()};
         if (!m.a || !m.b || hipEventRecord(m.a, stream) != hipSuccess) return -1;
         marks.push_back(m);
@@ -587,6 +591,12 @@ int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64
 int orth_profile_enable(orth_t *h, int32_t on) {
     if (!h) return ORTH_ERR_ARG;
     h->prof_on = on != 0;
+    return ORTH_OK;
+}
+
+int orth_profile_select(orth_t *h, uint32_t class_mask) {
+    if (!h) return ORTH_ERR_ARG;
+    h->prof_mask = class_mask;
     return ORTH_OK;
 }
 
@@ -1046,7 +1056,8 @@ int orth_tune_leaf_rows(int64_t n, int32_t s, int32_t k_max, int32_t steps, int3
     hipStream_t st = static_cast<hipStream_t>(stream);
     double *ws = static_cast<double *>(d_workspace);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         (void)hipGetLastError();
         return ORTH_ERR_HIP;

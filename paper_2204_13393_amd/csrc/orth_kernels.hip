@@ -20,7 +20,10 @@
 // Layout: every operand is column-major; rows are streamed with coalesced
 // column reads straight into the matrix-core operands (the Gram products
 // take rows as the contraction index, the row updates take them as the
-// output index of a transposed product), so no basis tile passes through LDS.
+// output index of a transposed product).  For blocks of 16 and more
+// columns the leaf-level row update (k_rowlds) stages its basis and
+// coefficient operands in LDS through direct loads instead, so that enough
+// bytes stay in flight while the matrix cores, busier at those widths, work.
 // No floating-point atomics: every sum has a fixed order.
 
 #include "orth_internal.h"
@@ -553,15 +556,140 @@ __host__ __device__ constexpr int rowmfma_tr() { return S <= 8 ? 8 : ((S >= 32 &
 template <int S, bool EXPL>
 __host__ __device__ constexpr int rowmfma_pf() { return 1; }
 
+// The end of a row block, once acc holds q [P | C_top] for the lane's TR
+// rows: u = (x - q P) N^{-1} on the matrix cores, stored as new basis
+// columns (and as C_i rows, or as the FP32 copy), then with EXPL the
+// explicit block q C_top + u C_bot.
+template <int S, bool EXPL, int TR>
+__device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, int64_t rb, bool fast,
+                                                 const bool (&ok)[TR], const int64_t (&prow)[TR],
+                                                 dbl4 (&acc)[TR][EXPL ? (2 * S + 15) / 16 : (S + 15) / 16],
+                                                 const double *recNi, const double *cbase, bool ident_only) {
+    constexpr int M = EXPL ? 2 * S : S;
+    constexpr int NTM = (M + 15) / 16;
+    constexpr int NTS = (S + 15) / 16;
+    constexpr int NV = S < 4 ? 1 : 4;
+    constexpr int KS = (S + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int il = lane & 15, g = lane >> 4;
+    const int64_t rl = rb + 2 * il;
+    // x - q P for the block's columns j = 16 T + 4 v + g < S, the lane's
+    // TR rows of column j read (and later written) as 16-byte pairs
+    double tv[TR][NTS][4];
+#pragma unroll
+    for (int T = 0; T < NTS; ++T)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = 16 * T + 4 * v + g;
+            double x[TR];
+#pragma unroll
+            for (int t = 0; t < TR; ++t) x[t] = 0.0;
+            if (v < NV && j < S) {
+                const double *col = a.U1.ptr + (int64_t)j * a.U1.ld;
+                if (fast) {
+                    load_rows<TR>(col + rl, x);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TR; ++t) x[t] = ok[t] ? col[prow[t]] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) tv[t][T][v] = (v < NV && j < S) ? x[t] - acc[t][T][v] : 0.0;
+        }
+    // u = (x - q P) N^{-1}: products over l = 4 ks + g (N^{-1} upper triangular)
+    dbl4 uv[TR][NTS];
+#pragma unroll
+    for (int T = 0; T < NTS; ++T) {
+        double an[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int l = 4 * ks + g, jo = 16 * T + il;
+            an[ks] = 0.0;
+            if (l < S && jo < S && l <= jo) an[ks] = ident_only ? (l == jo ? 1.0 : 0.0) : recNi[l * S + jo];
+        }
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            uv[t][T] = zero4();
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (4 * ks <= 16 * T + 15) uv[t][T] = mfma16(an[ks], tv[t][ks / 4][ks % 4], uv[t][T]);
+        }
+    }
+#pragma unroll
+    for (int T = 0; T < NTS; ++T)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int j = 16 * T + 4 * v + g;
+            if (j >= S) continue;
+            double y[TR];
+#pragma unroll
+            for (int t = 0; t < TR; ++t) y[t] = uv[t][T][v];
+            double *col = a.Qnew.ptr + (int64_t)j * a.Qnew.ld;
+            if (fast) {
+                store_rows<TR>(col + rl, y);
+            } else {
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+                    if (ok[t]) col[prow[t]] = y[t];
+            }
+            if (!EXPL && a.Crow) {            // C_i rows for the leaf finalize
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+                    if (ok[t]) {
+                        const int64_t r = lane_row(rb, il, t);
+                        const int64_t lf = r / a.geom.map.seg_len;
+                        const int64_t cc = r - lf * a.geom.map.seg_len;
+                        a.Crow[lf * a.crow_seg + cc * 2 * S + S + j] = y[t];
+                    }
+            }
+            if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
+                float *ch = a.Qnew_hi + (int64_t)j * a.Qnew.ld;
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+                    if (ok[t]) ch[prow[t]] = (float)y[t];
+            }
+        }
+    if (EXPL) {
+        // U| = q C_top + u C_bot, C_bot = C rows k..k+S-1; rows are logical
+#pragma unroll
+        for (int T = 0; T < NTM; ++T) {
+            if (16 * T + 15 < S) continue;        // tile without C columns
+            double ac[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int l = 4 * ks + g, m = 16 * T + il;
+                ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(k + l) * 2 * S + m] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) acc[t][T] = mfma16(ac[ks], uv[t][ks / 4][ks % 4], acc[t][T]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = 16 * T + 4 * v + g;
+                if (m < S || m >= 2 * S) continue;
+                double y[TR];
+#pragma unroll
+                for (int t = 0; t < TR; ++t) y[t] = acc[t][T][v];
+                double *col = a.Uout.ptr + (int64_t)(m - S) * a.Uout.ld;
+                if (fast) {
+                    store_rows<TR>(col + rl, y);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) col[lane_row(rb, il, t)] = y[t];
+                }
+            }
+        }
+    }
+}
+
 template <int S, bool EXPL, int TR, int PF>
 __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
     if (failed(a.status)) return;
     constexpr int RB = 16 * TR;              // rows per wave block
     constexpr int M = EXPL ? 2 * S : S;      // coefficient columns [P | C_top]
     constexpr int NTM = (M + 15) / 16;       // 16-column output tiles
-    constexpr int NTS = (S + 15) / 16;       // tiles of the new block
-    constexpr int NV = S < 4 ? 1 : 4;        // accumulator registers holding block columns
-    constexpr int KS = (S + 3) / 4;          // 4-deep steps over the block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
     const int k = a.k;
@@ -641,116 +769,265 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
             }
         }
 
-        // x - q P for the block's columns j = 16 T + 4 v + g < S, the lane's
-        // TR rows of column j read (and later written) as 16-byte pairs
-        double tv[TR][NTS][4];
-#pragma unroll
-        for (int T = 0; T < NTS; ++T)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int j = 16 * T + 4 * v + g;
-                double x[TR];
-#pragma unroll
-                for (int t = 0; t < TR; ++t) x[t] = 0.0;
-                if (v < NV && j < S) {
-                    const double *col = a.U1.ptr + (int64_t)j * a.U1.ld;
-                    if (fast) {
-                        load_rows<TR>(col + rl, x);
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < TR; ++t) x[t] = ok[t] ? col[prow[t]] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < TR; ++t) tv[t][T][v] = (v < NV && j < S) ? x[t] - acc[t][T][v] : 0.0;
-            }
-        // u = (x - q P) N^{-1}: products over l = 4 ks + g (N^{-1} upper triangular)
-        dbl4 uv[TR][NTS];
-#pragma unroll
-        for (int T = 0; T < NTS; ++T) {
-            double an[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int l = 4 * ks + g, jo = 16 * T + il;
-                an[ks] = 0.0;
-                if (l < S && jo < S && l <= jo) an[ks] = ident_only ? (l == jo ? 1.0 : 0.0) : recNi[l * S + jo];
-            }
-#pragma unroll
-            for (int t = 0; t < TR; ++t) {
-                uv[t][T] = zero4();
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    if (4 * ks <= 16 * T + 15) uv[t][T] = mfma16(an[ks], tv[t][ks / 4][ks % 4], uv[t][T]);
-            }
-        }
-#pragma unroll
-        for (int T = 0; T < NTS; ++T)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int j = 16 * T + 4 * v + g;
-                if (j >= S) continue;
-                double y[TR];
-#pragma unroll
-                for (int t = 0; t < TR; ++t) y[t] = uv[t][T][v];
-                double *col = a.Qnew.ptr + (int64_t)j * a.Qnew.ld;
-                if (fast) {
-                    store_rows<TR>(col + rl, y);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < TR; ++t)
-                        if (ok[t]) col[prow[t]] = y[t];
-                }
-                if (!EXPL && a.Crow) {            // C_i rows for the leaf finalize
-#pragma unroll
-                    for (int t = 0; t < TR; ++t)
-                        if (ok[t]) {
-                            const int64_t r = lane_row(rb, il, t);
-                            const int64_t lf = r / a.geom.map.seg_len;
-                            const int64_t cc = r - lf * a.geom.map.seg_len;
-                            a.Crow[lf * a.crow_seg + cc * 2 * S + S + j] = y[t];
-                        }
-                }
-                if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
-                    float *ch = a.Qnew_hi + (int64_t)j * a.Qnew.ld;
-#pragma unroll
-                    for (int t = 0; t < TR; ++t)
-                        if (ok[t]) ch[prow[t]] = (float)y[t];
-                }
-            }
-        if (EXPL) {
-            // U| = q C_top + u C_bot, C_bot = C rows k..k+S-1; rows are logical
-#pragma unroll
-            for (int T = 0; T < NTM; ++T) {
-                if (16 * T + 15 < S) continue;        // tile without C columns
-                double ac[KS];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const int l = 4 * ks + g, m = 16 * T + il;
-                    ac[ks] = (l < S && m >= S && m < 2 * S) ? cbase[(int64_t)(k + l) * 2 * S + m] : 0.0;
-                }
-#pragma unroll
-                for (int t = 0; t < TR; ++t)
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) acc[t][T] = mfma16(ac[ks], uv[t][ks / 4][ks % 4], acc[t][T]);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int m = 16 * T + 4 * v + g;
-                    if (m < S || m >= 2 * S) continue;
-                    double y[TR];
-#pragma unroll
-                    for (int t = 0; t < TR; ++t) y[t] = acc[t][T][v];
-                    double *col = a.Uout.ptr + (int64_t)(m - S) * a.Uout.ld;
-                    if (fast) {
-                        store_rows<TR>(col + rl, y);
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < TR; ++t)
-                            if (ok[t]) col[lane_row(rb, il, t)] = y[t];
-                    }
-                }
-            }
-        }
+        rowmfma_epilogue<S, EXPL, TR>(a, k, rb, fast, ok, prow, acc, recNi, cbase, ident_only);
     }
+}
+
+// ---------------------------------------------------------------- row update, LDS-staged
+// The leaf-level row update with its basis and coefficient operands staged
+// in LDS by direct loads (global_load_lds_dwordx4): a load in flight holds
+// no register, so a workgroup keeps NST - 1 stages of BK basis columns in
+// flight while the matrix cores work on the oldest one.  The workgroup
+// walks its chunk in tiles of BM = 64 TR rows (16 TR per wave, the lanes'
+// rows as in rowmfma_body); the stream of (tile, stage) pairs runs on
+// without a break, so the first stages of the next tile load during the
+// epilogue of this one.  The products, their order and the epilogue are
+// those of rowmfma_body, so both kernels give the same bits.
+//
+// Requirements (checked by the launcher): identity row map, even chunk
+// starts (16-byte row pairs), BK a multiple of 4.
+// rows per lane, basis columns per stage and stages of the LDS ring (the
+// fastest measured; the wide finalize keeps two rows per lane, its
+// accumulators and epilogue already take the register file of two waves)
+template <int S, bool EXPL>
+__host__ __device__ constexpr int rowlds_tr() { return (S >= 32 && EXPL) ? 2 : 4; }
+template <int S, bool EXPL>
+__host__ __device__ constexpr int rowlds_bk() { return (S >= 32 && EXPL) ? 16 : 8; }
+template <int S, bool EXPL>
+__host__ __device__ constexpr int rowlds_nst() { return (S >= 32 && EXPL) ? 2 : 3; }
+
+template <int S, bool EXPL, int TR, int BK, int NST>
+struct RowLds {
+    static constexpr int M = EXPL ? 2 * S : S;          // coefficient columns
+    static constexpr int NTM = (M + 15) / 16;
+    static constexpr int RW = 16 * TR;                   // rows per wave
+    static constexpr int BM = kWaves * RW;               // rows per tile
+    static constexpr int QN = BK * BM;                   // basis doubles per stage
+    static constexpr int CN = BK * M;                    // coefficient doubles per stage
+    static constexpr int LQ = QN / 128 / kWaves;         // basis loads per wave per stage
+    static constexpr int CL = (CN / 2 + 64 * kWaves - 1) / (64 * kWaves);   // coefficient loads per wave
+    // coefficient area: every lane of every wave loads (the wait counts
+    // assume equal loads per wave), lanes past CN into the spare tail; reads
+    // past column M of the last row stay inside it as well
+    static constexpr int CP = (CL * 128 * kWaves > CN + 16) ? CL * 128 * kWaves : CN + 16;
+    static constexpr int L = LQ + CL;                    // direct loads per wave per stage
+    static constexpr size_t lds_bytes() { return (size_t)NST * (QN + CP) * 8; }
+    static_assert(QN % (128 * kWaves) == 0, "basis stage must split evenly over the waves");
+    static_assert(BK % 4 == 0 && TR % 2 == 0, "4-column steps, row pairs");
+    static_assert((NST - 1) * L < 64, "wait counts fit the counter");
+};
+
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wait until at most n vector-memory operations of this wave are
+// outstanding (n a multiple of the loads per stage, below 64).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int L, int NST>
+__device__ __forceinline__ void wait_stage(int ahead) {
+    // ahead: stages issued after the one needed (0 .. NST - 2)
+    if constexpr (NST >= 4) { if (ahead >= 2) { wait_vm<2 * L>(); return; } }
+    if constexpr (NST >= 3) { if (ahead >= 1) { wait_vm<L>(); return; } }
+    wait_vm<0>();
+}
+
+// LDS operands of one 4-column step: TR basis rows (TR / 2 16-byte reads at
+// q + 256 u bytes) and NTM coefficients (at c + 128 T bytes), with the wait
+// for them inside the same statement.
+template <int TR, int NTM>
+__device__ __forceinline__ void lds_step(uint32_t q, uint32_t c, double (&qv)[TR], double (&cv)[NTM]);
+
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+template <>
+__device__ __forceinline__ void lds_step<2, 4>(uint32_t q, uint32_t c, double (&qv)[2], double (&cv)[4]) {
+    dbl2v a;
+    asm volatile("ds_read_b128 %0, %5\n\t"
+                 "ds_read_b64 %1, %6\n\t"
+                 "ds_read_b64 %2, %6 offset:128\n\t"
+                 "ds_read_b64 %3, %6 offset:256\n\t"
+                 "ds_read_b64 %4, %6 offset:384\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(cv[0]), "=&v"(cv[1]), "=&v"(cv[2]), "=&v"(cv[3])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y;
+}
+
+template <>
+__device__ __forceinline__ void lds_step<4, 2>(uint32_t q, uint32_t c, double (&qv)[4], double (&cv)[2]) {
+    dbl2v a, b;
+    asm volatile("ds_read_b128 %0, %4\n\t"
+                 "ds_read_b128 %1, %4 offset:256\n\t"
+                 "ds_read_b64 %2, %5\n\t"
+                 "ds_read_b64 %3, %5 offset:128\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(b), "=&v"(cv[0]), "=&v"(cv[1])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y; qv[2] = b.x; qv[3] = b.y;
+}
+
+template <>
+__device__ __forceinline__ void lds_step<4, 1>(uint32_t q, uint32_t c, double (&qv)[4], double (&cv)[1]) {
+    dbl2v a, b;
+    asm volatile("ds_read_b128 %0, %3\n\t"
+                 "ds_read_b128 %1, %3 offset:256\n\t"
+                 "ds_read_b64 %2, %4\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(b), "=&v"(cv[0])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y; qv[2] = b.x; qv[3] = b.y;
+}
+
+template <>
+__device__ __forceinline__ void lds_step<8, 1>(uint32_t q, uint32_t c, double (&qv)[8], double (&cv)[1]) {
+    dbl2v a, b, d, e;
+    asm volatile("ds_read_b128 %0, %5\n\t"
+                 "ds_read_b128 %1, %5 offset:256\n\t"
+                 "ds_read_b128 %2, %5 offset:512\n\t"
+                 "ds_read_b128 %3, %5 offset:768\n\t"
+                 "ds_read_b64 %4, %6\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(b), "=&v"(d), "=&v"(e), "=&v"(cv[0])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y; qv[2] = b.x; qv[3] = b.y;
+    qv[4] = d.x; qv[5] = d.y; qv[6] = e.x; qv[7] = e.y;
+}
+
+template <>
+__device__ __forceinline__ void lds_step<2, 1>(uint32_t q, uint32_t c, double (&qv)[2], double (&cv)[1]) {
+    dbl2v a;
+    asm volatile("ds_read_b128 %0, %2\n\t"
+                 "ds_read_b64 %1, %3\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(cv[0])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y;
+}
+
+template <>
+__device__ __forceinline__ void lds_step<2, 2>(uint32_t q, uint32_t c, double (&qv)[2], double (&cv)[2]) {
+    dbl2v a;
+    asm volatile("ds_read_b128 %0, %3\n\t"
+                 "ds_read_b64 %1, %4\n\t"
+                 "ds_read_b64 %2, %4 offset:128\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(cv[0]), "=&v"(cv[1])
+                 : "v"(q), "v"(c) : "memory");
+    qv[0] = a.x; qv[1] = a.y;
+}
+
+template <int S, bool EXPL, int TR, int BK, int NST>
+__device__ __forceinline__ void rowlds_body(const FinalizeArgs &a, int bx, double *lds) {
+    using C = RowLds<S, EXPL, TR, BK, NST>;
+    constexpr int M = C::M, NTM = C::NTM, RW = C::RW, BM = C::BM;
+    if (failed(a.status)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int il = lane & 15, g = lane >> 4;
+    const int k = a.k;
+    int leaf;
+    int64_t r0, r1;
+    a.geom.chunk(bx, leaf, r0, r1);
+    const double *rec = a.small + (int64_t)leaf * a.small_stride;
+    const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
+    const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
+    const bool ident_only = a.single_sweep != 0;
+    const double *cbase = EXPL ? a.Cptr + (int64_t)leaf * a.cseg : nullptr;
+    const double *coef = EXPL ? cbase : recP;           // rows c of [P2 | C] or of P
+
+    const int nk = (k + BK - 1) / BK;                    // stages per tile
+    const int ntile = (int)((r1 - r0 + BM - 1) / BM);
+    const int nz = nk * ntile;                           // (tile, stage) pairs
+
+    // direct loads of stage z into slot z % NST: basis columns c0 .. c0 + BK - 1
+    // of the tile's rows (one 1 KB load = 128 rows of one column), then the
+    // coefficient rows c0 .. c0 + BK - 1 (contiguous, M doubles each)
+    auto issue = [&](int z) {
+        const int tile = z / nk, kb = z - tile * nk;
+        const int64_t R0 = r0 + (int64_t)tile * BM;
+        const int c0 = kb * BK;
+        double *qs = lds + (size_t)(z % NST) * (C::QN + C::CP);
+        double *cs = qs + C::QN;
+#pragma unroll
+        for (int j = 0; j < C::LQ; ++j) {
+            const int gi = wave * C::LQ + j;             // 1 KB piece of the stage
+            const int cc = gi / (BM / 128), part = gi % (BM / 128);
+            int c = c0 + cc;
+            if (c >= k) c = c0;                          // past k: a valid column, never used
+            int64_t row = R0 + part * 128 + 2 * lane;
+            if (row >= r1) row = r0;                     // past the chunk: a valid pair, never stored
+            const double *src = a.Q.ptr + (int64_t)c * a.Q.ld + row;
+            __builtin_amdgcn_global_load_lds((global_void *)src, (lds_void *)(qs + cc * BM + part * 128), 16, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < C::CL; ++j) {
+            const int e = ((wave * C::CL + j) * 64 + lane) * 2;   // first double of this lane
+            const bool use = e < C::CN && c0 + e / M < k;        // else a valid row, never read
+            const double *src = coef + (int64_t)c0 * M + (use ? e : 0);
+            __builtin_amdgcn_global_load_lds((global_void *)src, (lds_void *)(cs + (wave * C::CL + j) * 128), 16, 0, 0);
+        }
+    };
+
+    for (int z = 0; z < NST - 1 && z < nz; ++z) issue(z);
+
+    for (int tile = 0; tile < ntile; ++tile) {
+        const int64_t R0 = r0 + (int64_t)tile * BM;
+        const int64_t rb = R0 + (int64_t)wave * RW;
+        int64_t prow[TR];
+        bool ok[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int64_t r = lane_row(rb, il, t);
+            ok[t] = r < r1;
+            prow[t] = ok[t] ? r : r0;
+        }
+        const bool fast = rb + RW <= r1;
+        dbl4 acc[TR][NTM];
+#pragma unroll
+        for (int t = 0; t < TR; ++t)
+#pragma unroll
+            for (int T = 0; T < NTM; ++T) acc[t][T] = zero4();
+
+        for (int kb = 0; kb < nk; ++kb) {
+            const int z = tile * nk + kb;
+            const int ahead = min(NST - 2, nz - 1 - z);
+            wait_stage<C::L, NST>(ahead);
+            __builtin_amdgcn_s_barrier();                // stage z everywhere; slot of z - 1 free
+            if (z + NST - 1 < nz) issue(z + NST - 1);
+            const double *qs = lds + (size_t)(z % NST) * (C::QN + C::CP);
+            const double *cs = qs + C::QN;
+            const uint32_t qa = (uint32_t)(uintptr_t)(lds_void *)(qs + g * BM + wave * RW + 2 * il);
+            const uint32_t ca = (uint32_t)(uintptr_t)(lds_void *)(cs + g * M + il);
+            const int csteps = min(BK, k - kb * BK) / 4;
+#pragma unroll
+            for (int st = 0; st < BK / 4; ++st) {
+                if (st < csteps) {
+                    double qv[TR], cv[NTM];
+                    lds_step<TR, NTM>(qa + st * 4 * BM * 8, ca + st * 4 * M * 8, qv, cv);
+#pragma unroll
+                    for (int T = 0; T < NTM; ++T) {
+                        const int m = 16 * T + il;
+                        if (m >= M || (ident_only && m < S)) cv[T] = 0.0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+#pragma unroll
+                        for (int T = 0; T < NTM; ++T) acc[t][T] = mfma16(cv[T], qv[t], acc[t][T]);
+                }
+            }
+        }
+        rowmfma_epilogue<S, EXPL, TR>(a, k, rb, fast, ok, prow, acc, recNi, cbase, ident_only);
+    }
+}
+
+template <int S, bool EXPL, int CLS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rowlds(FinalizeArgs a) {
+    extern __shared__ double lds_dyn[];
+    rowlds_body<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>(a, blockIdx.x, lds_dyn);
 }
 
 template <int S, bool EXPL, int CLS>
@@ -1164,9 +1441,37 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// the LDS-staged kernel takes leaf-level launches of blocks of 16 and more
+// columns (narrower blocks run at the streaming rate without it) whose row
+// pairs and coefficient rows are 16-byte aligned
+static bool rowlds_eligible(const FinalizeArgs &a, int s) {
+    const auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (s < 16 || a.geom.map.seg_len != 0) return false;
+    if ((a.geom.leaf_rows & 1) || (a.geom.chunk_rows & 1) || (a.Q.ld & 1) || !al16(a.Q.ptr)) return false;
+    if (!al16(a.small) || (a.small_stride & 1) || ((int64_t)a.kmax * s & 1)) return false;
+    if (a.Cptr && (!al16(a.Cptr) || (a.cseg & 1))) return false;
+    return true;
+}
+
+template <int S, bool EXPL, int CLS>
+static hipError_t launch_rowlds(const FinalizeArgs &a, hipStream_t st) {
+    using C = RowLds<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rowlds<S, EXPL, CLS>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes());
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_rowlds<S, EXPL, CLS>), dim3(a.geom.nchunks()), dim3(kThreads), C::lds_bytes(), st, a);
+    return hipGetLastError();
+}
+
 template <int S>
 static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
     const dim3 grid(a.geom.nchunks());
+    if constexpr (S >= 16) {
+        if (rowlds_eligible(a, S)) {
+            if (a.Cptr != nullptr) return launch_rowlds<S, true, 7>(a, st);
+            return launch_rowlds<S, false, 2>(a, st);   // the leaf correction is the only leaf-level one
+        }
+    }
     if (a.Cptr != nullptr) {
         hipLaunchKernelGGL((k_rowmfma<S, true, 7>), grid, dim3(kThreads), 0, st, a);
     } else {

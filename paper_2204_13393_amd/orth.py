@@ -45,6 +45,7 @@ SIGNATURES = [
     ("orth_leaf_count", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_export_local", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64]),
     ("orth_profile_enable", ctypes.c_int, [_vp, _i32]),
+    ("orth_profile_select", ctypes.c_int, [_vp, ctypes.c_uint32]),
     ("orth_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     ("orth_profile_reset", ctypes.c_int, [_vp]),
     ("orth_destroy", ctypes.c_int, [_vp]),
@@ -151,6 +152,10 @@ KERNEL_CLASSES = ["leaf_gram", "leaf_chol", "leaf_correct", "root_gram", "root_c
 
 def orth_profile_enable(h, on):
     return load().orth_profile_enable(h, int(on))
+
+
+def orth_profile_select(h, class_mask):
+    return load().orth_profile_select(h, int(class_mask) & 0xFFFFFFFF)
 
 
 def orth_profile_read(h):

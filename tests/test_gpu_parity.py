@@ -61,6 +61,9 @@ CASES = [
     (5000, 16, 256, 2500),    # k + s = 272: two column groups in the Gram kernel
     (9000, 8, 504, 4500),     # k + s = 512, coefficient blocks of 64 columns
     (20000, 4, 32, 16384),    # one leaf of 10 chunks: its 40 Gram slots are pre-summed
+    (4100, 32, 96, 1366),     # LDS-staged row update: even leaves, last one ragged (1368 rows)
+    (5001, 16, 64, 1001),     # odd leaf height: row pairs unaligned, the register-streamed row update
+    (9000, 16, 80, 4500),     # LDS-staged row update over 3 chunks per leaf (2048, 2048, 404 rows)
 ]
 
 # the widest basis the planner accepts (k_max + s = 2048), s = 32, one leaf,
