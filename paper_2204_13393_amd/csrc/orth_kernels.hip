@@ -80,6 +80,28 @@ __device__ __forceinline__ void load_run(const float *p, double (&v)[R]) {
     }
 }
 
+// direct loads into LDS (global_load_lds_dwordx4 takes an LDS pointer)
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wait until at most n vector-memory operations of this wave are
+// outstanding (n a multiple of the loads per stage, below 64).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int L, int NST>
+__device__ __forceinline__ void wait_stage(int ahead) {
+    // ahead: stages issued after the one needed (0 .. NST - 2)
+    if constexpr (NST >= 4) { if (ahead >= 2) { wait_vm<2 * L>(); return; } }
+    if constexpr (NST >= 3) { if (ahead >= 1) { wait_vm<L>(); return; } }
+    wait_vm<0>();
+}
+
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
 }  // namespace
 
 // ---------------------------------------------------------------- sweep 1
@@ -817,32 +839,11 @@ struct RowLds {
     static_assert((NST - 1) * L < 64, "wait counts fit the counter");
 };
 
-typedef __attribute__((address_space(1))) void global_void;
-typedef __attribute__((address_space(3))) void lds_void;
-
-// Wait until at most n vector-memory operations of this wave are
-// outstanding (n a multiple of the loads per stage, below 64).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
-
-template <int L, int NST>
-__device__ __forceinline__ void wait_stage(int ahead) {
-    // ahead: stages issued after the one needed (0 .. NST - 2)
-    if constexpr (NST >= 4) { if (ahead >= 2) { wait_vm<2 * L>(); return; } }
-    if constexpr (NST >= 3) { if (ahead >= 1) { wait_vm<L>(); return; } }
-    wait_vm<0>();
-}
-
 // LDS operands of one 4-column step: TR basis rows (TR / 2 16-byte reads at
 // q + 256 u bytes) and NTM coefficients (at c + 128 T bytes), with the wait
 // for them inside the same statement.
 template <int TR, int NTM>
 __device__ __forceinline__ void lds_step(uint32_t q, uint32_t c, double (&qv)[TR], double (&cv)[NTM]);
-
-typedef double dbl2v __attribute__((ext_vector_type(2)));
 
 template <>
 __device__ __forceinline__ void lds_step<2, 4>(uint32_t q, uint32_t c, double (&qv)[2], double (&cv)[4]) {
@@ -926,7 +927,8 @@ __device__ __forceinline__ void rowlds_body(const FinalizeArgs &a, int bx, doubl
     using C = RowLds<S, EXPL, TR, BK, NST>;
     constexpr int M = C::M, NTM = C::NTM, RW = C::RW, BM = C::BM;
     if (failed(a.status)) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index in a scalar register: the tile loop's branches are uniform
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int il = lane & 15, g = lane >> 4;
     const int k = a.k;
     int leaf;
