@@ -121,7 +121,11 @@ typedef double dbl2v __attribute__((ext_vector_type(2)));
 template <int S>
 __host__ __device__ constexpr int gram_rpl() { return 8; }
 
-template <int S>
+// TZ (the reduction level): the basis is the stacked tree factor, whose
+// column c holds zeros below segment row (c / s + 1) s (it was written when
+// each segment had that many rows, and the rest was zero-filled at create).
+// Those entries are taken as zeros without being read.
+template <int S, bool TZ = false>
 __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
@@ -141,11 +145,13 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     a.geom.chunk(bx, leaf, r0, r1);
 
     const double *colp[kGramTPW];
+    int cz[kGramTPW];                           // TZ: segment rows of column c that can be nonzero
 #pragma unroll
     for (int t = 0; t < kGramTPW; ++t) {
         const int c = (tile0 + t) * 16 + il;
         colp[t] = c < k ? a.Q.ptr + (int64_t)c * a.Q.ld
                         : (c < ncol ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr);
+        cz[t] = c < k ? (c / S + 1) * S : ncol;
     }
     const double *xcol[NT];
 #pragma unroll
@@ -166,17 +172,23 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
         // this lane's RPL rows are contiguous in memory: always at the leaf
         // level, and at the reduction level when they sit in one segment
         bool contig = rm + MS <= r1;
-        int64_t pb = rb;
+        int64_t pb = rb, rs = 0;
         if (!ident) {
             const int64_t q0 = rb / a.geom.map.seg_len;
             contig = contig && (rb + RPL - 1) / a.geom.map.seg_len == q0;
-            pb = q0 * a.geom.map.seg_stride + (rb - q0 * a.geom.map.seg_len);
+            rs = rb - q0 * a.geom.map.seg_len;
+            pb = q0 * a.geom.map.seg_stride + rs;
         }
         if (contig) {
 #pragma unroll
             for (int t = 0; t < kGramTPW; ++t) {
-                if (colp[t]) {
+                if (colp[t] && (!TZ || rs + RPL <= cz[t])) {
                     load_run<RPL>(colp[t] + pb, av[t]);
+                } else if (TZ && S % RPL != 0 && colp[t] && rs < cz[t]) {
+                    // a run across the bound (only when s < RPL: otherwise runs and
+                    // bounds are both multiples of RPL within the segment)
+#pragma unroll
+                    for (int u = 0; u < RPL; ++u) av[t][u] = rs + u < cz[t] ? colp[t][pb + u] : 0.0;
                 } else {
 #pragma unroll
                     for (int u = 0; u < RPL; ++u) av[t][u] = 0.0;
@@ -197,8 +209,10 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
                 const int64_t row = rb + u;
                 const bool ok = row < r1;
                 const int64_t prow = a.geom.map.phys(ok ? row : r0);
+                const int64_t srow = TZ ? row % a.geom.map.seg_len : 0;
 #pragma unroll
-                for (int t = 0; t < kGramTPW; ++t) av[t][u] = (ok && colp[t]) ? colp[t][prow] : 0.0;
+                for (int t = 0; t < kGramTPW; ++t)
+                    av[t][u] = (ok && colp[t] && (!TZ || srow < cz[t])) ? colp[t][prow] : 0.0;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? xcol[nt][prow] : 0.0;
             }
@@ -229,7 +243,7 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
 
 template <int S, int CLS>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
-    gram_body<S>(a, blockIdx.x, blockIdx.y);
+    gram_body<S, CLS == 3 || CLS == 10>(a, blockIdx.x, blockIdx.y);   // reduction level: TZ
 }
 
 // The mixed form's sweep-1 Gram: the basis columns come from the FP32 copy
@@ -706,7 +720,9 @@ __device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, i
     }
 }
 
-template <int S, bool EXPL, int TR, int PF>
+// TZ (the reduction level): basis column c is zero below segment row
+// (c / s + 1) s and is not read there (as in gram_body).
+template <int S, bool EXPL, int TR, int PF, bool TZ = false>
 __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
     if (failed(a.status)) return;
     constexpr int RB = 16 * TR;              // rows per wave block
@@ -730,11 +746,13 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
         const int64_t rl = rb + 2 * il;              // this lane's first row
         int64_t prow[TR];
         bool ok[TR];
+        int srow[TR];                                // TZ: row within its segment
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
             const int64_t r = lane_row(rb, il, t);
             ok[t] = r < r1;
             prow[t] = a.geom.map.phys(ok[t] ? r : r0);
+            srow[t] = TZ ? (int)(r % a.geom.map.seg_len) : 0;
         }
         const bool fast = ident && rb + RB <= r1;   // the lane's rows are contiguous and present
         dbl4 acc[TR][NTM];
@@ -756,8 +774,9 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
                 if (fast) {
                     load_rows<TR>(col + rl, q);
                 } else {
+                    const int cz = (c / S + 1) * S;
 #pragma unroll
-                    for (int t = 0; t < TR; ++t) q[t] = ok[t] ? col[prow[t]] : 0.0;
+                    for (int t = 0; t < TR; ++t) q[t] = (ok[t] && (!TZ || srow[t] < cz)) ? col[prow[t]] : 0.0;
                 }
 #pragma unroll
                 for (int T = 0; T < NTM; ++T) {
@@ -1034,7 +1053,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
 template <int S, bool EXPL, int CLS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rowmfma(FinalizeArgs a) {
-    rowmfma_body<S, EXPL, rowmfma_tr<S, EXPL>(), rowmfma_pf<S, EXPL>()>(a, blockIdx.x);
+    // the reduction level's correction and finalize (classes 5, 6): TZ
+    rowmfma_body<S, EXPL, rowmfma_tr<S, EXPL>(), rowmfma_pf<S, EXPL>(), CLS == 5 || CLS == 6>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- apply Q C
