@@ -381,13 +381,205 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) { reduce_body
 // [P; N] to the next level (or H and R at the root).
 constexpr int kCholCB = 64;   // P rows per LDS chunk
 
+// blocks of 16 and more columns: the wide form below
+__host__ __device__ constexpr size_t chol_lds_bytes_s(int s) {
+    return s >= 16 ? (size_t)9 * s * s * 8 + 16 : ((size_t)5 * s * s + (size_t)kCholCB * s) * 8 + 16;
+}
 template <int S>
-__host__ __device__ constexpr size_t chol_lds_bytes() {
-    return ((size_t)5 * S * S + (size_t)kCholCB * S) * 8 + 16;
+__host__ __device__ constexpr size_t chol_lds_bytes() { return chol_lds_bytes_s(S); }
+
+// a double from lane l (l wave-uniform)
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The same steps for s = 16, 32 with the two products whose length grows with
+// k on the matrix cores: P^T P (the four waves take interleaved 4-row steps
+// and their partial sums are added in wave order) and, after the second
+// sweep, P = P1 + P2 N1 (16-row tiles over the waves).  The factorisation and
+// the inverse run in one wave, lane j holding column j in registers: the
+// pivot row is broadcast with readlane, so no step needs a workgroup barrier.
+template <int S>
+__device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
+    static_assert(S == 16 || S == 32, "wide blocks only");
+    constexpr int NT = S / 16;
+    if (failed(a.status)) return;
+    extern __shared__ double lds[];
+    double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
+    double *part = n1 + S * S;                                // 4 x S x S partial sums of P^T P
+    int &bad = *reinterpret_cast<int *>(part + 4 * S * S);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int il = lane & 15, g = lane >> 4;
+    const int leaf = bx;
+    const int k = a.k, ncol = k + S;
+    if (tid == 0) bad = 0;
+    double *rec = a.small + (int64_t)leaf * a.small_stride;
+    double *recP1 = rec;
+    double *recN1 = rec + (int64_t)a.kmax * S;
+    double *recN1i = recN1 + S * S;
+    double *recP2 = recN1i + S * S;
+    double *recN2i = recP2 + (int64_t)a.kmax * S;
+    double *recP = a.sweep == 1 ? recP1 : recP2;
+
+    // 1. fixed-order slot sum: P -> leaf record, G -> LDS
+    const int first = leaf * a.slots_per_leaf;
+    const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
+    for (int e = tid; e < ncol * S; e += kThreads) {
+        double v = 0.0;
+        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        if (e < k * S) {
+            recP[e] = v;
+            if (a.pc && a.sweep == 2) a.pc[(int64_t)leaf * a.pc_stride + (int64_t)(e / S) * 2 * S + e % S] = v;
+        }
+        else gs[e - k * S] = v;
+    }
+    if (a.sweep == 2 && a.final_sweep == 2)
+        for (int e = tid; e < S * S; e += kThreads) n1[e] = recN1[e];
+    __syncthreads();
+
+    // 2. P^T P: A[i][kk] = P[c][16 ti + i], B[kk][j] = P[c][16 tj + j] for the
+    //    rows c = c0 + kk of one 4-row step
+    {
+        dbl4 pp[NT][NT];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj) pp[ti][tj] = zero4();
+        for (int c0 = 4 * wave; c0 < k; c0 += 4 * kWaves) {
+            const int c = c0 + g;
+            double pv[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) pv[t] = c < k ? recP[(int64_t)c * S + 16 * t + il] : 0.0;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) pp[ti][tj] = mfma16(pv[ti], pv[tj], pp[ti][tj]);
+        }
+        double *pw = part + wave * S * S;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pw[(16 * ti + 4 * v + g) * S + 16 * tj + il] = pp[ti][tj][v];
+    }
+    __syncthreads();
+    for (int e = tid; e < S * S; e += kThreads)
+        sm[e] = gs[e] - (((part[e] + part[S * S + e]) + part[2 * S * S + e]) + part[3 * S * S + e]);
+    __syncthreads();
+
+    // 3-4. N^T N = sm (upper) and N^{-1}, one wave, lane j < S owns column j
+    if (wave == 0) {
+        const int j = lane;
+        const bool own = j < S;
+        double col[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) col[i] = own ? sm[i * S + j] : 0.0;
+        int fail = 0;
+#pragma unroll
+        for (int kk = 0; kk < S; ++kk) {
+            const double piv = readlane_d(col[kk], kk);
+            if (!(piv > 0.0) || !isfinite(piv)) { fail = kk + 1; break; }
+            const double nkk = sqrt(piv);
+            const double r = j == kk ? nkk : (j > kk && own ? col[kk] / nkk : 0.0);   // N[kk][j]
+            col[kk] = r;
+#pragma unroll
+            for (int i = kk + 1; i < S; ++i) {
+                const double ri = readlane_d(r, i);                                   // N[kk][i]
+                if (j >= i && own) col[i] -= ri * r;
+            }
+        }
+        if (fail) {
+            if (lane == 0) bad = fail;
+        } else if (own) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                if (i > j) col[i] = 0.0;
+                nm[i * S + j] = col[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0 && atomicCAS(&a.status->code, 0, 3) == 0) {
+            a.status->level = a.level;
+            a.status->leaf = leaf;
+            a.status->sweep = a.sweep;
+            a.status->column = bad - 1;
+            a.status->instance = a.instance;
+        }
+        return;
+    }
+    if (wave == 0 && lane < S) {
+        // back substitution N x = e_j, x[l] = 0 past j; the rows of N are read
+        // by every lane at once (LDS broadcast)
+        const int j = lane;
+        double x[S];
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = i + 1; l < S; ++l) t = fma(nm[i * S + l], x[l], t);
+            x[i] = i > j ? 0.0 : (i == j ? 1.0 / nm[i * S + i] : -t / nm[i * S + i]);
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) ni[i * S + j] = x[i];
+    }
+    __syncthreads();
+    if (a.sweep == 1) {
+        for (int e = tid; e < S * S; e += kThreads) { recN1[e] = nm[e]; recN1i[e] = ni[e]; }
+    } else {
+        for (int e = tid; e < S * S; e += kThreads) recN2i[e] = ni[e];
+    }
+    if (a.sweep != a.final_sweep) return;
+
+    // 5. [P; N] of this leaf
+    const int64_t ybase = (int64_t)leaf * a.yseg;
+    auto put = [&](int c, int jj, double v) {
+        if (a.Yout) a.Yout[(int64_t)jj * a.ldy + ybase + c] = v;
+        if (c < k) {
+            if (a.H) a.H[(int64_t)jj * a.ldh + c] = v;
+        } else if (a.R) {
+            a.R[(int64_t)jj * a.ldr + (c - k)] = v;
+        }
+    };
+    if (a.sweep == 1) {
+        for (int e = tid; e < ncol * S; e += kThreads) {
+            const int c = e / S, jj = e % S;
+            put(c, jj, c < k ? recP1[e] : nm[(c - k) * S + jj]);
+        }
+        return;
+    }
+    // P = P1 + P2 N1: A[ci][kk] = P2[16 rt + ci][4 ks + kk], B[kk][j] = N1[4 ks + kk][16 tj + j]
+    for (int rt = wave; 16 * rt < k; rt += kWaves) {
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+            dbl4 d = zero4();
+#pragma unroll
+            for (int ks = 0; ks < S / 4; ++ks)
+                d = mfma16(recP2[(int64_t)(16 * rt + il) * S + 4 * ks + g], n1[(4 * ks + g) * S + 16 * tj + il], d);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * rt + 4 * v + g, jj = 16 * tj + il;
+                put(c, jj, recP1[(int64_t)c * S + jj] + d[v]);
+            }
+        }
+    }
+    // N = N2 N1
+    for (int e = tid; e < S * S; e += kThreads) {
+        const int i = e / S, jj = e % S;
+        double v = 0.0;
+        for (int l = i; l <= jj; ++l) v = fma(nm[i * S + l], n1[l * S + jj], v);
+        put(k + i, jj, v);
+    }
 }
 
 template <int S>
-__device__ __forceinline__ void chol_body(const CholArgs &a, int bx) {
+__device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
     if (failed(a.status)) return;
     constexpr int EPT = (S * S + kThreads - 1) / kThreads;   // S x S entries per thread
     extern __shared__ double lds[];
@@ -519,6 +711,15 @@ __device__ __forceinline__ void chol_body(const CholArgs &a, int bx) {
         } else if (a.R) {
             a.R[(int64_t)j * a.ldr + (c - k)] = v;
         }
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void chol_body(const CholArgs &a, int bx) {
+    if constexpr (S >= 16) {
+        chol_wide_body<S>(a, bx);
+    } else {
+        chol_narrow_body<S>(a, bx);
     }
 }
 
@@ -1447,6 +1648,12 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st) {
 
 template <int S>
 static hipError_t chol_s(const CholArgs &a, hipStream_t st) {
+    if (chol_lds_bytes<S>() > 65536) {           // the wide form at s = 32 takes 72 KB
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol<S>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)chol_lds_bytes<S>());
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), chol_lds_bytes<S>(), st, a);
     return hipGetLastError();
 }
@@ -1570,9 +1777,7 @@ hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_
 namespace orth {
 
 size_t batch_phase_lds(int phase, int s) {
-    auto chol = [](int s) -> size_t {
-        return ((size_t)5 * s * s + (size_t)kCholCB * s) * 8 + 16;
-    };
+    auto chol = [](int s) -> size_t { return chol_lds_bytes_s(s); };
     switch (phase) {
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
             return chol(s);
@@ -1587,6 +1792,11 @@ static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, 
             hipLaunchKernelGGL((kb_gram<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
+            if (lds > 65536) {
+                const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_chol<S>),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
             hipLaunchKernelGGL((kb_chol<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_RRED1: case BP_RRED2:

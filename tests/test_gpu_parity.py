@@ -290,6 +290,37 @@ def test_breakdown_poisons_handle(torch_cuda):
     gpu.h = None
 
 
+@pytest.mark.parametrize("s,col", [(16, 11), (32, 19), (32, 0)])
+def test_breakdown_wide_blocks(torch_cuda, s, col):
+    """Zero column at s = 16, 32 (the wide Cholesky): the pivot of that column is 0."""
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("breakdown wide", s, col)
+    n = 4096
+    gpu = Orthogonalizer(n, s, 4 * s, 1024)
+    gpu.step(to_dev(normal_block(n, s, 5)))
+    assert gpu.status()[0] == 0
+    Y = normal_block(n, s, 6)
+    Y[:, col] = 0.0
+    gpu.step(to_dev(Y))
+    st, info = gpu.status()
+    assert st == orth.ORTH_ERR_BREAKDOWN
+    assert info[0] == 0 and info[2] == 1 and info[3] == col, info
+    gpu.close()
+
+
+def test_nan_input_breaks_down_wide(torch_cuda):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("nan breakdown wide")
+    n, s = 3000, 32
+    gpu = Orthogonalizer(n, s, 64, 1000)
+    W = normal_block(n, s, 2)
+    W[1700, 5] = np.nan
+    gpu.step(to_dev(W))
+    st, info = gpu.status()
+    assert st == orth.ORTH_ERR_BREAKDOWN, (st, info)
+    gpu.close()
+
+
 def test_nan_input_breaks_down(torch_cuda):
     from paper_2204_13393_amd import Orthogonalizer, orth
     _say("nan breakdown")
