@@ -477,6 +477,57 @@ def bench_lap3d(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_kappa_sweep(args):
+    """Subalgorithm sweep (Sec. 6.1, the kappa sweep and the local x reduction
+    combinations): QR of Stewart matrices X = U diag(sigma) V^T,
+    sigma_j = kappa^(-j/31), n = 2^16, 32 columns in blocks of s = 4 (eight
+    orth_step calls), leaves of 256 rows, for kappa = 10^0 .. 10^12 and the
+    four combinations of BCGS-PIP / BCGS-PIP+ at the leaves and at the
+    reduction.  Per case: status (breakdown or not) and e_perp of the
+    explicit basis.  The matrices come from synth.stewart (seed 11)."""
+    import numpy as np
+    import torch
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    from synth import stewart
+    n, m, s, leaf = 1 << 16, 32, 4, 256
+    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
+    combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip")]
+    eye = torch.eye(m, dtype=torch.float64, device="cuda")
+    rows = []
+    print("[bench] kappa sweep: Stewart n = 2^16, 32 columns, s = 4, leaves of 256 rows", file=sys.stderr, flush=True)
+    for e in range(13):
+        kappa = 10.0 ** e
+        A = stewart(n, m, kappa, 11)
+        At = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
+        row = {"kappa": kappa}
+        for local, red in combos:
+            g = Orthogonalizer(n, s, m, leaf, variant=v[local], reduction_variant=v[red])
+            for j in range(m // s):
+                g.step(At[j * s:(j + 1) * s].contiguous())
+                if g.status()[0]:
+                    break
+            st, info = g.status()
+            if st == 0:
+                # e_perp on the host (FP64 BLAS): a 32 x 32 Gram of 2^16 rows
+                Q = g.apply_Q(eye).cpu().numpy()
+                row[f"{local}/{red}"] = float(np.linalg.norm(Q @ Q.T - np.eye(m), "fro"))
+            else:
+                row[f"{local}/{red}"] = {"breakdown": {"level": info[0], "sweep": info[2], "column": info[3]}}
+            g.close()
+        rows.append(row)
+        print(f"[bench] kappa 1e{e}: " + ", ".join(f"{c}: {row[c] if isinstance(row[c], dict) else f'{row[c]:.2e}'}"
+                                                  for c in row if c != "kappa"), file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "workload": "subalgorithm-sweep-stewart-2^16x32-s4",
+        "results": rows,
+        "columns": "local/reduction subalgorithm; value = e_perp of the explicit Q, or the breakdown record",
+        "dtype": "f64",
+        "data": "synthetic: Stewart matrices from synth.stewart(2^16, 32, kappa, 11)",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_stewart(args):
     """Precision workload: block-column QR (Sec. 2, the block-column QR
     algorithm) of one n x 240 matrix W = G diag(sigma) V^T with n = 2^24,
@@ -578,7 +629,7 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
-                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart"],
+                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep"],
                     help="the default single-basis run, the batched form (512 instances), "
                          "the large-block 3D run, or the precision workload (Stewart matrices)")
     args = ap.parse_args()
@@ -592,6 +643,8 @@ def main():
         return bench_batched(args)
     if args.workload == "lap3d-256-s32":
         return bench_lap3d(args)
+    if args.workload == "kappa-sweep":
+        return bench_kappa_sweep(args)
     if args.workload == "stewart":
         return bench_stewart(args)
 

@@ -137,6 +137,15 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
 int orth_set_variant(orth_t *h, int32_t variant);
 
 /*
+ * orth_set_level_variants -- the subalgorithm of each level separately: the
+ * leaves' local problems and the reduction problem (Sec. 4.1 lets each be
+ * any PQR method; the experiments of Sec. 6 vary them independently).
+ * orth_set_variant(h, v) equals orth_set_level_variants(h, v, v).
+ * Host-side only.  Errors: ARG, POISONED.
+ */
+int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant);
+
+/*
  * orth_step -- solve the PQR problem eq. (1.1) for the new block W and grow
  * the basis by s columns (Sec. 4.1, TreeTSPQR; one step of the block
  * Arnoldi process, Sec. 2).

@@ -142,7 +142,8 @@ LevelGeom root_geom(const Plan &pl, int64_t seg_len, int chunk) {
 struct orth_ctx {
     Plan pl;
     int32_t k = 0;
-    int32_t variant = ORTH_PIP_PLUS;
+    int32_t variant = ORTH_PIP_PLUS;       // the leaves' subalgorithm
+    int32_t variant_red = ORTH_PIP_PLUS;   // the reduction's
     bool poisoned = false;
     hipStream_t stream = nullptr;
     double *ws = nullptr;
@@ -244,9 +245,15 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
 }
 
 int orth_set_variant(orth_t *h, int32_t variant) {
-    if (!h || (variant != ORTH_PIP_PLUS && variant != ORTH_PIP)) return ORTH_ERR_ARG;
+    return orth_set_level_variants(h, variant, variant);
+}
+
+int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant) {
+    const auto ok = [](int32_t v) { return v == ORTH_PIP_PLUS || v == ORTH_PIP; };
+    if (!h || !ok(leaf_variant) || !ok(reduction_variant)) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
-    h->variant = variant;
+    h->variant = leaf_variant;
+    h->variant_red = reduction_variant;
     return ORTH_OK;
 }
 
@@ -404,7 +411,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     if (ldw < pl.n || ldu < pl.n || ldr < s) return ORTH_ERR_ARG;
     if (k > 0 && (!d_H || ldh < k)) return ORTH_ERR_ARG;
     if (k + s > kmax) return ORTH_ERR_CAPACITY;
-    const bool two = h->variant == ORTH_PIP_PLUS;
+    const bool two = h->variant == ORTH_PIP_PLUS;          // leaves
+    const bool two_red = h->variant_red == ORTH_PIP_PLUS;  // reduction
     hipStream_t st = h->stream;
     const int ncol = k + s;
     int rc;
@@ -446,7 +454,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.ldh = ldh;
         L.R = d_R;
         L.ldr = ldr;
-        if ((rc = run_level(h, L, k, two))) goto fail;
+        if ((rc = run_level(h, L, k, two_red))) goto fail;
 
         // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s], and
         // row-major per leaf (C_i) for the leaf finalize
@@ -460,7 +468,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.small = h->SR();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
-        f.single_sweep = two ? 0 : 1;
+        f.single_sweep = two_red ? 0 : 1;
         f.Cptr = nullptr;
         f.Crow = h->CL();
         f.crow_seg = (int64_t)kmax * 2 * s;

@@ -38,6 +38,7 @@ SIGNATURES = [
     ("orth_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32]),
     ("orth_create", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
+    ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
     ("orth_step", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64]),
     ("orth_apply_Q", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
     ("orth_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -112,6 +113,10 @@ def orth_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes,
 
 def orth_set_variant(h, variant):
     return load().orth_set_variant(h, variant)
+
+
+def orth_set_level_variants(h, leaf_variant, reduction_variant):
+    return load().orth_set_level_variants(h, leaf_variant, reduction_variant)
 
 
 def orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu):
@@ -271,7 +276,7 @@ class Orthogonalizer:
     """
 
     def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
-                 precision=ORTH_FP64):
+                 precision=ORTH_FP64, reduction_variant=None):
         import torch
         load()
         self.n, self.s, self.k_max = int(n), int(s), int(k_max)
@@ -288,7 +293,8 @@ class Orthogonalizer:
                               _stream_ptr(stream))
         _check("orth_create", code)
         self.h = h
-        _check("orth_set_variant", orth_set_variant(self.h, variant))
+        red = variant if reduction_variant is None else reduction_variant
+        _check("orth_set_level_variants", orth_set_level_variants(self.h, variant, red))
         _, self.p, self.leaf_rows = orth_leaf_count(self.h)
 
     @property

@@ -1,0 +1,144 @@
+"""Subalgorithm sweeps on the GPU path (Sec. 6.1, the kappa sweep and the
+local x reduction combinations), against the oracle TreeTSPQR.
+
+Workload of the paper's stability experiments: Stewart matrices
+X = U diag(sigma) V^T, sigma_j = kappa^(-j/(m-1)), n = 2^16 rows, m = 32
+columns in blocks of s = 4, leaves of 256 rows; the QR of X through eight
+orth_step calls, e_perp = ||I - Q^T Q||_F of the explicit basis.
+
+What the paper states and the tests check:
+  * TreeTSPQR is as stable as its subalgorithm: with BCGS-PIP+ at both levels
+    e_perp is O(eps) while eps kappa^2 <= 1/2 (checked: <= 1e-13 for
+    kappa <= 1e6); with BCGS-PIP it is O(eps kappa^2) (checked: at most
+    100 eps kappa^2, and at kappa = 1e6 at least 1e3 times the PIP+ error);
+  * both the local and the reduction subalgorithm must be stable: at
+    kappa = 1e6 every combination with a BCGS-PIP level shows the
+    O(eps kappa^2) error (>= 1e-10), only PIP+ / PIP+ stays at O(eps); at
+    the paper's kappa = 1e8 those combinations break down or end with
+    e_perp >= 1e-6 (PIP+ / PIP+ sits at eps kappa^2 ~ 2, past the bound,
+    and is only reported);
+  * far past eps kappa^2 = 1/2 (kappa = 1e10) no combination is stable: each
+    breaks down (a Cholesky pivot <= 0) or ends with e_perp >= 1e-6, on the
+    GPU and in the oracle alike;
+  * parity: where both finish, the GPU's e_perp is within a factor of 10 of
+    the oracle's on the same matrix and partition (kappa <= 1e6, where the
+    errors are not dominated by the chaotic regime near the breakdown).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import TreeTSPQR, metrics
+from oracle.krylov import block_column_qr
+from oracle.pqr import Breakdown
+from synth import stewart
+
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -52
+N, M, S, LEAF = 2 ** 16, 32, 4, 256
+COMBOS = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip")]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    return torch
+
+
+def _gpu_e_perp(A, local, reduction):
+    """(status, e_perp or None) of the GPU QR of A in blocks of S."""
+    import torch
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
+    g = Orthogonalizer(N, S, M, LEAF, variant=v[local], reduction_variant=v[reduction])
+    for j in range(M // S):
+        g.step(to_dev(A[:, j * S:(j + 1) * S]))
+        if g.status()[0]:
+            break
+    st = g.status()[0]
+    e = None
+    if st == 0:
+        Q = to_host(g.apply_Q(torch.eye(M, dtype=torch.float64, device="cuda")))
+        e = metrics.e_perp(Q)
+    g.close()
+    return st, e
+
+
+def _oracle_e_perp(A, local, reduction):
+    tree = TreeTSPQR(N, S, LEAF, local, reduction)
+    try:
+        block_column_qr(A, S, tree)
+    except Breakdown:
+        return None
+    return metrics.e_perp(tree.explicit_Q())
+
+
+@pytest.fixture(scope="module")
+def sweep(torch_cuda):
+    out = {}
+    for kappa in (1e0, 1e3, 1e6, 1e8, 1e10):
+        A = stewart(N, M, kappa, 11)
+        for local, red in COMBOS:
+            _say("sweep", kappa, local, red)
+            st, eg = _gpu_e_perp(A, local, red)
+            eo = _oracle_e_perp(A, local, red)
+            out[(kappa, local, red)] = (st, eg, eo)
+            print(f"  kappa {kappa:.0e} local {local:4s} reduction {red:4s}: "
+                  f"gpu {'breakdown' if st else f'{eg:.2e}'}  oracle {'breakdown' if eo is None else f'{eo:.2e}'}",
+                  flush=True)
+    return out
+
+
+def test_pip_plus_is_order_eps(sweep):
+    for kappa in (1e0, 1e3, 1e6):
+        st, eg, eo = sweep[(kappa, "pip+", "pip+")]
+        assert st == 0 and eg <= 1e-13, (kappa, st, eg)
+        assert eo is not None and eo <= 1e-13, (kappa, eo)
+
+
+def test_pip_is_order_eps_kappa2(sweep):
+    for kappa in (1e3, 1e6):
+        st, eg, eo = sweep[(kappa, "pip", "pip")]
+        assert st == 0 and eg <= 100 * EPS * kappa ** 2, (kappa, eg)
+    assert sweep[(1e6, "pip", "pip")][1] >= 1e3 * sweep[(1e6, "pip+", "pip+")][1]
+
+
+def test_both_levels_must_be_stable(sweep):
+    for local, red in COMBOS[1:]:
+        st, eg, eo = sweep[(1e6, local, red)]
+        assert st == 0 and eg >= 1e-10, (local, red, eg)
+        assert eo is not None and eo >= 1e-10, (local, red, eo)
+        # the paper's local x reduction map is taken at kappa = 1e8 (eps kappa^2 ~ 2)
+        st, eg, eo = sweep[(1e8, local, red)]
+        assert st != 0 or eg >= 1e-6, (local, red, st, eg)
+        assert eo is None or eo >= 1e-6, (local, red, eo)
+
+
+def test_past_the_bound_nothing_is_stable(sweep):
+    for local, red in COMBOS:
+        st, eg, eo = sweep[(1e10, local, red)]
+        assert st != 0 or eg >= 1e-6, (local, red, st, eg)
+        assert eo is None or eo >= 1e-6, (local, red, eo)
+
+
+def test_gpu_matches_oracle(sweep):
+    for (kappa, local, red), (st, eg, eo) in sweep.items():
+        if kappa > 1e6:
+            continue
+        assert st == 0 and eo is not None, (kappa, local, red)
+        lo = max(min(eg, eo), 1e-15)
+        assert max(eg, eo) <= 10 * lo, (kappa, local, red, eg, eo)
