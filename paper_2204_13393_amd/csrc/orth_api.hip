@@ -230,7 +230,8 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     h->ws = static_cast<double *>(d_workspace);
     // tree factors must start at zero: the reduction level relies on the
     // zero rows below every T_i's current k x k block
-    hipError_t e = launch_fill(h->T(), pl.ldt * (int64_t)pl.kmax, 0.0, h->stream);
+    hipError_t e = prepare_kernels(pl.s);
+    if (e == hipSuccess) e = launch_fill(h->T(), pl.ldt * (int64_t)pl.kmax, 0.0, h->stream);
     if (e == hipSuccess) e = launch_fill(h->Y(), pl.ldt * (int64_t)pl.s, 0.0, h->stream);
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
@@ -780,6 +781,13 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
     b->L = L;
     b->stream = static_cast<hipStream_t>(stream);
     b->ws = static_cast<double *>(d_workspace);
+    for (int32_t w : L.widths) {
+        if (prepare_kernels(w) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return ORTH_ERR_HIP;
+        }
+    }
     b->desc.resize(count);
     for (int32_t i = 0; i < count; ++i) {
         const Plan &pl = L.plans[i];

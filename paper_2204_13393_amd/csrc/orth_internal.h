@@ -307,6 +307,9 @@ hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st);
 hipError_t launch_finalize(int s, const FinalizeArgs &a, int cls, hipStream_t st);
+// once per handle, on its device: raise the dynamic-LDS limit of the kernels
+// a block width s uses beyond 64 KB
+hipError_t prepare_kernels(int s);
 hipError_t launch_apply(const ApplyArgs &a, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);

@@ -1648,12 +1648,6 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st) {
 
 template <int S>
 static hipError_t chol_s(const CholArgs &a, hipStream_t st) {
-    if (chol_lds_bytes<S>() > 65536) {           // the wide form at s = 32 takes 72 KB
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol<S>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)chol_lds_bytes<S>());
-        if (e != hipSuccess) return e;
-    }
     hipLaunchKernelGGL((k_chol<S>), dim3(a.nleaf), dim3(kThreads), chol_lds_bytes<S>(), st, a);
     return hipGetLastError();
 }
@@ -1685,9 +1679,6 @@ static bool rowlds_eligible(const FinalizeArgs &a, int s) {
 template <int S, bool EXPL, int CLS>
 static hipError_t launch_rowlds(const FinalizeArgs &a, hipStream_t st) {
     using C = RowLds<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>;
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rowlds<S, EXPL, CLS>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes());
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rowlds<S, EXPL, CLS>), dim3(a.geom.nchunks()), dim3(kThreads), C::lds_bytes(), st, a);
     return hipGetLastError();
 }
@@ -1711,6 +1702,38 @@ static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
         }
     }
     return hipGetLastError();
+}
+
+// Kernels whose dynamic LDS exceeds 64 KB need the limit raised once per
+// function on the current device (host-side, outside any stream, so never
+// inside a captured graph): the LDS-staged row updates and the wide Cholesky
+// at s = 32.
+template <int S, bool EXPL, int CLS>
+static hipError_t raise_rowlds_lds() {
+    using C = RowLds<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rowlds<S, EXPL, CLS>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes());
+}
+
+template <int S>
+static hipError_t raise_wide_lds() {
+    hipError_t e = raise_rowlds_lds<S, true, 7>();
+    if (e == hipSuccess) e = raise_rowlds_lds<S, false, 2>();
+    if (e == hipSuccess && chol_lds_bytes<S>() > 65536)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol<S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds_bytes<S>());
+    if (e == hipSuccess && chol_lds_bytes<S>() > 65536)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_chol<S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds_bytes<S>());
+    return e;
+}
+
+hipError_t prepare_kernels(int s) {
+    switch (s) {
+        case 16: return raise_wide_lds<16>();
+        case 32: return raise_wide_lds<32>();
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_finalize(int s, const FinalizeArgs &a, int cls, hipStream_t st) {
@@ -1792,11 +1815,6 @@ static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, 
             hipLaunchKernelGGL((kb_gram<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
-            if (lds > 65536) {
-                const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_chol<S>),
-                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                if (e != hipSuccess) return e;
-            }
             hipLaunchKernelGGL((kb_chol<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_RRED1: case BP_RRED2:

@@ -436,3 +436,68 @@ def test_pip_variant_matches_oracle_tree(torch_cuda):
         if j:
             assert np.max(np.abs(to_host(H) - P)) <= 1e-11
     gpu.close()
+
+
+def test_graph_replay_wide_blocks(torch_cuda):
+    """Three s = 32 steps (LDS-staged row updates, wide Cholesky) captured in a
+    hipGraph and replayed from freshly created handles on the same workspace,
+    eager work and synchronisation between replays: every replay equals the
+    eager run bitwise."""
+    import torch
+    from paper_2204_13393_amd import orth
+    _say("graph wide")
+    n, s, kmax, leaf = 4096, 32, 96, 1024
+    X = [to_dev(normal_block(n, s, 60 + j)) for j in range(3)]
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64)
+    side = torch.cuda.Stream()
+
+    def buffers():
+        H = torch.zeros((kmax, kmax), dtype=torch.float64, device="cuda")
+        U = torch.empty((kmax, n), dtype=torch.float64, device="cuda")
+        return H, U
+
+    def run(h, H, U):
+        for j in range(3):
+            k = j * s
+            col = H[j * s:(j + 1) * s]
+            hp = col.data_ptr() if k else 0
+            assert orth.orth_step(h, X[j].data_ptr(), n, hp, kmax, col[:, k:].data_ptr(), kmax,
+                                  U[k:k + s].data_ptr(), n) == 0
+
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    He, Ue = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        run(h, He, Ue)
+    side.synchronize()
+    assert orth.orth_status(h)[1] == 0
+    orth.orth_destroy(h)
+    He_h, Ue_h = to_host(He), to_host(Ue)
+
+    Hg, Ug = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, wp, nbytes, side.cuda_stream)
+        assert code == 0
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        run(h, Hg, Ug)
+    orth.orth_destroy(h)
+    for rep in range(3):
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        Hg.zero_()
+        Ug.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        code, st, info = orth.orth_status(h)
+        assert code == 0 and st == 0, info
+        assert np.array_equal(to_host(Hg), He_h), rep
+        assert np.array_equal(to_host(Ug), Ue_h), rep
+        orth.orth_destroy(h)
+        x = torch.randn(1000, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
