@@ -283,6 +283,7 @@ struct LevelRun {
     int64_t ldh;
     double *R;
     int64_t ldr;
+    LevelGeom rgeom;      // chunks of the correction (row update) launch
 };
 
 int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
@@ -370,7 +371,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     f.U1 = L.X;
     f.sweep = 1;
     f.k = k;
-    f.geom = L.geom;
+    f.geom = L.rgeom;
     f.small = L.small;
     f.small_stride = small_stride(kmax, s);
     f.kmax = kmax;
@@ -425,6 +426,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.X = Operand{d_W, ldw};
         L.U1 = OutOperand{h->U1L(), pl.ldq};
         L.geom = leaf_geom(pl, kLeafChunk);
+        L.rgeom = leaf_geom(pl, kFinalChunk);
         L.Qhi = h->Qhi();
         L.pc = h->CL();
         L.part = h->PL();
@@ -445,6 +447,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.X = Operand{h->Y(), pl.ldt};
         L.U1 = OutOperand{h->U1R(), pl.ldt};
         L.geom = root_geom(pl, ncol, kRootChunk);
+        L.rgeom = root_geom(pl, ncol, kRootRowChunk);
         L.part = h->PR();
         L.part2 = h->PR2();
         L.part_cap = pl.slot_cap;
@@ -465,7 +468,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.U1 = Operand{h->U1R(), pl.ldt};
         f.sweep = 2;
         f.k = k;
-        f.geom = root_geom(pl, ncol, kFinalChunk);
+        f.geom = root_geom(pl, ncol, kRootRowChunk);
         f.small = h->SR();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -522,7 +525,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         ApplyArgs r{};
         r.Q = Operand{h->T(), pl.ldt};
         r.k = k;
-        r.geom = root_geom(pl, k, kFinalChunk);
+        r.geom = root_geom(pl, k, kRootRowChunk);
         r.Cptr = d_C + (int64_t)j0 * ldc;
         r.ldc = ldc;
         r.cseg = 0;

@@ -79,7 +79,12 @@ __host__ __device__ inline int gram_col_groups(int ncol) {
 __host__ __device__ inline int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
 constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
-constexpr int kFinalChunk = 2048;     // rows per workgroup in the row updates
+constexpr int kFinalChunk = 2048;     // rows per workgroup in the leaf row updates
+// rows per workgroup in the reduction-level row updates: the reduction level
+// has p (k + s) rows, and 512-row chunks give its correction and finalize
+// enough workgroups (its Gram keeps 2048: more chunks mean more partial sums
+// for the Cholesky to add)
+constexpr int kRootRowChunk = 512;
 constexpr int kReduceGroup = 16;      // slots pre-summed per group at a single-leaf level
 
 __host__ __device__ inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -297,7 +302,7 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
             return 1;
         case BP_RCORR:
         case BP_RFIN:
-            return make_root_geom(d.p, d.kmax, ncol, kFinalChunk).nchunks();
+            return make_root_geom(d.p, d.kmax, ncol, kRootRowChunk).nchunks();
     }
     return 0;
 }

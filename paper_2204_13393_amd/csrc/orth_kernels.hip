@@ -1520,7 +1520,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.Qnew = OutOperand{d.U1R, d.ldt};
             f.U1 = Operand{d.Y, d.ldt};
             f.sweep = 1;
-            f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
+            f.geom = make_root_geom(d.p, d.kmax, ncol, kRootRowChunk);
             f.small = d.SR;
             rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
@@ -1530,7 +1530,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.U1 = Operand{d.U1R, d.ldt};
             f.sweep = 2;
             f.single_sweep = a.two ? 0 : 1;
-            f.geom = make_root_geom(d.p, d.kmax, ncol, kFinalChunk);
+            f.geom = make_root_geom(d.p, d.kmax, ncol, kRootRowChunk);
             f.small = d.SR;
             f.Crow = d.CL;
             f.crow_seg = (int64_t)d.kmax * 2 * S;
