@@ -381,6 +381,8 @@ def bench_lap3d(args):
     nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_MIXED_SPLIT32)
     o.close()
 
+    fallbacks = {}      # steps whose first sweep was redone in FP64, per form
+
     def run(profiled, precision=orth.ORTH_FP64):
         code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sp)
         if code:
@@ -406,6 +408,7 @@ def bench_lap3d(args):
             ms += e0.elapsed_time(e1)
         code, st, info = orth.orth_status(h)
         prof = orth.orth_profile_read(h)[1] if profiled else None
+        fallbacks[precision] = fallbacks.get(precision, 0) + orth.orth_mixed_fallbacks(h)[1]
         orth.orth_destroy(h)
         if st:
             raise RuntimeError(f"breakdown {info}")
@@ -449,8 +452,9 @@ def bench_lap3d(args):
         code, h = orth.orth_create(n, s, kmax, leaf, prec, ws_ptr, nbytes, sp)
         orth.orth_step(h, W.data_ptr(), n, 0, 1, H.data_ptr(), kmax, V[:s].data_ptr(), n)
         code, st, info = orth.orth_status(h)
+        redo = orth.orth_mixed_fallbacks(h)[1]
         orth.orth_destroy(h)
-        ill[name] = {"status": "breakdown" if st else "ok", "info": info}
+        ill[name] = {"status": "breakdown" if st else "ok", "info": info, "fp64_redo_steps": redo}
     out = {
         "metric": METRIC,
         "workload": "lap3d-256-s32",
@@ -467,6 +471,7 @@ def bench_lap3d(args):
             "value_effective": total_bytes / (best_mixed / 1e3) / 1e9,
             "speedup_vs_fp64": best / best_mixed,
             "e_perp": e_perp_mixed,
+            "fp64_redo_steps": fallbacks[orth.ORTH_MIXED_SPLIT32],
             "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
                         for name, (ms, cnt) in prof_mixed.items() if cnt},
         },
@@ -536,8 +541,9 @@ def bench_stewart(args):
     Gaussian / sqrt(n), orthonormal to about 2 sqrt(240/n) = 0.008 at this n, so
     the singular values of W are sigma to within 1%.  FP64 and mixed forms.
     Per form and range: status (and the call after which a breakdown was
-    reported), time of the calls (HIP events around each), e_perp of the
-    explicit Q and ||W - Q R||_F / ||W||_F."""
+    reported), the calls in which the mixed form redid its first sweep in
+    FP64, time of the calls (HIP events around each), e_perp of the explicit Q
+    and ||W - Q R||_F / ||W||_F."""
     import math
     import torch
     from paper_2204_13393_amd import Orthogonalizer, orth
@@ -585,9 +591,10 @@ def bench_stewart(args):
                         failed = {"call": j, "info": info}
                         break
                     ms += e0.elapsed_time(e1)
+                code, nfall = orth.orth_mixed_fallbacks(h)
                 orth.orth_destroy(h)
             row = {"form": name, "sigma_min": smin, "status": "breakdown" if failed else "ok",
-                   "breakdown": failed}
+                   "breakdown": failed, "fallback_steps": nfall}
             if not failed:
                 Gq = torch.mm(Qt, Qt.t())
                 Gq -= torch.eye(m, dtype=torch.float64, device=dev)
@@ -732,6 +739,8 @@ def main():
         with_bytes = [c for c, (ms, cnt) in pr.items() if cnt and kernel_bytes(c, n, s, p, 8) > 0]
         return pr, max(with_bytes, key=lambda c: pr[c][0])
 
+    fallbacks = {}      # steps whose first sweep was redone in FP64, per form
+
     def timed_runs(precision, dom):
         """Warmup, then args.steps timed sequences over the resident inputs,
         events around the launches of class `dom` only; returns (ms per
@@ -760,10 +769,12 @@ def main():
         wall_ms = (t1 - t0) * 1e3 / args.steps
         gpu_ms = ev0.elapsed_time(ev1) / args.steps
         dom_ms, dom_n = 0.0, 0
+        fallbacks[precision] = 0
         for h in handles:
             code, st, info = orth.orth_status(h)
             if code or st:
                 raise RuntimeError(f"orth_step breakdown: {info}")
+            fallbacks[precision] += orth.orth_mixed_fallbacks(h)[1]
             if dom is not None:
                 code, pr = orth.orth_profile_read(h)
                 dom_ms += pr[dom][0]
@@ -855,6 +866,7 @@ def main():
             "speedup_vs_fp64": ms_per_step / ms_mixed,
             "e_perp": e_perp_mixed,
             "e_perp_gate_1e-10": e_perp_mixed <= 1e-10,
+            "fp64_redo_steps": fallbacks[orth.ORTH_MIXED_SPLIT32],
             "kernels": per_class(prof_mixed) if prof_mixed else {},
         },
         "roofline": roofline,

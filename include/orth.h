@@ -82,9 +82,13 @@ enum orth_code {
  *                       entry written); the workspace grows by 4 bytes per
  *                       leaf basis entry.  The first sweep stays stable
  *                       while 6e-8 kappa^2 << 1/2 (kappa the condition
- *                       number of the projected block); beyond it a pivot
- *                       may fail (BREAKDOWN).  Single handles only:
- *                       orth_batch_create returns UNSUPPORTED.
+ *                       number of the projected block); when a leaf's
+ *                       pivot fails in that sweep, the step redoes its
+ *                       first sweep from the FP64 bases on the device (no
+ *                       host synchronisation; counted by
+ *                       orth_mixed_fallbacks), so the mixed form breaks
+ *                       down only where the FP64 form does.  Single handles
+ *                       only: orth_batch_create returns UNSUPPORTED.
  */
 enum orth_precision {
     ORTH_FP64 = 0,
@@ -188,6 +192,13 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
  */
 int orth_status(orth_t *h, int32_t *status, int32_t *info);
 
+/*
+ * orth_mixed_fallbacks -- synchronise the handle's stream and read how many
+ * steps of the mixed form redid their first CholeskyQR sweep from the FP64
+ * bases (0 for the FP64 form).  Errors: ARG, HIP.
+ */
+int orth_mixed_fallbacks(orth_t *h, int64_t *count);
+
 /* orth_basis_width -- current k (host state, no synchronisation). */
 int orth_basis_width(const orth_t *h, int32_t *k);
 
@@ -219,7 +230,8 @@ enum orth_kernel_class {
     ORTH_K_APPLY = 8,          /* orth_apply_Q launches                         */
     ORTH_K_LEAF_GRAM2 = 9,     /* leaves, sweep-2 Gram [Q_i U1_i]^T U1_i        */
     ORTH_K_ROOT_GRAM2 = 10,    /* reduction level, sweep-2 Gram                 */
-    ORTH_K_COUNT = 11
+    ORTH_K_LEAF_FALLBACK = 11, /* mixed form: FP64 redo of the first sweep      */
+    ORTH_K_COUNT = 12
 };
 
 /*

@@ -306,6 +306,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     ga.partials = L.part;
     ga.part_stride = pstride;
     ga.status = h->status();
+    ga.clear_retry = L.Qhi ? 1 : 0;
     {
         const int pm = h->begin(cls0 + 0);
         e = launch_gram(s, ga, cls0 + 0, st);
@@ -334,8 +335,10 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     c.status = h->status();
 
     // sum the slots of each leaf; pre-reduce when a single leaf owns many
-    auto chol = [&](int sweep, int ppc) -> int {
+    auto chol = [&](int sweep, int ppc, int cls, bool soft, bool cond) -> int {
         c.sweep = sweep;
+        c.soft = soft ? 1 : 0;
+        c.cond = cond ? 1 : 0;
         c.partials = L.part;
         c.slots_per_leaf = L.geom.cpl * ppc;
         c.slots_last = L.geom.cpl_last * ppc;
@@ -350,19 +353,35 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
             r.nentries = ncol * s;
             r.out = L.part2;
             r.status = h->status();
-            const int pm = h->begin(cls0 + 1);
+            r.cond = cond ? 1 : 0;
+            const int pm = h->begin(cls);
             e = launch_reduce(r, st);
             h->end(pm);
             if (e != hipSuccess) return ORTH_ERR_HIP;
             c.partials = L.part2;
             c.slots_per_leaf = c.slots_last = (int32_t)ceil_div(r.nslots, kReduceGroup);
         }
-        const int pm = h->begin(cls0 + 1);
+        const int pm = h->begin(cls);
         e = launch_chol(s, c, st);
         h->end(pm);
         return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
     };
-    if (int rc = chol(1, gram_row_groups(ncol))) return rc;
+    // the mixed form's first sweep reads the FP32 copy: a failed pivot there
+    // flags the step instead of breaking down
+    if (int rc = chol(1, gram_row_groups(ncol), cls0 + 1, L.Qhi != nullptr, false)) return rc;
+    if (L.Qhi) {
+        // the fallback: redo the first sweep from the FP64 basis when flagged
+        // (these launches return at once otherwise); a failure now is a breakdown
+        GramArgs gf = ga;
+        gf.Qhi = nullptr;
+        gf.cond = 1;
+        gf.clear_retry = 0;
+        const int pm = h->begin(ORTH_K_LEAF_FALLBACK);
+        e = launch_gram(s, gf, ORTH_K_LEAF_FALLBACK, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        if (int rc = chol(1, gram_row_groups(ncol), ORTH_K_LEAF_FALLBACK, false, true)) return rc;
+    }
 
     // correction u1 = (x - q P1) N1^{-1}, stored to the level's U1 scratch
     FinalizeArgs f{};
@@ -396,7 +415,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
-    return chol(2, gram_row_groups(ncol));
+    return chol(2, gram_row_groups(ncol), cls0 + 1, false, false);
 }
 
 }  // namespace
@@ -567,6 +586,18 @@ int orth_status(orth_t *h, int32_t *status, int32_t *info) {
         info[2] = ds.sweep;
         info[3] = ds.column;
     }
+    return ORTH_OK;
+}
+
+int orth_mixed_fallbacks(orth_t *h, int64_t *count) {
+    if (!h || !count) return ORTH_ERR_ARG;
+    DevStatus ds{};
+    if (hipStreamSynchronize(h->stream) != hipSuccess ||
+        hipMemcpy(&ds, h->status(), sizeof(ds), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    *count = ds.fallbacks;
     return ORTH_OK;
 }
 

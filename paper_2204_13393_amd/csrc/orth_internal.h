@@ -125,7 +125,9 @@ struct DevStatus {
     int32_t sweep;       // CholeskyQR sweep 1 or 2
     int32_t column;      // pivot column
     int32_t instance;    // batch instance (-1 for a single handle)
-    int32_t pad[2];
+    int32_t retry;       // mixed form: a first-sweep leaf pivot failed on the FP32
+                         // copy in this step; the sweep is redone from the FP64 basis
+    int32_t fallbacks;   // mixed form: steps that took that fallback
 };
 
 // Per-leaf small-matrix record, in doubles:
@@ -156,7 +158,9 @@ struct GramArgs {
     LevelGeom geom;
     double *partials;     // slot (chunk * row_groups + rg): [k + s][s]
     int64_t part_stride;  // doubles per slot
-    const DevStatus *status;
+    DevStatus *status;
+    int32_t cond;         // 1: run only when status->retry is set (the mixed form's fallback)
+    int32_t clear_retry;  // 1: the first thread clears status->retry (the step's first Gram)
 };
 
 // fixed-order pre-reduction of many partial slots of one leaf:
@@ -169,6 +173,7 @@ struct ReduceArgs {
     int32_t nentries;
     double *out;
     const DevStatus *status;
+    int32_t cond;         // 1: run only when status->retry is set
 };
 
 // per-leaf Cholesky of one sweep (and the combination after sweep 2)
@@ -200,6 +205,8 @@ struct CholArgs {
     // the per-leaf coefficient record [c][2s] (nullptr: not needed)
     double *pc;
     int64_t pc_stride;        // doubles per leaf record
+    int32_t soft;             // 1: a failed pivot sets status->retry instead of the breakdown
+    int32_t cond;             // 1: run only when status->retry is set
 };
 
 // row update: sweep 1: u1 = (x - q P1) N1^{-1} (U1 = x in, Qnew = u1 out);

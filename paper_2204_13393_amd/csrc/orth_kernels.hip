@@ -127,7 +127,7 @@ __host__ __device__ constexpr int gram_rpl() { return 8; }
 // Those entries are taken as zeros without being read.
 template <int S, bool TZ = false>
 __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
-    if (failed(a.status)) return;
+    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
     constexpr int NT = (S + 15) / 16;
     constexpr int RPL = gram_rpl<S>();
     constexpr int MS = 4 * RPL;                 // rows per macro-step
@@ -253,6 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
 // the FP64 kernel.
 template <int S>
 __device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) {
+    if (a.clear_retry && bx == 0 && by == 0 && threadIdx.x == 0) a.status->retry = 0;
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
     constexpr int RPL = S >= 16 ? 8 : 16;
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_hi(GramArgs a) {
 // ---------------------------------------------------------------- reduce
 // Fixed-order pre-sum of groups of partial slots (one thread per entry).
 __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int bx, int by) {
-    if (failed(a.status)) return;
+    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
     const int e = bx * kThreads + threadIdx.x;
     if (e >= a.nentries) return;
     const int grp = by;
@@ -380,6 +381,23 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) { reduce_body
 // back substitution, and after the final sweep combine the sweeps and write
 // [P; N] to the next level (or H and R at the root).
 constexpr int kCholCB = 64;   // P rows per LDS chunk
+
+// A failed pivot: the first failure wins the status record (the breakdown),
+// or, for the mixed form's first sweep on the FP32 copy (soft), the step is
+// flagged for the FP64 redo of that sweep instead.
+__device__ __forceinline__ void chol_fail(const CholArgs &a, int leaf, int column) {
+    if (a.soft) {
+        a.status->retry = 1;
+        return;
+    }
+    if (atomicCAS(&a.status->code, 0, 3) == 0) {
+        a.status->level = a.level;
+        a.status->leaf = leaf;
+        a.status->sweep = a.sweep;
+        a.status->column = column;
+        a.status->instance = a.instance;
+    }
+}
 
 // blocks of 16 and more columns: the wide form below
 __host__ __device__ constexpr size_t chol_lds_bytes_s(int s) {
@@ -406,7 +424,7 @@ template <int S>
 __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
     static_assert(S == 16 || S == 32, "wide blocks only");
     constexpr int NT = S / 16;
-    if (failed(a.status)) return;
+    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
     extern __shared__ double lds[];
     double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
     double *part = n1 + S * S;                                // 4 x S x S partial sums of P^T P
@@ -505,15 +523,10 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
     }
     __syncthreads();
     if (bad) {
-        if (tid == 0 && atomicCAS(&a.status->code, 0, 3) == 0) {
-            a.status->level = a.level;
-            a.status->leaf = leaf;
-            a.status->sweep = a.sweep;
-            a.status->column = bad - 1;
-            a.status->instance = a.instance;
-        }
+        if (tid == 0) chol_fail(a, leaf, bad - 1);
         return;
     }
+    if (a.cond && leaf == 0 && tid == 0) a.status->fallbacks += 1;
     if (wave == 0 && lane < S) {
         // back substitution N x = e_j, x[l] = 0 past j; the rows of N are read
         // by every lane at once (LDS broadcast)
@@ -580,7 +593,7 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
 
 template <int S>
 __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
-    if (failed(a.status)) return;
+    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
     constexpr int EPT = (S * S + kThreads - 1) / kThreads;   // S x S entries per thread
     extern __shared__ double lds[];
     double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
@@ -660,15 +673,10 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
         __syncthreads();
     }
     if (bad) {
-        if (tid == 0 && atomicCAS(&a.status->code, 0, 3) == 0) {
-            a.status->level = a.level;
-            a.status->leaf = leaf;
-            a.status->sweep = a.sweep;
-            a.status->column = bad - 1;
-            a.status->instance = a.instance;
-        }
+        if (tid == 0) chol_fail(a, leaf, bad - 1);
         return;
     }
+    if (a.cond && leaf == 0 && tid == 0) a.status->fallbacks += 1;
     // 4. N^{-1}, lane j owns column j
     if (tid < S) {
         const int j = tid;
@@ -1603,6 +1611,7 @@ static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
         case 0: hipLaunchKernelGGL((k_gram<S, 0>), grid, dim3(kThreads), 0, st, a); break;
         case 3: hipLaunchKernelGGL((k_gram<S, 3>), grid, dim3(kThreads), 0, st, a); break;
         case 9: hipLaunchKernelGGL((k_gram<S, 9>), grid, dim3(kThreads), 0, st, a); break;
+        case 11: hipLaunchKernelGGL((k_gram<S, 11>), grid, dim3(kThreads), 0, st, a); break;
         default: hipLaunchKernelGGL((k_gram<S, 10>), grid, dim3(kThreads), 0, st, a); break;
     }
     return hipGetLastError();

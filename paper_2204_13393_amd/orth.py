@@ -39,6 +39,7 @@ SIGNATURES = [
     ("orth_create", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
+    ("orth_mixed_fallbacks", ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
     ("orth_step", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64]),
     ("orth_apply_Q", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
     ("orth_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -119,6 +120,12 @@ def orth_set_level_variants(h, leaf_variant, reduction_variant):
     return load().orth_set_level_variants(h, leaf_variant, reduction_variant)
 
 
+def orth_mixed_fallbacks(h):
+    n = _i64(0)
+    code = load().orth_mixed_fallbacks(h, ctypes.byref(n))
+    return code, n.value
+
+
 def orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu):
     return load().orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu)
 
@@ -152,7 +159,7 @@ def orth_export_local(h, d_Qloc, ldq, d_T, ldt):
 
 KERNEL_CLASSES = ["leaf_gram", "leaf_chol", "leaf_correct", "root_gram", "root_chol",
                   "root_correct", "root_finalize", "leaf_finalize", "apply", "leaf_gram2",
-                  "root_gram2"]
+                  "root_gram2", "leaf_fallback"]
 
 
 def orth_profile_enable(h, on):

@@ -37,7 +37,7 @@ import re
 import sys
 from collections import defaultdict
 
-GRAM = {0: "leaf_gram", 3: "root_gram", 9: "leaf_gram2", 10: "root_gram2"}
+GRAM = {0: "leaf_gram", 3: "root_gram", 9: "leaf_gram2", 10: "root_gram2", 11: "leaf_fallback"}
 ROWUPD = {2: "leaf_correct", 5: "root_correct", 6: "root_finalize", 7: "leaf_finalize"}
 
 

@@ -94,6 +94,7 @@ def test_null_handle_calls():
     assert orth.orth_apply_Q(None, 0, 1, 1, 0, 1) == orth.ORTH_ERR_ARG
     assert orth.orth_set_variant(None, 0) == orth.ORTH_ERR_ARG
     assert orth.orth_set_level_variants(None, 0, 1) == orth.ORTH_ERR_ARG
+    assert orth.orth_mixed_fallbacks(None)[0] == orth.ORTH_ERR_ARG
     assert orth.orth_destroy(None) == orth.ORTH_OK
     assert orth.orth_laplacian_apply(0, 1, 0, 1, 1, 1, 1, 1, 0.0, None) == orth.ORTH_ERR_ARG
     assert orth.orth_probe_copy(0, 0, 1, None) == orth.ORTH_ERR_ARG
