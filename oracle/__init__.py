@@ -15,8 +15,11 @@ pqr          The PQR problem, eq. (1.1): the unique reference solution
              (block CGS twice with Householder inner QR), BCGS-PIP and
              BCGS-PIP+ (Sec. 3, Sec. 3.1) and a breakdown-detecting
              Cholesky.
+hhpqr        The Householder method for the PQR problem (Sec. 2.2,
+             Algorithm "HH"), the basis held as unit reflectors.
 tspqr        TreeTSPQR (Sec. 4.1) with the locally orthogonal basis
-             representation, single- and multi-level trees.
+             representation, single- and multi-level trees; BCGS-PIP,
+             BCGS-PIP+ or Householder leaves.
 krylov       Block Arnoldi (Sec. 2, Algorithm "Block Arnoldi") and the
              block-column QR driver (Sec. 2, Algorithm "Block Column-oriented
              QR-factorization").
@@ -33,6 +36,7 @@ itself live in ``tests/test_oracle_*.py``.
 from .householder import householder_qr, house
 from .pqr import (Breakdown, cholesky_upper, triu_solve_right, pqr_reference,
                   bcgs_pip, bcgs_pip_plus, SUBALGORITHMS)
+from .hhpqr import HouseholderBasis, hh_pqr
 from .tspqr import TreeTSPQR, leaf_bounds
 from .krylov import block_arnoldi, block_column_qr
 from . import operators, metrics
@@ -40,6 +44,6 @@ from . import operators, metrics
 __all__ = [
     "householder_qr", "house", "Breakdown", "cholesky_upper",
     "triu_solve_right", "pqr_reference", "bcgs_pip", "bcgs_pip_plus",
-    "SUBALGORITHMS", "TreeTSPQR", "leaf_bounds", "block_arnoldi",
+    "SUBALGORITHMS", "HouseholderBasis", "hh_pqr", "TreeTSPQR", "leaf_bounds", "block_arnoldi",
     "block_column_qr", "operators", "metrics",
 ]

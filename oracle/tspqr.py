@@ -39,6 +39,7 @@ Readings adopted where the paper is silent:
 
 import numpy as np
 
+from .hhpqr import HouseholderBasis
 from .pqr import SUBALGORITHMS
 
 
@@ -69,18 +70,24 @@ class TreeTSPQR:
     local, reduction
                 subalgorithm names from ``oracle.pqr.SUBALGORITHMS``
                 ("pip" = BCGS-PIP, "pip+" = BCGS-PIP+, "ref" = the unique
-                reference solution).
+                reference solution); ``local`` may also be "hh": the
+                Householder method (Sec. 2.2), each leaf basis then held as
+                reflectors (``oracle.hhpqr.HouseholderBasis``).
     fan_in      None for the single-level tree, else the tree fan-in.
     """
 
     def __init__(self, n, s, leaf_rows, local="pip+", reduction="pip+", fan_in=None):
         self.n, self.s = int(n), int(s)
         self.bounds = leaf_bounds(self.n, int(leaf_rows))
-        self.local = SUBALGORITHMS[local]
+        self.householder = local == "hh"
+        self.local = None if self.householder else SUBALGORITHMS[local]
         self.reduction = SUBALGORITHMS[reduction]
         self.k = 0
         p = len(self.bounds)
-        self.leaves = [np.zeros((r1 - r0, 0)) for (r0, r1) in self.bounds]
+        if self.householder:
+            self.leaves = [HouseholderBasis(r1 - r0) for (r0, r1) in self.bounds]
+        else:
+            self.leaves = [np.zeros((r1 - r0, 0)) for (r0, r1) in self.bounds]
         # levels[l] = list of nodes; node = {"children": (c0, c1), "S": [k x k blocks]}
         self.levels = []
         count = p
@@ -109,7 +116,10 @@ class TreeTSPQR:
         Y = []        # per-unit coefficient blocks [P_i; N_i], (k+s) x s
         locals_ = []
         for i, (r0, r1) in enumerate(self.bounds):
-            Pi, Ni, Ui = self.local(self.leaves[i], X[r0:r1])
+            if self.householder:
+                Pi, Ni, Ui = self.leaves[i].pqr(X[r0:r1])     # appends the reflectors
+            else:
+                Pi, Ni, Ui = self.local(self.leaves[i], X[r0:r1])
             locals_.append(Ui)
             Y.append(np.vstack([Pi, Ni]))
         # 2. reduction, level by level; keep each node's new columns
@@ -140,8 +150,9 @@ class TreeTSPQR:
                     bot = np.hstack([np.zeros((s, k)), blk[k:]])
                     grown.append(np.vstack([top, bot]))
                 node["S"] = grown
-        for i in range(self.p):
-            self.leaves[i] = np.hstack([self.leaves[i], locals_[i]])
+        if not self.householder:
+            for i in range(self.p):
+                self.leaves[i] = np.hstack([self.leaves[i], locals_[i]])
         self.k = k + s
         U = self.apply_Q(np.vstack([np.zeros((k, s)), np.eye(s)]))
         return P, N, U
@@ -162,6 +173,8 @@ class TreeTSPQR:
                 for Sc in node["S"]:
                     nxt.append(Sc @ Cv)
             coeff = nxt
+        if self.householder:
+            return np.vstack([B.apply(Ci) for B, Ci in zip(self.leaves, coeff)])
         return np.vstack([Qi @ Ci for Qi, Ci in zip(self.leaves, coeff)])
 
     def explicit_Q(self):
