@@ -65,8 +65,8 @@ enum orth_code {
 };
 
 /*
- * Precision form.  Arithmetic is FP64 on the matrix cores in both forms;
- * the bases, tree factors, s x s Cholesky factors and H, R, U are FP64.
+ * Storage form of the leaf bases.  Arithmetic is FP64 in every form; the
+ * bases, tree factors, s x s factors and H, R, U are FP64.
  *   ORTH_FP64           every pass reads the FP64 leaf bases.
  *   ORTH_MIXED_SPLIT32  the leaf bases are also kept as an FP32 copy
  *                       (rounded to nearest), and the first CholeskyQR
@@ -89,10 +89,32 @@ enum orth_code {
  *                       orth_mixed_fallbacks), so the mixed form breaks
  *                       down only where the FP64 form does.  Single handles
  *                       only: orth_batch_create returns UNSUPPORTED.
+ *   ORTH_FP64_HOUSEHOLDER  the leaves run the Householder method (Sec. 2.2,
+ *                       Algorithm "HH") instead of BCGS-PIP+: each leaf basis
+ *                       is held as unit reflectors (column c zero above leaf
+ *                       row c) with its compact-WY factor T_i (k_max x k_max
+ *                       per leaf in the workspace).  A step forms Q_k^T w
+ *                       (Gram, T^T M, row update), factors w~[k:] by
+ *                       Householder in one workgroup per leaf, grows T from
+ *                       [V v_new]^T v_new, and assembles U = Q_{k+s}[C; 0]
+ *                       with a row update; the reduction level stays
+ *                       BCGS-PIP+ (the paper's proposed combination, Sec.
+ *                       5.2).  The leaves never break down, so a leaf whose
+ *                       local block is nearly dependent is fine; the
+ *                       reduction still needs u kappa^2 <= 1/2 for the
+ *                       global block.  Results equal the FP64 form's to
+ *                       rounding where both succeed.  Limits (else
+ *                       UNSUPPORTED): s <= 16, every leaf at most 8192 rows
+ *                       for s <= 4, 4096 for s = 8, 1024 for s = 16 (the
+ *                       panel is held in registers), and k_max s <= 4096.
+ *                       orth_apply_Q returns UNSUPPORTED; orth_export_local
+ *                       exports the reflectors as d_Qloc.  Single handles
+ *                       only.
  */
 enum orth_precision {
     ORTH_FP64 = 0,
-    ORTH_MIXED_SPLIT32 = 1
+    ORTH_MIXED_SPLIT32 = 1,
+    ORTH_FP64_HOUSEHOLDER = 2
 };
 
 /* Variant of the leaf and reduction subalgorithm (Sec. 3, Sec. 3.1). */
@@ -176,7 +198,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw,
  * for the explicit basis (C = I).
  *   d_C, ldc   k x m, ldc >= k;  m >= 1
  *   d_Y, ldy   n x m output, ldy >= n; must not overlap the workspace or C.
- * Errors: ARG (also for k = 0), POISONED, HIP.
+ * Errors: ARG (also for k = 0), POISONED, HIP; UNSUPPORTED for
+ * ORTH_FP64_HOUSEHOLDER handles.
  */
 int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
                  double *d_Y, int64_t ldy);
@@ -210,7 +233,8 @@ int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows);
  * inspection and tests (Sec. 4.1): the stacked local bases
  * blockdiag(Q_1..Q_p) flattened to an n x k matrix (leaf i's rows hold Q_i)
  * into d_Qloc (ldq >= n), and the tree factors T_i (k x k, upper
- * triangular) stacked into a (p*k) x k matrix d_T (ldt >= p*k).
+ * triangular) stacked into a (p*k) x k matrix d_T (ldt >= p*k).  For an
+ * ORTH_FP64_HOUSEHOLDER handle d_Qloc receives the leaf reflectors.
  * Either destination may be NULL.  Enqueued on the handle's stream.
  * Errors: ARG, POISONED, HIP.
  */
@@ -231,7 +255,9 @@ enum orth_kernel_class {
     ORTH_K_LEAF_GRAM2 = 9,     /* leaves, sweep-2 Gram [Q_i U1_i]^T U1_i        */
     ORTH_K_ROOT_GRAM2 = 10,    /* reduction level, sweep-2 Gram                 */
     ORTH_K_LEAF_FALLBACK = 11, /* mixed form: FP64 redo of the first sweep      */
-    ORTH_K_COUNT = 12
+    ORTH_K_LEAF_HH_PANEL = 12, /* Householder leaves: panel factorisation       */
+    ORTH_K_LEAF_HH_SMALL = 13, /* Householder leaves: per-leaf T, Z, E C work   */
+    ORTH_K_COUNT = 14
 };
 
 /*

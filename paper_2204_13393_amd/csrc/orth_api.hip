@@ -54,11 +54,12 @@ int32_t max_cols(int32_t) { return 2048; }
 struct Plan {
     int64_t n;
     int32_t s, kmax, leaf_rows, p;
-    int32_t precision;           // ORTH_FP64, or ORTH_MIXED_SPLIT32 (adds the FP32 copy of the leaf bases)
+    int32_t precision;           // ORTH_FP64, ORTH_MIXED_SPLIT32 (adds the FP32 copy of the leaf
+                                 // bases) or ORTH_FP64_HOUSEHOLDER (reflector leaves)
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, total;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -72,11 +73,23 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
                int *why) {
     *why = ORTH_ERR_ARG;
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
-    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32) return false;
+    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32 && precision != ORTH_FP64_HOUSEHOLDER)
+        return false;
     if (kmax + s > max_cols(s)) { *why = ORTH_ERR_UNSUPPORTED; return false; }
     if (leaf_rows == 0) leaf_rows = default_leaf_rows(n, kmax);
     if (leaf_rows < kmax || leaf_rows > n) return false;
     if (n > ((int64_t)1 << 40)) return false;
+    if (precision == ORTH_FP64_HOUSEHOLDER) {
+        // the panel kernel holds a whole leaf in registers, the per-leaf
+        // small products stage (k_max) s doubles in LDS
+        const int32_t p = std::max<int32_t>(1, (int32_t)(n / leaf_rows));
+        const int64_t last = n - (int64_t)(p - 1) * leaf_rows;
+        const int64_t rows_max = std::max<int64_t>(last, p > 1 ? leaf_rows : last);
+        if (hh_max_leaf_rows(s) == 0 || rows_max > hh_max_leaf_rows(s) || (int64_t)kmax * s > kHhMaxCoef) {
+            *why = ORTH_ERR_UNSUPPORTED;
+            return false;
+        }
+    }
     pl.n = n;
     pl.s = s;
     pl.kmax = kmax;
@@ -127,6 +140,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oCL = take((int64_t)pl.p * kmax * 2 * s);
     // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
     pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
+    // Householder leaves: compact-WY factor per leaf (k_max x k_max, column-major)
+    pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)pl.p * kmax * kmax) : 0;
     pl.total = off;
     return true;
 }
@@ -196,6 +211,7 @@ struct orth_ctx {
     float *Qhi() const {
         return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
     }
+    double *TH() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oTH : nullptr; }
     double *PR() const { return ws + pl.oPR; }
     double *PR2() const { return ws + pl.oPR2; }
     double *SL() const { return ws + pl.oSL; }
@@ -233,6 +249,9 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     hipError_t e = prepare_kernels(pl.s);
     if (e == hipSuccess) e = launch_fill(h->T(), pl.ldt * (int64_t)pl.kmax, 0.0, h->stream);
     if (e == hipSuccess) e = launch_fill(h->Y(), pl.ldt * (int64_t)pl.s, 0.0, h->stream);
+    // Householder leaves: the compact-WY factors grow into zeros below their diagonal
+    if (e == hipSuccess && h->TH())
+        e = launch_fill(h->TH(), (int64_t)pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
                             (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, h->stream);
@@ -253,6 +272,8 @@ int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_v
     const auto ok = [](int32_t v) { return v == ORTH_PIP_PLUS || v == ORTH_PIP; };
     if (!h || !ok(leaf_variant) || !ok(reduction_variant)) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
+    // Householder leaves run Algorithm HH, which has no one-sweep variant
+    if (h->pl.precision == ORTH_FP64_HOUSEHOLDER && leaf_variant != ORTH_PIP_PLUS) return ORTH_ERR_UNSUPPORTED;
     h->variant = leaf_variant;
     h->variant_red = reduction_variant;
     return ORTH_OK;
@@ -418,6 +439,140 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     return chol(2, gram_row_groups(ncol), cls0 + 1, false, false);
 }
 
+// Householder leaves (Sec. 2.2): w~ = Q_k^T w through the compact-WY form
+// (Gram V^T w, T^T M, row update), the panel factorisation of w~[k:] in one
+// workgroup per leaf ([P_i; N_i] to the reduction level, the s reflectors to
+// the leaf basis), then the growth of T from [V v_new]^T v_new.
+int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
+    hipStream_t st = h->stream;
+    const int64_t pstride = (int64_t)ncol * s;
+    const LevelGeom gg = leaf_geom(pl, kLeafChunk);
+    const int rg = gram_row_groups(ncol);
+    if ((int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
+    hipError_t e;
+    HhArgs ha{};
+    ha.geom = gg;
+    ha.k = k;
+    ha.kmax = kmax;
+    ha.Q = h->Q();
+    ha.ldq = pl.ldq;
+    ha.T = h->TH();
+    ha.partials = h->PL();
+    ha.part_stride = pstride;
+    ha.slots_per_leaf = gg.cpl * rg;
+    ha.slots_last = gg.cpl_last * rg;
+    ha.small = h->SL();
+    ha.small_stride = small_stride(kmax, s);
+    ha.Yout = h->Y();
+    ha.ldy = pl.ldt;
+    ha.yseg = kmax;
+    ha.status = h->status();
+    GramArgs ga{};
+    ga.Q = Operand{h->Q(), pl.ldq};
+    ga.k = k;
+    ga.tile_groups = gram_tile_groups(ncol);
+    ga.geom = gg;
+    ga.partials = h->PL();
+    ga.part_stride = pstride;
+    ga.status = h->status();
+    ha.X = d_W;
+    ha.ldx = ldw;
+    if (k > 0) {
+        ga.X = Operand{d_W, ldw};
+        int pm = h->begin(ORTH_K_LEAF_GRAM);
+        e = launch_gram(s, ga, ORTH_K_LEAF_GRAM, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        pm = h->begin(ORTH_K_LEAF_HH_SMALL);
+        e = launch_hh(s, HH_PREP, ha, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        // w~ = w - V (T^T M) into the leaf scratch
+        FinalizeArgs f{};
+        f.Q = Operand{h->Q(), pl.ldq};
+        f.Qnew = OutOperand{h->U1L(), pl.ldq};
+        f.U1 = Operand{d_W, ldw};
+        f.sweep = 1;
+        f.k = k;
+        f.geom = leaf_geom(pl, kFinalChunk);
+        f.small = h->SL();
+        f.small_stride = small_stride(kmax, s);
+        f.kmax = kmax;
+        f.status = h->status();
+        pm = h->begin(ORTH_K_LEAF_CORRECT);
+        e = launch_finalize(s, f, ORTH_K_LEAF_CORRECT, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        ha.X = h->U1L();
+        ha.ldx = pl.ldq;
+    }
+    int pm = h->begin(ORTH_K_LEAF_HH_PANEL);
+    e = launch_hh(s, HH_PANEL, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    // [V v_new]^T v_new, then T grows
+    ga.X = Operand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
+    pm = h->begin(ORTH_K_LEAF_GRAM2);
+    e = launch_gram(s, ga, ORTH_K_LEAF_GRAM2, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    pm = h->begin(ORTH_K_LEAF_HH_SMALL);
+    e = launch_hh(s, HH_TUPD, ha, st);
+    h->end(pm);
+    return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
+}
+
+// Householder leaves, explicit output: U|_i = Q_{k+s} [C_i; 0] =
+// -V (T V[0:k+s]^T C_i) + E C_i
+int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, kmax = pl.kmax;
+    hipStream_t st = h->stream;
+    HhArgs ha{};
+    ha.geom = leaf_geom(pl, kFinalChunk);
+    ha.k = k;
+    ha.kmax = kmax;
+    ha.Q = h->Q();
+    ha.ldq = pl.ldq;
+    ha.T = h->TH();
+    ha.crec = h->CL();
+    ha.cseg = (int64_t)kmax * 2 * s;
+    ha.U = d_U;
+    ha.ldu = ldu;
+    ha.status = h->status();
+    int pm = h->begin(ORTH_K_LEAF_HH_SMALL);
+    hipError_t e = launch_hh(s, HH_COEF, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    // row update with the reflectors as basis (k + s columns: V, then v_new as
+    // the "u1" block copied to the scratch unchanged) and -Z as coefficients
+    FinalizeArgs f{};
+    f.Q = Operand{h->Q(), pl.ldq};
+    f.Qnew = OutOperand{h->U1L(), pl.ldq};
+    f.U1 = Operand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
+    f.sweep = 2;
+    f.k = k;
+    f.geom = leaf_geom(pl, kFinalChunk);
+    f.small = h->SL();
+    f.small_stride = small_stride(kmax, s);
+    f.kmax = kmax;
+    f.single_sweep = 1;
+    f.Cptr = h->CL();
+    f.cseg = (int64_t)kmax * 2 * s;
+    f.Uout = OutOperand{d_U, ldu};
+    f.status = h->status();
+    pm = h->begin(ORTH_K_LEAF_FINALIZE);
+    e = launch_finalize(s, f, ORTH_K_LEAF_FINALIZE, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    pm = h->begin(ORTH_K_LEAF_HH_SMALL);
+    e = launch_hh(s, HH_ADDEC, ha, st);
+    h->end(pm);
+    return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -439,7 +594,9 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     int rc;
 
     // ---- leaves: local PQR [Q_i W_i] = [Q_i U_i][[I, P_i], [0, N_i]]
-    {
+    if (pl.precision == ORTH_FP64_HOUSEHOLDER) {
+        if ((rc = run_leaves_hh(h, d_W, ldw, k))) goto fail;
+    } else {
         LevelRun L{};
         L.Q = Operand{h->Q(), pl.ldq};
         L.X = Operand{d_W, ldw};
@@ -502,7 +659,9 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         if (e != hipSuccess) { rc = ORTH_ERR_HIP; goto fail; }
     }
     // ---- leaves: U_i appended to Q_i, explicit U|_i = [Q_i U_i] [P~_i; N~_i]
-    {
+    if (pl.precision == ORTH_FP64_HOUSEHOLDER) {
+        if ((rc = finalize_leaves_hh(h, d_U, ldu, k))) goto fail;
+    } else {
         FinalizeArgs f{};
         f.Q = Operand{h->Q(), pl.ldq};
         f.Qnew = OutOperand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
@@ -537,6 +696,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
     const Plan &pl = h->pl;
     const int32_t k = h->k;
     if (k < 1 || m < 1 || !d_C || !d_Y || ldc < k || ldy < pl.n) return ORTH_ERR_ARG;
+    if (pl.precision == ORTH_FP64_HOUSEHOLDER) return ORTH_ERR_UNSUPPORTED;
     hipStream_t st = h->stream;
     for (int32_t j0 = 0; j0 < m; j0 += kApplyMB) {
         const int32_t mb = (m - j0) < kApplyMB ? (m - j0) : kApplyMB;

@@ -1,0 +1,367 @@
+// Householder leaves (Sec. 2.2, Algorithm "HH"; the node-level method of the
+// paper's proposed design, Sec. 5.2): every leaf basis is held as unit
+// reflectors V_i (n_i x k, column c zero above leaf row c) with the
+// compact-WY factor T_i (k x k upper triangular, Q = I - V T V^T for the
+// product H_0 ... H_{k-1}, H_c = I - 2 v_c v_c^T).  A step on leaf i:
+//
+//   M = V^T w                       leaf Gram kernel (basis V)
+//   Y = T^T M                       k_hh_prep        (this file)
+//   w~ = w - V Y = Q_k^T w          row-update kernel (coefficients Y, identity)
+//   P = w~[0:k]; Householder QR of w~[k:] -> s reflectors, N (s x s)
+//                                   k_hh_panel       (this file)
+//   [V v_new]^T v_new               leaf Gram kernel (block v_new)
+//   T grows: T[0:k, k:k+s] = -T W T_s, T_s from v_new^T v_new
+//                                   k_hh_tupd        (this file)
+//   ... reduction level (BCGS-PIP+, unchanged) gives C_i ((k+s) x s) ...
+//   Z = T (V[0:k+s]^T C_i)          k_hh_coef        (this file)
+//   U|_i = -V Z                     row-update kernel (coefficients -Z)
+//   U|_i[0:k+s] += C_i              k_hh_addec       (this file)
+//
+// The explicit block U|_i = Q_{k+s} [C_i; 0] = (I - V T V^T) [C_i; 0].  Every
+// kernel here runs one workgroup per leaf and sums partial Gram slots in slot
+// order, so results are bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "orth_internal.h"
+
+namespace orth {
+namespace {
+
+__device__ __forceinline__ bool hh_failed(const DevStatus *st) { return st->code != 0; }
+
+// sum over the 64 lanes of a wave (every lane gets the same value: the
+// butterfly adds the same two operands on both partners)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------ T^T M
+// Y = T_k^T M, M = V^T w from the leaf's partial slots (rows 0..k-1 of each
+// [k+s][s] slot); Y goes to the leaf record's first-sweep projection and the
+// record's first-sweep inverse normalizer is set to I, so the row-update
+// kernel's sweep-1 pass computes w - V Y.
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
+    if (hh_failed(a.status)) return;
+    extern __shared__ double lds[];                 // M, k x S row-major
+    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k;
+    const int first = leaf * a.slots_per_leaf;
+    const int cnt = leaf == a.geom.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
+    for (int e = tid; e < k * S; e += kThreads) {
+        double v = 0.0;
+        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        lds[e] = v;
+    }
+    __syncthreads();
+    const double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
+    double *rec = a.small + (int64_t)leaf * a.small_stride;
+    for (int e = tid; e < k * S; e += kThreads) {
+        const int r = e / S, j = e - (e / S) * S;
+        const double *tc = Tl + (int64_t)r * a.kmax;     // column r of T: T[c][r], c <= r
+        double v = 0.0;
+        for (int c = 0; c <= r; ++c) v = fma(tc[c], lds[c * S + j], v);
+        rec[e] = v;
+    }
+    double *n1i = rec + (int64_t)a.kmax * S + S * S;
+    for (int e = tid; e < S * S; e += kThreads) n1i[e] = (e / S == e % S) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------ panel
+// One workgroup factors leaf i's block w~ (n_i x s) held in registers: rows
+// below k form the projection P, rows k.. the panel, triangularised column by
+// column as in Algorithm "HH" (sign opposite to the pivot entry, sgn 0 = +1;
+// a column that is zero from its pivot down gets the reflector e_pivot and a
+// zero diagonal).  Each column costs one workgroup reduction: the dot
+// products of the column with itself and the later columns over the rows
+// from the pivot down, plus the pivot row's entries.
+constexpr int kHhThreads = 512;
+constexpr int kHhWaves = kHhThreads / 64;
+
+template <int S>
+__host__ __device__ constexpr int hh_rpt() { return S <= 4 ? 16 : (S == 8 ? 8 : 2); }
+
+template <int S>
+__global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
+    if (hh_failed(a.status)) return;
+    constexpr int RPT = hh_rpt<S>();
+    __shared__ double red[2][kHhWaves][S];
+    __shared__ double rowv[2][S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int leaf = blockIdx.x;
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    const int nl = (int)(a.geom.leaf_end(leaf) - r0);
+    const int k = a.k;
+
+    double x[RPT][S];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = tid + kHhThreads * q;
+#pragma unroll
+        for (int c = 0; c < S; ++c) x[q][c] = row < nl ? a.X[(r0 + row) + (int64_t)c * a.ldx] : 0.0;
+    }
+    double *Yl = a.Yout + (int64_t)leaf * a.yseg;   // [P; N] of this leaf, column c at Yl + c ldy
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = tid + kHhThreads * q;
+        if (row < k) {
+#pragma unroll
+            for (int c = 0; c < S; ++c) Yl[row + (int64_t)c * a.ldy] = x[q][c];
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int pj = k + j, b = j & 1;
+        double part[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) part[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhThreads * q;
+            if (row >= pj && row < nl) {
+#pragma unroll
+                for (int c = j; c < S; ++c) part[c] = fma(x[q][j], x[q][c], part[c]);
+            }
+        }
+#pragma unroll
+        for (int c = j; c < S; ++c) part[c] = wave_sum(part[c]);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = j; c < S; ++c) red[b][wave][c] = part[c];
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            if (tid + kHhThreads * q == pj) {
+#pragma unroll
+                for (int c = j; c < S; ++c) rowv[b][c] = x[q][c];
+            }
+        }
+        __syncthreads();
+        double d[S], av[S];
+#pragma unroll
+        for (int c = j; c < S; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kHhWaves; ++w) t += red[b][w][c];
+            d[c] = t;
+            av[c] = rowv[b][c];
+        }
+        const double lam = sqrt(d[j]);
+        const double u0 = av[j];
+        const bool zero = lam == 0.0;
+        // v~ = (rows from the pivot down) - sigma lambda e_pivot, ||v~||^2 =
+        // 2 lambda (lambda + |u0|); a NaN column runs the general branch
+        const double njj = zero ? 0.0 : (u0 >= 0.0 ? -lam : lam);
+        const double v0 = zero ? 1.0 : u0 - njj;
+        const double nv2 = zero ? 1.0 : 2.0 * lam * (lam + fabs(u0));
+        double coef[S];
+#pragma unroll
+        for (int c = j + 1; c < S; ++c) {
+            const double w = zero ? av[c] : d[c] - njj * av[c];   // v~^T (column c)
+            coef[c] = 2.0 * w / nv2;
+        }
+        if (tid == 0) {
+            double *yr = Yl + k + j;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                double v = 0.0;
+                if (c == j) v = njj;
+                else if (c > j) v = av[c] - v0 * coef[c];
+                yr[(int64_t)c * a.ldy] = v;
+            }
+        }
+        const double vn = sqrt(nv2);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhThreads * q;
+            if (row >= pj && row < nl) {
+                const double vi = row == pj ? v0 : x[q][j];
+#pragma unroll
+                for (int c = j + 1; c < S; ++c) x[q][c] = fma(-vi, coef[c], x[q][c]);
+                x[q][j] = vi / vn;
+            }
+        }
+    }
+    // the s reflectors, zero above their pivot rows
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = tid + kHhThreads * q;
+        if (row < nl) {
+#pragma unroll
+            for (int c = 0; c < S; ++c)
+                a.Q[(r0 + row) + (int64_t)(k + c) * a.ldq] = row >= k + c ? x[q][c] : 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------ T update
+// From the slots of [V v_new]^T v_new: W = V^T v_new (k x s) and
+// G = v_new^T v_new.  T_s (s x s, upper): diagonal 2, column j above the
+// diagonal -2 T_s[0:j, 0:j] G[0:j, j]; then T[0:k, k:k+s] = -T (W T_s).
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
+    if (hh_failed(a.status)) return;
+    extern __shared__ double lds[];
+    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k, K = k + S;
+    double *W = lds;                    // K x S row-major: W (rows < k), G (rows k..)
+    double *Ts = W + K * S;             // S x S row-major
+    const int first = leaf * a.slots_per_leaf;
+    const int cnt = leaf == a.geom.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
+    for (int e = tid; e < K * S; e += kThreads) {
+        double v = 0.0;
+        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        W[e] = v;
+    }
+    for (int e = tid; e < S * S; e += kThreads) Ts[e] = (e / S == e % S) ? 2.0 : 0.0;
+    __syncthreads();
+    const double *G = W + k * S;
+    for (int j = 1; j < S; ++j) {
+        if (tid < j) {
+            const int i = tid;
+            double v = 0.0;
+            for (int l = i; l < j; ++l) v = fma(Ts[i * S + l], G[l * S + j], v);
+            Ts[i * S + j] = -2.0 * v;
+        }
+        __syncthreads();
+    }
+    // B = W T_s, in place row by row (a row belongs to one thread)
+    for (int r = tid; r < k; r += kThreads) {
+        double bv[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int l = 0; l <= j; ++l) v = fma(W[r * S + l], Ts[l * S + j], v);
+            bv[j] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) W[r * S + j] = bv[j];
+    }
+    __syncthreads();
+    double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
+    for (int e = tid; e < k * S; e += kThreads) {
+        const int j = e / k, r = e - (e / k) * k;
+        double v = 0.0;
+        for (int c = r; c < k; ++c) v = fma(Tl[(int64_t)c * a.kmax + r], W[c * S + j], v);
+        Tl[(int64_t)(k + j) * a.kmax + r] = -v;
+    }
+    for (int e = tid; e < S * S; e += kThreads) {
+        const int j = e / S, i = e - (e / S) * S;
+        Tl[(int64_t)(k + j) * a.kmax + k + i] = i <= j ? Ts[i * S + j] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------ coefficients
+// C_i (the leaf's (k+s) x s block from the reduction, right half of its
+// record) -> Z = T (V[0:k+s]^T C_i); the record's right half becomes -Z (the
+// row-update kernel then forms -V Z) and its left half keeps C_i for the
+// final E C_i term.
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
+    if (hh_failed(a.status)) return;
+    extern __shared__ double lds[];
+    const int leaf = blockIdx.x, tid = threadIdx.x, K = a.k + S;
+    double *C = lds, *B = lds + K * S;             // K x S row-major each
+    double *rec = a.crec + (int64_t)leaf * a.cseg;  // row c: [left S | right S]
+    for (int e = tid; e < K * S; e += kThreads) {
+        const int r = e / S, j = e - (e / S) * S;
+        const double v = rec[(int64_t)r * 2 * S + S + j];
+        C[e] = v;
+        rec[(int64_t)r * 2 * S + j] = v;
+    }
+    __syncthreads();
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    for (int e = tid; e < K * S; e += kThreads) {
+        const int c = e / S, j = e - (e / S) * S;
+        const double *vc = a.Q + r0 + (int64_t)c * a.ldq;   // reflector c, leaf rows
+        double v = 0.0;
+        for (int r = c; r < K; ++r) v = fma(vc[r], C[r * S + j], v);
+        B[e] = v;
+    }
+    __syncthreads();
+    const double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
+    for (int e = tid; e < K * S; e += kThreads) {
+        const int j = e / K, r = e - (e / K) * K;
+        double v = 0.0;
+        for (int c = r; c < K; ++c) v = fma(Tl[(int64_t)c * a.kmax + r], B[c * S + j], v);
+        rec[(int64_t)r * 2 * S + S + j] = -v;
+    }
+}
+
+// U|_i[0:k+s] += C_i (left half of the leaf's record)
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_addec(HhArgs a) {
+    if (hh_failed(a.status)) return;
+    const int leaf = blockIdx.x, tid = threadIdx.x, K = a.k + S;
+    const double *rec = a.crec + (int64_t)leaf * a.cseg;
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    for (int e = tid; e < K * S; e += kThreads) {
+        const int r = e / S, j = e - (e / S) * S;
+        a.U[(r0 + r) + (int64_t)j * a.ldu] += rec[(int64_t)r * 2 * S + j];
+    }
+}
+
+template <int S>
+hipError_t hh_launch(HhKernel which, const HhArgs &a, hipStream_t st) {
+    const int nleaf = a.geom.nleaf;
+    const int K = a.k + S;
+    switch (which) {
+        case HH_PREP:
+            if (a.k < 1) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_hh_prep<S>), dim3(nleaf), dim3(kThreads), (size_t)a.k * S * 8, st, a);
+            break;
+        case HH_PANEL:
+            hipLaunchKernelGGL((k_hh_panel<S>), dim3(nleaf), dim3(kHhThreads), 0, st, a);
+            break;
+        case HH_TUPD:
+            hipLaunchKernelGGL((k_hh_tupd<S>), dim3(nleaf), dim3(kThreads), (size_t)(K * S + S * S) * 8, st, a);
+            break;
+        case HH_COEF:
+            hipLaunchKernelGGL((k_hh_coef<S>), dim3(nleaf), dim3(kThreads), (size_t)2 * K * S * 8, st, a);
+            break;
+        case HH_ADDEC:
+            hipLaunchKernelGGL((k_hh_addec<S>), dim3(nleaf), dim3(kThreads), 0, st, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t hh_max_leaf_rows(int s) {
+    switch (s) {
+        case 1: return (int64_t)kHhThreads * hh_rpt<1>();
+        case 2: return (int64_t)kHhThreads * hh_rpt<2>();
+        case 4: return (int64_t)kHhThreads * hh_rpt<4>();
+        case 8: return (int64_t)kHhThreads * hh_rpt<8>();
+        case 16: return (int64_t)kHhThreads * hh_rpt<16>();
+    }
+    return 0;
+}
+
+hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st) {
+    // host checks of the launch against what the kernels assume
+    if (a.geom.nleaf < 1 || a.k < 0 || (int64_t)(a.k + s) * s > kHhMaxCoef) return hipErrorInvalidValue;
+    if (which == HH_PANEL) {
+        const int64_t last = a.geom.leaf_end(a.geom.nleaf - 1) - a.geom.leaf_begin(a.geom.nleaf - 1);
+        const int64_t full = a.geom.nleaf > 1 ? a.geom.leaf_rows : last;
+        if (std::max(last, full) > hh_max_leaf_rows(s) || std::min(last, full) < a.k + s) return hipErrorInvalidValue;
+    }
+    switch (s) {
+        case 1: return hh_launch<1>(which, a, st);
+        case 2: return hh_launch<2>(which, a, st);
+        case 4: return hh_launch<4>(which, a, st);
+        case 8: return hh_launch<8>(which, a, st);
+        case 16: return hh_launch<16>(which, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace orth

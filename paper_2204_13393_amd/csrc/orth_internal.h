@@ -251,6 +251,38 @@ struct ApplyArgs {
     OutOperand Y;         // under geom.map
 };
 
+// ---- Householder leaves (orth_hh.hip) ----
+// leaf bases as unit reflectors V_i with compact-WY factors T_i (k_max x
+// k_max, column-major, leaf i at T + i k_max^2); see orth_hh.hip for the step
+struct HhArgs {
+    LevelGeom geom;           // leaf geometry (identity rows)
+    int32_t k, kmax;
+    double *Q;                // reflectors (the stored leaf bases)
+    int64_t ldq;
+    double *T;
+    // partial Gram slots of the leaf Gram kernel ([k+s][s] each)
+    const double *partials;
+    int64_t part_stride;
+    int32_t slots_per_leaf, slots_last;
+    double *small;            // per-leaf records (sweep-1 projection and inverse normalizer)
+    int64_t small_stride;
+    const double *X;          // panel input: Q_k^T w (or w at k = 0)
+    int64_t ldx;
+    double *Yout;             // next level's X: leaf i's [P_i; N_i] at rows i*yseg
+    int64_t ldy, yseg;
+    double *crec;             // per-leaf [left | right] records, row-major (k+s) x 2s
+    int64_t cseg;
+    double *U;                // explicit output (E C term)
+    int64_t ldu;
+    const DevStatus *status;
+};
+enum HhKernel { HH_PREP = 0, HH_PANEL, HH_TUPD, HH_COEF, HH_ADDEC };
+// (k + s) s bound of the per-leaf small products (their LDS staging)
+constexpr int64_t kHhMaxCoef = 4096;
+// largest leaf the panel kernel holds in registers for block width s (0: unsupported s)
+int64_t hh_max_leaf_rows(int s);
+hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st);
+
 // ---- batched form: many independent instances, one grouped launch per phase ----
 // Per-instance descriptor (device memory); regions carved like a single handle.
 struct BatchInst {

@@ -26,6 +26,7 @@ ORTH_ERR_WORKSPACE = 6
 ORTH_ERR_UNSUPPORTED = 7
 ORTH_FP64 = 0
 ORTH_MIXED_SPLIT32 = 1
+ORTH_FP64_HOUSEHOLDER = 2
 ORTH_PIP_PLUS = 0
 ORTH_PIP = 1
 
@@ -159,7 +160,7 @@ def orth_export_local(h, d_Qloc, ldq, d_T, ldt):
 
 KERNEL_CLASSES = ["leaf_gram", "leaf_chol", "leaf_correct", "root_gram", "root_chol",
                   "root_correct", "root_finalize", "leaf_finalize", "apply", "leaf_gram2",
-                  "root_gram2", "leaf_fallback"]
+                  "root_gram2", "leaf_fallback", "leaf_hh_panel", "leaf_hh_small"]
 
 
 def orth_profile_enable(h, on):

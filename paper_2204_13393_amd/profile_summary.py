@@ -50,6 +50,10 @@ def classify(name):
     m = re.search(r"k_row(?:mfma|lds)<(\d+), (?:true|false), (\d+)>", name)
     if m:
         return ROWUPD.get(int(m.group(2)), "rowupdate?")
+    if "k_hh_panel" in name:
+        return "leaf_hh_panel"
+    if re.search(r"k_hh_(?:prep|tupd|coef|addec)", name):
+        return "leaf_hh_small"
     for key, cls in (("k_chol", "chol"), ("k_reduce", "reduce"), ("k_apply", "apply"),
                      ("k_copy(", "copy_probe"), ("k_laplacian", "operator"), ("k_fill", "fill"),
                      ("k_copy_cols", "export")):

@@ -46,11 +46,32 @@ def test_workspace_bytes_arithmetic():
     (1000, 4, 10, 0, 0),     # k_max not a multiple of s
     (1000, 4, 40, 20, 0),    # leaf_rows < k_max
     (1000, 4, 40, 2000, 0),  # leaf_rows > n
-    (1000, 4, 40, 0, 2),     # unknown precision
+    (1000, 4, 40, 0, 3),     # unknown storage form
     (100000, 16, 2048, 0, 0),  # wider than the planner accepts (k_max + s > 2048)
 ])
 def test_workspace_rejects_bad_arguments(args):
     assert orth.orth_workspace_bytes(*args) == 0
+
+
+def test_householder_form_workspace_and_limits():
+    H = orth.ORTH_FP64_HOUSEHOLDER
+    # adds one k_max x k_max compact-WY factor per leaf
+    for (n, s, k, lr) in ((10000, 4, 44, 1000), (2 ** 24, 8, 248, 4096), (777, 1, 12, 100)):
+        f64 = orth.orth_workspace_bytes(n, s, k, lr, 0)
+        hh = orth.orth_workspace_bytes(n, s, k, lr, H)
+        p = max(1, n // lr)
+        assert p * k * k * 8 <= hh - f64 <= p * k * k * 8 + 256
+    # limits: the panel kernel's register capacity and k_max s <= 4096
+    assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 4096, H) > 0
+    assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 8192, H) == 0        # leaf rows > 4096 at s = 8
+    assert orth.orth_workspace_bytes(4096 + 4095, 8, 64, 4096, H) == 0    # the last leaf takes 8191 rows
+    assert orth.orth_workspace_bytes(2 ** 20, 4, 64, 8192, H) > 0
+    assert orth.orth_workspace_bytes(2 ** 20, 16, 64, 1024, H) > 0
+    assert orth.orth_workspace_bytes(2 ** 20, 16, 64, 2048, H) == 0
+    assert orth.orth_workspace_bytes(2 ** 20, 32, 64, 512, H) == 0        # s = 32 not supported
+    assert orth.orth_workspace_bytes(2 ** 20, 8, 1024, 4096, H) == 0      # k_max s > 4096
+    code, h = orth.orth_create(2 ** 20, 8, 64, 8192, H, 4096, 1 << 40, 0)
+    assert code == orth.ORTH_ERR_UNSUPPORTED
 
 
 def test_mixed_form_workspace_adds_the_fp32_copy():

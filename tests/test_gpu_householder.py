@@ -1,0 +1,221 @@
+"""GPU tests of the Householder leaves (ORTH_FP64_HOUSEHOLDER): leaf bases
+held as unit reflectors, Algorithm "HH" (Sec. 2.2) at the leaves, BCGS-PIP+
+at the reduction level.
+
+* parity with the oracle's TreeTSPQR with Householder leaves on the same
+  partition, step by step: H, R, U and the stored reflectors, at the
+  tolerances of test_gpu_parity.py (ragged last leaves, one leaf, the
+  register capacity of the panel kernel, s from 1 to 16);
+* the FP64 (BCGS-PIP+) form gives the same H, R, U where both succeed;
+* a leaf whose local block is nearly dependent on its basis: the BCGS-PIP+
+  leaves break down, the Householder leaves match the unique solution;
+* a globally dependent column and a NaN break down at the reduction level;
+* BCGS-PIP at the reduction; reruns are bitwise identical; calls the form
+  does not offer return UNSUPPORTED.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import TreeTSPQR, metrics, pqr_reference
+from synth import normal_block
+
+from gpu_util import kappa_after_projection, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    return torch
+
+
+CASES = [
+    # n, s, kmax, leaf_rows
+    (1000, 4, 24, 1000),      # one leaf
+    (10000, 4, 44, 1000),     # ten leaves
+    (3001, 8, 48, 700),       # ragged last leaf (901 rows)
+    (777, 1, 12, 100),        # s = 1, ragged (177 rows)
+    (5000, 2, 20, 1000),
+    (6000, 16, 96, 1000),     # s = 16 at its register capacity (1024 rows)
+    (16384, 8, 64, 4096),     # s = 8 at its capacity (4096 rows), 2 chunks per leaf
+    (8192, 4, 40, 8192),      # one leaf of 8192 rows (s = 4 capacity), 4 chunks
+    (5000, 8, 248, 2500),     # the headline basis width (k + s = 256)
+]
+
+
+def _inputs(rng, n, s, Q, step):
+    X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+    if step:
+        X = X + Q @ rng.standard_normal((Q.shape[1], s))
+    return X
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows", CASES)
+def test_householder_parity(torch_cuda, n, s, kmax, leaf_rows):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("householder parity", n, s, kmax, leaf_rows)
+    rng = np.random.default_rng(n * 7 + s)
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    tree = TreeTSPQR(n, s, leaf_rows, "hh", "pip+")
+    Q = np.zeros((n, 0))
+    Ugpu = []
+    kap_max = 1.0
+    for step in range(kmax // s):
+        X = _inputs(rng, n, s, Q, step)
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        H, R, U = to_host(Hd), to_host(Rd), to_host(Ud)
+        P, N, Ur = pqr_reference(Q, X)
+        Pt, Nt, Ut = tree.step(X)
+        kap = kappa_after_projection(N, X)
+        kap_max = max(kap_max, kap)
+        xn = np.linalg.norm(X)
+        if step:
+            assert np.linalg.norm(H - P) / xn <= 1e-12, step
+            assert np.linalg.norm(H - Pt) / xn <= 1e-12, step
+        assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0)
+        assert np.linalg.norm(R - N) / xn <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ut)) <= 1e-12 * kap, step
+        Ugpu.append(U)
+        Q = np.hstack([Q, Ur])
+    st, info = gpu.status()
+    assert st == 0, info
+    assert metrics.e_perp(np.hstack(Ugpu)) <= 1e-12
+    # the stored reflectors against the oracle's, leaf by leaf
+    Vd, T = gpu.export_local()
+    Vg = to_host(Vd)
+    for (r0, r1), B in zip(tree.bounds, tree.leaves):
+        assert np.max(np.abs(Vg[r0:r1] - B.V)) <= 1e-11 * kap_max
+        for c in range(gpu.k):
+            assert np.all(Vg[r0:r0 + c, c] == 0.0)
+    assert metrics.e_perp(to_host(T)) <= 1e-12
+    code = orth.orth_apply_Q(gpu.h, Vd.data_ptr(), gpu.k, 1, Vd.data_ptr(), n)
+    assert code == orth.ORTH_ERR_UNSUPPORTED
+    gpu.close()
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows", [(10000, 4, 44, 1000), (16384, 8, 64, 4096)])
+def test_householder_equals_cholesky_qr_form(torch_cuda, n, s, kmax, leaf_rows):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("householder vs fp64 form", n, s)
+    rng = np.random.default_rng(5)
+    hh = Orthogonalizer(n, s, kmax, leaf_rows, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    cq = Orthogonalizer(n, s, kmax, leaf_rows)
+    Q = np.zeros((n, 0))
+    for step in range(kmax // s):
+        X = _inputs(rng, n, s, Q, step)
+        a = [to_host(t) for t in hh.step(to_dev(X))]
+        b = [to_host(t) for t in cq.step(to_dev(X))]
+        xn = np.linalg.norm(X)
+        for x, y in zip(a[:2], b[:2]):
+            assert np.linalg.norm(x - y) <= 1e-12 * xn
+        assert np.max(np.abs(a[2] - b[2])) <= 1e-11
+        Q = np.hstack([Q, b[2]])
+    assert hh.status()[0] == 0 and cq.status()[0] == 0
+    hh.close()
+    cq.close()
+
+
+def test_householder_leaf_survives_local_dependence(torch_cuda):
+    """Leaf 0's rows of the second block lie in that leaf's basis up to
+    1e-11; the other leaves' rows are random.  The BCGS-PIP+ leaves break
+    down in leaf 0; the Householder leaves give the unique solution."""
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("householder local dependence")
+    n, s, kmax, leaf = 8192, 4, 16, 2048
+    rng = np.random.default_rng(17)
+    X0 = rng.standard_normal((n, s))
+    tree = TreeTSPQR(n, s, leaf, "hh", "pip+")
+    tree.step(X0)
+    Q0 = tree.leaves[0].explicit()           # leaf 0's local basis after the first step
+    X1 = rng.standard_normal((n, s))
+    X1[:leaf] = Q0 @ rng.standard_normal((s, s)) + 1e-11 * rng.standard_normal((leaf, s))
+    U0 = pqr_reference(None, X0)[2]
+    P, N, Ur = pqr_reference(U0, X1)
+
+    cq = Orthogonalizer(n, s, kmax, leaf)
+    cq.step(to_dev(X0))
+    cq.step(to_dev(X1))
+    st, info = cq.status()
+    assert st == orth.ORTH_ERR_BREAKDOWN and info[0] == 0 and info[1] == 0, info
+    cq.close()
+
+    hh = Orthogonalizer(n, s, kmax, leaf, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    U0g = to_host(hh.step(to_dev(X0))[2])
+    H, R, U = (to_host(t) for t in hh.step(to_dev(X1)))
+    st, info = hh.status()
+    assert st == 0, info
+    xn = np.linalg.norm(X1)
+    assert np.linalg.norm(H - P) <= 1e-12 * xn and np.linalg.norm(R - N) <= 1e-12 * xn
+    assert np.max(np.abs(U - Ur)) <= 1e-11
+    assert metrics.e_perp(np.hstack([U0g, U])) <= 1e-12
+    hh.close()
+
+
+def test_householder_breakdown_at_reduction(torch_cuda):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("householder breakdown")
+    n, s = 6000, 8
+    g = Orthogonalizer(n, s, 24, 2000, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    g.step(to_dev(normal_block(n, s, 1)))
+    Y = normal_block(n, s, 2)
+    Y[:, 5] = 0.0
+    g.step(to_dev(Y))
+    st, info = g.status()
+    assert st == orth.ORTH_ERR_BREAKDOWN and info[0] == 1, info
+    assert orth.orth_step(g.h, 0, n, 0, 16, 0, s, 0, n) == orth.ORTH_ERR_POISONED
+    g.close()
+    g = Orthogonalizer(n, s, 24, 2000, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    W = normal_block(n, s, 3)
+    W[4321, 2] = np.nan
+    g.step(to_dev(W))
+    assert g.status()[0] == orth.ORTH_ERR_BREAKDOWN
+    g.close()
+
+
+def test_householder_pip_reduction_and_determinism(torch_cuda):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("householder pip reduction")
+    n, s, kmax, leaf = 5000, 4, 24, 1000
+    rng = np.random.default_rng(23)
+    Xs = []
+    Q = np.zeros((n, 0))
+    for step in range(kmax // s):
+        X = _inputs(rng, n, s, Q, step)
+        Xs.append(X)
+        Q = np.hstack([Q, pqr_reference(Q, X)[2]])
+    runs = []
+    for rep in range(2):
+        g = Orthogonalizer(n, s, kmax, leaf, precision=orth.ORTH_FP64_HOUSEHOLDER,
+                           reduction_variant=orth.ORTH_PIP)
+        assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP, orth.ORTH_PIP) == orth.ORTH_ERR_UNSUPPORTED
+        tree = TreeTSPQR(n, s, leaf, "hh", "pip")
+        out = []
+        for X in Xs:
+            H, R, U = (to_host(t) for t in g.step(to_dev(X)))
+            Pt, Nt, Ut = tree.step(X)
+            xn = np.linalg.norm(X)
+            if H.size:
+                assert np.linalg.norm(H - Pt) <= 1e-12 * xn
+            assert np.linalg.norm(R - Nt) <= 1e-11 * xn
+            assert np.max(np.abs(U - Ut)) <= 1e-10
+            out.append((H, R, U))
+        assert g.status()[0] == 0
+        runs.append(out)
+        g.close()
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
