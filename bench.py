@@ -55,6 +55,8 @@ def kernel_bytes(cls, n, s, p, k):
         return 8.0 * n * (k + s) + 8.0 * n * s        # read Q_i, W_i; write u1
     if cls == "leaf_finalize":
         return 8.0 * n * (k + s) + 16.0 * n * s       # read Q_i, u1; write U_i, U
+    if cls == "leaf_hh_panel":
+        return 16.0 * n * s                           # read w~, write the s reflectors
     tri = k * (k + 1) / 2.0
     if cls in ("root_gram", "root_gram2"):
         return 8.0 * p * (tri + (k + s) * s)
@@ -488,7 +490,7 @@ def bench_kappa_sweep(args):
     sigma_j = kappa^(-j/31), n = 2^16, 32 columns in blocks of s = 4 (eight
     orth_step calls), leaves of 256 rows, for kappa = 10^0 .. 10^12 and the
     four combinations of BCGS-PIP / BCGS-PIP+ at the leaves and at the
-    reduction.  Per case: status (breakdown or not) and e_perp of the
+    reduction, plus Householder leaves (Sec. 2.2) with either reduction.  Per case: status (breakdown or not) and e_perp of the
     explicit basis.  The matrices come from synth.stewart (seed 11)."""
     import numpy as np
     import torch
@@ -496,8 +498,7 @@ def bench_kappa_sweep(args):
     from synth import stewart
     n, m, s, leaf = 1 << 16, 32, 4, 256
     v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
-    combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip")]
-    eye = torch.eye(m, dtype=torch.float64, device="cuda")
+    combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip"), ("hh", "pip+"), ("hh", "pip")]
     rows = []
     print("[bench] kappa sweep: Stewart n = 2^16, 32 columns, s = 4, leaves of 256 rows", file=sys.stderr, flush=True)
     for e in range(13):
@@ -506,15 +507,20 @@ def bench_kappa_sweep(args):
         At = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
         row = {"kappa": kappa}
         for local, red in combos:
-            g = Orthogonalizer(n, s, m, leaf, variant=v[local], reduction_variant=v[red])
+            if local == "hh":
+                g = Orthogonalizer(n, s, m, leaf, precision=orth.ORTH_FP64_HOUSEHOLDER, reduction_variant=v[red])
+            else:
+                g = Orthogonalizer(n, s, m, leaf, variant=v[local], reduction_variant=v[red])
+            blocks = []
             for j in range(m // s):
-                g.step(At[j * s:(j + 1) * s].contiguous())
+                blocks.append(g.step(At[j * s:(j + 1) * s].contiguous())[2].clone())
                 if g.status()[0]:
                     break
             st, info = g.status()
             if st == 0:
-                # e_perp on the host (FP64 BLAS): a 32 x 32 Gram of 2^16 rows
-                Q = g.apply_Q(eye).cpu().numpy()
+                # e_perp on the host (FP64 BLAS): a 32 x 32 Gram of 2^16 rows of
+                # the explicit blocks U the calls returned
+                Q = torch.cat(blocks).cpu().numpy()
                 row[f"{local}/{red}"] = float(np.linalg.norm(Q @ Q.T - np.eye(m), "fro"))
             else:
                 row[f"{local}/{red}"] = {"breakdown": {"level": info[0], "sweep": info[2], "column": info[3]}}
@@ -539,7 +545,8 @@ def bench_stewart(args):
     s = 8 (30 calls), leaf height 4096; sigma log-spaced from 1 to 1e-6 and
     from 1 to 1e-12 (kappa 1e6 and 1e12); V Haar (QR of a Gaussian), G
     Gaussian / sqrt(n), orthonormal to about 2 sqrt(240/n) = 0.008 at this n, so
-    the singular values of W are sigma to within 1%.  FP64 and mixed forms.
+    the singular values of W are sigma to within 1%.  FP64, mixed and
+    Householder-leaf forms.
     Per form and range: status (and the call after which a breakdown was
     reported), the calls in which the mixed form redid its first sweep in
     FP64, time of the calls (HIP events around each), e_perp of the explicit Q
@@ -560,16 +567,17 @@ def bench_stewart(args):
     Vh, _ = torch.linalg.qr(torch.randn((m, m), dtype=torch.float64, device=dev, generator=gen))
     Qt = torch.empty((m, n), dtype=torch.float64, device=dev)          # explicit Q, column-major n x m
     Rt = torch.zeros((m, m), dtype=torch.float64, device=dev)          # R, column-major m x m
-    o = Orthogonalizer(n, s, m, leaf, precision=orth.ORTH_MIXED_SPLIT32)
-    ws_ptr = (o.workspace.data_ptr() + 255) // 256 * 256
-    nbytes = orth.orth_workspace_bytes(n, s, m, leaf, orth.ORTH_MIXED_SPLIT32)
-    o.close()
+    forms = (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32),
+             ("householder", orth.ORTH_FP64_HOUSEHOLDER))
+    nbytes = max(orth.orth_workspace_bytes(n, s, m, leaf, f) for _, f in forms)
+    wsbuf = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
+    ws_ptr = (wsbuf.data_ptr() + 255) // 256 * 256
     results = []
     for smin in (1e-6, 1e-12):
         sig = torch.logspace(0.0, math.log10(smin), m, dtype=torch.float64, device=dev)
         Wt = torch.mm(Vh * sig, Gt)            # W^T = V diag(sigma) G^T
         wnorm = float(torch.linalg.norm(Wt))
-        for name, prec in (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32)):
+        for name, prec in forms:
             for rep in range(args.warmup + 1):
                 Rt.zero_()
                 code, h = orth.orth_create(n, s, m, leaf, prec, ws_ptr, nbytes, sp)
@@ -615,11 +623,15 @@ def bench_stewart(args):
     mx = {r["sigma_min"]: r for r in results if r["form"] == "mixed"}
     speed = {str(k): fp[k]["ms_30_calls"] / mx[k]["ms_30_calls"]
              for k in fp if fp[k]["status"] == "ok" and mx[k]["status"] == "ok"}
+    hx = {r["sigma_min"]: r for r in results if r["form"] == "householder"}
+    speed_hh = {str(k): fp[k]["ms_30_calls"] / hx[k]["ms_30_calls"]
+                for k in fp if fp[k]["status"] == "ok" and hx[k]["status"] == "ok"}
     out = {
         "metric": METRIC,
         "workload": "stewart-2^24x240-s8",
         "results": results,
         "mixed_speedup_vs_fp64": speed,
+        "householder_speedup_vs_fp64": speed_hh,
         "dtype": "f64",
         "data": "synthetic: W = G diag(sigma) V^T, G Gaussian/sqrt(n), V Haar (torch, seed 7)",
     }
@@ -674,7 +686,10 @@ def main():
     # --- inputs: start block + 30 Krylov blocks, resident in HBM
     R0 = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, W["seed"]).T)).to(dev)
     # one workspace for both forms (the mixed form's is the larger: it adds the FP32 copy)
-    nbytes = max(orth.orth_workspace_bytes(n, s, kmax, leaf, p_) for p_ in (orth.ORTH_FP64, orth.ORTH_MIXED_SPLIT32))
+    # (and the Householder form, when this shape is within its limits, adds the T factors)
+    nbytes = max(orth.orth_workspace_bytes(n, s, kmax, leaf, p_)
+                 for p_ in (orth.ORTH_FP64, orth.ORTH_MIXED_SPLIT32, orth.ORTH_FP64_HOUSEHOLDER))
+    hh_ok = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64_HOUSEHOLDER) > 0
     ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
     ws_ptr = (ws.data_ptr() + 255) // 256 * 256
     Xs = [R0]
@@ -795,16 +810,25 @@ def main():
     ms_mixed, dom_mixed_timed, e_perp_mixed = timed_runs(orth.ORTH_MIXED_SPLIT32, dom_mixed)
     print(f"[bench] mixed form: {ms_mixed:.2f} ms per sequence, e_perp {e_perp_mixed:.2e}",
           file=sys.stderr, flush=True)
+    # the Householder leaves (Algorithm HH at the leaves, BCGS-PIP+ reduction) on the same inputs
+    hh = None
+    if hh_ok:
+        prof_hh, dom_hh = (None, None) if args.no_profile else profiled_sequence(orth.ORTH_FP64_HOUSEHOLDER)
+        ms_hh, _, e_perp_hh = timed_runs(orth.ORTH_FP64_HOUSEHOLDER, dom_hh)
+        print(f"[bench] householder leaves: {ms_hh:.2f} ms per sequence, e_perp {e_perp_hh:.2e}",
+              file=sys.stderr, flush=True)
+        hh = (ms_hh, e_perp_hh, prof_hh)
 
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
     value = total_bytes / (ms_per_step / 1e3) / 1e9
 
-    def per_class(pr):
+    def per_class(pr, first_step_skips=()):
         out = {}
         for name, (ms, cnt) in pr.items():
             if cnt == 0:
                 continue
-            byts = sum(kernel_bytes(name, n, s, p, k) for k in widths)
+            ks = widths[1:] if name in first_step_skips else widths
+            byts = sum(kernel_bytes(name, n, s, p, k) for k in ks)
             out[name] = {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3,
                          "gbs": (byts / (ms / 1e3) / 1e9) if byts else None}
         return out
@@ -868,6 +892,18 @@ def main():
             "e_perp_gate_1e-10": e_perp_mixed <= 1e-10,
             "fp64_redo_steps": fallbacks[orth.ORTH_MIXED_SPLIT32],
             "kernels": per_class(prof_mixed) if prof_mixed else {},
+        },
+        "householder_leaves": None if hh is None else {
+            "form": "fp64_householder: Algorithm HH at the leaves (reflectors + compact-WY T), "
+                    "BCGS-PIP+ reduction",
+            "ms_per_step": hh[0],
+            "value_effective": total_bytes / (hh[0] / 1e3) / 1e9,
+            "unit": "GB/s (BCGS-PIP+ algorithmic bytes)",
+            "speedup_vs_fp64": ms_per_step / hh[0],
+            "e_perp": hh[1],
+            "e_perp_gate_1e-10": hh[1] <= 1e-10,
+            # the first call (k = 0) has no Q_k^T w passes
+            "kernels": per_class(hh[2], ("leaf_gram", "leaf_correct")) if hh[2] else {},
         },
         "roofline": roofline,
         "kernels": kernels,

@@ -140,8 +140,9 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oCL = take((int64_t)pl.p * kmax * 2 * s);
     // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
     pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
-    // Householder leaves: compact-WY factor per leaf (k_max x k_max, column-major)
-    pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)pl.p * kmax * kmax) : 0;
+    // Householder leaves: per leaf the compact-WY factor (column- and
+    // row-major) and the reflectors' top rows (row-major), k_max x k_max each
+    pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
     pl.total = off;
     return true;
 }
@@ -251,7 +252,7 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     if (e == hipSuccess) e = launch_fill(h->Y(), pl.ldt * (int64_t)pl.s, 0.0, h->stream);
     // Householder leaves: the compact-WY factors grow into zeros below their diagonal
     if (e == hipSuccess && h->TH())
-        e = launch_fill(h->TH(), (int64_t)pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
+        e = launch_fill(h->TH(), (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
                             (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, h->stream);

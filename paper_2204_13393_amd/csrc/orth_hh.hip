@@ -40,6 +40,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Per-leaf small matrices, k_max x k_max doubles each, at T + leaf 3 k_max^2:
+//   Tc  the compact-WY factor T, column-major (element (r, c) at c k_max + r)
+//   Tr  the same factor row-major (element (r, c) at r k_max + c)
+//   Vr  the top k_max rows of the leaf's reflectors, row-major
+// Each product below keeps one output row per lane and walks the
+// contraction index with one coalesced load per step (the copy whose
+// contiguous direction runs along the lanes), the other operand broadcast
+// from LDS.  Entries below (T) or above (V) the diagonal are stored zeros,
+// so a wave walks one range for all its lanes.
+__device__ __forceinline__ double *hh_tc(const HhArgs &a, int leaf) {
+    return a.T + (int64_t)leaf * 3 * a.kmax * a.kmax;
+}
+
 // ------------------------------------------------------------ T^T M
 // Y = T_k^T M, M = V^T w from the leaf's partial slots (rows 0..k-1 of each
 // [k+s][s] slot); Y goes to the leaf record's first-sweep projection and the
@@ -58,16 +71,28 @@ __global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
         lds[e] = v;
     }
     __syncthreads();
-    const double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
+    const int64_t km = a.kmax;
+    const double *Tr = hh_tc(a, leaf) + km * km;
     double *rec = a.small + (int64_t)leaf * a.small_stride;
-    for (int e = tid; e < k * S; e += kThreads) {
-        const int r = e / S, j = e - (e / S) * S;
-        const double *tc = Tl + (int64_t)r * a.kmax;     // column r of T: T[c][r], c <= r
-        double v = 0.0;
-        for (int c = 0; c <= r; ++c) v = fma(tc[c], lds[c * S + j], v);
-        rec[e] = v;
+    for (int rb = 0; rb < k; rb += kThreads) {
+        const int r = rb + tid;
+        // Y[r] = sum over c <= r of T(c, r) M[c]: T row c, lanes along r
+        const int wmax = rb + (tid & ~63) + 63;
+        const int cend = wmax + 1 < k ? wmax + 1 : k;
+        double acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        for (int c = 0; c < cend; ++c) {
+            const double t = r < k ? Tr[(int64_t)c * km + r] : 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc[j] = fma(t, lds[c * S + j], acc[j]);
+        }
+        if (r < k) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) rec[(int64_t)r * S + j] = acc[j];
+        }
     }
-    double *n1i = rec + (int64_t)a.kmax * S + S * S;
+    double *n1i = rec + km * S + S * S;
     for (int e = tid; e < S * S; e += kThreads) n1i[e] = (e / S == e % S) ? 1.0 : 0.0;
 }
 
@@ -202,7 +227,9 @@ __global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
 // ------------------------------------------------------------ T update
 // From the slots of [V v_new]^T v_new: W = V^T v_new (k x s) and
 // G = v_new^T v_new.  T_s (s x s, upper): diagonal 2, column j above the
-// diagonal -2 T_s[0:j, 0:j] G[0:j, j]; then T[0:k, k:k+s] = -T (W T_s).
+// diagonal -2 T_s[0:j, 0:j] G[0:j, j]; then T[0:k, k:k+s] = -T (W T_s), in
+// both copies of T.  Also copies the reflectors' new top rows k..k+s-1 to
+// the row-major Vr.
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
     if (hh_failed(a.status)) return;
@@ -243,16 +270,38 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
         for (int j = 0; j < S; ++j) W[r * S + j] = bv[j];
     }
     __syncthreads();
-    double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
-    for (int e = tid; e < k * S; e += kThreads) {
-        const int j = e / k, r = e - (e / k) * k;
-        double v = 0.0;
-        for (int c = r; c < k; ++c) v = fma(Tl[(int64_t)c * a.kmax + r], W[c * S + j], v);
-        Tl[(int64_t)(k + j) * a.kmax + r] = -v;
+    const int64_t km = a.kmax;
+    double *Tc = hh_tc(a, leaf), *Tr = Tc + km * km, *Vr = Tr + km * km;
+    for (int rb = 0; rb < k; rb += kThreads) {
+        const int r = rb + tid;
+        // -(T B)[r] = -sum over c >= r of T(r, c) B[c]: T column c, lanes along r
+        const int wmin = rb + (tid & ~63);
+        double acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        for (int c = wmin; c < k; ++c) {
+            const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc[j] = fma(t, W[c * S + j], acc[j]);
+        }
+        if (r < k) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                Tc[(int64_t)(k + j) * km + r] = -acc[j];
+                Tr[(int64_t)r * km + k + j] = -acc[j];
+            }
+        }
     }
     for (int e = tid; e < S * S; e += kThreads) {
         const int j = e / S, i = e - (e / S) * S;
-        Tl[(int64_t)(k + j) * a.kmax + k + i] = i <= j ? Ts[i * S + j] : 0.0;
+        const double v = i <= j ? Ts[i * S + j] : 0.0;
+        Tc[(int64_t)(k + j) * km + k + i] = v;
+        Tr[(int64_t)(k + i) * km + k + j] = v;
+    }
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    for (int e = tid; e < S * K; e += kThreads) {
+        const int i = e / K, c = e - (e / K) * K;
+        Vr[(int64_t)(k + i) * km + c] = a.Q[(r0 + k + i) + (int64_t)c * a.ldq];
     }
 }
 
@@ -275,21 +324,42 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
         rec[(int64_t)r * 2 * S + j] = v;
     }
     __syncthreads();
-    const int64_t r0 = a.geom.leaf_begin(leaf);
-    for (int e = tid; e < K * S; e += kThreads) {
-        const int c = e / S, j = e - (e / S) * S;
-        const double *vc = a.Q + r0 + (int64_t)c * a.ldq;   // reflector c, leaf rows
-        double v = 0.0;
-        for (int r = c; r < K; ++r) v = fma(vc[r], C[r * S + j], v);
-        B[e] = v;
+    const int64_t km = a.kmax;
+    const double *Tc = hh_tc(a, leaf), *Vr = Tc + 2 * km * km;
+    for (int cb = 0; cb < K; cb += kThreads) {
+        const int c = cb + tid;
+        // B[c] = sum over r >= c of V(r, c) C[r]: V row r, lanes along c
+        const int wmin = cb + (tid & ~63);
+        double acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        for (int r = wmin; r < K; ++r) {
+            const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc[j] = fma(v, C[r * S + j], acc[j]);
+        }
+        if (c < K) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) B[c * S + j] = acc[j];
+        }
     }
     __syncthreads();
-    const double *Tl = a.T + (int64_t)leaf * a.kmax * a.kmax;
-    for (int e = tid; e < K * S; e += kThreads) {
-        const int j = e / K, r = e - (e / K) * K;
-        double v = 0.0;
-        for (int c = r; c < K; ++c) v = fma(Tl[(int64_t)c * a.kmax + r], B[c * S + j], v);
-        rec[(int64_t)r * 2 * S + S + j] = -v;
+    for (int rb = 0; rb < K; rb += kThreads) {
+        const int r = rb + tid;
+        // Z[r] = sum over c >= r of T(r, c) B[c]: T column c, lanes along r
+        const int wmin = rb + (tid & ~63);
+        double acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        for (int c = wmin; c < K; ++c) {
+            const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc[j] = fma(t, B[c * S + j], acc[j]);
+        }
+        if (r < K) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) rec[(int64_t)r * 2 * S + S + j] = -acc[j];
+        }
     }
 }
 

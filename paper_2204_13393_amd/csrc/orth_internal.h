@@ -252,8 +252,9 @@ struct ApplyArgs {
 };
 
 // ---- Householder leaves (orth_hh.hip) ----
-// leaf bases as unit reflectors V_i with compact-WY factors T_i (k_max x
-// k_max, column-major, leaf i at T + i k_max^2); see orth_hh.hip for the step
+// leaf bases as unit reflectors V_i with compact-WY factors T_i; per leaf
+// three k_max x k_max blocks at T + i 3 k_max^2 (T column-major, T row-major,
+// the reflectors' top rows row-major); see orth_hh.hip for the step
 struct HhArgs {
     LevelGeom geom;           // leaf geometry (identity rows)
     int32_t k, kmax;
