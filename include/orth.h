@@ -210,7 +210,9 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
  *           handle is poisoned.
  *   info    optional (may be NULL): 4 ints {tree level (0 = leaves,
  *           1 = reduction), leaf index, CholeskyQR sweep (1 or 2), pivot
- *           column}.
+ *           column}.  The first failure wins; when several leaves fail in
+ *           the same launch, which of them is recorded depends on the
+ *           order the workgroups ran in (the breakdown itself does not).
  * Errors: ARG, HIP.
  */
 int orth_status(orth_t *h, int32_t *status, int32_t *info);
