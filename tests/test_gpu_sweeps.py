@@ -20,9 +20,15 @@ What the paper states and the tests check:
   * far past eps kappa^2 = 1/2 (kappa = 1e10) no combination is stable: each
     breaks down (a Cholesky pivot <= 0) or ends with e_perp >= 1e-6, on the
     GPU and in the oracle alike;
+  * Householder leaves (Sec. 2.2) never break down: with the BCGS-PIP+
+    reduction e_perp is O(eps) up to kappa = 1e8; at kappa = 1e9, where
+    every CholeskyQR leaf combination breaks down at the leaves, a
+    breakdown can only come from the reduction level (past its bound);
   * parity: where both finish, the GPU's e_perp is within a factor of 10 of
     the oracle's on the same matrix and partition (kappa <= 1e6, where the
     errors are not dominated by the chaotic regime near the breakdown).
+
+e_perp is taken of the explicit blocks the calls returned.
 """
 
 import sys
@@ -42,6 +48,7 @@ pytestmark = pytest.mark.gpu
 EPS = 2.0 ** -52
 N, M, S, LEAF = 2 ** 16, 32, 4, 256
 COMBOS = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip")]
+HH = [("hh", "pip+"), ("hh", "pip")]
 
 
 def _say(*a):
@@ -60,22 +67,22 @@ def torch_cuda():
 
 
 def _gpu_e_perp(A, local, reduction):
-    """(status, e_perp or None) of the GPU QR of A in blocks of S."""
-    import torch
+    """(status, e_perp or None, breakdown level) of the GPU QR of A in blocks of S."""
     from paper_2204_13393_amd import Orthogonalizer, orth
     v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
-    g = Orthogonalizer(N, S, M, LEAF, variant=v[local], reduction_variant=v[reduction])
+    if local == "hh":
+        g = Orthogonalizer(N, S, M, LEAF, precision=orth.ORTH_FP64_HOUSEHOLDER, reduction_variant=v[reduction])
+    else:
+        g = Orthogonalizer(N, S, M, LEAF, variant=v[local], reduction_variant=v[reduction])
+    blocks = []
     for j in range(M // S):
-        g.step(to_dev(A[:, j * S:(j + 1) * S]))
+        blocks.append(to_host(g.step(to_dev(A[:, j * S:(j + 1) * S]))[2]))
         if g.status()[0]:
             break
-    st = g.status()[0]
-    e = None
-    if st == 0:
-        Q = to_host(g.apply_Q(torch.eye(M, dtype=torch.float64, device="cuda")))
-        e = metrics.e_perp(Q)
+    st, info = g.status()
+    e = metrics.e_perp(np.hstack(blocks)) if st == 0 else None
     g.close()
-    return st, e
+    return st, e, info[0]
 
 
 def _oracle_e_perp(A, local, reduction):
@@ -90,13 +97,14 @@ def _oracle_e_perp(A, local, reduction):
 @pytest.fixture(scope="module")
 def sweep(torch_cuda):
     out = {}
-    for kappa in (1e0, 1e3, 1e6, 1e8, 1e10):
+    for kappa in (1e0, 1e3, 1e6, 1e8, 1e9, 1e10):
         A = stewart(N, M, kappa, 11)
-        for local, red in COMBOS:
+        for local, red in COMBOS + HH:
             _say("sweep", kappa, local, red)
-            st, eg = _gpu_e_perp(A, local, red)
+            st, eg, level = _gpu_e_perp(A, local, red)
             eo = _oracle_e_perp(A, local, red)
             out[(kappa, local, red)] = (st, eg, eo)
+            out[("level", kappa, local, red)] = level
             print(f"  kappa {kappa:.0e} local {local:4s} reduction {red:4s}: "
                   f"gpu {'breakdown' if st else f'{eg:.2e}'}  oracle {'breakdown' if eo is None else f'{eo:.2e}'}",
                   flush=True)
@@ -135,8 +143,31 @@ def test_past_the_bound_nothing_is_stable(sweep):
         assert eo is None or eo >= 1e-6, (local, red, eo)
 
 
+def test_householder_leaves_never_break_down(sweep):
+    for kappa in (1e0, 1e3, 1e6, 1e8):
+        st, eg, eo = sweep[(kappa, "hh", "pip+")]
+        assert st == 0 and eg <= 1e-13, (kappa, st, eg)
+        assert eo is not None and eo <= 1e-13, (kappa, eo)
+    # past u kappa^2 <= 1/2 a breakdown may come, but only from the reduction
+    # level (in the oracle the leaves cannot raise one at all)
+    for kappa in (1e9, 1e10):
+        for red in ("pip+", "pip"):
+            st, eg, eo = sweep[(kappa, "hh", red)]
+            assert st == 0 or sweep[("level", kappa, "hh", red)] == 1, (kappa, red)
+    # where the CholeskyQR leaves themselves fail
+    for local, red in COMBOS:
+        st, eg, eo = sweep[(1e9, local, red)]
+        assert st != 0 and sweep[("level", 1e9, local, red)] == 0, (local, red, st)
+    # the BCGS-PIP reduction shows its O(eps kappa^2) error with any leaves
+    st, eg, eo = sweep[(1e6, "hh", "pip")]
+    assert st == 0 and eg >= 1e-10 and eo is not None and eo >= 1e-10, (eg, eo)
+
+
 def test_gpu_matches_oracle(sweep):
-    for (kappa, local, red), (st, eg, eo) in sweep.items():
+    for key, val in sweep.items():
+        if key[0] == "level":
+            continue
+        (kappa, local, red), (st, eg, eo) = key, val
         if kappa > 1e6:
             continue
         assert st == 0 and eo is not None, (kappa, local, red)
