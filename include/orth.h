@@ -107,7 +107,8 @@ enum orth_code {
  *                       UNSUPPORTED): s <= 16, every leaf at most 8192 rows
  *                       for s <= 4, 4096 for s = 8, 1024 for s = 16 (the
  *                       panel is held in registers), and k_max s <= 4096.
- *                       orth_apply_Q returns UNSUPPORTED; orth_export_local
+ *                       orth_apply_Q forms Q_k [C_i; 0] per leaf through
+ *                       the same compact-WY products; orth_export_local
  *                       exports the reflectors as d_Qloc.  Single handles
  *                       only.
  */
@@ -198,8 +199,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw,
  * for the explicit basis (C = I).
  *   d_C, ldc   k x m, ldc >= k;  m >= 1
  *   d_Y, ldy   n x m output, ldy >= n; must not overlap the workspace or C.
- * Errors: ARG (also for k = 0), POISONED, HIP; UNSUPPORTED for
- * ORTH_FP64_HOUSEHOLDER handles.
+ * Errors: ARG (also for k = 0), POISONED, HIP.
  */
 int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
                  double *d_Y, int64_t ldy);

@@ -59,7 +59,7 @@ struct Plan {
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, total;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -143,6 +143,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
+    // and orth_apply_Q's second coefficient scratch (-Z_i), like CA
+    pl.oCA2 = precision == ORTH_FP64_HOUSEHOLDER ? take(pl.ldt * kApplyMB) : 0;
     pl.total = off;
     return true;
 }
@@ -213,6 +215,7 @@ struct orth_ctx {
         return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
     }
     double *TH() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oTH : nullptr; }
+    double *CA2() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oCA2 : nullptr; }
     double *PR() const { return ws + pl.oPR; }
     double *PR2() const { return ws + pl.oPR2; }
     double *SL() const { return ws + pl.oSL; }
@@ -697,7 +700,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
     const Plan &pl = h->pl;
     const int32_t k = h->k;
     if (k < 1 || m < 1 || !d_C || !d_Y || ldc < k || ldy < pl.n) return ORTH_ERR_ARG;
-    if (pl.precision == ORTH_FP64_HOUSEHOLDER) return ORTH_ERR_UNSUPPORTED;
+    const bool hh = pl.precision == ORTH_FP64_HOUSEHOLDER;
     hipStream_t st = h->stream;
     for (int32_t j0 = 0; j0 < m; j0 += kApplyMB) {
         const int32_t mb = (m - j0) < kApplyMB ? (m - j0) : kApplyMB;
@@ -715,18 +718,42 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         hipError_t e = launch_apply(r, st);
         h->end(pm0);
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
-        // leaves: Y_i = Q_i C_i
+        // leaves: Y_i = Q_i C_i; with Householder leaves Y_i = -V Z_i + E C_i,
+        // Z_i = T (V[0:k]^T C_i)
+        HhArgs ha{};
+        if (hh) {
+            ha.geom = leaf_geom(pl, kFinalChunk);
+            ha.k = k;
+            ha.kmax = pl.kmax;
+            ha.T = h->TH();
+            ha.ca = h->CA();
+            ha.ca_out = h->CA2();
+            ha.ldca = pl.ldt;
+            ha.m = mb;
+            ha.U = d_Y + (int64_t)j0 * ldy;
+            ha.ldu = ldy;
+            const int pm = h->begin(ORTH_K_APPLY);
+            e = launch_hh_apply(HH_APPLY_COEF, ha, st);
+            h->end(pm);
+            if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+        }
         ApplyArgs a{};
         a.Q = Operand{h->Q(), pl.ldq};
         a.k = k;
         a.geom = leaf_geom(pl, kFinalChunk);
-        a.Cptr = h->CA();
+        a.Cptr = hh ? h->CA2() : h->CA();
         a.ldc = pl.ldt;
         a.cseg = pl.kmax;
         a.m = mb;
         a.Y = OutOperand{d_Y + (int64_t)j0 * ldy, ldy};
         { const int pm = h->begin(ORTH_K_APPLY); e = launch_apply(a, st); h->end(pm); }
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+        if (hh) {
+            const int pm = h->begin(ORTH_K_APPLY);
+            e = launch_hh_apply(HH_APPLY_ADD, ha, st);
+            h->end(pm);
+            if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+        }
     }
     return ORTH_OK;
 }

@@ -376,6 +376,75 @@ __global__ __launch_bounds__(kThreads) void k_hh_addec(HhArgs a) {
     }
 }
 
+// ------------------------------------------------------------ apply
+// orth_apply_Q: Y_i = Q_k [C_i; 0] = -V Z_i + E C_i with Z_i = T (V[0:k]^T C_i),
+// C_i the leaf's coefficient block (k x m) from the reduction level.  MBI
+// columns at a time, so the two k x MBI LDS blocks fit in 64 KB.
+template <int MBI>
+__global__ __launch_bounds__(kThreads) void k_hh_apply_coef(HhArgs a) {
+    extern __shared__ double lds[];
+    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k;
+    const int64_t km = a.kmax;
+    double *C = lds, *B = lds + (int64_t)k * MBI;   // k x MBI row-major each
+    const double *Tc = hh_tc(a, leaf), *Vr = Tc + 2 * km * km;
+    const double *cin = a.ca + leaf * km;
+    double *cout = a.ca_out + leaf * km;
+    for (int j0 = 0; j0 < a.m; j0 += MBI) {
+        const int nb = a.m - j0 < MBI ? a.m - j0 : MBI;
+        for (int e = tid; e < k * MBI; e += kThreads) {
+            const int c = e / MBI, jj = e - (e / MBI) * MBI;
+            C[e] = jj < nb ? cin[(int64_t)(j0 + jj) * a.ldca + c] : 0.0;
+        }
+        __syncthreads();
+        for (int cb = 0; cb < k; cb += kThreads) {
+            const int c = cb + tid;
+            const int wmin = cb + (tid & ~63);
+            double acc[MBI];
+#pragma unroll
+            for (int j = 0; j < MBI; ++j) acc[j] = 0.0;
+            for (int r = wmin; r < k; ++r) {
+                const double v = c < k ? Vr[(int64_t)r * km + c] : 0.0;
+#pragma unroll
+                for (int j = 0; j < MBI; ++j) acc[j] = fma(v, C[r * MBI + j], acc[j]);
+            }
+            if (c < k) {
+#pragma unroll
+                for (int j = 0; j < MBI; ++j) B[c * MBI + j] = acc[j];
+            }
+        }
+        __syncthreads();
+        for (int rb = 0; rb < k; rb += kThreads) {
+            const int r = rb + tid;
+            const int wmin = rb + (tid & ~63);
+            double acc[MBI];
+#pragma unroll
+            for (int j = 0; j < MBI; ++j) acc[j] = 0.0;
+            for (int c = wmin; c < k; ++c) {
+                const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
+#pragma unroll
+                for (int j = 0; j < MBI; ++j) acc[j] = fma(t, B[c * MBI + j], acc[j]);
+            }
+            if (r < k) {
+#pragma unroll
+                for (int j = 0; j < MBI; ++j)
+                    if (j < nb) cout[(int64_t)(j0 + j) * a.ldca + r] = -acc[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Y_i[0:k] += C_i
+__global__ __launch_bounds__(kThreads) void k_hh_apply_add(HhArgs a) {
+    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k;
+    const double *cin = a.ca + leaf * (int64_t)a.kmax;
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    for (int e = tid; e < k * a.m; e += kThreads) {
+        const int j = e / k, c = e - (e / k) * k;
+        a.U[(r0 + c) + (int64_t)j * a.ldu] += cin[(int64_t)j * a.ldca + c];
+    }
+}
+
 template <int S>
 hipError_t hh_launch(HhKernel which, const HhArgs &a, hipStream_t st) {
     const int nleaf = a.geom.nleaf;
@@ -404,6 +473,32 @@ hipError_t hh_launch(HhKernel which, const HhArgs &a, hipStream_t st) {
 }
 
 }  // namespace
+
+hipError_t launch_hh_apply(HhKernel which, const HhArgs &a, hipStream_t st) {
+    if (a.geom.nleaf < 1 || a.k < 1 || a.k > a.kmax || a.m < 1 || a.m > 16) return hipErrorInvalidValue;
+    const int nleaf = a.geom.nleaf;
+    if (which == HH_APPLY_ADD) {
+        hipLaunchKernelGGL(k_hh_apply_add, dim3(nleaf), dim3(kThreads), 0, st, a);
+        return hipGetLastError();
+    }
+    if (which != HH_APPLY_COEF) return hipErrorInvalidValue;
+    // columns per pass: two k x MBI blocks within 64 KB of LDS
+    const int64_t k = a.k;
+    if (k * 16 <= kHhMaxCoef) {
+        hipLaunchKernelGGL((k_hh_apply_coef<16>), dim3(nleaf), dim3(kThreads), (size_t)(2 * k * 16 * 8), st, a);
+    } else if (k * 8 <= kHhMaxCoef) {
+        hipLaunchKernelGGL((k_hh_apply_coef<8>), dim3(nleaf), dim3(kThreads), (size_t)(2 * k * 8 * 8), st, a);
+    } else if (k * 4 <= kHhMaxCoef) {
+        hipLaunchKernelGGL((k_hh_apply_coef<4>), dim3(nleaf), dim3(kThreads), (size_t)(2 * k * 4 * 8), st, a);
+    } else if (k * 2 <= kHhMaxCoef) {
+        hipLaunchKernelGGL((k_hh_apply_coef<2>), dim3(nleaf), dim3(kThreads), (size_t)(2 * k * 2 * 8), st, a);
+    } else if (k <= kHhMaxCoef) {
+        hipLaunchKernelGGL((k_hh_apply_coef<1>), dim3(nleaf), dim3(kThreads), (size_t)(2 * k * 8), st, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 int64_t hh_max_leaf_rows(int s) {
     switch (s) {

@@ -276,13 +276,22 @@ struct HhArgs {
     double *U;                // explicit output (E C term)
     int64_t ldu;
     const DevStatus *status;
+    // orth_apply_Q: per-leaf coefficient blocks C_i (k x m) in, -Z_i out, element
+    // (c, j) at [j * ldca + leaf * kmax + c]; m <= 16 columns
+    const double *ca;
+    double *ca_out;
+    int64_t ldca;
+    int32_t m;
 };
-enum HhKernel { HH_PREP = 0, HH_PANEL, HH_TUPD, HH_COEF, HH_ADDEC };
+enum HhKernel { HH_PREP = 0, HH_PANEL, HH_TUPD, HH_COEF, HH_ADDEC, HH_APPLY_COEF, HH_APPLY_ADD };
 // (k + s) s bound of the per-leaf small products (their LDS staging)
 constexpr int64_t kHhMaxCoef = 4096;
 // largest leaf the panel kernel holds in registers for block width s (0: unsupported s)
 int64_t hh_max_leaf_rows(int s);
 hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st);
+// orth_apply_Q with Householder leaves: HH_APPLY_COEF (Z_i = T V_top^T C_i, -Z_i
+// to ca_out), then the apply kernel, then HH_APPLY_ADD (Y_i[0:k] += C_i)
+hipError_t launch_hh_apply(HhKernel which, const HhArgs &a, hipStream_t st);
 
 // ---- batched form: many independent instances, one grouped launch per phase ----
 // Per-instance descriptor (device memory); regions carved like a single handle.

@@ -5,13 +5,14 @@ at the reduction level.
 * parity with the oracle's TreeTSPQR with Householder leaves on the same
   partition, step by step: H, R, U and the stored reflectors, at the
   tolerances of test_gpu_parity.py (ragged last leaves, one leaf, the
-  register capacity of the panel kernel, s from 1 to 16);
+  register capacity of the panel kernel, s from 1 to 16), and Y = Q C
+  through orth_apply_Q;
 * the FP64 (BCGS-PIP+) form gives the same H, R, U where both succeed;
 * a leaf whose local block is nearly dependent on its basis: the BCGS-PIP+
   leaves break down, the Householder leaves match the unique solution;
 * a globally dependent column and a NaN break down at the reduction level;
-* BCGS-PIP at the reduction; reruns are bitwise identical; calls the form
-  does not offer return UNSUPPORTED.
+* BCGS-PIP at the reduction; reruns are bitwise identical; BCGS-PIP at the
+  leaves is refused (UNSUPPORTED).
 """
 
 import sys
@@ -102,8 +103,12 @@ def test_householder_parity(torch_cuda, n, s, kmax, leaf_rows):
         for c in range(gpu.k):
             assert np.all(Vg[r0:r0 + c, c] == 0.0)
     assert metrics.e_perp(to_host(T)) <= 1e-12
-    code = orth.orth_apply_Q(gpu.h, Vd.data_ptr(), gpu.k, 1, Vd.data_ptr(), n)
-    assert code == orth.ORTH_ERR_UNSUPPORTED
+    # Y = Q C through the reflectors and the tree factors (17 columns: two
+    # column blocks of the apply)
+    V = np.hstack(Ugpu)
+    C = rng.standard_normal((gpu.k, 17))
+    Y = to_host(gpu.apply_Q(to_dev(C)))
+    assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
     gpu.close()
 
 
@@ -219,3 +224,69 @@ def test_householder_pip_reduction_and_determinism(torch_cuda):
     for a, b in zip(*runs):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def test_householder_graph_replay(torch_cuda):
+    """Four steps with Householder leaves captured in a hipGraph and replayed
+    from freshly created handles on the same workspace, eager work and
+    synchronisation between replays: every replay equals the eager run
+    bitwise (the step makes no host call and allocates nothing)."""
+    import torch
+    from paper_2204_13393_amd import orth
+    _say("householder graph")
+    n, s, kmax, leaf = 16384, 8, 32, 4096
+    H_ = orth.ORTH_FP64_HOUSEHOLDER
+    X = [to_dev(normal_block(n, s, 80 + j)) for j in range(4)]
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, H_)
+    side = torch.cuda.Stream()
+
+    def buffers():
+        return (torch.zeros((kmax, kmax), dtype=torch.float64, device="cuda"),
+                torch.empty((kmax, n), dtype=torch.float64, device="cuda"))
+
+    def run(h, H, U):
+        for j in range(4):
+            k = j * s
+            col = H[j * s:(j + 1) * s]
+            hp = col.data_ptr() if k else 0
+            assert orth.orth_step(h, X[j].data_ptr(), n, hp, kmax, col[:, k:].data_ptr(), kmax,
+                                  U[k:k + s].data_ptr(), n) == 0
+
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    He, Ue = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, H_, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        run(h, He, Ue)
+    side.synchronize()
+    assert orth.orth_status(h)[1] == 0
+    orth.orth_destroy(h)
+    He_h, Ue_h = to_host(He), to_host(Ue)
+    assert metrics.e_perp(Ue_h) <= 1e-12
+
+    Hg, Ug = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, H_, wp, nbytes, side.cuda_stream)
+        assert code == 0
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        run(h, Hg, Ug)
+    orth.orth_destroy(h)
+    for rep in range(3):
+        code, h = orth.orth_create(n, s, kmax, leaf, H_, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        Hg.zero_()
+        Ug.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        code, st, info = orth.orth_status(h)
+        assert code == 0 and st == 0, info
+        assert np.array_equal(to_host(Hg), He_h), rep
+        assert np.array_equal(to_host(Ug), Ue_h), rep
+        orth.orth_destroy(h)
+        x = torch.randn(1000, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
