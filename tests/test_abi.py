@@ -85,10 +85,11 @@ def test_mixed_form_workspace_adds_the_fp32_copy():
         assert n * k * 4 <= mixed - f64 <= (n + 64) * k * 4 + 256
 
 
-def test_mixed_form_is_single_handle_only():
-    assert orth.orth_batch_workspace_bytes([5000, 3000], [4, 8], [16, 32], None, orth.ORTH_MIXED_SPLIT32) == 0
-    code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, orth.ORTH_MIXED_SPLIT32,
-                                     4096, 1 << 30, None)
+@pytest.mark.parametrize("form", ["mixed", "householder"])
+def test_other_forms_are_single_handle_only(form):
+    f = orth.ORTH_MIXED_SPLIT32 if form == "mixed" else orth.ORTH_FP64_HOUSEHOLDER
+    assert orth.orth_batch_workspace_bytes([5000, 3000], [4, 8], [16, 32], None, f) == 0
+    code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, f, 4096, 1 << 30, None)
     assert code == orth.ORTH_ERR_UNSUPPORTED
 
 
