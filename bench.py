@@ -40,6 +40,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = dict(name="lap2d-4096x4096-s8", nx=4096, ny=4096, s=8, steps=30, leaf_rows=4096, seed=0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2204_13393_amd", "csrc", "orth_kernels.hip")
+KERNEL_HDR = os.path.join(ROOT, "paper_2204_13393_amd", "csrc", "orth_internal.h")
 
 
 def step_bytes(n, s, p, k):
@@ -103,8 +104,13 @@ class TimingEvent:
 
 
 def source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the kernel source and the shared header (launch geometry,
+    chunk heights): counters taken on other sources are not used."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, KERNEL_HDR):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def load_traffic(kernel_cls):

@@ -8,7 +8,7 @@ orth_kernel_class (k_gram_hi to leaf_gram, reported as leaf_gram_hi).
 
     python -m paper_2204_13393_amd.profile_summary trace  <kernel_trace.csv>
     python -m paper_2204_13393_amd.profile_summary counters <fetch.csv> <write.csv> \
-            --copy-gib G --sha <sha256 of orth_kernels.hip> --out traffic.json
+            --copy-gib G --sha <sha256 of orth_kernels.hip followed by orth_internal.h> --out traffic.json
 
 `trace` prints per-class dispatch counts, total and average durations.
 `mfma` reads one --pmc pass of SQ_INSTS_VALU_MFMA_MOPS_F64,
