@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        #pragma unroll 4      // four loads in flight per lane
         for (int c = 0; c < cend; ++c) {
             const double t = r < k ? Tr[(int64_t)c * km + r] : 0.0;
 #pragma unroll
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        #pragma unroll 4      // four loads in flight per lane
         for (int c = wmin; c < k; ++c) {
             const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
@@ -333,6 +335,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        #pragma unroll 4      // four loads in flight per lane
         for (int r = wmin; r < K; ++r) {
             const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
 #pragma unroll
@@ -351,6 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
+        #pragma unroll 4      // four loads in flight per lane
         for (int c = wmin; c < K; ++c) {
             const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
@@ -402,6 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_apply_coef(HhArgs a) {
             double acc[MBI];
 #pragma unroll
             for (int j = 0; j < MBI; ++j) acc[j] = 0.0;
+            #pragma unroll 4      // four loads in flight per lane
             for (int r = wmin; r < k; ++r) {
                 const double v = c < k ? Vr[(int64_t)r * km + c] : 0.0;
 #pragma unroll
@@ -419,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_apply_coef(HhArgs a) {
             double acc[MBI];
 #pragma unroll
             for (int j = 0; j < MBI; ++j) acc[j] = 0.0;
+            #pragma unroll 4      // four loads in flight per lane
             for (int c = wmin; c < k; ++c) {
                 const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
