@@ -159,7 +159,8 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
 
 /*
  * orth_set_variant -- choose ORTH_PIP_PLUS (default) or ORTH_PIP for the
- * following steps.  Host-side only.  Errors: ARG, POISONED.
+ * following steps.  Host-side only.  Errors: ARG, POISONED, UNSUPPORTED
+ * (ORTH_PIP on an ORTH_FP64_HOUSEHOLDER handle).
  */
 int orth_set_variant(orth_t *h, int32_t variant);
 
@@ -167,8 +168,11 @@ int orth_set_variant(orth_t *h, int32_t variant);
  * orth_set_level_variants -- the subalgorithm of each level separately: the
  * leaves' local problems and the reduction problem (Sec. 4.1 lets each be
  * any PQR method; the experiments of Sec. 6 vary them independently).
- * orth_set_variant(h, v) equals orth_set_level_variants(h, v, v).
- * Host-side only.  Errors: ARG, POISONED.
+ * orth_set_variant(h, v) equals orth_set_level_variants(h, v, v).  The
+ * leaves of an ORTH_FP64_HOUSEHOLDER handle run the Householder method:
+ * their variant must stay ORTH_PIP_PLUS (else UNSUPPORTED), the reduction's
+ * may be either.
+ * Host-side only.  Errors: ARG, POISONED, UNSUPPORTED.
  */
 int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant);
 
