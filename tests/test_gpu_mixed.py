@@ -241,3 +241,71 @@ def test_mixed_fallback_still_breaks_down_where_fp64_does(torch_cuda):
     assert st == orth.ORTH_ERR_BREAKDOWN
     assert info[0] == 0 and info[2] == 1 and info[3] == 6, info
     g.close()
+
+
+def test_mixed_fallback_in_a_graph(torch_cuda):
+    """Three steps of the fallback case captured in a hipGraph and replayed
+    from freshly created handles: the redo is decided on the device (no host
+    read), so every replay equals the eager run bitwise and counts one redo."""
+    import torch
+    from paper_2204_13393_amd import orth
+    _say("mixed fallback graph")
+    n, s, kmax, leaf = 8192, 8, 24, 2048
+    rng = np.random.default_rng(21)
+    W0, _ = np.linalg.qr(rng.standard_normal((n, s)))
+    X1 = W0 @ rng.standard_normal((s, s)) + 1e-5 * rng.standard_normal((n, s)) / np.sqrt(n)
+    X2 = normal_block(n, s, 22)
+    X = [to_dev(x) for x in (W0, X1, X2)]
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, MIXED)
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    side = torch.cuda.Stream()
+
+    def buffers():
+        return (torch.zeros((kmax, kmax), dtype=torch.float64, device="cuda"),
+                torch.empty((kmax, n), dtype=torch.float64, device="cuda"))
+
+    def run(h, H, U):
+        for j in range(3):
+            k = j * s
+            col = H[j * s:(j + 1) * s]
+            hp = col.data_ptr() if k else 0
+            assert orth.orth_step(h, X[j].data_ptr(), n, hp, kmax, col[:, k:].data_ptr(), kmax,
+                                  U[k:k + s].data_ptr(), n) == 0
+
+    He, Ue = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, MIXED, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        run(h, He, Ue)
+    side.synchronize()
+    assert orth.orth_status(h)[1] == 0 and orth.orth_mixed_fallbacks(h)[1] == 1
+    orth.orth_destroy(h)
+    He_h, Ue_h = to_host(He), to_host(Ue)
+
+    Hg, Ug = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_create(n, s, kmax, leaf, MIXED, wp, nbytes, side.cuda_stream)
+        assert code == 0
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        run(h, Hg, Ug)
+    orth.orth_destroy(h)
+    for rep in range(3):
+        code, h = orth.orth_create(n, s, kmax, leaf, MIXED, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        Hg.zero_()
+        Ug.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        code, st, info = orth.orth_status(h)
+        assert code == 0 and st == 0, info
+        assert orth.orth_mixed_fallbacks(h)[1] == 1, rep
+        assert np.array_equal(to_host(Hg), He_h), rep
+        assert np.array_equal(to_host(Ug), Ue_h), rep
+        orth.orth_destroy(h)
+        x = torch.randn(1000, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
