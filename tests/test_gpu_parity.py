@@ -359,12 +359,14 @@ def test_capacity_and_argument_errors(torch_cuda):
     gpu.close()
 
 
-def test_w_may_alias_u(torch_cuda):
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_w_may_alias_u(torch_cuda, form):
+    """W and U may be the same buffer, in every storage form."""
     from paper_2204_13393_amd import Orthogonalizer
-    _say("alias")
+    _say("alias", form)
     n, s = 3000, 4
-    a = Orthogonalizer(n, s, 12, 1000)
-    b = Orthogonalizer(n, s, 12, 1000)
+    a = Orthogonalizer(n, s, 12, 1000, precision=form)
+    b = Orthogonalizer(n, s, 12, 1000, precision=form)
     for j in range(3):
         X = normal_block(n, s, 10 + j)
         _, Ra, Ua = a.step(to_dev(X))
