@@ -660,8 +660,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (one MI355X); "
-              "sharding across GPUs is not part of it", file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU (one MI355X); "
+              "sharding the basis across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":

@@ -61,7 +61,7 @@ enum orth_code {
     ORTH_ERR_HIP = 4,        /* a HIP runtime call failed (no device, launch error) */
     ORTH_ERR_POISONED = 5,   /* handle saw a breakdown earlier; only destroy works */
     ORTH_ERR_WORKSPACE = 6,  /* workspace missing, too small or misaligned */
-    ORTH_ERR_UNSUPPORTED = 7 /* valid request this build does not implement */
+    ORTH_ERR_UNSUPPORTED = 7 /* valid request the library does not implement */
 };
 
 /*
