@@ -79,7 +79,13 @@ __host__ __device__ inline int gram_col_groups(int ncol) {
 __host__ __device__ inline int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
 constexpr int kRootChunk = 2048;      // rows per workgroup at the reduction level
-constexpr int kFinalChunk = 2048;     // rows per workgroup in the leaf row updates
+// rows per workgroup in the leaf row updates: one 512-row pass of a
+// workgroup's four waves at s <= 8 (eight rows per lane); measured 2.7%
+// faster per s = 8 sequence than 2048 (1% at s = 16, equal at s = 32)
+constexpr int kFinalChunk = 512;
+// the batched form's leaf row updates keep 2048-row chunks (1% faster there:
+// its instances are short and each workgroup first locates its instance)
+constexpr int kBatchFinalChunk = 2048;
 // rows per workgroup in the reduction-level row updates: the reduction level
 // has p (k + s) rows, and 512-row chunks give its correction and finalize
 // enough workgroups (its Gram keeps 2048: more chunks mean more partial sums
@@ -336,7 +342,7 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
             return d.p;
         case BP_LCORR:
         case BP_LFIN:
-            return make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk).nchunks();
+            return make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk).nchunks();
         case BP_RGRAM:
         case BP_RGRAM2:
             return make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_col_groups(ncol);

@@ -1519,7 +1519,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.Qnew = OutOperand{d.U1L, d.ldq};
             f.U1 = Operand{a.W[inst], d.n};
             f.sweep = 1;
-            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
+            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk);
             f.small = d.SL;
             rowmfma_body<S, false, rowmfma_tr<S, false>(), rowmfma_pf<S, false>()>(f, local);
             return;
@@ -1550,7 +1550,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.U1 = Operand{d.U1L, d.ldq};
             f.sweep = 2;
             f.single_sweep = a.two ? 0 : 1;
-            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kFinalChunk);
+            f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk);
             f.small = d.SL;
             f.Cptr = d.CL;
             f.cseg = (int64_t)d.kmax * 2 * S;
