@@ -17,6 +17,9 @@ pqr          The PQR problem, eq. (1.1): the unique reference solution
              Cholesky.
 hhpqr        The Householder method for the PQR problem (Sec. 2.2,
              Algorithm "HH"), the basis held as unit reflectors.
+deflate      Deflation of BCGS-PIP(+) by the truncated eigen decomposition
+             of G - P^T P (Sec. 3.1) and the deflated PQR solution from
+             the SVD of the residual.
 tspqr        TreeTSPQR (Sec. 4.1) with the locally orthogonal basis
              representation, single- and multi-level trees; BCGS-PIP,
              BCGS-PIP+ or Householder leaves.
@@ -37,6 +40,8 @@ from .householder import householder_qr, house
 from .pqr import (Breakdown, cholesky_upper, triu_solve_right, pqr_reference,
                   bcgs_pip, bcgs_pip_plus, SUBALGORITHMS)
 from .hhpqr import HouseholderBasis, hh_pqr
+from .deflate import (truncated_sqrt, deflating_pip, deflating_pip_plus,
+                      pqr_deflated_reference)
 from .tspqr import TreeTSPQR, leaf_bounds
 from .krylov import block_arnoldi, block_column_qr
 from . import operators, metrics
@@ -44,6 +49,7 @@ from . import operators, metrics
 __all__ = [
     "householder_qr", "house", "Breakdown", "cholesky_upper",
     "triu_solve_right", "pqr_reference", "bcgs_pip", "bcgs_pip_plus",
-    "SUBALGORITHMS", "HouseholderBasis", "hh_pqr", "TreeTSPQR", "leaf_bounds", "block_arnoldi",
+    "SUBALGORITHMS", "HouseholderBasis", "hh_pqr", "truncated_sqrt",
+    "deflating_pip", "deflating_pip_plus", "pqr_deflated_reference", "TreeTSPQR", "leaf_bounds", "block_arnoldi",
     "block_column_qr", "operators", "metrics",
 ]

@@ -38,7 +38,7 @@ class Breakdown(ArithmeticError):
 
     Sec. 3.1 notes that the textbook Cholesky factorisation is not
     rank-revealing; the oracle reports breakdown instead of deflating
-    (deflation by a truncated SVD of G - P^T P is a separate feature).
+    (deflation by a truncated SVD of G - P^T P is ``oracle.deflate``).
     """
 
     def __init__(self, index, pivot):

@@ -40,7 +40,10 @@ Readings adopted where the paper is silent:
 import numpy as np
 
 from .hhpqr import HouseholderBasis
+from .deflate import deflating_pip, deflating_pip_plus
 from .pqr import SUBALGORITHMS
+
+DEFLATING = {"pip": deflating_pip, "pip+": deflating_pip_plus}
 
 
 def leaf_bounds(n, leaf_rows):
@@ -74,14 +77,25 @@ class TreeTSPQR:
                 Householder method (Sec. 2.2), each leaf basis then held as
                 reflectors (``oracle.hhpqr.HouseholderBasis``).
     fan_in      None for the single-level tree, else the tree fan-in.
+    deflate     None, or the relative tolerance delta of the deflating
+                reduction (``oracle.deflate``, Sec. 3.1): the single
+                reduction node drops the directions whose residual singular
+                value is at most delta ||X||_F.  ``last_rank`` is the rank t
+                of the latest block; the width stays s (zero columns).
     """
 
-    def __init__(self, n, s, leaf_rows, local="pip+", reduction="pip+", fan_in=None):
+    def __init__(self, n, s, leaf_rows, local="pip+", reduction="pip+", fan_in=None, deflate=None):
         self.n, self.s = int(n), int(s)
         self.bounds = leaf_bounds(self.n, int(leaf_rows))
         self.householder = local == "hh"
         self.local = None if self.householder else SUBALGORITHMS[local]
         self.reduction = SUBALGORITHMS[reduction]
+        self.deflate = deflate
+        self.last_rank = None
+        if deflate is not None:
+            if reduction not in DEFLATING or not deflate > 0.0:
+                raise ValueError("deflation needs reduction 'pip' or 'pip+' and delta > 0")
+            self.reduction = DEFLATING[reduction]
         self.k = 0
         p = len(self.bounds)
         if self.householder:
@@ -98,6 +112,8 @@ class TreeTSPQR:
             count = len(groups)
             if count == 1:
                 break
+        if deflate is not None and len(self.levels) != 1:
+            raise ValueError("deflation is defined for the single-level tree")
 
     @property
     def p(self):
@@ -133,7 +149,10 @@ class TreeTSPQR:
                 # old k coordinates, zero rows over the child's s new ones
                 B = np.vstack([np.vstack([Sc, np.zeros((s, k))]) for Sc in node["S"]])
                 Yv = np.vstack(Y[c0:c1])
-                Pv, Nv, Uv = self.reduction(B, Yv)
+                if self.deflate is None:
+                    Pv, Nv, Uv = self.reduction(B, Yv)
+                else:
+                    Pv, Nv, Uv, self.last_rank = self.reduction(B, Yv, self.deflate)
                 cols_level.append(Uv)
                 Y_up.append(np.vstack([Pv, Nv]))
             new_cols.append(cols_level)
