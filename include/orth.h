@@ -177,6 +177,43 @@ int orth_set_variant(orth_t *h, int32_t variant);
 int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant);
 
 /*
+ * orth_set_deflation -- deflation at the reduction level (Sec. 3.1) for the
+ * following steps: the reduction's first sweep takes the eigen
+ * decomposition G - P^T P = V Lambda V^T in place of the Cholesky
+ * factorisation and keeps the t eigenvalues above (delta ||W||_F)^2, i.e.
+ * the directions whose residual singular value exceeds delta ||W||_F.
+ *   t = s   the step is the plain one (R triangular, as without deflation);
+ *   t < s   R = [Lambda~^{1/2} V~^T; 0] (kept eigenvalues in decreasing
+ *           order, each eigenvector signed so that its entry of largest
+ *           magnitude is positive), then the second sweep (ORTH_PIP_PLUS
+ *           reduction) multiplies by its s x s factor diag(L, 0) from the
+ *           left (R = N2 N1).  Columns t..s-1 of U and rows t..s-1 of R
+ *           are zero, and the basis still grows by s columns (the zero
+ *           ones included: a zero column of a later W is dropped again, and
+ *           orth_apply_Q's coefficients for them do not matter).
+ *   delta   0 turns deflation off (the default; a rank-deficient block then
+ *           breaks down); 0 < delta < 1 turns it on.  The Gram matrix holds
+ *           rounding errors of about 1e-16 ||W||_F^2, so delta should stay
+ *           well above 1e-8 (1e-6 is a safe choice).
+ * The rank of the latest step is on the device; orth_deflation_info reads
+ * it.  Only ORTH_FP64_HOUSEHOLDER handles deflate: BCGS-PIP leaves break
+ * down on a block that is rank deficient as a whole, since every leaf's
+ * part of it is rank deficient too.  Host-side only.
+ * Errors: ARG (delta < 0, >= 1 or NaN), POISONED, UNSUPPORTED (other forms).
+ */
+int orth_set_deflation(orth_t *h, double delta);
+
+/*
+ * orth_deflation_info -- synchronise the handle's stream and read the
+ * deflation record.  Any output pointer may be NULL.
+ *   rank     t of the latest step taken with deflation on (s before any)
+ *   steps    steps so far with t < s
+ *   dropped  columns dropped so far (sum of s - t)
+ * Handles that cannot deflate report s, 0, 0.  Errors: ARG, HIP.
+ */
+int orth_deflation_info(orth_t *h, int32_t *rank, int64_t *steps, int64_t *dropped);
+
+/*
  * orth_step -- solve the PQR problem eq. (1.1) for the new block W and grow
  * the basis by s columns (Sec. 4.1, TreeTSPQR; one step of the block
  * Arnoldi process, Sec. 2).

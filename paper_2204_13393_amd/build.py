@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborth.so")
-SOURCES = ["orth_kernels.hip", "orth_hh.hip", "orth_api.hip"]
+SOURCES = ["orth_kernels.hip", "orth_hh.hip", "orth_deflate.hip", "orth_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

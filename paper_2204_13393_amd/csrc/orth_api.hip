@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/orth.h"
+#include "orth_deflate.h"
 #include "orth_internal.h"
 
 using namespace orth;
@@ -59,7 +60,7 @@ struct Plan {
     int64_t ldq, ldt;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
-    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, total;
+    int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -145,6 +146,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
     // and orth_apply_Q's second coefficient scratch (-Z_i), like CA
     pl.oCA2 = precision == ORTH_FP64_HOUSEHOLDER ? take(pl.ldt * kApplyMB) : 0;
+    // deflation state (counters and the first sweep's s x s W), Householder leaves only
+    pl.oDF = precision == ORTH_FP64_HOUSEHOLDER ? take(defl_state_doubles(s)) : 0;
     pl.total = off;
     return true;
 }
@@ -162,6 +165,7 @@ struct orth_ctx {
     int32_t k = 0;
     int32_t variant = ORTH_PIP_PLUS;       // the leaves' subalgorithm
     int32_t variant_red = ORTH_PIP_PLUS;   // the reduction's
+    double defl_delta = 0.0;               // > 0: the reduction level deflates (Sec. 3.1)
     bool poisoned = false;
     hipStream_t stream = nullptr;
     double *ws = nullptr;
@@ -216,6 +220,9 @@ struct orth_ctx {
     }
     double *TH() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oTH : nullptr; }
     double *CA2() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oCA2 : nullptr; }
+    DeflState *DF() const {
+        return pl.precision == ORTH_FP64_HOUSEHOLDER ? reinterpret_cast<DeflState *>(ws + pl.oDF) : nullptr;
+    }
     double *PR() const { return ws + pl.oPR; }
     double *PR2() const { return ws + pl.oPR2; }
     double *SL() const { return ws + pl.oSL; }
@@ -256,6 +263,9 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     // Householder leaves: the compact-WY factors grow into zeros below their diagonal
     if (e == hipSuccess && h->TH())
         e = launch_fill(h->TH(), (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
+    if (e == hipSuccess && h->DF())
+        e = launch_fill_i32(reinterpret_cast<int32_t *>(h->DF()), (int64_t)(sizeof(DeflState) / sizeof(int32_t)), 0,
+                            h->stream);
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
                             (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, h->stream);
@@ -309,6 +319,7 @@ struct LevelRun {
     double *R;
     int64_t ldr;
     LevelGeom rgeom;      // chunks of the correction (row update) launch
+    const DeflArgs *defl; // reduction level with deflation: eigen-based first sweep
 };
 
 int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
@@ -387,7 +398,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
             c.slots_per_leaf = c.slots_last = (int32_t)ceil_div(r.nslots, kReduceGroup);
         }
         const int pm = h->begin(cls);
-        e = launch_chol(s, c, st);
+        e = L.defl ? launch_defl(s, c, *L.defl, st) : launch_chol(s, c, st);
         h->end(pm);
         return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
     };
@@ -425,6 +436,16 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     {
         const int pm = h->begin(cls0 + 2);
         e = launch_finalize(s, f, cls0 + 2, st);
+        if (e == hipSuccess && L.defl) {
+            // after a drop the row update formed x - q P1; u1 = (x - q P1) W
+            DeflRowArgs dr{};
+            dr.U = L.U1.ptr;
+            dr.ld = L.U1.ld;
+            dr.geom = L.rgeom;
+            dr.state = L.defl->state;
+            dr.status = h->status();
+            e = launch_defl_rows(s, dr, st);
+        }
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
@@ -638,6 +659,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.ldh = ldh;
         L.R = d_R;
         L.ldr = ldr;
+        DeflArgs dargs{h->defl_delta * h->defl_delta, h->DF()};
+        L.defl = h->defl_delta > 0.0 ? &dargs : nullptr;
         if ((rc = run_level(h, L, k, two_red))) goto fail;
 
         // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s], and
@@ -774,6 +797,31 @@ int orth_status(orth_t *h, int32_t *status, int32_t *info) {
         info[2] = ds.sweep;
         info[3] = ds.column;
     }
+    return ORTH_OK;
+}
+
+int orth_set_deflation(orth_t *h, double delta) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    if (!(delta >= 0.0 && delta < 1.0)) return ORTH_ERR_ARG;      // NaN fails too
+    if (delta > 0.0 && !h->DF()) return ORTH_ERR_UNSUPPORTED;
+    h->defl_delta = delta;
+    return ORTH_OK;
+}
+
+int orth_deflation_info(orth_t *h, int32_t *rank, int64_t *steps, int64_t *dropped) {
+    if (!h) return ORTH_ERR_ARG;
+    DeflState d{};
+    if (h->DF()) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess ||
+            hipMemcpy(&d, h->DF(), sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            return ORTH_ERR_HIP;
+        }
+    }
+    if (rank) *rank = h->pl.s - d.dropped;
+    if (steps) *steps = d.steps;
+    if (dropped) *dropped = d.total;
     return ORTH_OK;
 }
 

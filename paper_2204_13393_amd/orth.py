@@ -41,6 +41,8 @@ SIGNATURES = [
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
     ("orth_mixed_fallbacks", ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
+    ("orth_set_deflation", ctypes.c_int, [_vp, ctypes.c_double]),
+    ("orth_deflation_info", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("orth_step", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64]),
     ("orth_apply_Q", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
     ("orth_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -125,6 +127,17 @@ def orth_mixed_fallbacks(h):
     n = _i64(0)
     code = load().orth_mixed_fallbacks(h, ctypes.byref(n))
     return code, n.value
+
+
+def orth_set_deflation(h, delta):
+    return load().orth_set_deflation(h, float(delta))
+
+
+def orth_deflation_info(h):
+    """(code, rank of the latest step, steps with a drop, columns dropped)."""
+    t, st, dr = _i32(0), _i64(0), _i64(0)
+    code = load().orth_deflation_info(h, ctypes.byref(t), ctypes.byref(st), ctypes.byref(dr))
+    return code, t.value, st.value, dr.value
 
 
 def orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu):
@@ -339,6 +352,16 @@ class Orthogonalizer:
         code, st, info = orth_status(self.h)
         _check("orth_status", code)
         return st, info
+
+    def set_deflation(self, delta):
+        """Deflate at the reduction level with relative tolerance delta (0: off)."""
+        _check("orth_set_deflation", orth_set_deflation(self.h, delta))
+
+    def deflation_info(self):
+        """(rank of the latest step, steps with a drop, columns dropped)."""
+        code, t, steps, dropped = orth_deflation_info(self.h)
+        _check("orth_deflation_info", code)
+        return t, steps, dropped
 
     def export_local(self):
         """(Qloc (k, n) column-major n x k, T (k, p*k) column-major (p k) x k)."""
