@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 
 METRIC = "block-Arnoldi orth step time + HBM GB/s, mixed vs FP64 at \u2016I\u2212Q\u1d40Q\u2016\u22641e-10"
 HBM_PEAK_GBS = 8000.0
+DEFL_DELTA = 1e-6       # relative tolerance of the deflating runs
 WORKLOAD = dict(name="lap2d-4096x4096-s8", nx=4096, ny=4096, s=8, steps=30, leaf_rows=4096, seed=0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2204_13393_amd", "csrc", "orth_kernels.hip")
@@ -552,7 +553,10 @@ def bench_stewart(args):
     from 1 to 1e-12 (kappa 1e6 and 1e12); V Haar (QR of a Gaussian), G
     Gaussian / sqrt(n), orthonormal to about 2 sqrt(240/n) = 0.008 at this n, so
     the singular values of W are sigma to within 1%.  FP64, mixed and
-    Householder-leaf forms.
+    Householder-leaf forms, and the Householder leaves with deflation at the
+    reduction level (Sec. 3.1, delta = 1e-6): a call drops the directions
+    whose residual singular value is below delta ||W_j||_F, so the kappa =
+    1e12 run goes on where the other forms break down, with a smaller basis.
     Per form and range: status (and the call after which a breakdown was
     reported), the calls in which the mixed form redid its first sweep in
     FP64, time of the calls (HIP events around each), e_perp of the explicit Q
@@ -574,7 +578,8 @@ def bench_stewart(args):
     Qt = torch.empty((m, n), dtype=torch.float64, device=dev)          # explicit Q, column-major n x m
     Rt = torch.zeros((m, m), dtype=torch.float64, device=dev)          # R, column-major m x m
     forms = (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32),
-             ("householder", orth.ORTH_FP64_HOUSEHOLDER))
+             ("householder", orth.ORTH_FP64_HOUSEHOLDER),
+             ("householder+deflation", orth.ORTH_FP64_HOUSEHOLDER))
     nbytes = max(orth.orth_workspace_bytes(n, s, m, leaf, f) for _, f in forms)
     wsbuf = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
     ws_ptr = (wsbuf.data_ptr() + 255) // 256 * 256
@@ -589,6 +594,10 @@ def bench_stewart(args):
                 code, h = orth.orth_create(n, s, m, leaf, prec, ws_ptr, nbytes, sp)
                 if code:
                     raise orth.OrthError("orth_create", code)
+                if name.endswith("deflation"):
+                    code = orth.orth_set_deflation(h, DEFL_DELTA)
+                    if code:
+                        raise orth.OrthError("orth_set_deflation", code)
                 ms, failed = 0.0, None
                 for j in range(m // s):
                     k = j * s
@@ -606,12 +615,20 @@ def bench_stewart(args):
                         break
                     ms += e0.elapsed_time(e1)
                 code, nfall = orth.orth_mixed_fallbacks(h)
+                _, _, dsteps, dcols = orth.orth_deflation_info(h)
                 orth.orth_destroy(h)
             row = {"form": name, "sigma_min": smin, "status": "breakdown" if failed else "ok",
                    "breakdown": failed, "fallback_steps": nfall}
+            if name.endswith("deflation"):
+                row.update({"delta": DEFL_DELTA, "deflated_calls": dsteps, "columns_dropped": dcols})
             if not failed:
-                Gq = torch.mm(Qt, Qt.t())
-                Gq -= torch.eye(m, dtype=torch.float64, device=dev)
+                # e_perp over the kept columns (a dropped column of Q is exactly zero)
+                keep = torch.linalg.vector_norm(Qt, dim=1) > 0.5
+                Qk = Qt[keep]
+                row["columns_kept"] = int(Qk.shape[0])
+                Gq = torch.mm(Qk, Qk.t())
+                Gq -= torch.eye(Qk.shape[0], dtype=torch.float64, device=dev)
+                del Qk
                 row["e_perp"] = float(torch.linalg.matrix_norm(Gq, "fro"))
                 del Gq
                 res2 = 0.0
@@ -630,6 +647,7 @@ def bench_stewart(args):
     speed = {str(k): fp[k]["ms_30_calls"] / mx[k]["ms_30_calls"]
              for k in fp if fp[k]["status"] == "ok" and mx[k]["status"] == "ok"}
     hx = {r["sigma_min"]: r for r in results if r["form"] == "householder"}
+    hd = {r["sigma_min"]: r for r in results if r["form"] == "householder+deflation"}
     speed_hh = {str(k): fp[k]["ms_30_calls"] / hx[k]["ms_30_calls"]
                 for k in fp if fp[k]["status"] == "ok" and hx[k]["status"] == "ok"}
     out = {
@@ -638,6 +656,8 @@ def bench_stewart(args):
         "results": results,
         "mixed_speedup_vs_fp64": speed,
         "householder_speedup_vs_fp64": speed_hh,
+        "deflation_overhead_vs_householder": {str(k): hd[k]["ms_30_calls"] / hx[k]["ms_30_calls"]
+                                              for k in hx if hx[k]["status"] == "ok" and hd[k]["status"] == "ok"},
         "dtype": "f64",
         "data": "synthetic: W = G diag(sigma) V^T, G Gaussian/sqrt(n), V Haar (torch, seed 7)",
     }
@@ -716,10 +736,16 @@ def main():
             if code:
                 raise orth.OrthError("orth_step", code)
 
+    defl_delta = [0.0]      # > 0: Householder handles deflate at the reduction level
+
     def make_handle(precision=orth.ORTH_FP64):
         code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sptr)
         if code:
             raise orth.OrthError("orth_create", code)
+        if defl_delta[0] > 0.0:
+            code = orth.orth_set_deflation(h, defl_delta[0])
+            if code:
+                raise orth.OrthError("orth_set_deflation", code)
         return h
 
     # closed-loop Arnoldi once, to produce the Krylov blocks (not timed)
@@ -761,6 +787,7 @@ def main():
         return pr, max(with_bytes, key=lambda c: pr[c][0])
 
     fallbacks = {}      # steps whose first sweep was redone in FP64, per form
+    drops = {}          # columns dropped by deflation, per form
 
     def timed_runs(precision, dom):
         """Warmup, then args.steps timed sequences over the resident inputs,
@@ -791,11 +818,13 @@ def main():
         gpu_ms = ev0.elapsed_time(ev1) / args.steps
         dom_ms, dom_n = 0.0, 0
         fallbacks[precision] = 0
+        drops[precision] = 0
         for h in handles:
             code, st, info = orth.orth_status(h)
             if code or st:
                 raise RuntimeError(f"orth_step breakdown: {info}")
             fallbacks[precision] += orth.orth_mixed_fallbacks(h)[1]
+            drops[precision] += orth.orth_deflation_info(h)[3]
             if dom is not None:
                 code, pr = orth.orth_profile_read(h)
                 dom_ms += pr[dom][0]
@@ -824,6 +853,16 @@ def main():
         print(f"[bench] householder leaves: {ms_hh:.2f} ms per sequence, e_perp {e_perp_hh:.2e}",
               file=sys.stderr, flush=True)
         hh = (ms_hh, e_perp_hh, prof_hh)
+        # the same with deflation switched on (Sec. 3.1): the reduction level's
+        # first sweep takes the Jacobi eigen decomposition in place of the
+        # Cholesky factorisation; these full-rank blocks drop nothing
+        defl_delta[0] = DEFL_DELTA
+        prof_hd = None if args.no_profile else profiled_sequence(orth.ORTH_FP64_HOUSEHOLDER)[0]
+        ms_hd, _, e_perp_hd = timed_runs(orth.ORTH_FP64_HOUSEHOLDER, None)
+        defl_delta[0] = 0.0
+        print(f"[bench] householder leaves with deflation: {ms_hd:.2f} ms per sequence, "
+              f"{drops[orth.ORTH_FP64_HOUSEHOLDER]} columns dropped", file=sys.stderr, flush=True)
+        hh_defl = (ms_hd, e_perp_hd, prof_hd, drops[orth.ORTH_FP64_HOUSEHOLDER])
 
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
     value = total_bytes / (ms_per_step / 1e3) / 1e9
@@ -910,6 +949,16 @@ def main():
             "e_perp_gate_1e-10": hh[1] <= 1e-10,
             # the first call (k = 0) has no Q_k^T w passes
             "kernels": per_class(hh[2], ("leaf_gram", "leaf_correct")) if hh[2] else {},
+            "with_deflation": {
+                "delta": DEFL_DELTA,
+                "ms_per_step": hh_defl[0],
+                "overhead_vs_householder": hh_defl[0] / hh[0],
+                "columns_dropped": hh_defl[3],
+                "e_perp": hh_defl[1],
+                # root_chol holds the Jacobi eigen solver, root_correct the u1 W pass
+                "kernels": {c: v for c, v in per_class(hh_defl[2]).items()
+                            if c in ("root_chol", "root_correct")} if hh_defl[2] else {},
+            },
         },
         "roofline": roofline,
         "kernels": kernels,

@@ -327,3 +327,72 @@ def test_deflation_graph_replay(torch_cuda):
         x = torch.randn(1000, device="cuda", dtype=torch.float64)
         torch.cuda.synchronize()
         assert torch.isfinite(x.sum())
+
+
+def test_deflation_full_size_stewart(torch_cuda):
+    """The precision workload at its full size (n = 2^24, s = 8, 30 calls,
+    leaf height 4096, sigma from 1 to 1e-12): with deflation the run ends
+    without breakdown; per call, the rank equals the number of singular
+    values of the projected block (torch's SVD of W_j - Q Q^T W_j on the
+    device) above delta ||W_j||_F wherever none lies within a factor 2 of
+    that threshold; dropped columns of Q and rows of R are exact zeros; the
+    kept columns are orthonormal; W = Q R to the dropped energy."""
+    import torch
+    from paper_2204_13393_amd import orth
+    n, m, s, leaf = 1 << 24, 240, 8, 4096
+    _say("deflation full size stewart", n, m, s, leaf)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    Gt = torch.randn((m, n), dtype=torch.float64, device="cuda", generator=gen)
+    Gt /= math.sqrt(n)
+    Vh, _ = torch.linalg.qr(torch.randn((m, m), dtype=torch.float64, device="cuda", generator=gen))
+    sig = torch.logspace(0.0, -12.0, m, dtype=torch.float64, device="cuda")
+    Wt = torch.mm(Vh * sig, Gt)
+    del Gt
+    Qt = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+    Rt = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    H_ = orth.ORTH_FP64_HOUSEHOLDER
+    nbytes = orth.orth_workspace_bytes(n, s, m, leaf, H_)
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    code, h = orth.orth_create(n, s, m, leaf, H_, wp, nbytes, torch.cuda.current_stream().cuda_stream)
+    assert code == 0
+    assert orth.orth_set_deflation(h, DELTA) == 0
+    checked, total_drop = 0, 0
+    for j in range(m // s):
+        k = j * s
+        col = Rt[k:k + s]
+        assert orth.orth_step(h, Wt[k:k + s].data_ptr(), n, col.data_ptr(), m, col[:, k:].data_ptr(), m,
+                              Qt[k:k + s].data_ptr(), n) == 0
+        code, t, _, dropped = orth.orth_deflation_info(h)
+        assert code == 0
+        # Qt row c is column c of Q; Rt[c, r] = R[r, c]
+        assert torch.all(Qt[k + t:k + s] == 0.0) and torch.all(Rt[k:k + s, k + t:k + s] == 0.0), j
+        Wj = Wt[k:k + s]
+        Rj = Wj - torch.mm(torch.mm(Wj, Qt[:k].t()), Qt[:k]) if k else Wj.clone()
+        Rj -= torch.mm(torch.mm(Rj, Qt[:k].t()), Qt[:k]) if k else 0.0
+        sv = torch.linalg.svdvals(torch.mm(Rj, Rj.t())).sqrt()
+        thr = DELTA * float(torch.linalg.norm(Wj))
+        if not bool(torch.any((sv > 0.5 * thr) & (sv < 2.0 * thr))):
+            assert t == int(torch.count_nonzero(sv > thr)), j
+            checked += 1
+        total_drop += s - t
+        del Rj
+    assert dropped == total_drop > 0
+    assert checked >= 10
+    code, st, info = orth.orth_status(h)
+    assert code == 0 and st == 0, info
+    orth.orth_destroy(h)
+    keep = torch.linalg.vector_norm(Qt, dim=1) > 0.5
+    assert int(keep.sum()) == m - total_drop
+    Qk = Qt[keep]
+    Gq = torch.mm(Qk, Qk.t())
+    Gq -= torch.eye(Qk.shape[0], dtype=torch.float64, device="cuda")
+    assert float(torch.linalg.matrix_norm(Gq, "fro")) <= 1e-12
+    del Gq, Qk
+    res2 = 0.0
+    for c0 in range(0, n, 1 << 21):
+        D = Wt[:, c0:c0 + (1 << 21)] - torch.mm(Rt, Qt[:, c0:c0 + (1 << 21)])     # W^T = R^T Q^T
+        res2 += float(torch.sum(D * D))
+        del D
+    assert math.sqrt(res2) / float(torch.linalg.norm(Wt)) <= 1e-5
