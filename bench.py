@@ -497,15 +497,19 @@ def bench_kappa_sweep(args):
     sigma_j = kappa^(-j/31), n = 2^16, 32 columns in blocks of s = 4 (eight
     orth_step calls), leaves of 256 rows, for kappa = 10^0 .. 10^12 and the
     four combinations of BCGS-PIP / BCGS-PIP+ at the leaves and at the
-    reduction, plus Householder leaves (Sec. 2.2) with either reduction.  Per case: status (breakdown or not) and e_perp of the
-    explicit basis.  The matrices come from synth.stewart (seed 11)."""
+    reduction, plus Householder leaves (Sec. 2.2) with either reduction, and
+    Householder leaves with a deflating BCGS-PIP+ reduction (Sec. 3.1,
+    delta = 1e-6).  Per case: status (breakdown or not) and e_perp of the
+    explicit basis (of its kept columns, with the count dropped, for the
+    deflating case).  The matrices come from synth.stewart (seed 11)."""
     import numpy as np
     import torch
     from paper_2204_13393_amd import Orthogonalizer, orth
     from synth import stewart
     n, m, s, leaf = 1 << 16, 32, 4, 256
     v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
-    combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip"), ("hh", "pip+"), ("hh", "pip")]
+    combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip"), ("hh", "pip+"), ("hh", "pip"),
+              ("hh", "pip+/deflation")]
     rows = []
     print("[bench] kappa sweep: Stewart n = 2^16, 32 columns, s = 4, leaves of 256 rows", file=sys.stderr, flush=True)
     for e in range(13):
@@ -514,8 +518,12 @@ def bench_kappa_sweep(args):
         At = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
         row = {"kappa": kappa}
         for local, red in combos:
+            defl = red.endswith("/deflation")
             if local == "hh":
-                g = Orthogonalizer(n, s, m, leaf, precision=orth.ORTH_FP64_HOUSEHOLDER, reduction_variant=v[red])
+                g = Orthogonalizer(n, s, m, leaf, precision=orth.ORTH_FP64_HOUSEHOLDER,
+                                   reduction_variant=v[red.split("/")[0]])
+                if defl:
+                    g.set_deflation(DEFL_DELTA)
             else:
                 g = Orthogonalizer(n, s, m, leaf, variant=v[local], reduction_variant=v[red])
             blocks = []
@@ -528,7 +536,13 @@ def bench_kappa_sweep(args):
                 # e_perp on the host (FP64 BLAS): a 32 x 32 Gram of 2^16 rows of
                 # the explicit blocks U the calls returned
                 Q = torch.cat(blocks).cpu().numpy()
-                row[f"{local}/{red}"] = float(np.linalg.norm(Q @ Q.T - np.eye(m), "fro"))
+                if defl:
+                    keep = np.linalg.norm(Q, axis=1) > 0.5          # dropped columns are zero
+                    Qk = Q[keep]
+                    row[f"{local}/{red}"] = {"e_perp": float(np.linalg.norm(Qk @ Qk.T - np.eye(len(Qk)), "fro")),
+                                             "dropped": int(m - keep.sum())}
+                else:
+                    row[f"{local}/{red}"] = float(np.linalg.norm(Q @ Q.T - np.eye(m), "fro"))
             else:
                 row[f"{local}/{red}"] = {"breakdown": {"level": info[0], "sweep": info[2], "column": info[3]}}
             g.close()
