@@ -18,8 +18,9 @@
 // U and rows of N are zero, and a later zero column is dropped again.
 //
 // The eigen decomposition is cyclic Jacobi with the round-robin ordering:
-// s/2 disjoint rotations per round, s - 1 rounds per sweep, a fixed number
-// of sweeps (every workgroup ends after the same work).
+// s/2 disjoint rotations per round, s - 1 rounds per sweep, until every
+// off-diagonal entry is negligible against its diagonal pair, at most
+// kJacobiSweeps sweeps (so every launch ends).
 
 #include <hip/hip_runtime.h>
 
@@ -95,10 +96,11 @@ __device__ void sym_schur2(double app, double apq, double aqq, double &c, double
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_defl(CholArgs a, DeflArgs d) {
     if (a.status->code != 0) return;
-    __shared__ double gs[S * S], sm[S * S], A[S * S], V[S * S], nm[S * S], ni[S * S], n1[S * S];
+    __shared__ double gs[S * S], sm[S * S], AV[2 * S * S], nm[S * S], ni[S * S], n1[S * S];
+    double *A = AV, *V = AV + S * S;
     __shared__ double lam[S], rc[S], rsn[S];
     __shared__ int rp[S], rq[S], ord[S];
-    __shared__ int t_sh, bad;
+    __shared__ int t_sh, bad, done;
     const int tid = threadIdx.x;
     const int k = a.k, ncol = k + S;
     DeflState *ds = d.state;
@@ -123,14 +125,35 @@ __global__ __launch_bounds__(kThreads) void k_defl(CholArgs a, DeflArgs d) {
     if (a.sweep == 2)
         for (int e = tid; e < S * S; e += kThreads) n1[e] = recN1[e];
     __syncthreads();
-    // 2. sm = G - P^T P
-    for (int e = tid; e < S * S; e += kThreads) {
-        const int i = e / S, j = e % S;
-        double acc = 0.0;
-        for (int c = 0; c < k; ++c) acc = fma(recP[(int64_t)c * S + i], recP[(int64_t)c * S + j], acc);
-        sm[e] = gs[e] - acc;
-        nm[e] = 0.0;
-        ni[e] = 0.0;
+    // 2. sm = G - P^T P, P staged through LDS (A and V, free until step 3)
+    //    in chunks of 2 S rows; each entry sums its rows in increasing order
+    constexpr int EPT = (S * S + kThreads - 1) / kThreads;
+    constexpr int CB = 2 * S;
+    double acc[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) acc[m] = 0.0;
+    for (int c0 = 0; c0 < k; c0 += CB) {
+        const int cb = k - c0 < CB ? k - c0 : CB;
+        for (int e = tid; e < cb * S; e += kThreads) A[e] = recP[(int64_t)c0 * S + e];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EPT; ++m) {
+            const int e = tid + kThreads * m;
+            if (e < S * S) {
+                const int i = e / S, j = e % S;
+                for (int c = 0; c < cb; ++c) acc[m] = fma(A[c * S + i], A[c * S + j], acc[m]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+        const int e = tid + kThreads * m;
+        if (e < S * S) {
+            sm[e] = gs[e] - acc[m];
+            nm[e] = 0.0;
+            ni[e] = 0.0;
+        }
     }
     __syncthreads();
 
@@ -144,6 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_defl(CholArgs a, DeflArgs d) {
         __syncthreads();
         if constexpr (S > 1) {
             constexpr int H = S / 2;
+            if (tid == 0) done = 0;
             for (int sw = 0; sw < kJacobiSweeps; ++sw) {
                 for (int r = 0; r < S - 1; ++r) {
                     // round r pairs S-1 with r and (r + i) with (r - i) mod S-1
@@ -181,6 +205,22 @@ __global__ __launch_bounds__(kThreads) void k_defl(CholArgs a, DeflArgs d) {
                     }
                     __syncthreads();
                 }
+                // converged: every off-diagonal entry below 1e-18 of the
+                // geometric mean of its diagonal pair (or exactly zero)
+                if (tid == 0) {
+                    int conv = 1;
+                    for (int i = 0; i < S && conv; ++i)
+                        for (int j = i + 1; j < S; ++j) {
+                            const double a = fabs(A[i * S + j]);
+                            if (a != 0.0 && !(a <= 1e-18 * sqrt(fabs(A[i * S + i]) * fabs(A[j * S + j])))) {
+                                conv = 0;
+                                break;
+                            }
+                        }
+                    done = conv;
+                }
+                __syncthreads();
+                if (done) break;
             }
         }
         // 4. order, rank, and the breakdown of a non-finite block
