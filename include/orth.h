@@ -222,7 +222,8 @@ int orth_deflation_info(orth_t *h, int32_t *rank, int64_t *steps, int64_t *dropp
  *   d_H, ldh   k x s output, H = Q^T W; ldh >= max(1, k).  May be NULL when
  *              k = 0 (the first step is the QR of the start block).
  *   d_R, ldr   s x s output, upper triangular with positive diagonal, zeros
- *              written below the diagonal; ldr >= s.
+ *              written below the diagonal; ldr >= s.  (A deflating step,
+ *              see orth_set_deflation, writes the row-padded t x s factor.)
  *   d_U, ldu   n x s output, the explicit new orthonormal block; ldu >= n.
  * H and R may point into the caller's block Hessenberg matrix (column block
  * j: d_H at its top, d_R = d_H + k with ldh = ldr = its leading dimension).

@@ -56,12 +56,13 @@ def test_workspace_rejects_bad_arguments(args):
 def test_householder_form_workspace_and_limits():
     H = orth.ORTH_FP64_HOUSEHOLDER
     # adds three k_max x k_max blocks per leaf (T in both orders, the
-    # reflectors' top rows) and a second apply_Q coefficient scratch
+    # reflectors' top rows), a second apply_Q coefficient scratch and the
+    # deflation state (64 bytes and an s x s matrix)
     for (n, s, k, lr) in ((10000, 4, 44, 1000), (2 ** 24, 8, 248, 4096), (777, 1, 12, 100)):
         f64 = orth.orth_workspace_bytes(n, s, k, lr, 0)
         hh = orth.orth_workspace_bytes(n, s, k, lr, H)
         p = max(1, n // lr)
-        extra = 3 * p * k * k * 8 + (p * k + 64) * 16 * 8     # and the apply scratch
+        extra = 3 * p * k * k * 8 + (p * k + 64) * 16 * 8 + 64 + s * s * 8 + 256
         assert 3 * p * k * k * 8 <= hh - f64 <= extra + 512
     # limits: the panel kernel's register capacity and k_max s <= 4096
     assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 4096, H) > 0
@@ -119,6 +120,8 @@ def test_null_handle_calls():
     assert orth.orth_set_variant(None, 0) == orth.ORTH_ERR_ARG
     assert orth.orth_set_level_variants(None, 0, 1) == orth.ORTH_ERR_ARG
     assert orth.orth_mixed_fallbacks(None)[0] == orth.ORTH_ERR_ARG
+    assert orth.orth_set_deflation(None, 1e-6) == orth.ORTH_ERR_ARG
+    assert orth.orth_deflation_info(None)[0] == orth.ORTH_ERR_ARG
     assert orth.orth_destroy(None) == orth.ORTH_OK
     assert orth.orth_laplacian_apply(0, 1, 0, 1, 1, 1, 1, 1, 0.0, None) == orth.ORTH_ERR_ARG
     assert orth.orth_probe_copy(0, 0, 1, None) == orth.ORTH_ERR_ARG
