@@ -127,6 +127,9 @@ enum orth_variant {
 
 /*
  * orth_workspace_bytes -- device workspace size for orth_create.
+ * Resource management: sizes the storage of the locally orthogonal basis
+ * (Sec. 4.1: per-leaf local bases Q_i and tree factors T_i, k_max columns
+ * each) plus the step's scratch; no passage defines the call itself.
  *   n          rows of the basis (>= 1)
  *   s          block width, one of 1, 2, 4, 8, 16, 32
  *   k_max      largest basis width the handle will reach (multiple of s,
@@ -145,6 +148,10 @@ size_t orth_workspace_bytes(int64_t n, int32_t s, int32_t k_max,
 
 /*
  * orth_create -- make a handle with an empty basis (k = 0).
+ * Resource management: carves the workspace into the locally orthogonal
+ * representation of Sec. 4.1 (an empty one: the first orth_step is the
+ * tree TSQR of the start block, Sec. 4.1, as the block Arnoldi process of
+ * Sec. 2 starts from the QR of its start block).
  *   d_workspace      device buffer of >= orth_workspace_bytes(...) bytes,
  *                    256-byte aligned; owned by the caller, must outlive
  *                    the handle and must not be touched while it lives
@@ -158,8 +165,8 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
                 void *stream, orth_t **out);
 
 /*
- * orth_set_variant -- choose ORTH_PIP_PLUS (default) or ORTH_PIP for the
- * following steps.  Host-side only.  Errors: ARG, POISONED, UNSUPPORTED
+ * orth_set_variant -- choose ORTH_PIP_PLUS (default; BCGS-PIP+, Sec. 3.1)
+ * or ORTH_PIP (BCGS-PIP, Sec. 3) for the following steps.  Host-side only.  Errors: ARG, POISONED, UNSUPPORTED
  * (ORTH_PIP on an ORTH_FP64_HOUSEHOLDER handle).
  */
 int orth_set_variant(orth_t *h, int32_t variant);
@@ -205,7 +212,8 @@ int orth_set_deflation(orth_t *h, double delta);
 
 /*
  * orth_deflation_info -- synchronise the handle's stream and read the
- * deflation record.  Any output pointer may be NULL.
+ * deflation record (the rank t of the t < s case of eq. (1.1), Sec. 1, as
+ * the truncated decomposition of Sec. 3.1 decides it).  Any output pointer may be NULL.
  *   rank     t of the latest step taken with deflation on (s before any)
  *   steps    steps so far with t < s
  *   dropped  columns dropped so far (sum of s - t)
@@ -247,7 +255,9 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
                  double *d_Y, int64_t ldy);
 
 /*
- * orth_status -- synchronise the handle's stream and read the device status.
+ * orth_status -- synchronise the handle's stream and read the device status
+ * (breakdown: a Cholesky pivot that is not positive and finite; Sec. 3.1
+ * notes that the textbook Cholesky is not rank revealing).
  *   status  receives ORTH_OK or ORTH_ERR_BREAKDOWN.  After a breakdown the
  *           handle is poisoned.
  *   info    optional (may be NULL): 4 ints {tree level (0 = leaves,
@@ -260,16 +270,20 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
 int orth_status(orth_t *h, int32_t *status, int32_t *info);
 
 /*
- * orth_mixed_fallbacks -- synchronise the handle's stream and read how many
+ * orth_mixed_fallbacks -- (the mixed form; the reiteration of Sec. 3.1
+ * restores accuracy only where the first sweep did not break down)
+ * synchronise the handle's stream and read how many
  * steps of the mixed form redid their first CholeskyQR sweep from the FP64
  * bases (0 for the FP64 form).  Errors: ARG, HIP.
  */
 int orth_mixed_fallbacks(orth_t *h, int64_t *count);
 
-/* orth_basis_width -- current k (host state, no synchronisation). */
+/* orth_basis_width -- current k (host state, no synchronisation).
+ * Resource management, no passage: the k of eq. (1.1) for the next step. */
 int orth_basis_width(const orth_t *h, int32_t *k);
 
-/* orth_leaf_count -- number of leaves p and the leaf height in use. */
+/* orth_leaf_count -- number of leaves p and the leaf height in use (the
+ * local problem size of Sec. 4.1 and Sec. 6.2).  Host state only. */
 int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows);
 
 /*
@@ -285,58 +299,10 @@ int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows);
 int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq,
                       double *d_T, int64_t ldt);
 
-/* Kernel classes timed by the profiler (one class per launch site). */
-enum orth_kernel_class {
-    ORTH_K_LEAF_GRAM = 0,      /* leaves, sweep-1 Gram [Q_i W_i]^T W_i          */
-    ORTH_K_LEAF_CHOL = 1,      /* leaves, per-leaf Cholesky (both sweeps)       */
-    ORTH_K_LEAF_CORRECT = 2,   /* leaves, u1 = (w - q P1) N1^-1                 */
-    ORTH_K_ROOT_GRAM = 3,      /* reduction level, sweep-1 Gram                 */
-    ORTH_K_ROOT_CHOL = 4,      /* reduction level Cholesky and pre-sums         */
-    ORTH_K_ROOT_CORRECT = 5,   /* reduction level correction                    */
-    ORTH_K_ROOT_FINALIZE = 6,  /* reduction level new columns [P~_i; N~_i]      */
-    ORTH_K_LEAF_FINALIZE = 7,  /* leaves: U_i appended, explicit U assembled    */
-    ORTH_K_APPLY = 8,          /* orth_apply_Q launches                         */
-    ORTH_K_LEAF_GRAM2 = 9,     /* leaves, sweep-2 Gram [Q_i U1_i]^T U1_i        */
-    ORTH_K_ROOT_GRAM2 = 10,    /* reduction level, sweep-2 Gram                 */
-    ORTH_K_LEAF_FALLBACK = 11, /* mixed form: FP64 redo of the first sweep      */
-    ORTH_K_LEAF_HH_PANEL = 12, /* Householder leaves: panel factorisation       */
-    ORTH_K_LEAF_HH_SMALL = 13, /* Householder leaves: per-leaf T, Z, E C work   */
-    ORTH_K_COUNT = 14
-};
-
-/*
- * orth_profile_enable -- on != 0: every later launch of the handle is
- * bracketed by a pair of HIP events recorded on the handle's stream; on = 0
- * stops recording.  Events are host-side objects (no device allocation).
- * Errors: ARG, HIP.
- */
-int orth_profile_enable(orth_t *h, int32_t on);
-
-/*
- * orth_profile_select -- restrict the bracketing to the classes whose bit
- * (1u << class) is set in class_mask; the default is every class.  Each
- * event pair adds a short gap on the stream, so a timing run that needs one
- * class's launch durations brackets only that class.
- * Errors: ARG.
- */
-int orth_profile_select(orth_t *h, uint32_t class_mask);
-
-/*
- * orth_profile_read -- synchronise the stream, then add the elapsed time of
- * every recorded event pair to per-class totals and clear the record.
- *   total_ms   array of ORTH_K_COUNT doubles: milliseconds per class
- *   launches   array of ORTH_K_COUNT int64: launches per class
- * Totals accumulate across reads until orth_profile_reset.
- * Errors: ARG, HIP.
- */
-int orth_profile_read(orth_t *h, double *total_ms, int64_t *launches);
-
-/* orth_profile_reset -- drop pending events and zero the totals. */
-int orth_profile_reset(orth_t *h);
-
 /*
  * orth_destroy -- release the host state.  The workspace stays owned by the
  * caller.  Always allowed, also on a poisoned handle; NULL is a no-op.
+ * Resource management, no passage.
  */
 int orth_destroy(orth_t *h);
 
@@ -352,7 +318,8 @@ int orth_destroy(orth_t *h);
 typedef struct orth_batch_ctx orth_batch_t;
 
 /*
- * orth_batch_workspace_bytes -- workspace for orth_batch_create.  Host arrays
+ * orth_batch_workspace_bytes -- workspace for orth_batch_create (resource
+ * management: one Sec. 4.1 representation per instance).  Host arrays
  * of `count` entries: n[i], s[i], k_max[i] as for orth_workspace_bytes;
  * leaf_rows may be NULL (default height for every instance) or hold 0 for
  * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  precision
@@ -363,7 +330,8 @@ size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t
                                   int32_t precision);
 
 /*
- * orth_batch_create -- empty bases for every instance.  Copies the instance
+ * orth_batch_create -- empty bases for every instance (Sec. 4.1
+ * representation, k = 0; resource management).  Copies the instance
  * descriptors and launch tables into the workspace and zero-fills the tree
  * factors on `stream`, then synchronises that stream (creation only).
  * Errors: ARG, WORKSPACE, UNSUPPORTED, HIP.
@@ -372,11 +340,15 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
                       const int32_t *leaf_rows, int32_t precision, void *d_workspace,
                       size_t workspace_bytes, void *stream, orth_batch_t **out);
 
-/* orth_batch_set_variant -- ORTH_PIP_PLUS (default) or ORTH_PIP for all instances. */
+/* orth_batch_set_variant -- ORTH_PIP_PLUS (default, Sec. 3.1) or ORTH_PIP
+ * (Sec. 3) for all instances. */
 int orth_batch_set_variant(orth_batch_t *b, int32_t variant);
 
 /*
- * orth_batch_step -- one PQR step (eq. (1.1)) for every instance.
+ * orth_batch_step -- one PQR step (eq. (1.1)) for every instance, each by
+ * TreeTSPQR with BCGS-PIP+ leaves and reduction (Sec. 4.1, Sec. 3.1); the
+ * instances' local problems are independent (Sec. 4.1), so one launch per
+ * phase serves them all.
  *   d_W     DEVICE array of `count` device pointers: instance i's new block,
  *           n_i x s_i, column-major, ld = n_i (may alias the matching d_U[i])
  *   d_U     DEVICE array: explicit new blocks, n_i x s_i, ld = n_i
@@ -393,19 +365,23 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
                     double *const *d_Hess);
 
 /*
- * orth_batch_status -- synchronise and read the batch status word.  info (may
+ * orth_batch_status -- synchronise and read the batch status word (a
+ * Cholesky pivot that is not positive and finite, Sec. 3.1).  info (may
  * be NULL): 5 ints {instance, level, leaf, sweep, column} of the first
  * breakdown.  After a breakdown the batch is poisoned.  Errors: ARG, HIP.
  */
 int orth_batch_status(orth_batch_t *b, int32_t *status, int32_t *info);
 
-/* orth_batch_progress -- steps taken and the number of steps the batch allows. */
+/* orth_batch_progress -- steps taken and the number of steps the batch
+ * allows (host state; resource management, no passage). */
 int orth_batch_progress(const orth_batch_t *b, int32_t *steps_done, int32_t *steps_max);
 
-/* orth_batch_leaf_rows -- the leaf height chosen for every instance (count ints). */
+/* orth_batch_leaf_rows -- the leaf height chosen for every instance (count
+ * ints): the local problem size of Sec. 4.1 / Sec. 6.2.  Host state. */
 int orth_batch_leaf_rows(const orth_batch_t *b, int32_t *leaf_rows);
 
-/* orth_batch_destroy -- release the host state (NULL is a no-op). */
+/* orth_batch_destroy -- release the host state (NULL is a no-op).
+ * Resource management, no passage. */
 int orth_batch_destroy(orth_batch_t *b);
 
 /* ---- leaf-height autotuner -------------------------------------------------
@@ -445,26 +421,6 @@ int orth_tune_leaf_rows(int64_t n, int32_t s, int32_t k_max, int32_t steps,
                         int32_t copies, void *d_workspace, size_t workspace_bytes,
                         void *stream, int32_t *best_leaf_rows, int32_t *cand_rows,
                         double *cand_ms, int32_t max_cand, int32_t *ncand);
-
-/*
- * orth_laplacian_apply -- test operator for Arnoldi drivers (not part of the
- * method): Y = A X for the Dirichlet finite-difference Laplacian on an
- * nx x ny (nz = 1: 5-point, diagonal 4) or nx x ny x nz (7-point, diagonal
- * 6) grid plus `shift` on the diagonal, unknowns ordered i + nx*j + nx*ny*l.
- * X and Y are n x s (n = nx*ny*nz) column-major, ldx, ldy >= n, must not
- * overlap.  Errors: ARG, HIP.
- */
-int orth_laplacian_apply(const double *d_X, int64_t ldx, double *d_Y,
-                         int64_t ldy, int32_t s, int32_t nx, int32_t ny,
-                         int32_t nz, double shift, void *stream);
-
-/*
- * orth_probe_copy -- measurement probe: dst[i] = src[i] for i < count
- * doubles.  A plain streaming copy of known size, used to calibrate the
- * hardware byte counters and the achievable HBM bandwidth.  Errors: ARG, HIP.
- */
-int orth_probe_copy(const double *d_src, double *d_dst, int64_t count,
-                    void *stream);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/orth.h"
+#include "../../include/orth_measure.h"
 #include "orth_deflate.h"
 #include "orth_internal.h"
 

@@ -375,8 +375,8 @@ hipError_t launch_defl(int s, const CholArgs &a, const DeflArgs &d, hipStream_t 
         case 4: return defl_s<4>(a, d, st);
         case 8: return defl_s<8>(a, d, st);
         case 16: return defl_s<16>(a, d, st);
-        case 32: return defl_s<32>(a, d, st);
     }
+    // s = 32: only Householder-leaf handles deflate and those stop at s = 16
     return hipErrorInvalidValue;
 }
 
@@ -388,7 +388,6 @@ hipError_t launch_defl_rows(int s, const DeflRowArgs &a, hipStream_t st) {
         case 4: return defl_rows_s<4>(a, st);
         case 8: return defl_rows_s<8>(a, st);
         case 16: return defl_rows_s<16>(a, st);
-        case 32: return defl_rows_s<32>(a, st);
     }
     return hipErrorInvalidValue;
 }

@@ -33,7 +33,7 @@ ORTH_PIP = 1
 CODE_NAMES = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "BREAKDOWN", 4: "HIP", 5: "POISONED",
               6: "WORKSPACE", 7: "UNSUPPORTED"}
 
-# (name, restype, argtypes) for every symbol in include/orth.h
+# (name, restype, argtypes) for every symbol in include/orth.h and include/orth_measure.h
 _i32, _i64, _sz, _vp, _dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
 SIGNATURES = [
     ("orth_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32]),

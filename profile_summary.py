@@ -6,8 +6,8 @@ is the leaf first-sweep Gram of the mixed form, which reads the FP32 copy
 of the basis. So every dispatch in a kernel trace maps to one class of
 orth_kernel_class (k_gram_hi to leaf_gram, reported as leaf_gram_hi).
 
-    python -m paper_2204_13393_amd.profile_summary trace  <kernel_trace.csv>
-    python -m paper_2204_13393_amd.profile_summary counters <fetch.csv> <write.csv> \
+    python profile_summary.py trace  <kernel_trace.csv>
+    python profile_summary.py counters <fetch.csv> <write.csv> \
             --copy-gib G --sha <sha256 of orth_kernels.hip followed by orth_internal.h> --out traffic.json
 
 `trace` prints per-class dispatch counts, total and average durations.

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (CPU): the library loads, exports every symbol
-that include/orth.h declares, sizes workspaces by pure arithmetic, and rejects
-bad arguments before touching the GPU."""
+that include/orth.h and include/orth_measure.h declare, sizes workspaces by
+pure arithmetic, and rejects bad arguments before touching the GPU."""
 
 import os
 import re
@@ -9,13 +9,16 @@ import pytest
 
 from paper_2204_13393_amd import orth
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "orth.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+HEADERS = [os.path.join(INCLUDE, "orth.h"), os.path.join(INCLUDE, "orth_measure.h")]
 
 
-def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(orth_[a-zA-Z_]+)\s*\(", text)))
+def _declared(headers=HEADERS):
+    names = set()
+    for path in headers:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names.update(re.findall(r"\b(orth_[a-zA-Z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -26,6 +29,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     # the binding wraps exactly the declared set
     assert sorted(n for n, _, _ in orth.SIGNATURES) == names
+    # the measurement helpers stay out of the method's header
+    product = _declared(HEADERS[:1])
+    for helper in ("orth_laplacian_apply", "orth_probe_copy", "orth_profile_read"):
+        assert helper in names and helper not in product
 
 
 def test_workspace_bytes_arithmetic():
@@ -129,7 +136,7 @@ def test_null_handle_calls():
 
 def test_product_path_has_no_oracle_import():
     """The product package never imports the oracle (which is test-only)."""
-    pkg = os.path.join(os.path.dirname(HEADER), "..", "paper_2204_13393_amd")
+    pkg = os.path.join(INCLUDE, "..", "paper_2204_13393_amd")
     for root, _, files in os.walk(pkg):
         for f in files:
             if f.endswith(".py"):

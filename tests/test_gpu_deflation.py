@@ -81,6 +81,9 @@ CASES = [
     (5000, 2, 20, 1000),
     (6000, 16, 96, 1000),     # s = 16
     (16384, 8, 80, 4096),     # two chunks per leaf
+    # 256 leaves: from k + s = 72 on the reduction level has more than 16
+    # partial slots per sweep, pre-summed before the deflating factorisation
+    (65536, 8, 128, 256),
 ]
 
 
