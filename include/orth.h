@@ -61,7 +61,9 @@ enum orth_code {
     ORTH_ERR_HIP = 4,        /* a HIP runtime call failed (no device, launch error) */
     ORTH_ERR_POISONED = 5,   /* handle saw a breakdown earlier; only destroy works */
     ORTH_ERR_WORKSPACE = 6,  /* workspace missing, too small or misaligned */
-    ORTH_ERR_UNSUPPORTED = 7 /* valid request the library does not implement */
+    ORTH_ERR_UNSUPPORTED = 7, /* valid request the library does not implement */
+    ORTH_ERR_SCRATCH = 8     /* the request needs more than the fixed scratch of
+                                orth_apply_Q_noalloc */
 };
 
 /*
@@ -253,6 +255,30 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw,
  */
 int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
                  double *d_Y, int64_t ldy);
+
+/*
+ * orth_apply_Q_noalloc -- orth_apply_Q for callers that cannot allocate
+ * device memory at the time of the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * result and errors as orth_apply_Q (the same kernels, bit for bit); the
+ * per-leaf coefficient blocks that orth_apply_Q keeps in the handle's
+ * workspace live instead in a fixed 32 MiB device array inside the library
+ * (one per GPU, held until the process ends).  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and records no
+ * profiler events.
+ *   Limit: one column of coefficient blocks takes ldt = p * k_max doubles
+ *   (rounded up to an odd multiple of 32), twice that for an
+ *   ORTH_FP64_HOUSEHOLDER handle; it must fit the 4 Mi doubles of the array,
+ *   else ORTH_ERR_SCRATCH (checked before anything is enqueued).  Columns
+ *   are processed in blocks of min(16, 4 Mi / that size).
+ *   Every call on one GPU shares that GPU's array: calls that overlap in
+ *   time on one GPU (other streams, other handles, other threads) race and
+ *   must be ordered by the caller.  Nothing in the array needs to start at
+ *   zero (every entry a call reads it has written first).
+ * Errors: ARG (also for k = 0), POISONED, SCRATCH, HIP.
+ */
+int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
+                         double *d_Y, int64_t ldy);
 
 /*
  * orth_status -- synchronise the handle's stream and read the device status

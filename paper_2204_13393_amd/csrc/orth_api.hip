@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -34,6 +35,39 @@ namespace {
 
 constexpr int64_t kAlign = 32;        // doubles (256 bytes)
 constexpr int kApplyMB = 16;
+
+// Scratch of orth_apply_Q_noalloc: the per-leaf coefficient blocks of one
+// column block live in this file-scope device array instead of the handle's
+// workspace, so that call needs no device memory of its own.  32 MiB; every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in): static_scratch() looks up each device's address once.
+constexpr int64_t kStaticScratchDoubles = (int64_t)4 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on device dev (looked up with dev current)
+hipError_t static_scratch(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -169,6 +203,7 @@ struct orth_ctx {
     double defl_delta = 0.0;               // > 0: the reduction level deflates (Sec. 3.1)
     bool poisoned = false;
     hipStream_t stream = nullptr;
+    int device = 0;                        // the stream's device
     double *ws = nullptr;
     // profiler: event pairs recorded around launches
     bool prof_on = false;
@@ -256,6 +291,11 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     h->pl = pl;
     h->stream = static_cast<hipStream_t>(stream);
     h->ws = static_cast<double *>(d_workspace);
+    if (hipStreamGetDevice(h->stream, &h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return ORTH_ERR_HIP;
+    }
     // tree factors must start at zero: the reduction level relies on the
     // zero rows below every T_i's current k x k block
     hipError_t e = prepare_kernels(pl.s);
@@ -718,16 +758,24 @@ fail:
     return rc;
 }
 
-int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
-    if (!h) return ORTH_ERR_ARG;
-    if (h->poisoned) return ORTH_ERR_POISONED;
+}  // extern "C"
+
+namespace {
+
+// Y = Q C in column blocks of at most mb_max columns.  ca (and, with
+// Householder leaves, ca2) hold the per-leaf coefficient blocks of one column
+// block: ldt x mb_max doubles each.  prof: bracket the launches with the
+// handle's profiler events.
+int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy,
+                 double *ca, double *ca2, int32_t mb_max, bool prof) {
     const Plan &pl = h->pl;
     const int32_t k = h->k;
-    if (k < 1 || m < 1 || !d_C || !d_Y || ldc < k || ldy < pl.n) return ORTH_ERR_ARG;
     const bool hh = pl.precision == ORTH_FP64_HOUSEHOLDER;
     hipStream_t st = h->stream;
-    for (int32_t j0 = 0; j0 < m; j0 += kApplyMB) {
-        const int32_t mb = (m - j0) < kApplyMB ? (m - j0) : kApplyMB;
+    auto begin = [&](int cls) { return prof ? h->begin(cls) : -1; };
+    auto end = [&](int idx) { if (prof) h->end(idx); };
+    for (int32_t j0 = 0; j0 < m; j0 += mb_max) {
+        const int32_t mb = (m - j0) < mb_max ? (m - j0) : mb_max;
         // reduction level: C_i = T_i C (rows: p segments of k rows)
         ApplyArgs r{};
         r.Q = Operand{h->T(), pl.ldt};
@@ -737,10 +785,10 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         r.ldc = ldc;
         r.cseg = 0;
         r.m = mb;
-        r.Y = OutOperand{h->CA(), pl.ldt};
-        const int pm0 = h->begin(ORTH_K_APPLY);
+        r.Y = OutOperand{ca, pl.ldt};
+        const int pm0 = begin(ORTH_K_APPLY);
         hipError_t e = launch_apply(r, st);
-        h->end(pm0);
+        end(pm0);
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         // leaves: Y_i = Q_i C_i; with Householder leaves Y_i = -V Z_i + E C_i,
         // Z_i = T (V[0:k]^T C_i)
@@ -750,36 +798,66 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
             ha.k = k;
             ha.kmax = pl.kmax;
             ha.T = h->TH();
-            ha.ca = h->CA();
-            ha.ca_out = h->CA2();
+            ha.ca = ca;
+            ha.ca_out = ca2;
             ha.ldca = pl.ldt;
             ha.m = mb;
             ha.U = d_Y + (int64_t)j0 * ldy;
             ha.ldu = ldy;
-            const int pm = h->begin(ORTH_K_APPLY);
+            const int pm = begin(ORTH_K_APPLY);
             e = launch_hh_apply(HH_APPLY_COEF, ha, st);
-            h->end(pm);
+            end(pm);
             if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         }
         ApplyArgs a{};
         a.Q = Operand{h->Q(), pl.ldq};
         a.k = k;
         a.geom = leaf_geom(pl, kFinalChunk);
-        a.Cptr = hh ? h->CA2() : h->CA();
+        a.Cptr = hh ? ca2 : ca;
         a.ldc = pl.ldt;
         a.cseg = pl.kmax;
         a.m = mb;
         a.Y = OutOperand{d_Y + (int64_t)j0 * ldy, ldy};
-        { const int pm = h->begin(ORTH_K_APPLY); e = launch_apply(a, st); h->end(pm); }
+        { const int pm = begin(ORTH_K_APPLY); e = launch_apply(a, st); end(pm); }
         if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         if (hh) {
-            const int pm = h->begin(ORTH_K_APPLY);
+            const int pm = begin(ORTH_K_APPLY);
             e = launch_hh_apply(HH_APPLY_ADD, ha, st);
-            h->end(pm);
+            end(pm);
             if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         }
     }
     return ORTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
+    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, h->CA(), h->CA2(), kApplyMB, true);
+}
+
+int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    // one column of coefficient blocks per region (two regions with
+    // Householder leaves) must fit the static scratch
+    const int64_t regions = h->pl.precision == ORTH_FP64_HOUSEHOLDER ? 2 : 1;
+    const int64_t cols = kStaticScratchDoubles / (regions * h->pl.ldt);
+    if (cols < 1) return ORTH_ERR_SCRATCH;
+    if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
+    double *base = nullptr;
+    if (static_scratch(h->device, &base) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    const int32_t mb_max = (int32_t)std::min<int64_t>(kApplyMB, cols);
+    double *ca2 = regions == 2 ? base + h->pl.ldt * mb_max : nullptr;
+    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, base, ca2, mb_max, false);
 }
 
 int orth_status(orth_t *h, int32_t *status, int32_t *info) {

@@ -24,6 +24,7 @@ ORTH_ERR_HIP = 4
 ORTH_ERR_POISONED = 5
 ORTH_ERR_WORKSPACE = 6
 ORTH_ERR_UNSUPPORTED = 7
+ORTH_ERR_SCRATCH = 8
 ORTH_FP64 = 0
 ORTH_MIXED_SPLIT32 = 1
 ORTH_FP64_HOUSEHOLDER = 2
@@ -31,7 +32,7 @@ ORTH_PIP_PLUS = 0
 ORTH_PIP = 1
 
 CODE_NAMES = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "BREAKDOWN", 4: "HIP", 5: "POISONED",
-              6: "WORKSPACE", 7: "UNSUPPORTED"}
+              6: "WORKSPACE", 7: "UNSUPPORTED", 8: "SCRATCH"}
 
 # (name, restype, argtypes) for every symbol in include/orth.h and include/orth_measure.h
 _i32, _i64, _sz, _vp, _dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
@@ -45,6 +46,7 @@ SIGNATURES = [
     ("orth_deflation_info", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("orth_step", ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64]),
     ("orth_apply_Q", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
+    ("orth_apply_Q_noalloc", ctypes.c_int, [_vp, _dp, _i64, _i32, _dp, _i64]),
     ("orth_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_basis_width", ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     ("orth_leaf_count", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -146,6 +148,10 @@ def orth_step(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu):
 
 def orth_apply_Q(h, d_C, ldc, m, d_Y, ldy):
     return load().orth_apply_Q(h, d_C, ldc, m, d_Y, ldy)
+
+
+def orth_apply_Q_noalloc(h, d_C, ldc, m, d_Y, ldy):
+    return load().orth_apply_Q_noalloc(h, d_C, ldc, m, d_Y, ldy)
 
 
 def orth_status(h):

@@ -124,6 +124,7 @@ def test_create_validates_before_any_device_call():
 def test_null_handle_calls():
     assert orth.orth_step(None, 0, 1, 0, 1, 0, 1, 0, 1) == orth.ORTH_ERR_ARG
     assert orth.orth_apply_Q(None, 0, 1, 1, 0, 1) == orth.ORTH_ERR_ARG
+    assert orth.orth_apply_Q_noalloc(None, 0, 1, 1, 0, 1) == orth.ORTH_ERR_ARG
     assert orth.orth_set_variant(None, 0) == orth.ORTH_ERR_ARG
     assert orth.orth_set_level_variants(None, 0, 1) == orth.ORTH_ERR_ARG
     assert orth.orth_mixed_fallbacks(None)[0] == orth.ORTH_ERR_ARG
