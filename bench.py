@@ -361,13 +361,144 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c1(args):
+    """Small plain-FP64 block Arnoldi (latency): 2D 5-point Dirichlet Laplacian
+    on 100 x 100 (n = 10,000) shifted by 0.01 I, start block
+    default_rng(0).standard_normal((10000, 4)), s = 4, start block + 10 block
+    steps (k up to 40), leaf height 1000 (10 leaves).  Closed loop with the
+    library's stencil between steps.  Reports microseconds per orth_step:
+    eager (HIP events around each call, and host wall time of the call
+    itself), and the whole closed loop captured once in a hipGraph and
+    replayed (per step, stencil included; a graph of the stencils alone is
+    timed beside it).  Median and min over 5 sequences (args.steps if
+    larger)."""
+    import numpy as np
+    import torch
+    from paper_2204_13393_amd import orth
+    nx = ny = 100
+    n, s, steps, leaf, shift = nx * ny, 4, 10, 1000, 0.01
+    kmax = (steps + 1) * s
+    runs = max(5, args.steps)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    side = torch.cuda.Stream()
+    sp = side.cuda_stream
+    R0 = torch.from_numpy(np.ascontiguousarray(np.random.default_rng(0).standard_normal((n, s)).T)).to(dev)
+    V = torch.empty((kmax, n), dtype=torch.float64, device=dev)
+    W = torch.empty((s, n), dtype=torch.float64, device=dev)
+    H = torch.zeros((kmax, kmax), dtype=torch.float64, device=dev)
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64)
+    ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+
+    def create():
+        code, h = orth.orth_create(n, s, kmax, leaf, orth.ORTH_FP64, wp, nbytes, sp)
+        if code:
+            raise orth.OrthError("orth_create", code)
+        return h
+
+    def stencil(j):
+        if j == 0:
+            W.copy_(R0)
+        elif orth.orth_laplacian_apply(V[(j - 1) * s:j * s].data_ptr(), n, W.data_ptr(), n, s, nx, ny, 1,
+                                       shift, sp):
+            raise RuntimeError("stencil failed")
+
+    def step(h, j):
+        k = j * s
+        col = H[j * s:(j + 1) * s]
+        code = orth.orth_step(h, W.data_ptr(), n, col.data_ptr() if k else 0, kmax, col[:, k:].data_ptr(),
+                              kmax, V[k:k + s].data_ptr(), n)
+        if code:
+            raise orth.OrthError("orth_step", code)
+
+    def eager():
+        h = create()
+        ev, host_us = [], []
+        with torch.cuda.stream(side):
+            for j in range(steps + 1):
+                stencil(j)
+                e0, e1 = TimingEvent(), TimingEvent()
+                e0.record(side)
+                t0 = time.perf_counter()
+                step(h, j)
+                host_us.append((time.perf_counter() - t0) * 1e6)
+                e1.record(side)
+                ev.append((e0, e1))
+        side.synchronize()
+        code, st, info = orth.orth_status(h)
+        orth.orth_destroy(h)
+        if st:
+            raise RuntimeError(f"breakdown {info}")
+        return [a.elapsed_time(b) * 1e3 for a, b in ev], host_us
+
+    for _ in range(max(1, args.warmup)):
+        eager()
+    dev_us, host_us = [], []
+    for _ in range(runs):
+        d, hst = eager()
+        dev_us.append(float(np.mean(d)))
+        host_us.append(float(np.mean(hst)))
+    G = torch.mm(V, V.t()) - torch.eye(kmax, dtype=torch.float64, device=dev)
+    e_perp = float(torch.linalg.matrix_norm(G, "fro"))
+
+    # the closed loop captured once (its launches carry their own k) and replayed
+    def capture(with_orth):
+        h = create()
+        side.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            for j in range(steps + 1):
+                stencil(j)
+                if with_orth:
+                    step(h, j)
+        return g, h
+
+    out_graph = {}
+    for name, with_orth in (("closed_loop", True), ("stencils_only", False)):
+        g, h = capture(with_orth)
+        times = []
+        for r in range(runs + 1):
+            e0, e1 = TimingEvent(), TimingEvent()
+            e0.record(side)
+            with torch.cuda.stream(side):
+                g.replay()
+            e1.record(side)
+            side.synchronize()
+            if r:
+                times.append(e0.elapsed_time(e1) * 1e3 / (steps + 1))
+        orth.orth_destroy(h)
+        out_graph[name] = {"median_us_per_step": float(np.median(times)), "min_us_per_step": float(min(times))}
+    out = {
+        "metric": METRIC,
+        "workload": "lap2d-100x100-s4",
+        "unit": "us per orth_step",
+        "orth_calls": steps + 1,
+        "eager": {"median_us_per_step": float(np.median(dev_us)), "min_us_per_step": float(min(dev_us)),
+                  "host_call_us_median": float(np.median(host_us))},
+        "graph": {
+            **out_graph,
+            "orth_us_per_step_median": out_graph["closed_loop"]["median_us_per_step"]
+            - out_graph["stencils_only"]["median_us_per_step"],
+        },
+        "algorithmic_floor_us": step_bytes(n, s, n // leaf, kmax - s) / (HBM_PEAK_GBS * 1e3),
+        "e_perp": e_perp,
+        "runs": runs,
+        "dtype": "f64",
+        "data": "synthetic: default_rng(0) N(0,1) start block, 2D Dirichlet Laplacian 100x100 + 0.01 I",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_lap3d(args):
     """Large block: 3D 7-point Laplacian on 256^3 (n = 2^24), s = 32, start
-    block + 16 block-Arnoldi steps (k up to 512), leaf height 4096, FP64.
-    Closed loop; HIP events around every orth_step (stencils excluded).
-    A second, short run starts from a block with singular values log-spaced
-    from 1 to 1e-8 and reports whether CholeskyQR2 breaks down on it
-    (eps kappa^2 > 1/2 there)."""
+    block + 16 block-Arnoldi steps (k up to 512), leaf height 4096.  The
+    start block is W0 = G M with singular values sigma_j = 10^(-8 j / 31)
+    (G Gaussian from default_rng(5), M = R_G^{-1} diag(sigma) V^T, V the QR
+    factor of a Gaussian from default_rng(6); kappa = 1e8, eps kappa^2 ~ 1.1).
+    FP64 and mixed forms on that block (the timed line), then FP64 from an
+    N(0,1) start block (default_rng(5)) as a second, labelled line.  Closed
+    loop; HIP events around every orth_step (stencils excluded)."""
     import numpy as np
     import torch
     from paper_2204_13393_amd import Orthogonalizer, orth
@@ -379,8 +510,18 @@ def bench_lap3d(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
-    print("[bench] lap3d: generating the start block", file=sys.stderr, flush=True)
-    R0 = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, 5).T)).to(dev)
+    print("[bench] lap3d: generating the start blocks", file=sys.stderr, flush=True)
+    R0_normal = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, 5).T)).to(dev)
+    # the configured start block: sigma_j = 10^(-8 j / 31)
+    rng = np.random.default_rng(5)
+    Gm = rng.standard_normal((n, s))
+    Rg = np.linalg.cholesky(Gm.T @ Gm).T
+    Vh = np.linalg.qr(np.random.default_rng(6).standard_normal((s, s)))[0]
+    sig = 10.0 ** (-8.0 * np.arange(s) / (s - 1))
+    M = np.linalg.solve(Rg, np.diag(sig) @ Vh.T)
+    R0_sigma = torch.from_numpy(np.ascontiguousarray((Gm @ M).T)).to(dev)
+    del Gm
+    start = {"sigma": R0_sigma, "normal": R0_normal}
     V = torch.empty((kmax, n), dtype=torch.float64, device=dev)
     W = torch.empty((s, n), dtype=torch.float64, device=dev)
     H = torch.zeros((kmax, kmax), dtype=torch.float64, device=dev)
@@ -392,7 +533,8 @@ def bench_lap3d(args):
 
     fallbacks = {}      # steps whose first sweep was redone in FP64, per form
 
-    def run(profiled, precision=orth.ORTH_FP64):
+    def run(profiled, precision=orth.ORTH_FP64, block="sigma"):
+        R0 = start[block]
         code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sp)
         if code:
             raise orth.OrthError("orth_create", code)
@@ -423,47 +565,31 @@ def bench_lap3d(args):
             raise RuntimeError(f"breakdown {info}")
         return ms, prof
 
-    def timed(precision):
+    def timed(precision, block="sigma", profile=True):
         """Warmup, args.steps unprofiled runs (the time), then one run with
         every launch bracketed by events (the per-class breakdown)."""
         for _ in range(args.warmup):
-            run(False, precision)
+            run(False, precision, block)
         times = []
         for _ in range(args.steps):
-            ms, _ = run(False, precision)
+            ms, _ = run(False, precision, block)
             times.append(ms)
         G = torch.mm(V, V.t())
         G -= torch.eye(kmax, dtype=torch.float64, device=dev)
         ep = float(torch.linalg.matrix_norm(G, "fro"))
         del G
-        _, pr = run(True, precision)
+        pr = run(True, precision, block)[1] if profile else None
         return min(times), pr, ep
 
     best, prof, e_perp = timed(orth.ORTH_FP64)
     best_mixed, prof_mixed, e_perp_mixed = timed(orth.ORTH_MIXED_SPLIT32)
+    best_normal, _, e_perp_normal = timed(orth.ORTH_FP64, "normal", profile=False)
     p = n // leaf
     widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
     total_flops = sum((10.0 * s * k + 14.0 * s * s) * n for k in widths)
     kernels = {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
                for name, (ms, cnt) in prof.items() if cnt}
-    # ill-conditioned start block: sigma_j = 10^(-8 j / 31)
-    rng = np.random.default_rng(5)
-    Gm = rng.standard_normal((n, s))
-    Rg = np.linalg.cholesky(Gm.T @ Gm).T
-    Vh = np.linalg.qr(np.random.default_rng(6).standard_normal((s, s)))[0]
-    sig = 10.0 ** (-8.0 * np.arange(s) / (s - 1))
-    M = np.linalg.solve(Rg, np.diag(sig) @ Vh.T)
-    W.copy_(torch.from_numpy(np.ascontiguousarray((Gm @ M).T)))
-    del Gm
-    ill = {}
-    for name, prec in (("fp64", orth.ORTH_FP64), ("mixed", orth.ORTH_MIXED_SPLIT32)):
-        code, h = orth.orth_create(n, s, kmax, leaf, prec, ws_ptr, nbytes, sp)
-        orth.orth_step(h, W.data_ptr(), n, 0, 1, H.data_ptr(), kmax, V[:s].data_ptr(), n)
-        code, st, info = orth.orth_status(h)
-        redo = orth.orth_mixed_fallbacks(h)[1]
-        orth.orth_destroy(h)
-        ill[name] = {"status": "breakdown" if st else "ok", "info": info, "fp64_redo_steps": redo}
     out = {
         "metric": METRIC,
         "workload": "lap3d-256-s32",
@@ -484,9 +610,15 @@ def bench_lap3d(args):
             "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
                         for name, (ms, cnt) in prof_mixed.items() if cnt},
         },
-        "ill_conditioned_start_block": {"kappa": 1e8, **ill},
+        "normal_start_block": {
+            "start": "N(0,1), default_rng(5)",
+            "ms_per_sequence": best_normal,
+            "value": total_bytes / (best_normal / 1e3) / 1e9,
+            "e_perp": e_perp_normal,
+        },
         "dtype": "f64",
-        "data": "synthetic: N(0,1) start block (seed 5), 3D Dirichlet Laplacian 256^3",
+        "data": "synthetic: start block with singular values 10^(-8j/31) (kappa 1e8; G from default_rng(5), "
+                "V from default_rng(6)), 3D Dirichlet Laplacian 256^3",
     }
     print(json.dumps(out), flush=True)
 
@@ -688,9 +820,11 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
-                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep"],
+                    choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep",
+                             "lap2d-100x100-s4"],
                     help="the default single-basis run, the batched form (512 instances), "
-                         "the large-block 3D run, or the precision workload (Stewart matrices)")
+                         "the large-block 3D run, the precision workload (Stewart matrices), "
+                         "the subalgorithm sweep, or the small latency run (C1)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -700,6 +834,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "lap2d-100x100-s4":
+        return bench_c1(args)
     if args.workload == "lap3d-256-s32":
         return bench_lap3d(args)
     if args.workload == "kappa-sweep":

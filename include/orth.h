@@ -72,25 +72,29 @@ enum orth_code {
  *   ORTH_FP64           every pass reads the FP64 leaf bases.
  *   ORTH_MIXED_SPLIT32  the leaf bases are also kept as an FP32 copy
  *                       (rounded to nearest), and the first CholeskyQR
- *                       sweep's Gram product (Sec. 3.1) reads that copy: 4
- *                       instead of 8 bytes per basis entry, P1 and N1
- *                       accurate to about 6e-8 relative.  The correction
+ *                       sweep's Gram product (Sec. 3.1) runs on the FP32
+ *                       matrix cores: it reads that copy (4 instead of 8
+ *                       bytes per basis entry), rounds W to FP32 in
+ *                       registers, accumulates in FP32 over 64 rows at a
+ *                       time and in FP64 beyond, so P1 and N1 are accurate
+ *                       to about 1e-7 relative.  The correction
  *                       u1 = (w - q P1) N1^{-1}, the second sweep and the
- *                       assembly of U read the FP64 bases, so w = q P1 +
- *                       u1 N1 holds in the stored basis and the reiteration
- *                       wins the accuracy back (Sec. 3.1): results match the
- *                       FP64 form to rounding.  Leaf bytes per step drop
- *                       from 32 to 28 per basis entry (plus 4 bytes per new
- *                       entry written); the workspace grows by 4 bytes per
- *                       leaf basis entry.  The first sweep stays stable
- *                       while 6e-8 kappa^2 << 1/2 (kappa the condition
- *                       number of the projected block); when a leaf's
- *                       pivot fails in that sweep, the step redoes its
- *                       first sweep from the FP64 bases on the device (no
- *                       host synchronisation; counted by
- *                       orth_mixed_fallbacks), so the mixed form breaks
- *                       down only where the FP64 form does.  Single handles
- *                       only: orth_batch_create returns UNSUPPORTED.
+ *                       assembly of U are FP64 on the FP64 bases, so
+ *                       w = q P1 + u1 N1 holds in the stored basis and the
+ *                       reiteration wins the accuracy back (Sec. 3.1):
+ *                       results match the FP64 form to rounding.  Leaf
+ *                       bytes per step drop from 32 to 28 per basis entry
+ *                       (plus 4 bytes per new entry written); the workspace
+ *                       grows by 4 bytes per leaf basis entry.  The first
+ *                       sweep stays stable while about 1e-7 kappa^2 << 1/2
+ *                       (kappa the condition number of the projected
+ *                       block); when a leaf's pivot fails in that sweep,
+ *                       the step redoes its first sweep in FP64 from the
+ *                       FP64 bases on the device (no host synchronisation;
+ *                       counted by orth_mixed_fallbacks), so the mixed form
+ *                       breaks down only where the FP64 form does.  Single
+ *                       handles only: orth_batch_create returns
+ *                       UNSUPPORTED.
  *   ORTH_FP64_HOUSEHOLDER  the leaves run the Householder method (Sec. 2.2,
  *                       Algorithm "HH") instead of BCGS-PIP+: each leaf basis
  *                       is held as unit reflectors (column c zero above leaf

@@ -246,17 +246,55 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs a) {
     gram_body<S, CLS == 3 || CLS == 10>(a, blockIdx.x, blockIdx.y);   // reduction level: TZ
 }
 
-// The mixed form's sweep-1 Gram: the basis columns come from the FP32 copy
-// (4 bytes per entry, converted exactly to FP64), X stays FP64.  Same tiles,
-// slots and products as gram_body; each lane takes RPL consecutive rows per
-// column (16 for narrow blocks) so a wave keeps as many bytes in flight as
-// the FP64 kernel.
+// The mixed form's sweep-1 Gram on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32).  The basis columns come from the FP32 copy; X is
+// read in FP64 and rounded to FP32 in registers, so every product operand
+// is an FP32 number and P1 = Q^T X, G1 = X^T X carry relative errors of a
+// few FP32 units (about 1e-7): the first CholeskyQR sweep only has to leave
+// u1 nearly orthogonal, and the second sweep, in FP64, wins the accuracy
+// back (Sec. 3.1).  The FP32 accumulators are promoted to FP64 after every
+// macro-step (RPL products of 4 rows each), so rounding grows with the
+// macro-step, not with the leaf height.  Same tiles, slots and launch shape
+// as gram_body; each lane takes 16 consecutive rows per column.
+// Lane roles of the FP32 product (gfx950): A[i][kk] at lane i + 16 kk,
+// B[kk][j] at lane j + 16 kk, D[i][j] at lane j + 16 (i / 4), register i % 4.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ flt4 mfma16f(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int R>
+__device__ __forceinline__ void load_run_f(const float *p, float (&v)[R]) {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < R / 4; ++u) {
+            const float4 w = reinterpret_cast<const float4 *>(p)[u];
+            v[4 * u] = w.x;
+            v[4 * u + 1] = w.y;
+            v[4 * u + 2] = w.z;
+            v[4 * u + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < R; ++u) v[u] = p[u];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void load_run_f(const double *p, float (&v)[R]) {
+    double d[R];
+    load_run<R>(p, d);
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = (float)d[u];
+}
+
 template <int S>
-__device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) {
+__device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by) {
     if (a.clear_retry && bx == 0 && by == 0 && threadIdx.x == 0) a.status->retry = 0;
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
-    constexpr int RPL = S >= 16 ? 8 : 16;
+    constexpr int RPL = 16;                    // 64 contiguous bytes of the copy per lane and column
     constexpr int MS = 4 * RPL;                 // rows per macro-step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
@@ -285,35 +323,37 @@ __device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) 
         const int j = 16 * nt + il;
         xcol[nt] = j < S ? a.X.ptr + (int64_t)j * a.X.ld : nullptr;
     }
-    dbl4 acc[kGramTPW][NT];
+    double acc[kGramTPW][NT][4];
 #pragma unroll
     for (int t = 0; t < kGramTPW; ++t)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][nt][v] = 0.0;
 
     const bool ident = a.geom.map.seg_len == 0;
     for (int64_t rm = r0 + MS * rg; rm < r1; rm += MS * RG) {
-        double av[kGramTPW][RPL], bv[NT][RPL];
+        float av[kGramTPW][RPL], bv[NT][RPL];
         const int64_t rb = rm + RPL * g;
         if (ident && rm + MS <= r1) {
 #pragma unroll
             for (int t = 0; t < kGramTPW; ++t) {
                 if (colh[t]) {
-                    load_run<RPL>(colh[t] + rb, av[t]);
+                    load_run_f<RPL>(colh[t] + rb, av[t]);
                 } else if (colp[t]) {
-                    load_run<RPL>(colp[t] + rb, av[t]);
+                    load_run_f<RPL>(colp[t] + rb, av[t]);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < RPL; ++u) av[t][u] = 0.0;
+                    for (int u = 0; u < RPL; ++u) av[t][u] = 0.0f;
                 }
             }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 if (xcol[nt]) {
-                    load_run<RPL>(xcol[nt] + rb, bv[nt]);
+                    load_run_f<RPL>(xcol[nt] + rb, bv[nt]);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < RPL; ++u) bv[nt][u] = 0.0;
+                    for (int u = 0; u < RPL; ++u) bv[nt][u] = 0.0f;
                 }
             }
         } else {
@@ -324,18 +364,23 @@ __device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) 
                 const int64_t prow = a.geom.map.phys(ok ? row : r0);
 #pragma unroll
                 for (int t = 0; t < kGramTPW; ++t)
-                    av[t][u] = !ok ? 0.0 : (colh[t] ? (double)colh[t][prow] : (colp[t] ? colp[t][prow] : 0.0));
+                    av[t][u] = !ok ? 0.0f : (colh[t] ? colh[t][prow] : (colp[t] ? (float)colp[t][prow] : 0.0f));
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? xcol[nt][prow] : 0.0;
+                for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? (float)xcol[nt][prow] : 0.0f;
             }
         }
 #pragma unroll
-        for (int u = 0; u < RPL; ++u)
+        for (int t = 0; t < kGramTPW; ++t) {
+            if (tile0 + t >= nmt) continue;
 #pragma unroll
-            for (int t = 0; t < kGramTPW; ++t)
-                if (tile0 + t < nmt)
+            for (int nt = 0; nt < NT; ++nt) {
+                flt4 d = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[t][nt] = mfma16(av[t][u], bv[nt][u], acc[t][nt]);
+                for (int u = 0; u < RPL; ++u) d = mfma16f(av[t][u], bv[nt][u], d);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[t][nt][v] += (double)d[v];
+            }
+        }
     }
     double *out = a.partials + ((int64_t)bx * RG + rg) * a.part_stride;
 #pragma unroll
@@ -346,7 +391,7 @@ __device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) 
             const int j = 16 * nt + il;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int c = (tile0 + t) * 16 + 4 * v + g;
+                const int c = (tile0 + t) * 16 + 4 * g + v;
                 if (c < ncol && j < S) out[(int64_t)c * S + j] = acc[t][nt][v];
             }
         }
@@ -355,7 +400,7 @@ __device__ __forceinline__ void gram_hi_body(const GramArgs &a, int bx, int by) 
 
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_gram_hi(GramArgs a) {
-    gram_hi_body<S>(a, blockIdx.x, blockIdx.y);
+    gram_f32_body<S>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- reduce
@@ -889,9 +934,16 @@ __device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, i
             }
             if (EXPL && a.Qnew_hi) {          // mixed form: FP32 copy for the next sweep-1 Gram
                 float *ch = a.Qnew_hi + (int64_t)j * a.Qnew.ld;
+                if (fast && (reinterpret_cast<uintptr_t>(ch + rl) & 7) == 0) {
+                    // the lane's row pairs as 8-byte stores
 #pragma unroll
-                for (int t = 0; t < TR; ++t)
-                    if (ok[t]) ch[prow[t]] = (float)y[t];
+                    for (int u = 0; u < TR / 2; ++u)
+                        *reinterpret_cast<float2 *>(ch + rl + 32 * u) = float2{(float)y[2 * u], (float)y[2 * u + 1]};
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) ch[prow[t]] = (float)y[t];
+                }
             }
         }
     if (EXPL) {
