@@ -819,6 +819,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after timing, run one plain copy of this many GiB (counter calibration)")
+    ap.add_argument("--tree-fan-ins", default="",
+                    help="default workload: also time the FP64 sequence with reduction trees of these "
+                         "fan-ins (comma-separated)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
                     choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep",
                              "lap2d-100x100-s4"],
@@ -1042,6 +1045,53 @@ def main():
                     "avg_launch_us": avg_us, "launches_timed": dom_n,
                     "alg_bytes_per_launch": byts_per_launch}
 
+    # reduction trees (Sec. 4.1 applied recursively), on request: the FP64
+    # sequence with level-1 nodes of g leaves, level-2 nodes of g level-1
+    # nodes, ..., in its own workspace
+    trees = {}
+    fan_ins = [int(g) for g in args.tree_fan_ins.split(",") if g] if args.tree_fan_ins else []
+    if fan_ins:
+        del ws
+        torch.cuda.empty_cache()
+    for g in fan_ins:
+        tbytes = orth.orth_tree_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, g)
+        if tbytes == 0:
+            raise RuntimeError(f"fan-in {g} refused")
+        tws = torch.empty(tbytes // 8 + 32, dtype=torch.float64, device=dev)
+        tptr = (tws.data_ptr() + 255) // 256 * 256
+
+        def tree_handle():
+            code, th = orth.orth_create_tree(n, s, kmax, leaf, orth.ORTH_FP64, g, tptr, tbytes, sptr)
+            if code:
+                raise orth.OrthError("orth_create_tree", code)
+            return th
+        for _ in range(args.warmup):
+            th = tree_handle()
+            run_sequence(Xs, th)
+            orth.orth_destroy(th)
+        times = []
+        for _ in range(args.steps):
+            th = tree_handle()
+            e0, e1 = TimingEvent(), TimingEvent()
+            e0.record(stream)
+            run_sequence(Xs, th)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            code, st, info = orth.orth_status(th)
+            levels = orth.orth_tree_levels(th)[1]
+            orth.orth_destroy(th)
+            if code or st:
+                raise RuntimeError(f"tree fan-in {g}: breakdown {info}")
+        G = torch.mm(V, V.t()) - torch.eye(kmax, dtype=torch.float64, device=dev)
+        ep = float(torch.linalg.matrix_norm(G, "fro"))
+        del G, tws
+        torch.cuda.empty_cache()
+        trees[str(g)] = {"levels": levels, "ms_per_step": min(times), "e_perp": ep,
+                         "vs_single_level": min(times) / ms_per_step}
+        print(f"[bench] tree fan-in {g}: {levels} levels, {min(times):.2f} ms per sequence, "
+              f"e_perp {ep:.2e}", file=sys.stderr, flush=True)
+
     if args.copy_probe_gib > 0:
         cnt = int(args.copy_probe_gib * (1 << 30)) // 8
         src = torch.ones(cnt, dtype=torch.float64, device=dev)
@@ -1114,6 +1164,8 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
+    if trees:
+        out["reduction_trees"] = trees
     print(json.dumps(out), flush=True)
 
 

@@ -171,6 +171,46 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
                 void *stream, orth_t **out);
 
 /*
+ * orth_tree_workspace_bytes / orth_create_tree -- as orth_workspace_bytes
+ * and orth_create, with the reduction problem itself solved by TreeTSPQR
+ * (Sec. 4.1: the reduction step is a PQR problem on an orthonormal matrix,
+ * so the method can be "applied recursively"; the recursion-levels
+ * experiment of Sec. 6.1): level-1 nodes take fan_in consecutive leaves,
+ * level-2 nodes fan_in level-1 nodes, and so on up to one root; the last
+ * node of a level takes the children that remain.  Every node solves its
+ * local PQR problem on its children's stacked [[S_c, P_c], [0, N_c]] with
+ * the reduction subalgorithm and passes [P_v; N_v] up; the down-sweep forms
+ * each child's coefficient block C_c = [S_v,c Y~_v,c] C_v.  The basis is
+ * Q = blockdiag(Q_i) B_1 ... B_L with B_l the block-diagonal matrix of
+ * level-l node factors (each node stores one k_max x k_max block per child).
+ *   fan_in   0 (or >= the number of leaves): the single reduction level of
+ *            orth_create; otherwise >= 2
+ * The workspace grows by the upper levels' factors (about 1 / (fan_in - 1)
+ * of the level over the leaves).  Not with ORTH_FP64_HOUSEHOLDER (returns 0
+ * / UNSUPPORTED) and not with deflation.  Errors as orth_workspace_bytes
+ * and orth_create (fan_in < 0 or = 1: ARG).
+ */
+size_t orth_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
+                                 int32_t precision, int32_t fan_in);
+int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                     int32_t fan_in, void *d_workspace, size_t workspace_bytes, void *stream,
+                     orth_t **out);
+
+/* orth_tree_levels -- number of reduction levels (1 for a single level) and
+ * the fan-in in use (0 for a single level).  Host state only.  Resource
+ * management of the Sec. 4.1 recursion, no further passage. */
+int orth_tree_levels(const orth_t *h, int32_t *levels, int32_t *fan_in);
+
+/*
+ * orth_export_tree_level -- copy reduction level `level`'s stacked node
+ * factors out (Sec. 4.1: each node's k x k block per child, children in
+ * order; level 0 stacks the leaves' blocks, as orth_export_local's d_T)
+ * into d_T, a (children * k) x k matrix, ldt >= children * k.  For tests and
+ * inspection.  Enqueued on the handle's stream.  Errors: ARG, POISONED, HIP.
+ */
+int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt);
+
+/*
  * orth_set_variant -- choose ORTH_PIP_PLUS (default; BCGS-PIP+, Sec. 3.1)
  * or ORTH_PIP (BCGS-PIP, Sec. 3) for the following steps.  Host-side only.  Errors: ARG, POISONED, UNSUPPORTED
  * (ORTH_PIP on an ORTH_FP64_HOUSEHOLDER handle).
@@ -291,8 +331,9 @@ int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m,
  *   status  receives ORTH_OK or ORTH_ERR_BREAKDOWN.  After a breakdown the
  *           handle is poisoned.
  *   info    optional (may be NULL): 4 ints {tree level (0 = leaves,
- *           1 = reduction), leaf index, CholeskyQR sweep (1 or 2), pivot
- *           column}.  The first failure wins; when several leaves fail in
+ *           1 = the reduction level over them, l + 1 = level l of a
+ *           reduction tree), leaf or node index, CholeskyQR sweep (1 or 2),
+ *           pivot column}.  The first failure wins; when several leaves fail in
  *           the same launch, which of them is recorded depends on the
  *           order the workgroups ran in (the breakdown itself does not).
  * Errors: ARG, HIP.

@@ -87,9 +87,24 @@ bool valid_s(int32_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16
 // widest basis (k_max + s) the planner accepts
 int32_t max_cols(int32_t) { return 2048; }
 
+// levels of a reduction tree the planner accepts (fan-in >= 2 over at most
+// 2^31 leaves needs at most 31)
+constexpr int kMaxLevels = 32;
+
 struct Plan {
     int64_t n;
     int32_t s, kmax, leaf_rows, p;
+    // reduction tree (Sec. 4.1, "applied recursively"): nlev levels, level l
+    // has nchild[l] child segments grouped into nnode[l] nodes of fan_in
+    // (the last node takes the rest); level 0's children are the leaves and
+    // level nlev - 1 is the single root.  fan_in = 0: one level.
+    int32_t fan_in, nlev;
+    int32_t nchild[kMaxLevels], nnode[kMaxLevels];
+    int64_t ldtl[kMaxLevels];     // ld of level l's stacked factor, X and U1 (ldtl[0] = ldt)
+    // per-level regions (level 0's factor, X and U1 are oT, oY, oU1R; the
+    // root's records oSR when nlev = 1); oCl[l]: the [P2 | C] records of
+    // level l's nodes, for the levels below the root
+    int64_t oTl[kMaxLevels], oYl[kMaxLevels], oU1l[kMaxLevels], oSl[kMaxLevels], oCl[kMaxLevels];
     int32_t precision;           // ORTH_FP64, ORTH_MIXED_SPLIT32 (adds the FP32 copy of the leaf
                                  // bases) or ORTH_FP64_HOUSEHOLDER (reflector leaves)
     int64_t ldq, ldt;
@@ -106,8 +121,9 @@ int32_t default_leaf_rows(int64_t n, int32_t kmax) {
 }
 
 bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t precision, Plan &pl,
-               int *why) {
+               int *why, int32_t fan_in = 0) {
     *why = ORTH_ERR_ARG;
+    if (fan_in < 0 || fan_in == 1) return false;
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
     if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32 && precision != ORTH_FP64_HOUSEHOLDER)
         return false;
@@ -135,6 +151,23 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     if (pl.p < 1) pl.p = 1;
     pl.ldq = basis_ld(n);
     pl.ldt = basis_ld((int64_t)pl.p * kmax);
+    // the tree's levels: fan_in = 0 (or >= p) is the single reduction level
+    pl.fan_in = (fan_in == 0 || fan_in >= pl.p) ? 0 : fan_in;
+    pl.nlev = 0;
+    for (int32_t count = pl.p;;) {
+        if (pl.nlev == kMaxLevels) return false;
+        const int32_t nodes = pl.fan_in == 0 ? 1 : (int32_t)ceil_div(count, pl.fan_in);
+        pl.nchild[pl.nlev] = count;
+        pl.nnode[pl.nlev] = nodes;
+        pl.ldtl[pl.nlev] = basis_ld((int64_t)count * kmax);
+        ++pl.nlev;
+        if (nodes == 1) break;
+        count = nodes;
+    }
+    if (pl.nlev > 1 && precision == ORTH_FP64_HOUSEHOLDER) {
+        *why = ORTH_ERR_UNSUPPORTED;      // Householder leaves keep the single level
+        return false;
+    }
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
     const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
@@ -157,11 +190,15 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     for (int32_t k = 0; k + s <= kmax; k += s) {
         const int32_t ncol = k + s;
         const int64_t per = (int64_t)gram_row_groups(ncol) * ncol * s;
-        const int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
+        int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
+        for (int l = 0; l < pl.nlev; ++l)
+            nR = std::max(nR, (int64_t)make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in,
+                                                      kmax, ncol, kRootChunk).nchunks());
         slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
         // pre-summed slot groups of a level with a single local problem: the
         // reduction level, and the leaf level when there is one leaf
-        const int64_t single = pl.p == 1 ? std::max((int64_t)pl.nchunkL, nR) : nR;
+        const int64_t nroot = ceil_div((int64_t)pl.nchild[pl.nlev - 1] * ncol, kRootChunk);
+        const int64_t single = pl.p == 1 ? std::max((int64_t)pl.nchunkL, nroot) : nroot;
         red_max = std::max(red_max, ceil_div(single * gram_row_groups(ncol), kReduceGroup) * ncol * s);
     }
     pl.oPL = take(slot_max);
@@ -179,10 +216,22 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
-    // and orth_apply_Q's second coefficient scratch (-Z_i), like CA
-    pl.oCA2 = precision == ORTH_FP64_HOUSEHOLDER ? take(pl.ldt * kApplyMB) : 0;
+    // and orth_apply_Q's second coefficient scratch (-Z_i, or the tree's
+    // down-sweep in turn with CA), like CA
+    pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1) ? take(pl.ldt * kApplyMB) : 0;
     // deflation state (counters and the first sweep's s x s W), Householder leaves only
     pl.oDF = precision == ORTH_FP64_HOUSEHOLDER ? take(defl_state_doubles(s)) : 0;
+    // the tree's levels: level 0 stacks the leaves' factors in T, Y, U1R;
+    // every level above has its own; records per node (the root's is SR
+    // for a single level)
+    for (int l = 0; l < pl.nlev; ++l) {
+        const bool root = l == pl.nlev - 1;
+        pl.oTl[l] = l == 0 ? pl.oT : take(pl.ldtl[l] * kmax);
+        pl.oYl[l] = l == 0 ? pl.oY : take(pl.ldtl[l] * s);
+        pl.oU1l[l] = l == 0 ? pl.oU1R : take(pl.ldtl[l] * s);
+        pl.oSl[l] = (root && pl.nlev == 1) ? pl.oSR : take((int64_t)pl.nnode[l] * small_stride(kmax, s));
+        pl.oCl[l] = root ? 0 : take((int64_t)pl.nnode[l] * kmax * 2 * s);
+    }
     pl.total = off;
     return true;
 }
@@ -191,6 +240,11 @@ LevelGeom leaf_geom(const Plan &pl, int chunk) { return make_leaf_geom(pl.n, pl.
 
 LevelGeom root_geom(const Plan &pl, int64_t seg_len, int chunk) {
     return make_root_geom(pl.p, pl.kmax, seg_len, chunk);
+}
+
+// level l of the reduction tree (level 0 over the leaves)
+LevelGeom tree_geom(const Plan &pl, int l, int64_t seg_len, int chunk) {
+    return make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in, pl.kmax, seg_len, chunk);
 }
 
 }  // namespace
@@ -255,12 +309,22 @@ struct orth_ctx {
         return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
     }
     double *TH() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oTH : nullptr; }
-    double *CA2() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oCA2 : nullptr; }
+    // second apply scratch: Householder leaves (-Z_i) and reduction trees (the
+    // down-sweep alternates between CA and CA2)
+    double *CA2() const {
+        return (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1) ? ws + pl.oCA2 : nullptr;
+    }
     DeflState *DF() const {
         return pl.precision == ORTH_FP64_HOUSEHOLDER ? reinterpret_cast<DeflState *>(ws + pl.oDF) : nullptr;
     }
     double *PR() const { return ws + pl.oPR; }
     double *PR2() const { return ws + pl.oPR2; }
+    // reduction tree level l: stacked factor, X, U1 scratch, node records
+    double *Tl(int l) const { return ws + pl.oTl[l]; }
+    double *Yl(int l) const { return ws + pl.oYl[l]; }
+    double *U1l(int l) const { return ws + pl.oU1l[l]; }
+    double *Sl(int l) const { return ws + pl.oSl[l]; }
+    double *Cl(int l) const { return ws + pl.oCl[l]; }
     double *SL() const { return ws + pl.oSL; }
     double *SR() const { return ws + pl.oSR; }
     DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + pl.oST); }
@@ -270,19 +334,29 @@ extern "C" {
 
 size_t orth_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
                             int32_t precision) {
+    return orth_tree_workspace_bytes(n, s, k_max, leaf_rows, precision, 0);
+}
+
+size_t orth_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
+                                 int32_t precision, int32_t fan_in) {
     Plan pl;
     int why;
-    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why)) return 0;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in)) return 0;
     return (size_t)pl.total * sizeof(double);
 }
 
 int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
                 void *d_workspace, size_t workspace_bytes, void *stream, orth_t **out) {
+    return orth_create_tree(n, s, k_max, leaf_rows, precision, 0, d_workspace, workspace_bytes, stream, out);
+}
+
+int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                     int32_t fan_in, void *d_workspace, size_t workspace_bytes, void *stream, orth_t **out) {
     if (!out) return ORTH_ERR_ARG;
     *out = nullptr;
     Plan pl;
     int why;
-    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why)) return why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in)) return why;
     if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
         workspace_bytes < (size_t)pl.total * sizeof(double))
         return ORTH_ERR_WORKSPACE;
@@ -299,8 +373,10 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
     // tree factors must start at zero: the reduction level relies on the
     // zero rows below every T_i's current k x k block
     hipError_t e = prepare_kernels(pl.s);
-    if (e == hipSuccess) e = launch_fill(h->T(), pl.ldt * (int64_t)pl.kmax, 0.0, h->stream);
-    if (e == hipSuccess) e = launch_fill(h->Y(), pl.ldt * (int64_t)pl.s, 0.0, h->stream);
+    for (int l = 0; l < pl.nlev && e == hipSuccess; ++l) {
+        e = launch_fill(h->Tl(l), pl.ldtl[l] * (int64_t)pl.kmax, 0.0, h->stream);
+        if (e == hipSuccess) e = launch_fill(h->Yl(l), pl.ldtl[l] * (int64_t)pl.s, 0.0, h->stream);
+    }
     // Householder leaves: the compact-WY factors grow into zeros below their diagonal
     if (e == hipSuccess && h->TH())
         e = launch_fill(h->TH(), (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
@@ -682,45 +758,66 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.yseg = kmax;
         if ((rc = run_level(h, L, k, two))) goto fail;
     }
-    // ---- reduction: PQR on the stacked [[T_i, P_i], [0, N_i]] (segments of k+s rows)
-    {
+    // ---- reduction: PQR on the stacked [[T_c, P_c], [0, N_c]] of each node's
+    // children (segments of k+s rows), level by level up to the root
+    for (int l = 0; l < pl.nlev; ++l) {
+        const bool root = l == pl.nlev - 1;
         LevelRun L{};
-        L.Q = Operand{h->T(), pl.ldt};
-        L.X = Operand{h->Y(), pl.ldt};
-        L.U1 = OutOperand{h->U1R(), pl.ldt};
-        L.geom = root_geom(pl, ncol, kRootChunk);
-        L.rgeom = root_geom(pl, ncol, kRootRowChunk);
+        L.Q = Operand{h->Tl(l), pl.ldtl[l]};
+        L.X = Operand{h->Yl(l), pl.ldtl[l]};
+        L.U1 = OutOperand{h->U1l(l), pl.ldtl[l]};
+        L.geom = tree_geom(pl, l, ncol, kRootChunk);
+        L.rgeom = tree_geom(pl, l, ncol, kRootRowChunk);
         L.part = h->PR();
         L.part2 = h->PR2();
         L.part_cap = pl.slot_cap;
         L.part2_cap = pl.red_cap;
-        L.small = h->SR();
-        L.level = 1;
-        L.H = k > 0 ? d_H : nullptr;
-        L.ldh = ldh;
-        L.R = d_R;
-        L.ldr = ldr;
+        L.small = h->Sl(l);
+        L.level = l + 1;
+        L.pc = root ? nullptr : h->Cl(l);
+        if (root) {
+            L.H = k > 0 ? d_H : nullptr;
+            L.ldh = ldh;
+            L.R = d_R;
+            L.ldr = ldr;
+        } else {
+            L.Yout = h->Yl(l + 1);
+            L.ldy = pl.ldtl[l + 1];
+            L.yseg = kmax;
+        }
         DeflArgs dargs{h->defl_delta * h->defl_delta, h->DF()};
         L.defl = h->defl_delta > 0.0 ? &dargs : nullptr;
         if ((rc = run_level(h, L, k, two_red))) goto fail;
-
-        // reduction-level new columns [P~_i; N~_i] -> T_i[:, k:k+s], and
-        // row-major per leaf (C_i) for the leaf finalize
+    }
+    // ---- down the tree: every level's new columns [P~_c; N~_c] -> its
+    // factor's columns k..k+s-1; the root's are its children's coefficient
+    // blocks C_c, a lower node v forms its children's C_c = [S_v,c Y~_v,c] C_v
+    // (Sec. 4.1, assembly of U), down to the leaves' records
+    for (int l = pl.nlev - 1; l >= 0; --l) {
+        const bool root = l == pl.nlev - 1;
+        double *below = l == 0 ? h->CL() : h->Cl(l - 1);
         FinalizeArgs f{};
-        f.Q = Operand{h->T(), pl.ldt};
-        f.Qnew = OutOperand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
-        f.U1 = Operand{h->U1R(), pl.ldt};
+        f.Q = Operand{h->Tl(l), pl.ldtl[l]};
+        f.Qnew = OutOperand{h->Tl(l) + (int64_t)k * pl.ldtl[l], pl.ldtl[l]};
+        f.U1 = Operand{h->U1l(l), pl.ldtl[l]};
         f.sweep = 2;
         f.k = k;
-        f.geom = root_geom(pl, ncol, kRootRowChunk);
-        f.small = h->SR();
+        f.geom = tree_geom(pl, l, ncol, kRootRowChunk);
+        f.small = h->Sl(l);
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
         f.single_sweep = two_red ? 0 : 1;
-        f.Cptr = nullptr;
-        f.Crow = h->CL();
-        f.crow_seg = (int64_t)kmax * 2 * s;
         f.status = h->status();
+        if (root) {
+            f.Cptr = nullptr;
+            f.Crow = below;
+            f.crow_seg = (int64_t)kmax * 2 * s;
+        } else {
+            f.Cptr = h->Cl(l);
+            f.cseg = (int64_t)kmax * 2 * s;
+            f.Cout = below;
+            f.cout_seg = (int64_t)kmax * 2 * s;
+        }
         const int pm = h->begin(ORTH_K_ROOT_FINALIZE);
         const hipError_t e = launch_finalize(s, f, ORTH_K_ROOT_FINALIZE, st);
         h->end(pm);
@@ -774,22 +871,40 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
     hipStream_t st = h->stream;
     auto begin = [&](int cls) { return prof ? h->begin(cls) : -1; };
     auto end = [&](int idx) { if (prof) h->end(idx); };
+    // host check: the tree's down-sweep and the Householder products need
+    // the second scratch region
+    if (!ca || ((hh || pl.nlev > 1) && !ca2) || mb_max < 1) return ORTH_ERR_HIP;
     for (int32_t j0 = 0; j0 < m; j0 += mb_max) {
         const int32_t mb = (m - j0) < mb_max ? (m - j0) : mb_max;
-        // reduction level: C_i = T_i C (rows: p segments of k rows)
-        ApplyArgs r{};
-        r.Q = Operand{h->T(), pl.ldt};
-        r.k = k;
-        r.geom = root_geom(pl, k, kRootRowChunk);
-        r.Cptr = d_C + (int64_t)j0 * ldc;
-        r.ldc = ldc;
-        r.cseg = 0;
-        r.m = mb;
-        r.Y = OutOperand{ca, pl.ldt};
-        const int pm0 = begin(ORTH_K_APPLY);
-        hipError_t e = launch_apply(r, st);
-        end(pm0);
-        if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+        // down the reduction tree: a node's children get C_c = S_v,c C_v
+        // (rows: the level's child segments of k rows); the root's C is the
+        // caller's, every lower level's the level above's output, the two
+        // scratch regions in turn, so level 0 leaves C_i in `cur`
+        hipError_t e = hipSuccess;
+        double *cur = nullptr;
+        for (int l = pl.nlev - 1; l >= 0; --l) {
+            double *out = (cur == ca) ? ca2 : ca;
+            ApplyArgs r{};
+            r.Q = Operand{h->Tl(l), pl.ldtl[l]};
+            r.k = k;
+            r.geom = tree_geom(pl, l, k, kRootRowChunk);
+            if (l == pl.nlev - 1) {
+                r.Cptr = d_C + (int64_t)j0 * ldc;
+                r.ldc = ldc;
+                r.cseg = 0;
+            } else {
+                r.Cptr = cur;
+                r.ldc = pl.ldt;
+                r.cseg = pl.kmax;
+            }
+            r.m = mb;
+            r.Y = OutOperand{out, pl.ldt};
+            const int pm0 = begin(ORTH_K_APPLY);
+            e = launch_apply(r, st);
+            end(pm0);
+            if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+            cur = out;
+        }
         // leaves: Y_i = Q_i C_i; with Householder leaves Y_i = -V Z_i + E C_i,
         // Z_i = T (V[0:k]^T C_i)
         HhArgs ha{};
@@ -798,7 +913,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             ha.k = k;
             ha.kmax = pl.kmax;
             ha.T = h->TH();
-            ha.ca = ca;
+            ha.ca = cur;            // (one level: cur == ca)
             ha.ca_out = ca2;
             ha.ldca = pl.ldt;
             ha.m = mb;
@@ -813,7 +928,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         a.Q = Operand{h->Q(), pl.ldq};
         a.k = k;
         a.geom = leaf_geom(pl, kFinalChunk);
-        a.Cptr = hh ? ca2 : ca;
+        a.Cptr = hh ? ca2 : cur;
         a.ldc = pl.ldt;
         a.cseg = pl.kmax;
         a.m = mb;
@@ -845,8 +960,8 @@ int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, d
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
     // one column of coefficient blocks per region (two regions with
-    // Householder leaves) must fit the static scratch
-    const int64_t regions = h->pl.precision == ORTH_FP64_HOUSEHOLDER ? 2 : 1;
+    // Householder leaves or a reduction tree) must fit the static scratch
+    const int64_t regions = (h->pl.precision == ORTH_FP64_HOUSEHOLDER || h->pl.nlev > 1) ? 2 : 1;
     const int64_t cols = kStaticScratchDoubles / (regions * h->pl.ldt);
     if (cols < 1) return ORTH_ERR_SCRATCH;
     if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
@@ -926,6 +1041,26 @@ int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows) {
     if (!h) return ORTH_ERR_ARG;
     if (p) *p = h->pl.p;
     if (leaf_rows) *leaf_rows = h->pl.leaf_rows;
+    return ORTH_OK;
+}
+
+int orth_tree_levels(const orth_t *h, int32_t *levels, int32_t *fan_in) {
+    if (!h) return ORTH_ERR_ARG;
+    if (levels) *levels = h->pl.nlev;
+    if (fan_in) *fan_in = h->pl.fan_in;
+    return ORTH_OK;
+}
+
+int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt) {
+    if (!h) return ORTH_ERR_ARG;
+    if (h->poisoned) return ORTH_ERR_POISONED;
+    const Plan &pl = h->pl;
+    const int32_t k = h->k;
+    if (k < 1 || level < 0 || level >= pl.nlev || !d_T || ldt < (int64_t)pl.nchild[level] * k)
+        return ORTH_ERR_ARG;
+    const hipError_t e = launch_copy_cols(h->Tl(level), pl.ldtl[level], RowMap{k, pl.kmax}, d_T, ldt,
+                                          (int64_t)pl.nchild[level] * k, k, h->stream);
+    if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
     return ORTH_OK;
 }
 

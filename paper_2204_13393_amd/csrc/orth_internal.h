@@ -123,6 +123,25 @@ __host__ __device__ inline LevelGeom make_root_geom(int32_t p, int32_t kmax, int
     return g;
 }
 
+// a level of a reduction tree (Sec. 4.1, the reduction problem solved by
+// TreeTSPQR again): nchild child segments of seg_len rows (child c stored at
+// rows [c*kmax, c*kmax + seg_len)), grouped into nodes of fan_in
+// consecutive children, the last node taking the rest; fan_in >= nchild is
+// the single node of make_root_geom
+__host__ __device__ inline LevelGeom make_tree_geom(int32_t nchild, int32_t fan_in, int32_t kmax, int64_t seg_len,
+                                                    int chunk) {
+    if (fan_in >= nchild) return make_root_geom(nchild, kmax, seg_len, chunk);
+    LevelGeom g{};
+    g.nrows = (int64_t)nchild * seg_len;
+    g.nleaf = (int32_t)ceil_div64(nchild, fan_in);
+    g.leaf_rows = (int64_t)fan_in * seg_len;
+    g.chunk_rows = chunk;
+    g.cpl = (int32_t)ceil_div64(g.leaf_rows, chunk);
+    g.cpl_last = (int32_t)ceil_div64(g.nrows - (int64_t)(g.nleaf - 1) * g.leaf_rows, chunk);
+    g.map = RowMap{seg_len, kmax};
+    return g;
+}
+
 // Device status record (first failure wins).
 struct DevStatus {
     int32_t code;        // 0 ok, 3 breakdown
@@ -242,6 +261,11 @@ struct FinalizeArgs {
     double *Crow;
     int64_t crow_seg;
     OutOperand Uout;      // explicit output (identity RowMap, leaf level)
+    // tree level below the root: the explicit product [q u] C goes to the
+    // children's coefficient records instead (logical row r = child*(k+s) + c
+    // -> Cout[child*cout_seg + c*2s + s + j]); Uout unused
+    double *Cout;
+    int64_t cout_seg;
     const DevStatus *status;
 };
 

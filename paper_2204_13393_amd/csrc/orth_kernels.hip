@@ -968,6 +968,17 @@ __device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, i
                 double y[TR];
 #pragma unroll
                 for (int t = 0; t < TR; ++t) y[t] = acc[t][T][v];
+                if (a.Cout) {                 // tree level: the children's C records
+#pragma unroll
+                    for (int t = 0; t < TR; ++t)
+                        if (ok[t]) {
+                            const int64_t r = lane_row(rb, il, t);
+                            const int64_t lf = r / a.geom.map.seg_len;
+                            const int64_t cc = r - lf * a.geom.map.seg_len;
+                            a.Cout[lf * a.cout_seg + cc * 2 * S + m] = y[t];
+                        }
+                    continue;
+                }
                 double *col = a.Uout.ptr + (int64_t)(m - S) * a.Uout.ld;
                 if (fast) {
                     store_rows<TR>(col + rl, y);
@@ -1753,7 +1764,12 @@ static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
             return launch_rowlds<S, false, 2>(a, st);   // the leaf correction is the only leaf-level one
         }
     }
-    if (a.Cptr != nullptr) {
+    if (a.Cptr != nullptr && cls == 6) {
+        // a tree level below the root: explicit product into the children's
+        // records, stacked tree-factor rows (zero rows skipped)
+        if (!a.Cout || a.geom.map.seg_len == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_rowmfma<S, true, 6>), grid, dim3(kThreads), 0, st, a);
+    } else if (a.Cptr != nullptr) {
         hipLaunchKernelGGL((k_rowmfma<S, true, 7>), grid, dim3(kThreads), 0, st, a);
     } else {
         switch (cls) {

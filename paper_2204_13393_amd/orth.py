@@ -39,6 +39,10 @@ _i32, _i64, _sz, _vp, _dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, cty
 SIGNATURES = [
     ("orth_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32]),
     ("orth_create", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    ("orth_tree_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32, _i32]),
+    ("orth_create_tree", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    ("orth_tree_levels", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_export_tree_level", ctypes.c_int, [_vp, _i32, _dp, _i64]),
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
     ("orth_mixed_fallbacks", ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
@@ -115,6 +119,27 @@ def orth_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes,
     code = load().orth_create(n, s, k_max, leaf_rows, precision, d_workspace, workspace_bytes,
                               stream, ctypes.byref(h))
     return code, h
+
+
+def orth_tree_workspace_bytes(n, s, k_max, leaf_rows=0, precision=ORTH_FP64, fan_in=0):
+    return load().orth_tree_workspace_bytes(n, s, k_max, leaf_rows, precision, fan_in)
+
+
+def orth_create_tree(n, s, k_max, leaf_rows, precision, fan_in, d_workspace, workspace_bytes, stream):
+    h = ctypes.c_void_p()
+    code = load().orth_create_tree(n, s, k_max, leaf_rows, precision, fan_in, d_workspace, workspace_bytes,
+                                   stream, ctypes.byref(h))
+    return code, h
+
+
+def orth_tree_levels(h):
+    lv, fi = ctypes.c_int32(), ctypes.c_int32()
+    code = load().orth_tree_levels(h, ctypes.byref(lv), ctypes.byref(fi))
+    return code, lv.value, fi.value
+
+
+def orth_export_tree_level(h, level, d_T, ldt):
+    return load().orth_export_tree_level(h, level, d_T, ldt)
 
 
 def orth_set_variant(h, variant):
@@ -303,26 +328,27 @@ class Orthogonalizer:
     """
 
     def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
-                 precision=ORTH_FP64, reduction_variant=None):
+                 precision=ORTH_FP64, reduction_variant=None, fan_in=0):
         import torch
         load()
         self.n, self.s, self.k_max = int(n), int(s), int(k_max)
         self.precision = precision
         self.device = torch.device(device)
-        nbytes = orth_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision)
+        nbytes = orth_tree_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision, fan_in)
         if nbytes == 0:
             raise OrthError("orth_workspace_bytes", ORTH_ERR_ARG)
         self.stream = stream
         self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        code, h = orth_create(self.n, self.s, self.k_max, leaf_rows, precision, aligned, nbytes,
-                              _stream_ptr(stream))
+        code, h = orth_create_tree(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, aligned, nbytes,
+                                   _stream_ptr(stream))
         _check("orth_create", code)
         self.h = h
         red = variant if reduction_variant is None else reduction_variant
         _check("orth_set_level_variants", orth_set_level_variants(self.h, variant, red))
         _, self.p, self.leaf_rows = orth_leaf_count(self.h)
+        _, self.levels, self.fan_in = orth_tree_levels(self.h)
 
     @property
     def k(self):
@@ -378,6 +404,17 @@ class Orthogonalizer:
         _check("orth_export_local",
                orth_export_local(self.h, Qloc.data_ptr(), self.n, T.data_ptr(), self.p * k))
         return Qloc, T
+
+    def export_tree_level(self, level):
+        """Level `level`'s stacked node factors: (k, children*k), column-major (children k) x k."""
+        import torch
+        k = self.k
+        children = self.p
+        for _ in range(level):
+            children = (children + self.fan_in - 1) // self.fan_in
+        T = torch.empty((k, children * k), dtype=torch.float64, device=self.device)
+        _check("orth_export_tree_level", orth_export_tree_level(self.h, level, T.data_ptr(), children * k))
+        return T
 
     def close(self):
         if getattr(self, "h", None) is not None:

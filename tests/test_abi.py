@@ -189,3 +189,20 @@ def test_autotune_batch_buckets(monkeypatch, tmp_path):
     assert calls == [(16384, 4, 84, 64), (1 << 20, 8, 168, 8), (4096, 2, 42, 64)]
     # results are clipped to each instance's [k_max, n]
     assert rows == [8192, 8192, 8192, 3000, 5000]
+
+
+def test_tree_workspace_arguments():
+    """Reduction trees: fan-in 1 and negative fan-ins are refused, Householder
+    leaves keep the single level, a fan-in at or above the leaf count is the
+    single level, and the upper levels add storage (host arithmetic only)."""
+    one = orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 0)
+    assert one == orth.orth_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64) > 0
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 1) == 0
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, -2) == 0
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64_HOUSEHOLDER, 2) == 0
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 20) == one
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 2) > one
+    assert orth.orth_tree_levels(None)[0] == orth.ORTH_ERR_ARG
+    assert orth.orth_export_tree_level(None, 0, 0, 1) == orth.ORTH_ERR_ARG
+    code, h = orth.orth_create_tree(10000, 4, 16, 500, orth.ORTH_FP64, 1, 0, 0, None)
+    assert code == orth.ORTH_ERR_ARG and not h.value

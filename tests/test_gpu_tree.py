@@ -1,0 +1,167 @@
+"""GPU reduction trees (orth_create_tree): TreeTSPQR applied recursively
+(Sec. 4.1) against the oracle's TreeTSPQR with the same leaves and fan-in.
+
+* every call's H, R, U against the unique PQR solution (pqr_reference) and
+  the oracle tree's U, at the FP64 tolerances of test_gpu_parity.py
+  (||dH||_F / ||W||_F <= 1e-12, ||dR||_F / ||W||_F and max |dU| <= 1e-12
+  kappa_j);
+* every level's stacked node factors against the oracle tree's
+  (stacked_factor(level)): unique once the leaves and the tree are fixed,
+  within 1e-11 kappa;
+* Y = Q C through the representation, and orth_apply_Q_noalloc bit for bit;
+* the recursion-levels table of Sec. 6.1 (Stewart kappa = 1e4, n = 2^16, 32
+  columns, s = 4, 2^l leaves, fan-in 2): e_perp and ||A - QR|| in the band
+  [min / 10, 10 max] of the printed BCGS-PIP and BCGS-PIP+ columns, as the
+  oracle's own pin does.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import TreeTSPQR, metrics, pqr_reference
+from synth import stewart
+
+from gpu_util import kappa_after_projection, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    return torch
+
+
+CASES = [
+    # n, s, kmax, leaf_rows, fan_in, precision, reduction variant
+    (20000, 4, 40, 500, 2, 0, "pip+"),      # 40 leaves, 6 levels; a node with one child (5 -> 3)
+    (30000, 8, 64, 1000, 4, 0, "pip+"),     # 30 leaves, 3 levels, ragged nodes
+    (50000, 16, 96, 2000, 3, 0, "pip+"),    # 25 leaves -> 9 -> 3 -> 1
+    (8192, 32, 96, 1024, 2, 0, "pip+"),     # s = 32, 8 -> 4 -> 2 -> 1
+    (20000, 8, 48, 1000, 4, 1, "pip+"),     # mixed form under a tree
+    (12000, 4, 32, 600, 3, 0, "pip"),       # BCGS-PIP at every reduction level
+]
+
+
+def _levels_children(p, fan_in):
+    out = []
+    count = p
+    while True:
+        out.append(count)
+        nodes = 1 if fan_in >= count else -(-count // fan_in)
+        if nodes == 1:
+            return out
+        count = nodes
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows,fan_in,precision,red", CASES)
+def test_tree_parity(torch_cuda, n, s, kmax, leaf_rows, fan_in, precision, red):
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("tree", n, s, kmax, leaf_rows, fan_in, precision, red)
+    rng = np.random.default_rng(n + 7 * s + fan_in)
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows, precision=precision, fan_in=fan_in,
+                         reduction_variant=orth.ORTH_PIP if red == "pip" else orth.ORTH_PIP_PLUS)
+    p = n // leaf_rows
+    children = _levels_children(p, fan_in)
+    assert gpu.levels == len(children) > 1 and gpu.fan_in == fan_in
+    tree = TreeTSPQR(n, s, leaf_rows, "pip+", red, fan_in)
+    assert len(tree.levels) == gpu.levels
+    tol = 1e-12 if (precision == 0 and red == "pip+") else 1e-10
+    Q = np.zeros((n, 0))
+    Ugpu = []
+    kap_max = 1.0
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        H, R, U = to_host(Hd), to_host(Rd), to_host(Ud)
+        P, N, Ur = pqr_reference(Q, X)
+        Pt, Nt, Ut = tree.step(X)
+        kap = kappa_after_projection(N, X)
+        kap_max = max(kap_max, kap)
+        xn = np.linalg.norm(X)
+        if red == "pip+":
+            if step:
+                assert np.linalg.norm(H - P) / xn <= tol, step
+            assert np.linalg.norm(R - N) / xn <= tol * kap, step
+            assert np.max(np.abs(U - Ur)) <= tol * kap, step
+        # against the oracle tree with the same leaves, fan-in and subalgorithms
+        if step:
+            assert np.linalg.norm(H - Pt) / xn <= tol * kap, step
+        assert np.linalg.norm(R - Nt) / xn <= tol * kap, step
+        assert np.max(np.abs(U - Ut)) <= tol * kap, step
+        assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0)
+        Ugpu.append(U)
+        Q = np.hstack([Q, Ur])
+    st, info = gpu.status()
+    assert st == 0, info
+    V = np.hstack(Ugpu)
+    assert metrics.e_perp(V) <= (1e-12 if red == "pip+" else 1e-10)
+    # every level's node factors against the oracle tree's
+    for level in range(gpu.levels):
+        T = to_host(gpu.export_tree_level(level))
+        To = tree.stacked_factor(level)
+        assert T.shape == To.shape == (children[level] * gpu.k, gpu.k)
+        assert np.max(np.abs(T - To)) <= 1e-11 * kap_max, level
+    # Y = Q C, and the allocation-free form bit for bit
+    C = rng.standard_normal((gpu.k, 19))
+    Cd = to_dev(C)
+    Y = to_host(gpu.apply_Q(Cd))
+    assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
+    Y2 = torch.empty((19, n), dtype=torch.float64, device="cuda")
+    assert orth.orth_apply_Q_noalloc(gpu.h, Cd.data_ptr(), gpu.k, 19, Y2.data_ptr(), n) == 0
+    assert np.array_equal(to_host(Y2), Y)
+    gpu.close()
+
+
+@pytest.fixture(scope="module")
+def stewart_1e4():
+    return stewart(2 ** 16, 32, 1e4, 0)
+
+
+@pytest.mark.parametrize("level", [0, 1, 3, 5, 8])
+def test_recursion_levels_table(torch_cuda, stewart_1e4, level):
+    """Sec. 6.1 recursion-levels table on the GPU: 2^level leaves, fan-in 2."""
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    n, m, s = 2 ** 16, 32, 4
+    A = stewart_1e4
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_stability_tables.json")))
+    for variant, ecol, rcol in (("pip", 0, 3), ("pip+", 1, 4)):
+        _say("recursion", level, variant)
+        v = orth.ORTH_PIP if variant == "pip" else orth.ORTH_PIP_PLUS
+        gpu = Orthogonalizer(n, s, m, n // 2 ** level, variant=v, fan_in=2 if level else 0)
+        assert gpu.levels == max(1, level)
+        R = np.zeros((m, m))
+        for j in range(m // s):
+            Hd, Rd, _ = gpu.step(to_dev(A[:, j * s:(j + 1) * s]))
+            R[:j * s, j * s:(j + 1) * s] = to_host(Hd)
+            R[j * s:(j + 1) * s, j * s:(j + 1) * s] = to_host(Rd)
+        st, info = gpu.status()
+        assert st == 0, info
+        Q = to_host(gpu.apply_Q(torch.eye(m, dtype=torch.float64, device="cuda")))
+        e = metrics.e_perp(Q)
+        res = np.linalg.norm(A - Q @ R, "fro")
+        vals = [row[ecol] for row in gold["recursion_levels"].values()]
+        assert min(vals) / 10 <= e <= max(vals) * 10, (variant, level, e)
+        rvals = [row[rcol] for row in gold["recursion_levels"].values()]
+        assert min(rvals) / 10 <= res <= max(rvals) * 10, (variant, level, res)
+        print(f"[recursion] level {level} {variant}: e_perp {e:.2e} ||A-QR|| {res:.2e}", flush=True)
+        gpu.close()
