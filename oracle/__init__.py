@@ -23,6 +23,8 @@ deflate      Deflation of BCGS-PIP(+) by the truncated eigen decomposition
 tspqr        TreeTSPQR (Sec. 4.1) with the locally orthogonal basis
              representation, single- and multi-level trees; BCGS-PIP,
              BCGS-PIP+ or Householder leaves.
+flattspqr    FlatTSPQR (Sec. 4.2): the basis as a chain of per-block
+             factors, the local problems solved one after another.
 krylov       Block Arnoldi (Sec. 2, Algorithm "Block Arnoldi") and the
              block-column QR driver (Sec. 2, Algorithm "Block Column-oriented
              QR-factorization").
@@ -43,6 +45,7 @@ from .hhpqr import HouseholderBasis, hh_pqr
 from .deflate import (truncated_sqrt, deflating_pip, deflating_pip_plus,
                       pqr_deflated_reference)
 from .tspqr import TreeTSPQR, leaf_bounds
+from .flattspqr import FlatTSPQR
 from .krylov import block_arnoldi, block_column_qr
 from . import operators, metrics
 
@@ -50,6 +53,6 @@ __all__ = [
     "householder_qr", "house", "Breakdown", "cholesky_upper",
     "triu_solve_right", "pqr_reference", "bcgs_pip", "bcgs_pip_plus",
     "SUBALGORITHMS", "HouseholderBasis", "hh_pqr", "truncated_sqrt",
-    "deflating_pip", "deflating_pip_plus", "pqr_deflated_reference", "TreeTSPQR", "leaf_bounds", "block_arnoldi",
+    "deflating_pip", "deflating_pip_plus", "pqr_deflated_reference", "TreeTSPQR", "FlatTSPQR", "leaf_bounds", "block_arnoldi",
     "block_column_qr", "operators", "metrics",
 ]
