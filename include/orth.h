@@ -467,7 +467,7 @@ int orth_batch_destroy(orth_batch_t *b);
  * orth_tune_leaf_rows times `steps` calls (k = 0, s, 2s, ...) on synthetic
  * blocks (uniform in [-1, 1), a fixed hash of the call index, row and column)
  * for every candidate leaf height
- *     {256, 512, ..., 16384} restricted to [k_max, n], and n itself if n <= 16384,
+ *     {256, 512, ..., 65536} restricted to [k_max, n], and n itself if n <= 65536,
  * through one handle (copies = 1, orth_step) or through a batch of `copies`
  * identical instances (orth_batch_step; this saturates the GPU as a large
  * batch does).  Among candidates within 2% of the fastest the tallest is

@@ -1306,9 +1306,16 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
                 for (int32_t i = 0; i < count; ++i)
                     row[i + 1] = row[i] + (b->desc[i].s == L.widths[w] ? batch_phase_blocks(b->desc[i], ph, st, 1) : 0);
             }
+    // the LDS-staged leaf row updates for widths >= 16 whose instances all
+    // start their chunks on even rows (even leaf heights, or one leaf; the
+    // rest holds by construction)
+    std::vector<bool> rowlds(nw, true);
+    for (size_t w = 0; w < nw; ++w)
+        for (int32_t i = 0; i < count; ++i)
+            if (b->desc[i].s == L.widths[w] && (b->desc[i].leaf_rows & 1) && b->desc[i].p > 1) rowlds[w] = false;
     b->lds.assign((size_t)BP_COUNT * nw, 0);
     for (int ph = 0; ph < BP_COUNT; ++ph)
-        for (size_t w = 0; w < nw; ++w) b->lds[ph * nw + w] = batch_phase_lds(ph, L.widths[w]);
+        for (size_t w = 0; w < nw; ++w) b->lds[ph * nw + w] = batch_phase_lds(ph, L.widths[w], rowlds[w]);
     hipError_t e = hipMemcpyAsync(b->ws + L.o_desc, b->desc.data(), count * sizeof(BatchInst),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -1426,11 +1433,15 @@ int orth_batch_destroy(orth_batch_t *b) {
 
 namespace {
 
+// leaf heights 256 .. kTuneMaxLeaf in powers of two within [k_max, n], and n
+// itself when n is below the largest
+constexpr int64_t kTuneMaxLeaf = 65536;
+
 std::vector<int32_t> tune_candidates(int64_t n, int32_t kmax) {
     std::vector<int32_t> c;
-    for (int64_t lr = 256; lr <= 16384; lr *= 2)
+    for (int64_t lr = 256; lr <= kTuneMaxLeaf; lr *= 2)
         if (lr >= kmax && lr <= n) c.push_back((int32_t)lr);
-    if (n <= 16384 && n >= kmax && (c.empty() || c.back() != n)) c.push_back((int32_t)n);
+    if (n <= kTuneMaxLeaf && n >= kmax && (c.empty() || c.back() != n)) c.push_back((int32_t)n);
     return c;
 }
 

@@ -405,7 +405,10 @@ hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_
 hipError_t launch_synth(double *W, int64_t ld, int64_t n, int32_t s, uint64_t seed, hipStream_t st);
 // one phase for the instances of block width s (prefix table restricted to them)
 hipError_t launch_batch_phase(const BatchArgs &a, int s, int32_t blocks, size_t lds, hipStream_t st);
-size_t batch_phase_lds(int phase, int s);     // dynamic LDS one instance of width s needs
+// dynamic LDS one launch of a phase for width s needs; rowlds: the leaf row
+// updates of s >= 16 run LDS-staged (every instance of the width has even
+// leaf heights)
+size_t batch_phase_lds(int phase, int s, bool rowlds);
 
 
 }  // namespace orth

@@ -1568,6 +1568,36 @@ __device__ void batch_reduce(const BatchArgs &a, const BatchInst &d, int local) 
     reduce_body(r, local % eb, local / eb);
 }
 
+// the leaf row updates' arguments for instance d: the correction (BP_LCORR)
+// or the finalize with the explicit block (BP_LFIN)
+template <int S>
+__device__ __forceinline__ FinalizeArgs batch_leaf_rowupdate_args(const BatchArgs &a, const BatchInst &d, int inst) {
+    const int k = a.step * S;
+    FinalizeArgs f{};
+    f.k = k;
+    f.kmax = d.kmax;
+    f.small_stride = small_stride(d.kmax, S);
+    f.status = a.status;
+    f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk);
+    f.small = d.SL;
+    if (a.phase == BP_LCORR) {
+        f.Q = Operand{d.Q, d.ldq};
+        f.Qnew = OutOperand{d.U1L, d.ldq};
+        f.U1 = Operand{a.W[inst], d.n};
+        f.sweep = 1;
+    } else {
+        f.Q = Operand{d.Q, d.ldq};
+        f.Qnew = OutOperand{d.Q + (int64_t)k * d.ldq, d.ldq};
+        f.U1 = Operand{d.U1L, d.ldq};
+        f.sweep = 2;
+        f.single_sweep = a.two ? 0 : 1;
+        f.Cptr = d.CL;
+        f.cseg = (int64_t)d.kmax * 2 * S;
+        f.Uout = OutOperand{a.U[inst], d.n};
+    }
+    return f;
+}
+
 template <int S>
 __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst, int local) {
     const int k = a.step * S, ncol = k + S;
@@ -1658,6 +1688,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     batch_rowupdate<S>(a, d, inst, local);
 }
 
+// the leaf row updates of blocks of 16 and more columns, LDS-staged as the
+// single handles' (k_rowlds: same products, same bits); the host uses it
+// when every instance of the width meets rowlds_body's requirements (even
+// chunk starts: even leaf heights or a single leaf; the rest holds by
+// construction)
+template <int S, bool EXPL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_rowlds(BatchArgs a) {
+    extern __shared__ double lds_dyn[];
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    const FinalizeArgs f = batch_leaf_rowupdate_args<S>(a, d, inst);
+    rowlds_body<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>(f, local, lds_dyn);
+}
+
 // ---------------------------------------------------------------- launchers
 static int grid_for(int64_t count, int threads) {
     int64_t b = (count + threads - 1) / threads;
@@ -1742,7 +1787,10 @@ hipError_t launch_chol(int s, const CholArgs &a, hipStream_t st) {
 static bool rowlds_eligible(const FinalizeArgs &a, int s) {
     const auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     if (s < 16 || a.geom.map.seg_len != 0) return false;
-    if ((a.geom.leaf_rows & 1) || (a.geom.chunk_rows & 1) || (a.Q.ld & 1) || !al16(a.Q.ptr)) return false;
+    // even chunk starts: even chunks, and even leaf heights unless one leaf
+    if (((a.geom.leaf_rows & 1) && a.geom.nleaf > 1) || (a.geom.chunk_rows & 1) || (a.Q.ld & 1) ||
+        !al16(a.Q.ptr))
+        return false;
     if (!al16(a.small) || (a.small_stride & 1) || ((int64_t)a.kmax * s & 1)) return false;
     if (a.Cptr && (!al16(a.Cptr) || (a.cseg & 1))) return false;
     return true;
@@ -1796,6 +1844,14 @@ template <int S>
 static hipError_t raise_wide_lds() {
     hipError_t e = raise_rowlds_lds<S, true, 7>();
     if (e == hipSuccess) e = raise_rowlds_lds<S, false, 2>();
+    using CF = RowLds<S, true, rowlds_tr<S, true>(), rowlds_bk<S, true>(), rowlds_nst<S, true>()>;
+    using CC = RowLds<S, false, rowlds_tr<S, false>(), rowlds_bk<S, false>(), rowlds_nst<S, false>()>;
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_rowlds<S, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)CF::lds_bytes());
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_rowlds<S, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)CC::lds_bytes());
     if (e == hipSuccess && chol_lds_bytes<S>() > 65536)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol<S>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds_bytes<S>());
@@ -1876,11 +1932,20 @@ hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_
 
 namespace orth {
 
-size_t batch_phase_lds(int phase, int s) {
+template <int S, bool EXPL>
+static size_t rowlds_lds_bytes() {
+    return RowLds<S, EXPL, rowlds_tr<S, EXPL>(), rowlds_bk<S, EXPL>(), rowlds_nst<S, EXPL>()>::lds_bytes();
+}
+
+size_t batch_phase_lds(int phase, int s, bool rowlds) {
     auto chol = [](int s) -> size_t { return chol_lds_bytes_s(s); };
     switch (phase) {
         case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
             return chol(s);
+        case BP_LCORR: case BP_LFIN:
+            if (!rowlds || s < 16) return 0;
+            if (s == 16) return phase == BP_LFIN ? rowlds_lds_bytes<16, true>() : rowlds_lds_bytes<16, false>();
+            return phase == BP_LFIN ? rowlds_lds_bytes<32, true>() : rowlds_lds_bytes<32, false>();
     }
     return 0;
 }
@@ -1898,6 +1963,17 @@ static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, 
             hipLaunchKernelGGL(kb_reduce, dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         default:
+            if constexpr (S >= 16) {
+                // a nonzero LDS size for a leaf row update selects the LDS-staged kernel
+                if (lds > 0 && a.phase == BP_LCORR) {
+                    hipLaunchKernelGGL((kb_rowlds<S, false>), dim3(blocks), dim3(kThreads), lds, st, a);
+                    break;
+                }
+                if (lds > 0 && a.phase == BP_LFIN) {
+                    hipLaunchKernelGGL((kb_rowlds<S, true>), dim3(blocks), dim3(kThreads), lds, st, a);
+                    break;
+                }
+            }
             hipLaunchKernelGGL((kb_rowupdate<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
     }

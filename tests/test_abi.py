@@ -150,7 +150,7 @@ def test_tune_workspace_and_argument_checks():
     n, s, k = 20000, 4, 32
     need = orth.orth_tune_workspace_bytes(n, s, k, 1)
     assert need % 256 == 0
-    heights = (256, 512, 1024, 2048, 4096, 8192, 16384)
+    heights = (256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
     plan_max = max(orth.orth_workspace_bytes(n, s, k, lr, 0) for lr in heights)
     assert need >= plan_max + 2 * n * s * 8 + k * s * 8
     # batches of copies: the largest batch workspace plus per-copy U and Hess

@@ -1,7 +1,7 @@
 """GPU tests of the leaf-height autotuner (orth_tune_leaf_rows and its cache).
 
-* every admissible candidate {256, ..., 16384} within [k_max, n] (and n itself
-  when n <= 16384) is timed, through one handle and through batches of
+* every admissible candidate {256, ..., 65536} within [k_max, n] (and n itself
+  when n <= 65536) is timed, through one handle and through batches of
   identical copies, with a positive time (no breakdown on the synthetic
   blocks), and the reported best is the tallest within 2% of the fastest;
 * the Python cache returns the measured value without measuring again;
@@ -43,8 +43,8 @@ def test_tuner_times_every_candidate(torch_cuda, n, s, k_max, copies):
     from paper_2204_13393_amd import autotune
     _say("tune", n, s, k_max, copies)
     best, cand = autotune.measure_leaf_rows(n, s, k_max, steps=min(4, k_max // s), copies=copies)
-    expect = [lr for lr in (256, 512, 1024, 2048, 4096, 8192, 16384) if k_max <= lr <= n]
-    if n <= 16384 and n not in expect:
+    expect = [lr for lr in (256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536) if k_max <= lr <= n]
+    if n <= 65536 and n not in expect:
         expect.append(n)
     assert [r for r, _ in cand] == expect
     assert all(ms > 0 for _, ms in cand)
