@@ -822,6 +822,9 @@ def main():
     ap.add_argument("--tree-fan-ins", default="",
                     help="default workload: also time the FP64 sequence with reduction trees of these "
                          "fan-ins (comma-separated)")
+    ap.add_argument("--flat-blocks", default="",
+                    help="default workload: also time the FP64 sequence with FlatTSPQR over this many "
+                         "row blocks (comma-separated counts)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
                     choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep",
                              "lap2d-100x100-s4"],
@@ -1045,52 +1048,70 @@ def main():
                     "avg_launch_us": avg_us, "launches_timed": dom_n,
                     "alg_bytes_per_launch": byts_per_launch}
 
-    # reduction trees (Sec. 4.1 applied recursively), on request: the FP64
-    # sequence with level-1 nodes of g leaves, level-2 nodes of g level-1
-    # nodes, ..., in its own workspace
-    trees = {}
+    # other arrangements of the same FP64 sequence, on request, each in its
+    # own workspace: reduction trees (Sec. 4.1 applied recursively; level-1
+    # nodes of g leaves, level-2 nodes of g level-1 nodes, ...) and FlatTSPQR
+    # over P row blocks (Sec. 4.2)
     fan_ins = [int(g) for g in args.tree_fan_ins.split(",") if g] if args.tree_fan_ins else []
-    if fan_ins:
+    flat_ps = [int(q) for q in args.flat_blocks.split(",") if q] if args.flat_blocks else []
+    if fan_ins or flat_ps:
         del ws
         torch.cuda.empty_cache()
-    for g in fan_ins:
-        tbytes = orth.orth_tree_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, g)
-        if tbytes == 0:
-            raise RuntimeError(f"fan-in {g} refused")
-        tws = torch.empty(tbytes // 8 + 32, dtype=torch.float64, device=dev)
-        tptr = (tws.data_ptr() + 255) // 256 * 256
 
-        def tree_handle():
-            code, th = orth.orth_create_tree(n, s, kmax, leaf, orth.ORTH_FP64, g, tptr, tbytes, sptr)
+    def time_arrangement(nbytes_alt, create, label):
+        if nbytes_alt == 0:
+            raise RuntimeError(f"{label} refused")
+        aws = torch.empty(nbytes_alt // 8 + 32, dtype=torch.float64, device=dev)
+        aptr = (aws.data_ptr() + 255) // 256 * 256
+
+        def handle():
+            code, ah = create(aptr, nbytes_alt)
             if code:
-                raise orth.OrthError("orth_create_tree", code)
-            return th
+                raise orth.OrthError(label, code)
+            return ah
         for _ in range(args.warmup):
-            th = tree_handle()
-            run_sequence(Xs, th)
-            orth.orth_destroy(th)
+            ah = handle()
+            run_sequence(Xs, ah)
+            orth.orth_destroy(ah)
         times = []
         for _ in range(args.steps):
-            th = tree_handle()
+            ah = handle()
             e0, e1 = TimingEvent(), TimingEvent()
             e0.record(stream)
-            run_sequence(Xs, th)
+            run_sequence(Xs, ah)
             e1.record(stream)
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
-            code, st, info = orth.orth_status(th)
-            levels = orth.orth_tree_levels(th)[1]
-            orth.orth_destroy(th)
+            code, st, info = orth.orth_status(ah)
+            levels = orth.orth_tree_levels(ah)[1]
+            orth.orth_destroy(ah)
             if code or st:
-                raise RuntimeError(f"tree fan-in {g}: breakdown {info}")
+                raise RuntimeError(f"{label}: breakdown {info}")
         G = torch.mm(V, V.t()) - torch.eye(kmax, dtype=torch.float64, device=dev)
         ep = float(torch.linalg.matrix_norm(G, "fro"))
-        del G, tws
+        del G, aws
         torch.cuda.empty_cache()
-        trees[str(g)] = {"levels": levels, "ms_per_step": min(times), "e_perp": ep,
-                         "vs_single_level": min(times) / ms_per_step}
-        print(f"[bench] tree fan-in {g}: {levels} levels, {min(times):.2f} ms per sequence, "
-              f"e_perp {ep:.2e}", file=sys.stderr, flush=True)
+        return levels, min(times), ep
+
+    trees = {}
+    for g in fan_ins:
+        levels, ms, ep = time_arrangement(
+            orth.orth_tree_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, g),
+            lambda ptr, nb: orth.orth_create_tree(n, s, kmax, leaf, orth.ORTH_FP64, g, ptr, nb, sptr),
+            f"tree fan-in {g}")
+        trees[str(g)] = {"levels": levels, "ms_per_step": ms, "e_perp": ep, "vs_single_level": ms / ms_per_step}
+        print(f"[bench] tree fan-in {g}: {levels} levels, {ms:.2f} ms per sequence, e_perp {ep:.2e}",
+              file=sys.stderr, flush=True)
+    flats = {}
+    for q in flat_ps:
+        rows = n // q
+        _, ms, ep = time_arrangement(
+            orth.orth_flat_workspace_bytes(n, s, kmax, rows),
+            lambda ptr, nb: orth.orth_create_flat(n, s, kmax, rows, ptr, nb, sptr),
+            f"flat {q} blocks")
+        flats[str(q)] = {"block_rows": rows, "ms_per_step": ms, "e_perp": ep, "vs_tree": ms / ms_per_step}
+        print(f"[bench] flat {q} blocks of {rows} rows: {ms:.2f} ms per sequence, e_perp {ep:.2e}",
+              file=sys.stderr, flush=True)
 
     if args.copy_probe_gib > 0:
         cnt = int(args.copy_probe_gib * (1 << 30)) // 8
@@ -1166,6 +1187,8 @@ def main():
     }
     if trees:
         out["reduction_trees"] = trees
+    if flats:
+        out["flat_tspqr"] = flats
     print(json.dumps(out), flush=True)
 
 

@@ -211,6 +211,39 @@ int orth_tree_levels(const orth_t *h, int32_t *levels, int32_t *fan_in);
 int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt);
 
 /*
+ * orth_flat_workspace_bytes / orth_create_flat -- a handle that solves the
+ * PQR problem (eq. (1.1)) with FlatTSPQR (Sec. 4.2, Algorithm "FlatTSPQR")
+ * instead of TreeTSPQR.  The rows are cut into p = max(1, n / block_rows)
+ * blocks (the last takes the rest), handled one after the other: block 1's
+ * local problem is the PQR problem of its rows against its own factor F_1,
+ * block i's is the PQR problem of [W_i; P_{i-1}; N_{i-1}] against F_i
+ * extended by zero rows for N_{i-1}'s new coordinates; the last block's P
+ * and N are the call's H and R.  The basis is the chain
+ *   Q = [[F_1, 0], [0, I]] [[F_2, 0], [0, I]] ... F_p
+ * (F_i spans block i's rows and the k coordinates before it), held as the
+ * factors; orth_step's explicit U and orth_apply_Q run down that chain.
+ *   n, s, k_max   as orth_create (FP64 only; the local subalgorithm is
+ *                 orth_set_variant's, BCGS-PIP+ by default)
+ *   block_rows    kmax <= block_rows <= n (no default)
+ *   d_workspace, workspace_bytes, stream, out   as orth_create
+ * The workspace holds every factor ((block rows + k_max) x k_max doubles,
+ * padded) and a staging copy of every block's rows, about
+ * 8 n (k_max + s) bytes.  The p local problems run in sequence, each on a
+ * single block, so a call takes p times the latency of a leaf level: the
+ * flat form suits few blocks (the paper's setting: blocks that do not fit
+ * one memory level at once) where TreeTSPQR spreads the leaves over the chip.
+ * Not supported on such a handle (UNSUPPORTED): orth_apply_Q_noalloc,
+ * orth_export_local, orth_export_tree_level, deflation.  orth_leaf_count
+ * reports (p, block_rows); orth_tree_levels reports 0 levels.
+ * Errors: ARG (shapes, block_rows), UNSUPPORTED (k_max + s above the widest
+ * basis), WORKSPACE, HIP.  orth_flat_workspace_bytes returns 0 for invalid
+ * arguments; pure host arithmetic.
+ */
+size_t orth_flat_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t block_rows);
+int orth_create_flat(int64_t n, int32_t s, int32_t k_max, int32_t block_rows, void *d_workspace,
+                     size_t workspace_bytes, void *stream, orth_t **out);
+
+/*
  * orth_set_variant -- choose ORTH_PIP_PLUS (default; BCGS-PIP+, Sec. 3.1)
  * or ORTH_PIP (BCGS-PIP, Sec. 3) for the following steps.  Host-side only.  Errors: ARG, POISONED, UNSUPPORTED
  * (ORTH_PIP on an ORTH_FP64_HOUSEHOLDER handle).

@@ -238,10 +238,6 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
 
 LevelGeom leaf_geom(const Plan &pl, int chunk) { return make_leaf_geom(pl.n, pl.leaf_rows, pl.p, chunk); }
 
-LevelGeom root_geom(const Plan &pl, int64_t seg_len, int chunk) {
-    return make_root_geom(pl.p, pl.kmax, seg_len, chunk);
-}
-
 // level l of the reduction tree (level 0 over the leaves)
 LevelGeom tree_geom(const Plan &pl, int l, int64_t seg_len, int chunk) {
     return make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in, pl.kmax, seg_len, chunk);
@@ -249,8 +245,86 @@ LevelGeom tree_geom(const Plan &pl, int l, int64_t seg_len, int chunk) {
 
 }  // namespace
 
+namespace {
+
+// FlatTSPQR (Sec. 4.2): the rows in blocks of block_rows (the last takes the
+// rest), the basis as the chain of per-block factors.  Factor i is stored
+// with block i's m_i rows first and the chain's coordinates after them
+// (F_i: rows [0, m_i) and [m_i, m_i + k_max), k_max columns, ld ldf[i]);
+// the local problem of block i at width k is the PQR problem on the
+// contiguous rows [0, m_i + k + s) of F_i and of Y_i = [X_i; P_{i-1};
+// N_{i-1}] (a row order the PQR problem does not depend on).  Coordinate
+// rows k .. k+s-1 of the old columns are the zero rows Sec. 4.2's
+// extended factor inserts: the factors start at zero and those rows are
+// only written by later columns.
+struct FlatPlan {
+    int64_t n = 0;
+    int32_t s = 0, kmax = 0, block_rows = 0;
+    int32_t p = 0;
+    std::vector<int64_t> r0, rows, ldf, oF, oY;
+    int64_t ldmax = 0;                 // ld of the shared U1 scratch
+    int64_t oU1 = 0, oZ0 = 0, oZ1 = 0, oE = 0, oP = 0, oP2 = 0, oS = 0, oST = 0;
+    int64_t slot_cap = 0, red_cap = 0, total = 0;
+};
+
+bool make_flat_plan(int64_t n, int32_t s, int32_t kmax, int32_t block_rows, FlatPlan &fp) {
+    if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0 || kmax + s > max_cols(s)) return false;
+    if (block_rows < kmax || block_rows > n || block_rows > (1 << 29)) return false;
+    fp.n = n;
+    fp.s = s;
+    fp.kmax = kmax;
+    fp.block_rows = block_rows;
+    const int64_t p64 = std::max<int64_t>(1, n / block_rows);
+    if (p64 > (1 << 20)) return false;
+    fp.p = (int32_t)p64;
+    fp.r0.assign(fp.p, 0);
+    fp.rows.assign(fp.p, 0);
+    fp.ldf.assign(fp.p, 0);
+    fp.oF.assign(fp.p, 0);
+    fp.oY.assign(fp.p, 0);
+    int64_t off = 0, rows_max = 0;
+    auto take = [&](int64_t count) {
+        const int64_t o = off;
+        off = round_up(off + count, kAlign);
+        return o;
+    };
+    for (int32_t i = 0; i < fp.p; ++i) {
+        fp.r0[i] = (int64_t)i * block_rows;
+        fp.rows[i] = i == fp.p - 1 ? n - fp.r0[i] : block_rows;
+        fp.ldf[i] = basis_ld(fp.rows[i] + kmax);
+        rows_max = std::max(rows_max, fp.rows[i] + kmax);
+        fp.oF[i] = take(fp.ldf[i] * kmax);
+        fp.oY[i] = i == 0 ? 0 : take(fp.ldf[i] * s);   // block 1 reads W itself
+    }
+    fp.ldmax = basis_ld(rows_max);
+    fp.oU1 = take(fp.ldmax * s);
+    fp.oZ0 = take((int64_t)kmax * kApplyMB);     // chain coordinates of one column block
+    fp.oZ1 = take((int64_t)kmax * kApplyMB);
+    fp.oE = take((int64_t)(kmax + s) * s);        // [0; I_s] below k_max zero rows
+    // partial slots of one local problem (a single leaf of up to rows_max rows)
+    int64_t slot_max = 0, red_max = 0;
+    for (int32_t k = 0; k + s <= kmax; k += s) {
+        const int32_t ncol = k + s;
+        const int64_t chunks = ceil_div(rows_max, kLeafChunk);
+        slot_max = std::max(slot_max, chunks * gram_row_groups(ncol) * ncol * s);
+        red_max = std::max(red_max, ceil_div(chunks * gram_row_groups(ncol), kReduceGroup) * ncol * s);
+    }
+    fp.slot_cap = slot_max;
+    fp.red_cap = red_max;
+    fp.oP = take(slot_max);
+    fp.oP2 = take(red_max);
+    fp.oS = take(small_stride(kmax, s));
+    fp.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
+    fp.total = off;
+    return true;
+}
+
+}  // namespace
+
 struct orth_ctx {
     Plan pl;
+    bool flat = false;                     // FlatTSPQR handle (orth_create_flat)
+    FlatPlan fp;
     int32_t k = 0;
     int32_t variant = ORTH_PIP_PLUS;       // the leaves' subalgorithm
     int32_t variant_red = ORTH_PIP_PLUS;   // the reduction's
@@ -327,7 +401,7 @@ struct orth_ctx {
     double *Cl(int l) const { return ws + pl.oCl[l]; }
     double *SL() const { return ws + pl.oSL; }
     double *SR() const { return ws + pl.oSR; }
-    DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + pl.oST); }
+    DevStatus *status() const { return reinterpret_cast<DevStatus *>(ws + (flat ? fp.oST : pl.oST)); }
 };
 
 extern "C" {
@@ -386,6 +460,57 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->status()),
                             (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, h->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return ORTH_ERR_HIP;
+    }
+    *out = h;
+    return ORTH_OK;
+}
+
+size_t orth_flat_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t block_rows) {
+    FlatPlan fp;
+    if (!make_flat_plan(n, s, k_max, block_rows, fp)) return 0;
+    return (size_t)fp.total * sizeof(double);
+}
+
+int orth_create_flat(int64_t n, int32_t s, int32_t k_max, int32_t block_rows, void *d_workspace,
+                     size_t workspace_bytes, void *stream, orth_t **out) {
+    if (!out) return ORTH_ERR_ARG;
+    *out = nullptr;
+    FlatPlan fp;
+    if (!make_flat_plan(n, s, k_max, block_rows, fp)) {
+        return (valid_s(s) && k_max >= s && k_max % s == 0 && k_max + s > max_cols(s)) ? ORTH_ERR_UNSUPPORTED
+                                                                                         : ORTH_ERR_ARG;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
+        workspace_bytes < (size_t)fp.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    orth_ctx *h = new (std::nothrow) orth_ctx();
+    if (!h) return ORTH_ERR_HIP;
+    h->flat = true;
+    h->fp = std::move(fp);
+    // the level runs read the block width and capacity from the plan
+    h->pl.n = n;
+    h->pl.s = s;
+    h->pl.kmax = k_max;
+    h->pl.precision = ORTH_FP64;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->ws = static_cast<double *>(d_workspace);
+    if (hipStreamGetDevice(h->stream, &h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return ORTH_ERR_HIP;
+    }
+    // factors and staging start at zero (the rows a local problem inserts
+    // for the newest coordinates are zero rows of the older columns); the
+    // identity block of [0; I_s] sits at rows k_max .. k_max + s - 1
+    const FlatPlan &f = h->fp;
+    hipError_t e = prepare_kernels(s);
+    if (e == hipSuccess) e = launch_fill(h->ws, f.total, 0.0, h->stream);
+    for (int32_t j = 0; j < s && e == hipSuccess; ++j)
+        e = launch_fill(h->ws + f.oE + (int64_t)j * (k_max + s) + k_max + j, 1, 1.0, h->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete h;
@@ -715,6 +840,128 @@ int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
     return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
 }
 
+// FlatTSPQR (Sec. 4.2): Q = [Q_1 U] spans the chain
+//   Q = [[F_1, 0], [0, I]] [[F_2, 0], [0, I]] ... F_p
+// (rows of F_i: block i's rows first, then the k coordinates of the chain
+// before it).  Y = Q C right to left: block p's factor times C, its block
+// rows to Y and its coordinate rows on as the next factor's C, down to
+// block 1.  C: ldc-strided k x m; Y: ldy-strided n x m.
+int apply_flat_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
+    const FlatPlan &fp = h->fp;
+    const int32_t k = h->k;
+    hipStream_t st = h->stream;
+    double *Z[2] = {h->ws + fp.oZ0, h->ws + fp.oZ1};
+    for (int32_t j0 = 0; j0 < m; j0 += kApplyMB) {
+        const int32_t mb = (m - j0) < kApplyMB ? (m - j0) : kApplyMB;
+        const double *cin = d_C + (int64_t)j0 * ldc;
+        int64_t ldin = ldc;
+        for (int32_t i = fp.p - 1; i >= 0; --i) {
+            const Operand F{h->ws + fp.oF[i], fp.ldf[i]};
+            ApplyArgs a{};
+            a.k = k;
+            a.Cptr = cin;
+            a.ldc = ldin;
+            a.cseg = 0;
+            a.m = mb;
+            // block rows -> Y
+            a.Q = F;
+            a.geom = make_leaf_geom(fp.rows[i], (int32_t)fp.rows[i], 1, kFinalChunk);
+            a.Y = OutOperand{d_Y + fp.r0[i] + (int64_t)j0 * ldy, ldy};
+            int pm = h->begin(ORTH_K_APPLY);
+            hipError_t e = launch_apply(a, st);
+            h->end(pm);
+            if (e != hipSuccess) return ORTH_ERR_HIP;
+            if (i == 0) break;
+            // coordinate rows -> the C of block i - 1
+            double *out = Z[i & 1];
+            a.Q = Operand{F.ptr + fp.rows[i], F.ld};
+            a.geom = make_leaf_geom(k, k, 1, kFinalChunk);
+            a.Y = OutOperand{out, fp.kmax};
+            pm = h->begin(ORTH_K_APPLY);
+            e = launch_apply(a, st);
+            h->end(pm);
+            if (e != hipSuccess) return ORTH_ERR_HIP;
+            cin = out;
+            ldin = fp.kmax;
+        }
+    }
+    return ORTH_OK;
+}
+
+// One FlatTSPQR call: block 1's local problem [F_1 W_1] = [F_1 U_1][[I, P_1],
+// [0, N_1]], then block i's on [F_i^ext Y_i], Y_i = [W_i; P_{i-1}; N_{i-1}]
+// (the previous block's Cholesky writes [P; N] straight into Y_i's
+// coordinate rows), U_i appended to F_i; the last block's P and N are the
+// call's H and R.  The explicit U = Q [0; I_s] runs down the chain.
+int step_flat(orth_ctx *h, const double *d_W, int64_t ldw, double *d_H, int64_t ldh, double *d_R,
+              int64_t ldr, double *d_U, int64_t ldu) {
+    const FlatPlan &fp = h->fp;
+    const int32_t s = fp.s, k = h->k, kmax = fp.kmax, ncol = k + s;
+    if (!d_W || !d_R || !d_U) return ORTH_ERR_ARG;
+    if (ldw < fp.n || ldu < fp.n || ldr < s) return ORTH_ERR_ARG;
+    if (k > 0 && (!d_H || ldh < k)) return ORTH_ERR_ARG;
+    if (k + s > kmax) return ORTH_ERR_CAPACITY;
+    const bool two = h->variant == ORTH_PIP_PLUS;
+    hipStream_t st = h->stream;
+    // W's rows of every block after the first into its staging buffer
+    for (int32_t i = 1; i < fp.p; ++i) {
+        const hipError_t e = launch_copy_cols(d_W + fp.r0[i], ldw, RowMap{0, 0}, h->ws + fp.oY[i], fp.ldf[i],
+                                              fp.rows[i], s, st);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
+    for (int32_t i = 0; i < fp.p; ++i) {
+        const bool last = i == fp.p - 1;
+        const int64_t rows = i == 0 ? fp.rows[0] : fp.rows[i] + ncol;
+        double *F = h->ws + fp.oF[i];
+        LevelRun L{};
+        L.Q = Operand{F, fp.ldf[i]};
+        L.X = i == 0 ? Operand{d_W + fp.r0[0], ldw} : Operand{h->ws + fp.oY[i], fp.ldf[i]};
+        L.U1 = OutOperand{h->ws + fp.oU1, fp.ldmax};
+        L.geom = make_leaf_geom(rows, (int32_t)rows, 1, kLeafChunk);
+        L.rgeom = make_leaf_geom(rows, (int32_t)rows, 1, kFinalChunk);
+        L.part = h->ws + fp.oP;
+        L.part2 = h->ws + fp.oP2;
+        L.part_cap = fp.slot_cap;
+        L.part2_cap = fp.red_cap;
+        L.small = h->ws + fp.oS;
+        L.level = 0;
+        if (last) {
+            L.H = k > 0 ? d_H : nullptr;
+            L.ldh = ldh;
+            L.R = d_R;
+            L.ldr = ldr;
+        } else {
+            L.Yout = h->ws + fp.oY[i + 1] + fp.rows[i + 1];
+            L.ldy = fp.ldf[i + 1];
+            L.yseg = 0;
+        }
+        if (int rc = run_level(h, L, k, two)) return rc;
+        // U_i -> the factor's columns k .. k+s-1 (rows [0, rows))
+        FinalizeArgs f{};
+        f.Q = L.Q;
+        f.Qnew = OutOperand{F + (int64_t)k * fp.ldf[i], fp.ldf[i]};
+        f.U1 = Operand{L.U1.ptr, L.U1.ld};
+        f.sweep = 2;
+        f.k = k;
+        f.geom = L.rgeom;
+        f.small = L.small;
+        f.small_stride = small_stride(kmax, s);
+        f.kmax = kmax;
+        f.single_sweep = two ? 0 : 1;
+        f.Cptr = nullptr;
+        f.status = h->status();
+        const int pm = h->begin(ORTH_K_LEAF_FINALIZE);
+        const hipError_t e = launch_finalize(s, f, ORTH_K_LEAF_CORRECT, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
+    h->k = k + s;
+    // U = Q [0; I_s]: the identity block sits below k_max zero rows
+    const double *E = h->ws + fp.oE + (kmax - k);
+    if (int rc = apply_flat_impl(h, E, (int64_t)kmax + s, s, d_U, ldu)) return rc;
+    return ORTH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -723,6 +970,11 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
               int64_t ldr, double *d_U, int64_t ldu) {
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
+    if (h->flat) {
+        const int rc = step_flat(h, d_W, ldw, d_H, ldh, d_R, ldr, d_U, ldu);
+        if (rc) (void)hipGetLastError();
+        return rc;
+    }
     const Plan &pl = h->pl;
     const int32_t s = pl.s, k = h->k, kmax = pl.kmax;
     if (!d_W || !d_R || !d_U) return ORTH_ERR_ARG;
@@ -952,6 +1204,12 @@ extern "C" {
 int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
+    if (h->flat) {
+        if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->fp.n) return ORTH_ERR_ARG;
+        const int rc = apply_flat_impl(h, d_C, ldc, m, d_Y, ldy);
+        if (rc) (void)hipGetLastError();
+        return rc;
+    }
     if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
     return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, h->CA(), h->CA2(), kApplyMB, true);
 }
@@ -959,6 +1217,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
 int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
+    if (h->flat) return ORTH_ERR_UNSUPPORTED;
     // one column of coefficient blocks per region (two regions with
     // Householder leaves or a reduction tree) must fit the static scratch
     const int64_t regions = (h->pl.precision == ORTH_FP64_HOUSEHOLDER || h->pl.nlev > 1) ? 2 : 1;
@@ -1039,6 +1298,11 @@ int orth_basis_width(const orth_t *h, int32_t *k) {
 
 int orth_leaf_count(const orth_t *h, int32_t *p, int32_t *leaf_rows) {
     if (!h) return ORTH_ERR_ARG;
+    if (h->flat) {
+        if (p) *p = h->fp.p;
+        if (leaf_rows) *leaf_rows = h->fp.block_rows;
+        return ORTH_OK;
+    }
     if (p) *p = h->pl.p;
     if (leaf_rows) *leaf_rows = h->pl.leaf_rows;
     return ORTH_OK;
@@ -1053,6 +1317,7 @@ int orth_tree_levels(const orth_t *h, int32_t *levels, int32_t *fan_in) {
 
 int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt) {
     if (!h) return ORTH_ERR_ARG;
+    if (h->flat) return ORTH_ERR_UNSUPPORTED;
     if (h->poisoned) return ORTH_ERR_POISONED;
     const Plan &pl = h->pl;
     const int32_t k = h->k;
@@ -1066,6 +1331,7 @@ int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt) {
 
 int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64_t ldt) {
     if (!h) return ORTH_ERR_ARG;
+    if (h->flat) return ORTH_ERR_UNSUPPORTED;
     if (h->poisoned) return ORTH_ERR_POISONED;
     const Plan &pl = h->pl;
     const int32_t k = h->k;

@@ -43,6 +43,8 @@ SIGNATURES = [
     ("orth_create_tree", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     ("orth_tree_levels", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_export_tree_level", ctypes.c_int, [_vp, _i32, _dp, _i64]),
+    ("orth_flat_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_create_flat", ctypes.c_int, [_i64, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
     ("orth_mixed_fallbacks", ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
@@ -140,6 +142,17 @@ def orth_tree_levels(h):
 
 def orth_export_tree_level(h, level, d_T, ldt):
     return load().orth_export_tree_level(h, level, d_T, ldt)
+
+
+def orth_flat_workspace_bytes(n, s, k_max, block_rows):
+    return load().orth_flat_workspace_bytes(n, s, k_max, block_rows)
+
+
+def orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stream):
+    h = ctypes.c_void_p()
+    code = load().orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stream,
+                                   ctypes.byref(h))
+    return code, h
 
 
 def orth_set_variant(h, variant):
@@ -324,25 +337,35 @@ class Orthogonalizer:
     """One TreeTSPQR basis on one GPU, with a torch-owned workspace.
 
     Tensors are column-major: an n x s matrix is a contiguous float64 tensor
-    of shape (s, n) on the device.
+    of shape (s, n) on the device.  flat=True: FlatTSPQR over blocks of
+    leaf_rows rows instead (orth_create_flat; FP64, no reduction tree).
     """
 
     def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
-                 precision=ORTH_FP64, reduction_variant=None, fan_in=0):
+                 precision=ORTH_FP64, reduction_variant=None, fan_in=0, flat=False):
         import torch
         load()
         self.n, self.s, self.k_max = int(n), int(s), int(k_max)
         self.precision = precision
         self.device = torch.device(device)
-        nbytes = orth_tree_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision, fan_in)
+        self.flat = bool(flat)
+        if self.flat:
+            if precision != ORTH_FP64 or fan_in:
+                raise OrthError("orth_create_flat", ORTH_ERR_UNSUPPORTED)
+            nbytes = orth_flat_workspace_bytes(self.n, self.s, self.k_max, leaf_rows)
+        else:
+            nbytes = orth_tree_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision, fan_in)
         if nbytes == 0:
             raise OrthError("orth_workspace_bytes", ORTH_ERR_ARG)
         self.stream = stream
         self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        code, h = orth_create_tree(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, aligned, nbytes,
-                                   _stream_ptr(stream))
+        if self.flat:
+            code, h = orth_create_flat(self.n, self.s, self.k_max, leaf_rows, aligned, nbytes, _stream_ptr(stream))
+        else:
+            code, h = orth_create_tree(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, aligned, nbytes,
+                                       _stream_ptr(stream))
         _check("orth_create", code)
         self.h = h
         red = variant if reduction_variant is None else reduction_variant

@@ -206,3 +206,29 @@ def test_tree_workspace_arguments():
     assert orth.orth_export_tree_level(None, 0, 0, 1) == orth.ORTH_ERR_ARG
     code, h = orth.orth_create_tree(10000, 4, 16, 500, orth.ORTH_FP64, 1, 0, 0, None)
     assert code == orth.ORTH_ERR_ARG and not h.value
+
+
+def test_flat_workspace_arguments():
+    """FlatTSPQR handles (orth_create_flat): block_rows in [k_max, n] with no
+    default, the usual width rules, and a workspace that holds one factor of
+    (block rows + k_max) x k_max per block (host arithmetic only)."""
+    n, s, kmax = 10000, 4, 16
+    one = orth.orth_flat_workspace_bytes(n, s, kmax, n)
+    four = orth.orth_flat_workspace_bytes(n, s, kmax, 2500)
+    assert one >= 8 * (n + kmax) * kmax                    # the one factor
+    assert four >= 8 * ((n + 4 * kmax) * kmax + (n - 2500 + 3 * kmax) * s)   # factors, staging
+    assert orth.orth_flat_workspace_bytes(n, s, kmax, 0) == 0             # no default
+    assert orth.orth_flat_workspace_bytes(n, s, kmax, kmax - 1) == 0
+    assert orth.orth_flat_workspace_bytes(n, s, kmax, n + 1) == 0
+    assert orth.orth_flat_workspace_bytes(n, 3, 15, 100) == 0
+    assert orth.orth_flat_workspace_bytes(n, s, 18, 100) == 0            # k_max not a multiple of s
+    assert orth.orth_flat_workspace_bytes(0, s, kmax, 100) == 0
+    assert orth.orth_flat_workspace_bytes(100000, 32, 2048, 4096) == 0   # k_max + s above 2048
+    code, h = orth.orth_create_flat(n, s, kmax, 0, 0, 0, None)
+    assert code == orth.ORTH_ERR_ARG and not h.value
+    code, h = orth.orth_create_flat(100000, 32, 2048, 4096, 0, 0, None)
+    assert code == orth.ORTH_ERR_UNSUPPORTED and not h.value
+    code, h = orth.orth_create_flat(n, s, kmax, 2500, 0, four, None)
+    assert code == orth.ORTH_ERR_WORKSPACE and not h.value
+    code, h = orth.orth_create_flat(n, s, kmax, 2500, 256, four - 8, None)
+    assert code == orth.ORTH_ERR_WORKSPACE and not h.value

@@ -64,6 +64,7 @@ CASES = [
     (4100, 32, 96, 1366),     # LDS-staged row update: even leaves, last one ragged (1368 rows)
     (5001, 16, 64, 1001),     # odd leaf height: row pairs unaligned, the register-streamed row update
     (9000, 16, 80, 4500),     # LDS-staged row update over 3 chunks per leaf (2048, 2048, 404 rows)
+    (4097, 16, 64, 4097),     # one leaf of odd height: LDS-staged, its last row pair half past the end
 ]
 
 # the widest basis the planner accepts (k_max + s = 2048), s = 32, one leaf,
