@@ -4,7 +4,11 @@
 // reduction across processes, Sec. 5.2).
 //
 // Workspace carving (all regions 256-byte aligned, column-major FP64):
-//   Qloc  ldq x kmax     stacked local bases; leaf i owns rows of leaf i
+//   Qloc  the leaf bases: leaf i's m_i x kmax block at i * ldl * kmax with
+//         leading dimension ldl (ld_last for the last leaf) -- one leaf's
+//         columns together in memory (a few pages rather than one page per
+//         column); Householder leaves and the batched form keep one
+//         ldq x kmax column-major matrix
 //   T     ldt x kmax     tree factors; leaf i's T_i (kmax x kmax, upper
 //                        triangular) in rows [i*kmax, (i+1)*kmax)
 //   Y     ldt x s        reduction-level X: leaf i's [P_i; N_i] in its rows
@@ -108,6 +112,8 @@ struct Plan {
     int32_t precision;           // ORTH_FP64, ORTH_MIXED_SPLIT32 (adds the FP32 copy of the leaf
                                  // bases) or ORTH_FP64_HOUSEHOLDER (reflector leaves)
     int64_t ldq, ldt;
+    bool qblk;                   // leaf bases stored leaf by leaf (ldl, ld_last)
+    int64_t ldl, ld_last, qcount;
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
@@ -121,7 +127,7 @@ int32_t default_leaf_rows(int64_t n, int32_t kmax) {
 }
 
 bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t precision, Plan &pl,
-               int *why, int32_t fan_in = 0) {
+               int *why, int32_t fan_in = 0, bool blocked = false) {
     *why = ORTH_ERR_ARG;
     if (fan_in < 0 || fan_in == 1) return false;
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
@@ -151,6 +157,13 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     if (pl.p < 1) pl.p = 1;
     pl.ldq = basis_ld(n);
     pl.ldt = basis_ld((int64_t)pl.p * kmax);
+    pl.qblk = blocked && precision != ORTH_FP64_HOUSEHOLDER;
+    {
+        const int64_t last_rows = n - (int64_t)(pl.p - 1) * leaf_rows;
+        pl.ldl = pl.qblk ? basis_ld(leaf_rows) : pl.ldq;
+        pl.ld_last = pl.qblk ? basis_ld(last_rows) : pl.ldq;
+        pl.qcount = pl.qblk ? ((int64_t)(pl.p - 1) * pl.ldl + pl.ld_last) * kmax : pl.ldq * kmax;
+    }
     // the tree's levels: fan_in = 0 (or >= p) is the single reduction level
     pl.fan_in = (fan_in == 0 || fan_in >= pl.p) ? 0 : fan_in;
     pl.nlev = 0;
@@ -178,7 +191,7 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         off = round_up(off + count, kAlign);
         return o;
     };
-    pl.oQ = take(pl.ldq * kmax);
+    pl.oQ = take(pl.qcount);
     pl.oT = take(pl.ldt * kmax);
     pl.oY = take(pl.ldt * s);
     pl.oU1L = take(pl.ldq * s);
@@ -211,8 +224,8 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     pl.oST = take(sizeof(DevStatus) / sizeof(double) + 1);
     // per-leaf coefficient records [P2 | C_i], row-major (k_max x 2s per leaf)
     pl.oCL = take((int64_t)pl.p * kmax * 2 * s);
-    // mixed form: FP32 copy of the leaf bases (ldq x kmax floats)
-    pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.ldq * (int64_t)kmax, 2)) : 0;
+    // mixed form: FP32 copy of the leaf bases (their layout, in floats)
+    pl.oQH = precision == ORTH_MIXED_SPLIT32 ? take(ceil_div(pl.qcount, 2)) : 0;
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
@@ -372,6 +385,15 @@ struct orth_ctx {
     }
 
     double *Q() const { return ws + pl.oQ; }
+    // the leaf bases as a kernel operand from column c0 on
+    Operand Qop(int32_t c0 = 0) const {
+        if (!pl.qblk) return Operand{Q() + (int64_t)c0 * pl.ldq, pl.ldq, 0, 0, 0};
+        return Operand{Q(), pl.ldl, pl.ldl * pl.kmax, pl.ld_last, c0};
+    }
+    OutOperand Qout(int32_t c0) const {
+        if (!pl.qblk) return OutOperand{Q() + (int64_t)c0 * pl.ldq, pl.ldq, 0, 0, 0};
+        return OutOperand{Q(), pl.ldl, pl.ldl * pl.kmax, pl.ld_last, c0};
+    }
     double *T() const { return ws + pl.oT; }
     double *Y() const { return ws + pl.oY; }
     double *U1L() const { return ws + pl.oU1L; }
@@ -381,6 +403,11 @@ struct orth_ctx {
     double *CL() const { return ws + pl.oCL; }
     float *Qhi() const {
         return pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(ws + pl.oQH) : nullptr;
+    }
+    // the copy's new columns from c0 on (a blocked copy takes c0 from Qout's operand)
+    float *Qhi_at(int32_t c0) const {
+        float *q = Qhi();
+        return (q && !pl.qblk) ? q + (int64_t)c0 * pl.ldq : q;
     }
     double *TH() const { return pl.precision == ORTH_FP64_HOUSEHOLDER ? ws + pl.oTH : nullptr; }
     // second apply scratch: Householder leaves (-Z_i) and reduction trees (the
@@ -415,7 +442,7 @@ size_t orth_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t le
                                  int32_t precision, int32_t fan_in) {
     Plan pl;
     int why;
-    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in)) return 0;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in, true)) return 0;
     return (size_t)pl.total * sizeof(double);
 }
 
@@ -430,7 +457,7 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
     *out = nullptr;
     Plan pl;
     int why;
-    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in)) return why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in, true)) return why;
     if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
         workspace_bytes < (size_t)pl.total * sizeof(double))
         return ORTH_ERR_WORKSPACE;
@@ -992,7 +1019,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         if ((rc = run_leaves_hh(h, d_W, ldw, k))) goto fail;
     } else {
         LevelRun L{};
-        L.Q = Operand{h->Q(), pl.ldq};
+        L.Q = h->Qop();
         L.X = Operand{d_W, ldw};
         L.U1 = OutOperand{h->U1L(), pl.ldq};
         L.geom = leaf_geom(pl, kLeafChunk);
@@ -1080,9 +1107,9 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         if ((rc = finalize_leaves_hh(h, d_U, ldu, k))) goto fail;
     } else {
         FinalizeArgs f{};
-        f.Q = Operand{h->Q(), pl.ldq};
-        f.Qnew = OutOperand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
-        f.Qnew_hi = h->Qhi() ? h->Qhi() + (int64_t)k * pl.ldq : nullptr;
+        f.Q = h->Qop();
+        f.Qnew = h->Qout(k);
+        f.Qnew_hi = h->Qhi_at(k);
         f.U1 = Operand{h->U1L(), pl.ldq};
         f.sweep = 2;
         f.k = k;
@@ -1177,7 +1204,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
         }
         ApplyArgs a{};
-        a.Q = Operand{h->Q(), pl.ldq};
+        a.Q = h->Qop();
         a.k = k;
         a.geom = leaf_geom(pl, kFinalChunk);
         a.Cptr = hh ? ca2 : cur;
@@ -1339,7 +1366,9 @@ int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64
     if (d_Qloc && ldq < pl.n) return ORTH_ERR_ARG;
     if (d_T && ldt < (int64_t)pl.p * k) return ORTH_ERR_ARG;
     hipError_t e = hipSuccess;
-    if (d_Qloc) e = launch_copy_cols(h->Q(), pl.ldq, RowMap{0, 0}, d_Qloc, ldq, pl.n, k, h->stream);
+    if (d_Qloc)
+        e = pl.qblk ? launch_copy_leafblk(h->Qop(), leaf_geom(pl, kLeafChunk), d_Qloc, ldq, k, h->stream)
+                    : launch_copy_cols(h->Q(), pl.ldq, RowMap{0, 0}, d_Qloc, ldq, pl.n, k, h->stream);
     if (e == hipSuccess && d_T)
         e = launch_copy_cols(h->T(), pl.ldt, RowMap{k, pl.kmax}, d_T, ldt, (int64_t)pl.p * k, k,
                              h->stream);
@@ -1726,7 +1755,7 @@ bool tune_layout(int64_t n, int32_t s, int32_t kmax, int32_t copies, TuneLayout 
         int why;
         if (copies == 1) {
             Plan pl;
-            if (!make_plan(n, s, kmax, lr, ORTH_FP64, pl, &why)) return false;
+            if (!make_plan(n, s, kmax, lr, ORTH_FP64, pl, &why, 0, true)) return false;
             L.head = std::max(L.head, round_up(pl.total, kAlign));
         } else {
             std::vector<int64_t> nn(copies, n);

@@ -162,14 +162,66 @@ __host__ __device__ inline int64_t small_stride(int32_t kmax, int32_t s) {
     return 2 * (int64_t)kmax * s + 3 * (int64_t)s * s;
 }
 
-struct Operand {          // column-major matrix under a level's RowMap
+// Column-major matrix under a level's RowMap, or (lstride > 0, leaf level
+// only) stored leaf by leaf: leaf i's rows form their own column-major block
+// at ptr + i lstride with leading dimension ld (ld_last for the last leaf,
+// which may be taller), so that one leaf's columns lie together in memory.
+// c0: first column (blocked storage only; a plain operand's ptr already
+// points at its first column).
+struct Operand {
     const double *ptr;
     int64_t ld;
+    int64_t lstride;
+    int64_t ld_last;
+    int32_t c0;
 };
 struct OutOperand {
     double *ptr;
     int64_t ld;
+    int64_t lstride;
+    int64_t ld_last;
+    int32_t c0;
 };
+
+// Element offset, from an operand's ptr, of a leaf's (global row 0, column
+// 0) and that leaf's leading dimension: ptr + offset + c ld_leaf + r is
+// element (r, c) for every global row r of the leaf.
+__host__ __device__ inline int64_t leaf_offset(int64_t ld, int64_t lstride, int64_t ld_last, int32_t c0,
+                                               const LevelGeom &g, int32_t leaf, int64_t &ld_leaf) {
+    if (lstride == 0) {
+        ld_leaf = ld;
+        return 0;
+    }
+    ld_leaf = leaf == g.nleaf - 1 ? ld_last : ld;
+    return (int64_t)leaf * lstride + (int64_t)c0 * ld_leaf - g.leaf_begin(leaf);
+}
+
+// The operand as a plain column-major matrix over one leaf's global rows.
+// The base address is formed in integers: it may lie before the block (a
+// leaf's rows start at leaf_begin), every element read through it lies
+// inside.
+template <class Op>
+__host__ __device__ inline Op leaf_view(const Op &o, const LevelGeom &g, int32_t leaf) {
+    if (o.lstride == 0) return o;
+    Op v = o;
+    int64_t ldl;
+    const int64_t off = leaf_offset(o.ld, o.lstride, o.ld_last, o.c0, g, leaf, ldl);
+    v.ptr = reinterpret_cast<decltype(o.ptr)>(reinterpret_cast<uintptr_t>(o.ptr) + off * (int64_t)sizeof(double));
+    v.ld = ldl;
+    v.lstride = 0;
+    v.ld_last = 0;
+    v.c0 = 0;
+    return v;
+}
+
+// The FP32 copy of a blocked operand (same element layout, floats).
+template <class F, class Op>
+__host__ __device__ inline F *leaf_view_hi(F *hi, const Op &o, const LevelGeom &g, int32_t leaf) {
+    if (!hi || o.lstride == 0) return hi;
+    int64_t ldl;
+    const int64_t off = leaf_offset(o.ld, o.lstride, o.ld_last, o.c0, g, leaf, ldl);
+    return reinterpret_cast<F *>(reinterpret_cast<uintptr_t>(hi) + off * (int64_t)sizeof(float));
+}
 
 // ---- kernel launch descriptors (filled by the runtime) ----
 
@@ -399,6 +451,10 @@ hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
 hipError_t launch_copy_cols(const double *src, int64_t lds, RowMap smap, double *dst,
                             int64_t ldd, int64_t rows, int32_t cols, hipStream_t st);
+// dst (column-major, ldd) <- the first `cols` columns of a leaf-blocked
+// operand over the level's rows
+hipError_t launch_copy_leafblk(const Operand &src, const LevelGeom &g, double *dst, int64_t ldd, int32_t cols,
+                               hipStream_t st);
 hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
                             int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);

@@ -143,13 +143,14 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(bx, leaf, r0, r1);
+    const Operand Qv = leaf_view(a.Q, a.geom, leaf);    // the leaf's block of a blocked basis
 
     const double *colp[kGramTPW];
     int cz[kGramTPW];                           // TZ: segment rows of column c that can be nonzero
 #pragma unroll
     for (int t = 0; t < kGramTPW; ++t) {
         const int c = (tile0 + t) * 16 + il;
-        colp[t] = c < k ? a.Q.ptr + (int64_t)c * a.Q.ld
+        colp[t] = c < k ? Qv.ptr + (int64_t)c * Qv.ld
                         : (c < ncol ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr);
         cz[t] = c < k ? (c / S + 1) * S : ncol;
     }
@@ -308,13 +309,15 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(bx, leaf, r0, r1);
+    const float *qhi = leaf_view_hi(a.Qhi, a.Q, a.geom, leaf);   // the leaf's block of the copy
+    const int64_t qld = leaf_view(a.Q, a.geom, leaf).ld;
 
     const float *colh[kGramTPW];
     const double *colp[kGramTPW];
 #pragma unroll
     for (int t = 0; t < kGramTPW; ++t) {
         const int c = (tile0 + t) * 16 + il;
-        colh[t] = c < k ? a.Qhi + (int64_t)c * a.Q.ld : nullptr;
+        colh[t] = c < k ? qhi + (int64_t)c * qld : nullptr;
         colp[t] = (c >= k && c < ncol) ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr;
     }
     const double *xcol[NT];
@@ -850,6 +853,16 @@ __host__ __device__ constexpr int rowmfma_pf() { return 1; }
 // rows: u = (x - q P) N^{-1} on the matrix cores, stored as new basis
 // columns (and as C_i rows, or as the FP32 copy), then with EXPL the
 // explicit block q C_top + u C_bot.
+// A row update's arguments with the basis operands (Q, the new columns and
+// their FP32 copy) narrowed to one leaf's block of a blocked basis.
+__device__ __forceinline__ FinalizeArgs leaf_finalize_args(const FinalizeArgs &a_in, int leaf) {
+    FinalizeArgs a = a_in;
+    a.Q = leaf_view(a_in.Q, a_in.geom, leaf);
+    a.Qnew = leaf_view(a_in.Qnew, a_in.geom, leaf);
+    a.Qnew_hi = leaf_view_hi(a_in.Qnew_hi, a_in.Qnew, a_in.geom, leaf);
+    return a;
+}
+
 template <int S, bool EXPL, int TR>
 __device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, int64_t rb, bool fast,
                                                  const bool (&ok)[TR], const int64_t (&prow)[TR],
@@ -995,17 +1008,18 @@ __device__ __forceinline__ void rowmfma_epilogue(const FinalizeArgs &a, int k, i
 // TZ (the reduction level): basis column c is zero below segment row
 // (c / s + 1) s and is not read there (as in gram_body).
 template <int S, bool EXPL, int TR, int PF, bool TZ = false>
-__device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a, int bx) {
-    if (failed(a.status)) return;
+__device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a_in, int bx) {
+    if (failed(a_in.status)) return;
     constexpr int RB = 16 * TR;              // rows per wave block
     constexpr int M = EXPL ? 2 * S : S;      // coefficient columns [P | C_top]
     constexpr int NTM = (M + 15) / 16;       // 16-column output tiles
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
-    const int k = a.k;
+    const int k = a_in.k;
     int leaf;
     int64_t r0, r1;
-    a.geom.chunk(bx, leaf, r0, r1);
+    a_in.geom.chunk(bx, leaf, r0, r1);
+    const FinalizeArgs a = leaf_finalize_args(a_in, leaf);
     const double *rec = a.small + (int64_t)leaf * a.small_stride;
     // record: P1 [kmax][S] | N1 | N1^{-1} | P2 [kmax][S] | N2^{-1}
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
@@ -1214,17 +1228,18 @@ __device__ __forceinline__ void lds_step<2, 2>(uint32_t q, uint32_t c, double (&
 }
 
 template <int S, bool EXPL, int TR, int BK, int NST>
-__device__ __forceinline__ void rowlds_body(const FinalizeArgs &a, int bx, double *lds) {
+__device__ __forceinline__ void rowlds_body(const FinalizeArgs &a_in, int bx, double *lds) {
     using C = RowLds<S, EXPL, TR, BK, NST>;
     constexpr int M = C::M, NTM = C::NTM, RW = C::RW, BM = C::BM;
-    if (failed(a.status)) return;
+    if (failed(a_in.status)) return;
     // the wave index in a scalar register: the tile loop's branches are uniform
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int il = lane & 15, g = lane >> 4;
-    const int k = a.k;
+    const int k = a_in.k;
     int leaf;
     int64_t r0, r1;
-    a.geom.chunk(bx, leaf, r0, r1);
+    a_in.geom.chunk(bx, leaf, r0, r1);
+    const FinalizeArgs a = leaf_finalize_args(a_in, leaf);
     const double *rec = a.small + (int64_t)leaf * a.small_stride;
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
     const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
@@ -1341,6 +1356,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs a) {
     int64_t r0, r1;
     a.geom.chunk(blockIdx.x, leaf, r0, r1);
     const double *cbase = a.Cptr + (int64_t)leaf * a.cseg;
+    const Operand Qv = leaf_view(a.Q, a.geom, leaf);
     for (int64_t base = r0; base < r1; base += (int64_t)kThreads * RPT) {
         int64_t prow[RPT];
         bool ok[RPT];
@@ -1366,7 +1382,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs a) {
             for (int c = 0; c < cb; ++c) {
                 double q[RPT];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) q[i] = a.Q.ptr[(int64_t)(c0 + c) * a.Q.ld + prow[i]];
+                for (int i = 0; i < RPT; ++i) q[i] = Qv.ptr[(int64_t)(c0 + c) * Qv.ld + prow[i]];
 #pragma unroll
                 for (int j = 0; j < kApplyMB; ++j) {
                     const double w = cl[c * kApplyMB + j];
@@ -1403,6 +1419,18 @@ __global__ void k_copy_cols(const double *src, int64_t lds_, RowMap smap, double
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / rows, r = e - c * rows;
         dst[c * ldd + r] = src[c * lds_ + smap.phys(r)];
+    }
+}
+
+__global__ void k_copy_leafblk(Operand src, LevelGeom g, double *dst, int64_t ldd, int32_t cols) {
+    const int64_t rows = g.nrows, total = rows * cols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / rows, r = e - c * rows;
+        int32_t leaf = (int32_t)(r / g.leaf_rows);
+        if (leaf > g.nleaf - 1) leaf = g.nleaf - 1;
+        const Operand v = leaf_view(src, g, leaf);
+        dst[c * ldd + r] = v.ptr[c * v.ld + r];
     }
 }
 
@@ -1905,6 +1933,14 @@ hipError_t launch_copy_cols(const double *src, int64_t lds_, RowMap smap, double
     if (rows <= 0 || cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(rows * cols, 256)), dim3(256), 0, st, src, lds_,
                        smap, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_leafblk(const Operand &src, const LevelGeom &g, double *dst, int64_t ldd, int32_t cols,
+                               hipStream_t st) {
+    const int64_t total = g.nrows * cols;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_leafblk, dim3(grid_for(total, 256)), dim3(256), 0, st, src, g, dst, ldd, cols);
     return hipGetLastError();
 }
 

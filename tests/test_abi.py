@@ -60,17 +60,28 @@ def test_workspace_rejects_bad_arguments(args):
     assert orth.orth_workspace_bytes(*args) == 0
 
 
+def _basis_ld(rows):
+    """Leading dimension of a stored basis: rows rounded up to an odd
+    multiple of 32 doubles (256 bytes)."""
+    ld = -(-rows // 32) * 32
+    return ld + 32 if (ld // 32) % 2 == 0 else ld
+
+
 def test_householder_form_workspace_and_limits():
     H = orth.ORTH_FP64_HOUSEHOLDER
     # adds three k_max x k_max blocks per leaf (T in both orders, the
     # reflectors' top rows), a second apply_Q coefficient scratch and the
-    # deflation state (64 bytes and an s x s matrix)
+    # deflation state (64 bytes and an s x s matrix); its reflectors are one
+    # column-major matrix where the other forms store each leaf's block
+    # on its own
     for (n, s, k, lr) in ((10000, 4, 44, 1000), (2 ** 24, 8, 248, 4096), (777, 1, 12, 100)):
         f64 = orth.orth_workspace_bytes(n, s, k, lr, 0)
         hh = orth.orth_workspace_bytes(n, s, k, lr, H)
         p = max(1, n // lr)
+        last = n - (p - 1) * lr
+        qdiff = (_basis_ld(n) - (p - 1) * _basis_ld(lr) - _basis_ld(last)) * k * 8
         extra = 3 * p * k * k * 8 + (p * k + 64) * 16 * 8 + 64 + s * s * 8 + 256
-        assert 3 * p * k * k * 8 <= hh - f64 <= extra + 512
+        assert 3 * p * k * k * 8 - 512 <= hh - f64 - qdiff <= extra + 512
     # limits: the panel kernel's register capacity and k_max s <= 4096
     assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 4096, H) > 0
     assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 8192, H) == 0        # leaf rows > 4096 at s = 8
@@ -85,12 +96,15 @@ def test_householder_form_workspace_and_limits():
 
 
 def test_mixed_form_workspace_adds_the_fp32_copy():
-    # the FP32 copy of the leaf bases: 4 bytes per (ld x k_max) entry on top
+    # the FP32 copy of the leaf bases: 4 bytes per stored entry on top (each
+    # leaf's block padded to its own leading dimension)
     for (n, s, k, lr) in ((10000, 4, 44, 1000), (2 ** 24, 8, 248, 4096), (777, 1, 12, 100)):
         f64 = orth.orth_workspace_bytes(n, s, k, lr, 0)
         mixed = orth.orth_workspace_bytes(n, s, k, lr, orth.ORTH_MIXED_SPLIT32)
         assert f64 > 0 and mixed % 256 == 0
-        assert n * k * 4 <= mixed - f64 <= (n + 64) * k * 4 + 256
+        p = max(1, n // lr)
+        stored = ((p - 1) * _basis_ld(lr) + _basis_ld(n - (p - 1) * lr)) * k
+        assert stored * 4 <= mixed - f64 <= stored * 4 + 256
 
 
 @pytest.mark.parametrize("form", ["mixed", "householder"])
