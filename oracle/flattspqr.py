@@ -37,7 +37,7 @@ Readings adopted where the paper is silent:
 
 import numpy as np
 
-from .hhpqr import HouseholderBasis
+from .hhpqr import HouseholderBasis, hh_with_zero_rows
 from .pqr import SUBALGORITHMS
 from .tspqr import leaf_bounds
 
@@ -50,9 +50,7 @@ def _insert_zero_rows(B, at, count):
 def _hh_insert_zero_rows(basis, at, count):
     """A HouseholderBasis whose reflectors (and so whose basis) carry `count`
     zero rows before row `at`."""
-    out = HouseholderBasis(basis.n + count)
-    out.V = _insert_zero_rows(basis.V, at, count)
-    return out
+    return hh_with_zero_rows(basis, at, count)
 
 
 class FlatTSPQR:

@@ -124,3 +124,12 @@ class HouseholderBasis:
 def hh_pqr(basis, X):
     """Functional form: one Algorithm "HH" step on ``basis`` (mutated)."""
     return basis.pqr(X)
+
+
+def hh_with_zero_rows(basis, at, count):
+    """A HouseholderBasis whose reflectors (and so whose basis) carry `count`
+    zero rows inserted before row `at` (a zero row of every reflector stays
+    a zero row of every product of them)."""
+    out = HouseholderBasis(basis.n + count)
+    out.V = np.vstack([basis.V[:at], np.zeros((count, basis.V.shape[1])), basis.V[at:]])
+    return out

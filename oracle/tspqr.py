@@ -34,12 +34,20 @@ Readings adopted where the paper is silent:
 * a local problem needs at least k+s rows for full rank; the class refuses a
   step that would break that;
 * the first step (k = 0) is the same procedure with an empty basis: it is the
-  TSQR of the start block (Sec. 4.1, tree TSQR).
+  TSQR of the start block (Sec. 4.1, tree TSQR);
+* Householder as the reduction subalgorithm (the stability table of Sec. 6.1
+  uses one method at both levels): the single reduction node holds its basis
+  as unit reflectors over the stacked rows (Algorithm "HH", Sec. 2.2); every
+  step inserts s zero rows into them after each child's k rows, the rows of
+  that child's new coordinates, as the stacked factors are extended with
+  zero rows; the pivots are the node's leading rows (child 1's).  The
+  diagonal of N then carries the Householder signs and the new basis
+  columns the same signs, as with Householder leaves.
 """
 
 import numpy as np
 
-from .hhpqr import HouseholderBasis
+from .hhpqr import HouseholderBasis, hh_with_zero_rows
 from .deflate import deflating_pip, deflating_pip_plus
 from .pqr import SUBALGORITHMS
 
@@ -75,7 +83,9 @@ class TreeTSPQR:
                 ("pip" = BCGS-PIP, "pip+" = BCGS-PIP+, "ref" = the unique
                 reference solution); ``local`` may also be "hh": the
                 Householder method (Sec. 2.2), each leaf basis then held as
-                reflectors (``oracle.hhpqr.HouseholderBasis``).
+                reflectors (``oracle.hhpqr.HouseholderBasis``);
+                ``reduction`` may be "hh" for the single-level tree (the
+                reduction node's basis held as reflectors).
     fan_in      None for the single-level tree, else the tree fan-in.
     deflate     None, or the relative tolerance delta of the deflating
                 reduction (``oracle.deflate``, Sec. 3.1): the single
@@ -89,11 +99,12 @@ class TreeTSPQR:
         self.bounds = leaf_bounds(self.n, int(leaf_rows))
         self.householder = local == "hh"
         self.local = None if self.householder else SUBALGORITHMS[local]
-        self.reduction = SUBALGORITHMS[reduction]
+        self.hh_reduction = reduction == "hh"
+        self.reduction = None if self.hh_reduction else SUBALGORITHMS[reduction]
         self.deflate = deflate
         self.last_rank = None
         if deflate is not None:
-            if reduction not in DEFLATING or not deflate > 0.0:
+            if self.hh_reduction or reduction not in DEFLATING or not deflate > 0.0:
                 raise ValueError("deflation needs reduction 'pip' or 'pip+' and delta > 0")
             self.reduction = DEFLATING[reduction]
         self.k = 0
@@ -114,6 +125,9 @@ class TreeTSPQR:
                 break
         if deflate is not None and len(self.levels) != 1:
             raise ValueError("deflation is defined for the single-level tree")
+        if self.hh_reduction and len(self.levels) != 1:
+            raise ValueError("the Householder reduction is defined for the single-level tree")
+        self.root_hh = None      # the reduction node's reflectors (reduction "hh")
 
     @property
     def p(self):
@@ -149,7 +163,9 @@ class TreeTSPQR:
                 # old k coordinates, zero rows over the child's s new ones
                 B = np.vstack([np.vstack([Sc, np.zeros((s, k))]) for Sc in node["S"]])
                 Yv = np.vstack(Y[c0:c1])
-                if self.deflate is None:
+                if self.hh_reduction:
+                    Pv, Nv, Uv = self._hh_reduce(c1 - c0, Yv)
+                elif self.deflate is None:
                     Pv, Nv, Uv = self.reduction(B, Yv)
                 else:
                     Pv, Nv, Uv, self.last_rank = self.reduction(B, Yv, self.deflate)
@@ -175,6 +191,17 @@ class TreeTSPQR:
         self.k = k + s
         U = self.apply_Q(np.vstack([np.zeros((k, s)), np.eye(s)]))
         return P, N, U
+
+    def _hh_reduce(self, children, Yv):
+        """The reduction problem by Algorithm "HH" on the node's reflectors:
+        s zero rows inserted after every child's k rows, then one pqr."""
+        k, s = self.k, self.s
+        if self.root_hh is None:
+            self.root_hh = HouseholderBasis(children * s)
+        else:
+            for c in range(children - 1, -1, -1):
+                self.root_hh = hh_with_zero_rows(self.root_hh, c * k + k, s)
+        return self.root_hh.pqr(Yv)
 
     def apply_Q(self, C):
         """Y = Q C for C ((current k) x m): down-sweep of C, then leaf products.

@@ -115,3 +115,93 @@ def test_refuses_rank_deficient_local_problem():
     tree.step(rng.standard_normal((40, 4)))
     with pytest.raises(ValueError):
         tree.step(rng.standard_normal((40, 4)))
+
+
+# ---- Householder at the reduction (single-level tree)
+
+def _signfix(P, N, U):
+    d = np.sign(np.diag(N))
+    d[d == 0] = 1.0
+    return P, d[:, None] * N, U * d[None, :]
+
+
+@pytest.mark.parametrize("n,s,leaf_rows,local", [(1000, 4, 100, "pip+"), (1037, 3, 128, "hh"),
+                                                   (512, 8, 512, "hh"), (2000, 2, 90, "ref"),
+                                                   (777, 1, 70, "pip")])
+def test_householder_reduction_equals_unique_reference(n, s, leaf_rows, local):
+    """Open loop with the reduction node's basis as reflectors: (P, N D, U D)
+    with D = diag(sign N_ii) equals the unique solution; the basis stays
+    orthonormal and apply_Q matches the explicit basis."""
+    rng = np.random.default_rng(n + 7 * s)
+    tree = TreeTSPQR(n, s, leaf_rows, local, "hh")
+    Q = np.zeros((n, 0))
+    tol = 1e-11 if local == "pip" else 1e-13
+    for step in range(5):
+        X = rng.standard_normal((n, s)) * np.geomspace(1, 1e-2, s)
+        if step:
+            X += Q @ rng.standard_normal((Q.shape[1], s))
+        P, N, Uraw = tree.step(X)
+        P, N, U = _signfix(P, N, Uraw)
+        Pr, Nr, Ur = pqr_reference(Q, X)
+        assert np.linalg.norm(P - Pr) / np.linalg.norm(X) < tol
+        assert np.linalg.norm(N - Nr) / np.linalg.norm(X) < tol
+        assert np.max(np.abs(U - Ur)) < 100 * tol
+        Q = np.hstack([Q, Uraw])
+    Sv = tree.stacked_factor(0)
+    assert metrics.e_perp(Sv) < 1e-13
+    C = rng.standard_normal((tree.k, 3))
+    assert np.allclose(tree.apply_Q(C), tree.explicit_Q() @ C, atol=1e-12)
+    assert np.allclose(tree.explicit_Q(), Q, atol=1e-11)
+
+
+def test_householder_reduction_inserted_rows_are_zero():
+    """After the second call every old reflector of the reduction node has
+    exact zeros in the rows of each child's newest coordinates."""
+    n, s, lr = 400, 4, 100
+    rng = np.random.default_rng(3)
+    tree = TreeTSPQR(n, s, lr, "pip+", "hh")
+    tree.step(rng.standard_normal((n, s)))
+    tree.step(rng.standard_normal((n, s)))
+    V = tree.root_hh.V
+    assert V.shape == (4 * 2 * s, 2 * s)
+    for c in range(4):
+        assert np.all(V[c * 2 * s + s:c * 2 * s + 2 * s, :s] == 0.0)
+
+
+def test_householder_reduction_refusals():
+    with pytest.raises(ValueError):
+        TreeTSPQR(1000, 4, 100, "pip+", "hh", fan_in=2)
+    with pytest.raises(ValueError):
+        TreeTSPQR(1000, 4, 100, "hh", "hh", deflate=1e-6)
+
+
+@pytest.mark.parametrize("p", [8, 64, 256])
+def test_subproblem_count_householder_column(golden, stewart_1e4, p):
+    """The Householder column of the subproblems table (Sec. 6.1): one
+    method at both levels, so Householder leaves and a Householder
+    reduction; e_perp and ||A - QR|| within [min / 10, 10 max]."""
+    e, res_abs, res_rel = _run(stewart_1e4, p, None, "hh")
+    lo, hi = _band(golden, "subproblems", 2)
+    assert lo <= e <= hi, (p, e, lo, hi)
+    rlo, rhi = _band(golden, "subproblems", 5)
+    assert rlo <= res_abs <= rhi and rlo <= res_rel <= rhi
+
+
+def test_householder_at_both_levels_is_unconditionally_stable():
+    """Sec. 2.2 / 6.1: with Householder at both levels e_perp stays O(eps)
+    far past the CholeskyQR bound (kappa = 1e12, where BCGS-PIP+ at either
+    level breaks down or loses orthogonality)."""
+    from oracle.pqr import Breakdown
+    A = stewart(2 ** 14, 32, 1e12, 1)
+    n = A.shape[0]
+    tree = TreeTSPQR(n, 4, 256, "hh", "hh")
+    Q, R = block_column_qr(A, 4, tree)
+    assert metrics.e_perp(tree.explicit_Q()) <= 1e-13
+    assert metrics.qr_residual(A, Q, R) <= 1e-13
+    for local, red in (("pip+", "hh"), ("hh", "pip+")):
+        tree = TreeTSPQR(n, 4, 256, local, red)
+        try:
+            block_column_qr(A, 4, tree)
+        except Breakdown:
+            continue
+        assert metrics.e_perp(tree.explicit_Q()) >= 1e-6, (local, red)
