@@ -629,8 +629,10 @@ def bench_kappa_sweep(args):
     sigma_j = kappa^(-j/31), n = 2^16, 32 columns in blocks of s = 4 (eight
     orth_step calls), leaves of 256 rows, for kappa = 10^0 .. 10^12 and the
     four combinations of BCGS-PIP / BCGS-PIP+ at the leaves and at the
-    reduction, plus Householder leaves (Sec. 2.2) with either reduction, and
-    Householder leaves with a deflating BCGS-PIP+ reduction (Sec. 3.1,
+    reduction, plus Householder leaves (Sec. 2.2) with either reduction, a
+    Householder reduction with each kind of leaves (the full local x
+    reduction map), and Householder leaves with a deflating BCGS-PIP+
+    reduction (Sec. 3.1,
     delta = 1e-6).  Per case: status (breakdown or not) and e_perp of the
     explicit basis (of its kept columns, with the count dropped, for the
     deflating case).  The matrices come from synth.stewart (seed 11)."""
@@ -639,9 +641,9 @@ def bench_kappa_sweep(args):
     from paper_2204_13393_amd import Orthogonalizer, orth
     from synth import stewart
     n, m, s, leaf = 1 << 16, 32, 4, 256
-    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
+    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP, "hh": orth.ORTH_HOUSEHOLDER}
     combos = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip"), ("hh", "pip+"), ("hh", "pip"),
-              ("hh", "pip+/deflation")]
+              ("pip+", "hh"), ("pip", "hh"), ("hh", "hh"), ("hh", "pip+/deflation")]
     rows = []
     print("[bench] kappa sweep: Stewart n = 2^16, 32 columns, s = 4, leaves of 256 rows", file=sys.stderr, flush=True)
     for e in range(13):

@@ -127,8 +127,10 @@ enum orth_precision {
 /* Variant of the leaf and reduction subalgorithm (Sec. 3, Sec. 3.1). */
 enum orth_variant {
     ORTH_PIP_PLUS = 0,       /* BCGS-PIP+ (CholeskyQR2): the default, O(eps) */
-    ORTH_PIP = 1             /* BCGS-PIP (one CholeskyQR sweep), O(eps kappa^2):
+    ORTH_PIP = 1,            /* BCGS-PIP (one CholeskyQR sweep), O(eps kappa^2):
                                 kept to reproduce the paper's unstable column */
+    ORTH_HOUSEHOLDER = 2     /* Algorithm HH (Sec. 2.2); the reduction only
+                                (orth_set_level_variants) */
 };
 
 /*
@@ -257,7 +259,20 @@ int orth_set_variant(orth_t *h, int32_t variant);
  * orth_set_variant(h, v) equals orth_set_level_variants(h, v, v).  The
  * leaves of an ORTH_FP64_HOUSEHOLDER handle run the Householder method:
  * their variant must stay ORTH_PIP_PLUS (else UNSUPPORTED), the reduction's
- * may be either.
+ * may be any.
+ * reduction_variant = ORTH_HOUSEHOLDER: the reduction problem by Algorithm
+ * HH (the stability table of Sec. 6.1 runs one method at both levels).  The
+ * reduction's basis is then held as unit reflectors over the stacked rows
+ * (p segments of k_max rows; each call's s new coordinates of a segment are
+ * zero rows of the older reflectors) with its compact-WY factor, and one
+ * workgroup factors the stacked panel: offered on single-level handles
+ * with s <= 16, p k_max <= 8192 rows (s <= 4), 4096 (s = 8), 1024 (s = 16)
+ * and k_max s <= 4096, without deflation, chosen before the first step or
+ * kept (a switch to or from it once k > 0 is UNSUPPORTED).  R's diagonal
+ * then carries the Householder signs and U's columns the same signs: (H,
+ * R D, U D) with D = diag(sign R_jj) is the unique solution.
+ * orth_export_local's d_T and orth_export_tree_level are UNSUPPORTED then
+ * (the stored reduction factors are reflectors).
  * Host-side only.  Errors: ARG, POISONED, UNSUPPORTED.
  */
 int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant);

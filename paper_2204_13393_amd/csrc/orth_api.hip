@@ -117,6 +117,11 @@ struct Plan {
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
+    // Householder reduction (single level, the stacked problem within one
+    // workgroup's panel): the root's compact-WY factor, its coefficient
+    // record, its [P; N], its explicit new columns and a third apply scratch
+    bool hhroot;
+    int64_t oTHR, oCR, oHR, oUR, oCA3;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -229,9 +234,18 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
+    // the Householder reduction is offered when the stacked problem (p k_max
+    // physical rows) fits the panel kernel
+    pl.hhroot = pl.nlev == 1 && s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)pl.p * kmax <= hh_max_leaf_rows(s) &&
+                (int64_t)kmax * s <= kHhMaxCoef;
     // and orth_apply_Q's second coefficient scratch (-Z_i, or the tree's
     // down-sweep in turn with CA), like CA
-    pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1) ? take(pl.ldt * kApplyMB) : 0;
+    pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhroot) ? take(pl.ldt * kApplyMB) : 0;
+    pl.oTHR = pl.hhroot ? take((int64_t)3 * kmax * kmax) : 0;
+    pl.oCR = pl.hhroot ? take((int64_t)kmax * 2 * s) : 0;
+    pl.oHR = pl.hhroot ? take((int64_t)kmax * s) : 0;
+    pl.oUR = pl.hhroot ? take(pl.ldt * s) : 0;
+    pl.oCA3 = pl.hhroot ? take(pl.ldt * kApplyMB) : 0;
     // deflation state (counters and the first sweep's s x s W), Householder leaves only
     pl.oDF = precision == ORTH_FP64_HOUSEHOLDER ? take(defl_state_doubles(s)) : 0;
     // the tree's levels: level 0 stacks the leaves' factors in T, Y, U1R;
@@ -413,8 +427,15 @@ struct orth_ctx {
     // second apply scratch: Householder leaves (-Z_i) and reduction trees (the
     // down-sweep alternates between CA and CA2)
     double *CA2() const {
-        return (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1) ? ws + pl.oCA2 : nullptr;
+        return (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhroot) ? ws + pl.oCA2 : nullptr;
     }
+    // Householder reduction regions (null unless the plan offers it)
+    bool hh_red() const { return variant_red == ORTH_HOUSEHOLDER; }
+    double *THR() const { return pl.hhroot ? ws + pl.oTHR : nullptr; }
+    double *CR() const { return pl.hhroot ? ws + pl.oCR : nullptr; }
+    double *HR() const { return pl.hhroot ? ws + pl.oHR : nullptr; }
+    double *UR() const { return pl.hhroot ? ws + pl.oUR : nullptr; }
+    double *CA3() const { return pl.hhroot ? ws + pl.oCA3 : nullptr; }
     DeflState *DF() const {
         return pl.precision == ORTH_FP64_HOUSEHOLDER ? reinterpret_cast<DeflState *>(ws + pl.oDF) : nullptr;
     }
@@ -481,6 +502,9 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
     // Householder leaves: the compact-WY factors grow into zeros below their diagonal
     if (e == hipSuccess && h->TH())
         e = launch_fill(h->TH(), (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
+    // and so does the Householder reduction's (with the reflectors' top rows)
+    if (e == hipSuccess && h->THR())
+        e = launch_fill(h->THR(), (int64_t)3 * pl.kmax * pl.kmax, 0.0, h->stream);
     if (e == hipSuccess && h->DF())
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->DF()), (int64_t)(sizeof(DeflState) / sizeof(int32_t)), 0,
                             h->stream);
@@ -553,8 +577,15 @@ int orth_set_variant(orth_t *h, int32_t variant) {
 
 int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_variant) {
     const auto ok = [](int32_t v) { return v == ORTH_PIP_PLUS || v == ORTH_PIP; };
-    if (!h || !ok(leaf_variant) || !ok(reduction_variant)) return ORTH_ERR_ARG;
+    if (!h || !ok(leaf_variant) || !(ok(reduction_variant) || reduction_variant == ORTH_HOUSEHOLDER))
+        return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
+    // Householder at the reduction: single-level handles whose stacked
+    // problem fits the panel kernel, not with deflation, not mid-basis
+    if (reduction_variant == ORTH_HOUSEHOLDER && (h->flat || !h->pl.hhroot || h->defl_delta > 0.0))
+        return ORTH_ERR_UNSUPPORTED;
+    if ((reduction_variant == ORTH_HOUSEHOLDER) != (h->variant_red == ORTH_HOUSEHOLDER) && h->k > 0)
+        return ORTH_ERR_UNSUPPORTED;
     // Householder leaves run Algorithm HH, which has no one-sweep variant
     if (h->pl.precision == ORTH_FP64_HOUSEHOLDER && leaf_variant != ORTH_PIP_PLUS) return ORTH_ERR_UNSUPPORTED;
     h->variant = leaf_variant;
@@ -818,6 +849,161 @@ int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
     return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
 }
 
+// Householder reduction (Sec. 2.2 on the reduction problem of Sec. 4.1):
+// the stacked [P_i; N_i] (p segments of k_max physical rows, zero past each
+// segment's k+s rows) against the root's reflectors V (the level's factor
+// storage), one "leaf" of p k_max rows for the leaf-level kernels:
+// M = V^T Y, Y~ = T^T M, w~ = Y - V Y~, the panel (pivots: segment 0's rows
+// k .. k+s-1; [P; N] to the root scratch, then to H and R), [V v]^T v and T's
+// growth.  Zero rows stay zero through every product, so each segment's
+// rows k+s .. k+2s-1 are the zero rows the next call's new coordinates take.
+LevelGeom root_hh_geom(const Plan &pl, int chunk) {
+    const int64_t rows = (int64_t)pl.p * pl.kmax;
+    return make_leaf_geom(rows, (int32_t)rows, 1, chunk);
+}
+
+int run_root_hh(orth_ctx *h, int k, double *d_H, int64_t ldh, double *d_R, int64_t ldr) {
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
+    hipStream_t st = h->stream;
+    const int64_t pstride = (int64_t)ncol * s;
+    const LevelGeom gg = root_hh_geom(pl, kRootChunk);
+    const int rg = gram_row_groups(ncol);
+    if (!pl.hhroot || (int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
+    hipError_t e;
+    HhArgs ha{};
+    ha.geom = gg;
+    ha.k = k;
+    ha.kmax = kmax;
+    ha.Q = h->T();
+    ha.ldq = pl.ldt;
+    ha.T = h->THR();
+    ha.partials = h->PR();
+    ha.part_stride = pstride;
+    ha.slots_per_leaf = gg.cpl * rg;
+    ha.slots_last = gg.cpl_last * rg;
+    ha.small = h->SR();
+    ha.small_stride = small_stride(kmax, s);
+    ha.Yout = h->HR();
+    ha.ldy = kmax;
+    ha.yseg = 0;
+    ha.status = h->status();
+    ha.X = h->Y();
+    ha.ldx = pl.ldt;
+    GramArgs ga{};
+    ga.Q = Operand{h->T(), pl.ldt};
+    ga.k = k;
+    ga.tile_groups = gram_tile_groups(ncol);
+    ga.geom = gg;
+    ga.partials = h->PR();
+    ga.part_stride = pstride;
+    ga.status = h->status();
+    // the leaf-level instantiations (identity rows): the reflectors have no
+    // zero structure for the reduction kernels' skipping
+    if (k > 0) {
+        ga.X = Operand{h->Y(), pl.ldt};
+        int pm = h->begin(ORTH_K_ROOT_GRAM);
+        e = launch_gram(s, ga, ORTH_K_LEAF_GRAM, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        pm = h->begin(ORTH_K_ROOT_CHOL);
+        e = launch_hh(s, HH_PREP, ha, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        FinalizeArgs f{};
+        f.Q = Operand{h->T(), pl.ldt};
+        f.Qnew = OutOperand{h->U1R(), pl.ldt};
+        f.U1 = Operand{h->Y(), pl.ldt};
+        f.sweep = 1;
+        f.k = k;
+        f.geom = root_hh_geom(pl, kRootRowChunk);
+        f.small = h->SR();
+        f.small_stride = small_stride(kmax, s);
+        f.kmax = kmax;
+        f.status = h->status();
+        pm = h->begin(ORTH_K_ROOT_CORRECT);
+        e = launch_finalize(s, f, ORTH_K_LEAF_CORRECT, st);
+        h->end(pm);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+        ha.X = h->U1R();
+    }
+    int pm = h->begin(ORTH_K_ROOT_CHOL);
+    e = launch_hh(s, HH_PANEL, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    ga.X = Operand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
+    pm = h->begin(ORTH_K_ROOT_GRAM2);
+    e = launch_gram(s, ga, ORTH_K_LEAF_GRAM2, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    pm = h->begin(ORTH_K_ROOT_CHOL);
+    e = launch_hh(s, HH_TUPD, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    // [P; N] -> H (k x s) and R (s x s)
+    if (k > 0) e = launch_copy_cols(h->HR(), kmax, RowMap{0, 0}, d_H, ldh, k, s, st);
+    if (e == hipSuccess) e = launch_copy_cols(h->HR() + k, kmax, RowMap{0, 0}, d_R, ldr, s, s, st);
+    return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
+}
+
+// The root's new columns U_R = Q_{k+s} [0; I_s] = -V (T V[0:k+s]^T E) + E
+// over the stacked rows, then each segment's k+s rows -> the right half of
+// that leaf's record (its C_i = [P~_i; N~_i])
+int finalize_root_hh(orth_ctx *h, int k) {
+    const Plan &pl = h->pl;
+    const int32_t s = pl.s, kmax = pl.kmax, K = k + s;
+    hipStream_t st = h->stream;
+    const int64_t cseg = (int64_t)kmax * 2 * s;
+    // E = [0; I_s] in the right half of the root's record
+    hipError_t e = launch_fill(h->CR(), cseg, 0.0, st);
+    for (int32_t j = 0; j < s && e == hipSuccess; ++j)
+        e = launch_fill(h->CR() + (int64_t)(k + j) * 2 * s + s + j, 1, 1.0, st);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    HhArgs ha{};
+    ha.geom = root_hh_geom(pl, kRootRowChunk);
+    ha.k = k;
+    ha.kmax = kmax;
+    ha.Q = h->T();
+    ha.ldq = pl.ldt;
+    ha.T = h->THR();
+    ha.crec = h->CR();
+    ha.cseg = cseg;
+    ha.U = h->UR();
+    ha.ldu = pl.ldt;
+    ha.status = h->status();
+    int pm = h->begin(ORTH_K_ROOT_CHOL);
+    e = launch_hh(s, HH_COEF, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    FinalizeArgs f{};
+    f.Q = Operand{h->T(), pl.ldt};
+    f.Qnew = OutOperand{h->U1R(), pl.ldt};
+    f.U1 = Operand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
+    f.sweep = 2;
+    f.k = k;
+    f.geom = ha.geom;
+    f.small = h->SR();
+    f.small_stride = small_stride(kmax, s);
+    f.kmax = kmax;
+    f.single_sweep = 1;
+    f.Cptr = h->CR();
+    f.cseg = cseg;
+    f.Uout = OutOperand{h->UR(), pl.ldt};
+    f.status = h->status();
+    pm = h->begin(ORTH_K_ROOT_FINALIZE);
+    e = launch_finalize(s, f, ORTH_K_LEAF_FINALIZE, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    pm = h->begin(ORTH_K_ROOT_CHOL);
+    e = launch_hh(s, HH_ADDEC, ha, st);
+    h->end(pm);
+    if (e != hipSuccess) return ORTH_ERR_HIP;
+    pm = h->begin(ORTH_K_ROOT_FINALIZE);
+    e = launch_rows_to_records(h->UR(), pl.ldt, pl.p, kmax, K, s, h->CL(), cseg, st);
+    h->end(pm);
+    return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
+}
+
 // Householder leaves, explicit output: U|_i = Q_{k+s} [C_i; 0] =
 // -V (T V[0:k+s]^T C_i) + E C_i
 int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
@@ -1041,6 +1227,10 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     // children (segments of k+s rows), level by level up to the root
     for (int l = 0; l < pl.nlev; ++l) {
         const bool root = l == pl.nlev - 1;
+        if (h->hh_red()) {                       // Householder reduction (single level)
+            if ((rc = run_root_hh(h, k, k > 0 ? d_H : nullptr, ldh, d_R, ldr))) goto fail;
+            continue;
+        }
         LevelRun L{};
         L.Q = Operand{h->Tl(l), pl.ldtl[l]};
         L.X = Operand{h->Yl(l), pl.ldtl[l]};
@@ -1074,6 +1264,10 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     // (Sec. 4.1, assembly of U), down to the leaves' records
     for (int l = pl.nlev - 1; l >= 0; --l) {
         const bool root = l == pl.nlev - 1;
+        if (h->hh_red()) {
+            if ((rc = finalize_root_hh(h, k))) goto fail;
+            continue;
+        }
         double *below = l == 0 ? h->CL() : h->Cl(l - 1);
         FinalizeArgs f{};
         f.Q = Operand{h->Tl(l), pl.ldtl[l]};
@@ -1143,7 +1337,7 @@ namespace {
 // block: ldt x mb_max doubles each.  prof: bracket the launches with the
 // handle's profiler events.
 int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy,
-                 double *ca, double *ca2, int32_t mb_max, bool prof) {
+                 double *ca, double *ca2, double *ca3, int32_t mb_max, bool prof) {
     const Plan &pl = h->pl;
     const int32_t k = h->k;
     const bool hh = pl.precision == ORTH_FP64_HOUSEHOLDER;
@@ -1152,7 +1346,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
     auto end = [&](int idx) { if (prof) h->end(idx); };
     // host check: the tree's down-sweep and the Householder products need
     // the second scratch region
-    if (!ca || ((hh || pl.nlev > 1) && !ca2) || mb_max < 1) return ORTH_ERR_HIP;
+    if (!ca || ((hh || pl.nlev > 1) && !ca2) || (h->hh_red() && (!ca2 || !ca3)) || mb_max < 1) return ORTH_ERR_HIP;
     for (int32_t j0 = 0; j0 < m; j0 += mb_max) {
         const int32_t mb = (m - j0) < mb_max ? (m - j0) : mb_max;
         // down the reduction tree: a node's children get C_c = S_v,c C_v
@@ -1161,7 +1355,42 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         // scratch regions in turn, so level 0 leaves C_i in `cur`
         hipError_t e = hipSuccess;
         double *cur = nullptr;
-        for (int l = pl.nlev - 1; l >= 0; --l) {
+        if (h->hh_red()) {
+            // Householder reduction: Y_R = Q_k [C; 0] = -V Z + E C over the
+            // stacked rows (Z = T V[0:k]^T C), i.e. every leaf's C_i at its
+            // segment of ca3
+            e = launch_copy_cols(d_C + (int64_t)j0 * ldc, ldc, RowMap{0, 0}, ca, pl.ldt, k, mb, st);
+            HhArgs hr{};
+            hr.geom = root_hh_geom(pl, kRootRowChunk);
+            hr.k = k;
+            hr.kmax = pl.kmax;
+            hr.T = h->THR();
+            hr.ca = ca;
+            hr.ca_out = ca2;
+            hr.ldca = pl.ldt;
+            hr.m = mb;
+            hr.U = ca3;
+            hr.ldu = pl.ldt;
+            int pm = begin(ORTH_K_APPLY);
+            if (e == hipSuccess) e = launch_hh_apply(HH_APPLY_COEF, hr, st);
+            if (e == hipSuccess) {
+                ApplyArgs r{};
+                r.Q = Operand{h->T(), pl.ldt};
+                r.k = k;
+                r.geom = hr.geom;
+                r.Cptr = ca2;
+                r.ldc = pl.ldt;
+                r.cseg = 0;
+                r.m = mb;
+                r.Y = OutOperand{ca3, pl.ldt};
+                e = launch_apply(r, st);
+            }
+            if (e == hipSuccess) e = launch_hh_apply(HH_APPLY_ADD, hr, st);
+            end(pm);
+            if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
+            cur = ca3;
+        }
+        for (int l = h->hh_red() ? -1 : pl.nlev - 1; l >= 0; --l) {
             double *out = (cur == ca) ? ca2 : ca;
             ApplyArgs r{};
             r.Q = Operand{h->Tl(l), pl.ldtl[l]};
@@ -1238,7 +1467,7 @@ int orth_apply_Q(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d
         return rc;
     }
     if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
-    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, h->CA(), h->CA2(), kApplyMB, true);
+    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, h->CA(), h->CA2(), h->CA3(), kApplyMB, true);
 }
 
 int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, double *d_Y, int64_t ldy) {
@@ -1246,8 +1475,10 @@ int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, d
     if (h->poisoned) return ORTH_ERR_POISONED;
     if (h->flat) return ORTH_ERR_UNSUPPORTED;
     // one column of coefficient blocks per region (two regions with
-    // Householder leaves or a reduction tree) must fit the static scratch
-    const int64_t regions = (h->pl.precision == ORTH_FP64_HOUSEHOLDER || h->pl.nlev > 1) ? 2 : 1;
+    // Householder leaves or a reduction tree, three with the Householder
+    // reduction) must fit the static scratch
+    const int64_t regions =
+        h->hh_red() ? 3 : ((h->pl.precision == ORTH_FP64_HOUSEHOLDER || h->pl.nlev > 1) ? 2 : 1);
     const int64_t cols = kStaticScratchDoubles / (regions * h->pl.ldt);
     if (cols < 1) return ORTH_ERR_SCRATCH;
     if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
@@ -1257,8 +1488,9 @@ int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, d
         return ORTH_ERR_HIP;
     }
     const int32_t mb_max = (int32_t)std::min<int64_t>(kApplyMB, cols);
-    double *ca2 = regions == 2 ? base + h->pl.ldt * mb_max : nullptr;
-    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, base, ca2, mb_max, false);
+    double *ca2 = regions >= 2 ? base + h->pl.ldt * mb_max : nullptr;
+    double *ca3 = regions == 3 ? base + 2 * h->pl.ldt * mb_max : nullptr;
+    return apply_q_impl(h, d_C, ldc, m, d_Y, ldy, base, ca2, ca3, mb_max, false);
 }
 
 int orth_status(orth_t *h, int32_t *status, int32_t *info) {
@@ -1284,7 +1516,7 @@ int orth_set_deflation(orth_t *h, double delta) {
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
     if (!(delta >= 0.0 && delta < 1.0)) return ORTH_ERR_ARG;      // NaN fails too
-    if (delta > 0.0 && !h->DF()) return ORTH_ERR_UNSUPPORTED;
+    if (delta > 0.0 && (!h->DF() || h->hh_red())) return ORTH_ERR_UNSUPPORTED;
     h->defl_delta = delta;
     return ORTH_OK;
 }
@@ -1344,7 +1576,7 @@ int orth_tree_levels(const orth_t *h, int32_t *levels, int32_t *fan_in) {
 
 int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt) {
     if (!h) return ORTH_ERR_ARG;
-    if (h->flat) return ORTH_ERR_UNSUPPORTED;
+    if (h->flat || h->hh_red()) return ORTH_ERR_UNSUPPORTED;
     if (h->poisoned) return ORTH_ERR_POISONED;
     const Plan &pl = h->pl;
     const int32_t k = h->k;
@@ -1358,7 +1590,7 @@ int orth_export_tree_level(orth_t *h, int32_t level, double *d_T, int64_t ldt) {
 
 int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64_t ldt) {
     if (!h) return ORTH_ERR_ARG;
-    if (h->flat) return ORTH_ERR_UNSUPPORTED;
+    if (h->flat || (d_T && h->hh_red())) return ORTH_ERR_UNSUPPORTED;
     if (h->poisoned) return ORTH_ERR_POISONED;
     const Plan &pl = h->pl;
     const int32_t k = h->k;

@@ -455,6 +455,10 @@ hipError_t launch_copy_cols(const double *src, int64_t lds, RowMap smap, double 
 // operand over the level's rows
 hipError_t launch_copy_leafblk(const Operand &src, const LevelGeom &g, double *dst, int64_t ldd, int32_t cols,
                                hipStream_t st);
+// rec[i rec_seg + c 2s + s + j] = src[i seg_rows + c + j ld] for i < nseg,
+// c < rows, j < s (the right halves of per-leaf [. | C_i] records)
+hipError_t launch_rows_to_records(const double *src, int64_t ld, int32_t nseg, int64_t seg_rows, int32_t rows,
+                                 int32_t s, double *rec, int64_t rec_seg, hipStream_t st);
 hipError_t launch_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
                             int32_t nx, int32_t ny, int32_t nz, double shift, hipStream_t st);
 hipError_t launch_copy(const double *src, double *dst, int64_t count, hipStream_t st);

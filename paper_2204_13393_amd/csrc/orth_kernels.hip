@@ -1434,6 +1434,19 @@ __global__ void k_copy_leafblk(Operand src, LevelGeom g, double *dst, int64_t ld
     }
 }
 
+// the right halves of the per-leaf records [. | C_i] (row-major, 2s columns)
+// from a column-major matrix holding leaf i's rows at i * seg_rows
+__global__ void k_rows_to_records(const double *src, int64_t ld, int32_t nseg, int64_t seg_rows, int32_t rows,
+                                  int32_t s, double *rec, int64_t rec_seg) {
+    const int64_t total = (int64_t)nseg * rows * s;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ((int64_t)rows * s);
+        const int32_t rem = (int32_t)(e - i * rows * s), c = rem / s, j = rem - (rem / s) * s;
+        rec[i * rec_seg + (int64_t)c * 2 * s + s + j] = src[i * seg_rows + c + (int64_t)j * ld];
+    }
+}
+
 __global__ void k_laplacian(const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t s,
                             int32_t nx, int32_t ny, int32_t nz, double shift) {
     const int64_t n = (int64_t)nx * ny * nz;
@@ -1941,6 +1954,15 @@ hipError_t launch_copy_leafblk(const Operand &src, const LevelGeom &g, double *d
     const int64_t total = g.nrows * cols;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_leafblk, dim3(grid_for(total, 256)), dim3(256), 0, st, src, g, dst, ldd, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_to_records(const double *src, int64_t ld, int32_t nseg, int64_t seg_rows, int32_t rows,
+                                 int32_t s, double *rec, int64_t rec_seg, hipStream_t st) {
+    const int64_t total = (int64_t)nseg * rows * s;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_to_records, dim3(grid_for(total, 256)), dim3(256), 0, st, src, ld, nseg, seg_rows, rows,
+                       s, rec, rec_seg);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ ORTH_MIXED_SPLIT32 = 1
 ORTH_FP64_HOUSEHOLDER = 2
 ORTH_PIP_PLUS = 0
 ORTH_PIP = 1
+ORTH_HOUSEHOLDER = 2      # reduction variant only
 
 CODE_NAMES = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "BREAKDOWN", 4: "HIP", 5: "POISONED",
               6: "WORKSPACE", 7: "UNSUPPORTED", 8: "SCRATCH"}

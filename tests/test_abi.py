@@ -246,3 +246,15 @@ def test_flat_workspace_arguments():
     assert code == orth.ORTH_ERR_WORKSPACE and not h.value
     code, h = orth.orth_create_flat(n, s, kmax, 2500, 256, four - 8, None)
     assert code == orth.ORTH_ERR_WORKSPACE and not h.value
+
+
+def test_variant_constants_match_the_header():
+    """The binding's variant codes are the header's enum values, and the
+    level-variant setter checks its handle before anything else."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "orth.h")).read()
+    for name in ("ORTH_PIP_PLUS", "ORTH_PIP", "ORTH_HOUSEHOLDER"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, hdr)
+        assert m and int(m.group(1)) == getattr(orth, name), name
+    assert orth.orth_set_level_variants(None, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_ARG
+    assert orth.orth_set_level_variants(None, orth.ORTH_HOUSEHOLDER, orth.ORTH_PIP_PLUS) == orth.ORTH_ERR_ARG

@@ -1,0 +1,239 @@
+"""Householder as the reduction subalgorithm on the GPU
+(orth_set_level_variants(h, leaf, ORTH_HOUSEHOLDER); Sec. 2.2 on the
+reduction problem of Sec. 4.1) against the oracle's TreeTSPQR with
+reduction "hh".
+
+* every call's H, R, U against the unique PQR solution (pqr_reference, eq.
+  (1.1)) after the sign fix D = diag(sign R_jj) (R's diagonal carries the
+  Householder signs, U's columns the same signs), and against the oracle
+  tree with the same leaves and subalgorithms, at the FP64 tolerances of
+  the tree tests; BCGS-PIP leaves against the oracle only (1e-10);
+* Y = Q C through the representation, the allocation-free form bit for bit;
+* the refusals: exports of the reduction factors, deflation, a switch once
+  the basis is non-empty, shapes past the panel kernel;
+* the Householder column of the Sec. 6.1 subproblems table (Stewart kappa =
+  1e4, n = 2^16, 32 columns, s = 4, Householder at both levels): e_perp and
+  ||A - QR|| in [min / 10, 10 max] of the printed column, for 8, 64 and 256
+  subproblems; and O(eps) at kappa = 1e12, where no CholeskyQR level holds.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import TreeTSPQR, metrics, pqr_reference
+from synth import stewart
+
+from gpu_util import kappa_after_projection, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_13393_amd import orth
+    orth.load()
+    return torch
+
+
+def _signfix(H, R, U):
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return H, d[:, None] * R, U * d[None, :]
+
+
+CASES = [
+    # n, s, kmax, leaf_rows, leaves ("pip+", "pip", "hh" = Householder leaves, "mixed")
+    (4000, 4, 32, 250, "pip+"),      # 16 leaves: 512 stacked rows
+    (2000, 8, 48, 250, "hh"),        # Householder at both levels
+    (3000, 16, 48, 1000, "pip+"),    # s = 16: 144 stacked rows
+    (1037, 2, 16, 128, "pip+"),      # ragged last leaf
+    (777, 1, 12, 100, "hh"),         # s = 1
+    (6000, 4, 32, 500, "pip"),       # BCGS-PIP leaves
+    (8000, 8, 40, 1000, "mixed"),    # the mixed form's leaves
+    (65536, 4, 32, 256, "hh"),       # 256 leaves: 8192 stacked rows, the panel's limit at s = 4
+]
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows,leaves", CASES)
+def test_householder_reduction_parity(torch_cuda, n, s, kmax, leaf_rows, leaves):
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("hh reduction", n, s, kmax, leaf_rows, leaves)
+    rng = np.random.default_rng(n + 5 * s)
+    prec = {"hh": orth.ORTH_FP64_HOUSEHOLDER, "mixed": orth.ORTH_MIXED_SPLIT32}.get(leaves, orth.ORTH_FP64)
+    var = orth.ORTH_PIP if leaves == "pip" else orth.ORTH_PIP_PLUS
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows, precision=prec, variant=var,
+                         reduction_variant=orth.ORTH_HOUSEHOLDER)
+    tree = TreeTSPQR(n, s, leaf_rows, {"mixed": "pip+"}.get(leaves, leaves), "hh")
+    tol = 1e-10 if leaves == "pip" else 1e-12
+    Q = np.zeros((n, 0))
+    Ugpu = []
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        Hraw, Rraw, Uraw = to_host(Hd), to_host(Rd), to_host(Ud)
+        H, R, U = _signfix(Hraw, Rraw, Uraw)
+        P, N, Ur = pqr_reference(Q, X)
+        Pt, Nt, Ut = _signfix(*tree.step(X))
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if leaves != "pip":
+            if step:
+                assert np.linalg.norm(H - P) / xn <= tol, step
+            assert np.linalg.norm(R - N) / xn <= tol * kap, step
+            assert np.max(np.abs(U - Ur)) <= tol * kap, step
+        if step:
+            assert np.linalg.norm(H - Pt) / xn <= tol * kap, step
+        assert np.linalg.norm(R - Nt) / xn <= tol * kap, step
+        assert np.max(np.abs(U - Ut)) <= tol * kap, step
+        assert np.all(np.tril(Rraw, -1) == 0.0)
+        Ugpu.append(Uraw)
+        # the reference on the basis with the GPU's column signs (H is the
+        # projection on those columns)
+        Q = np.hstack([Q, Uraw])
+    st, info = gpu.status()
+    assert st == 0, info
+    V = np.hstack(Ugpu)
+    assert metrics.e_perp(V) <= (1e-12 if leaves != "pip" else 1e-10)
+    # Y = Q C through the representation (two column blocks), and the
+    # allocation-free form bit for bit
+    C = rng.standard_normal((gpu.k, 19))
+    Cd = to_dev(C)
+    Y = to_host(gpu.apply_Q(Cd))
+    assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
+    Y2 = torch.empty((19, n), dtype=torch.float64, device="cuda")
+    assert orth.orth_apply_Q_noalloc(gpu.h, Cd.data_ptr(), gpu.k, 19, Y2.data_ptr(), n) == 0
+    assert np.array_equal(to_host(Y2), Y)
+    # the refusals
+    T = torch.empty((gpu.k, gpu.p * gpu.k), dtype=torch.float64, device="cuda")
+    assert orth.orth_export_local(gpu.h, None, n, T.data_ptr(), gpu.p * gpu.k) == orth.ORTH_ERR_UNSUPPORTED
+    assert orth.orth_export_tree_level(gpu.h, 0, T.data_ptr(), gpu.p * gpu.k) == orth.ORTH_ERR_UNSUPPORTED
+    assert orth.orth_set_deflation(gpu.h, 1e-6) == orth.ORTH_ERR_UNSUPPORTED
+    assert orth.orth_set_level_variants(gpu.h, var, orth.ORTH_PIP_PLUS) == orth.ORTH_ERR_UNSUPPORTED
+    gpu.close()
+
+
+def test_householder_reduction_refusals(torch_cuda):
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    # the stacked problem past the panel kernel: 300 leaves x 32 rows > 8192 at s = 4
+    g = Orthogonalizer(300 * 256, 4, 32, 256)
+    assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
+    g.close()
+    # a reduction tree
+    g = Orthogonalizer(8000, 4, 32, 500, fan_in=4)
+    assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
+    g.close()
+    # s = 32, and the leaf variant may not be Householder
+    g = Orthogonalizer(8000, 32, 64, 1000)
+    assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
+    assert orth.orth_set_level_variants(g.h, orth.ORTH_HOUSEHOLDER, orth.ORTH_PIP_PLUS) == orth.ORTH_ERR_ARG
+    g.close()
+    # a deflating handle
+    g = Orthogonalizer(8000, 4, 32, 500, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    g.set_deflation(1e-6)
+    assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def stewart_1e4():
+    return stewart(2 ** 16, 32, 1e4, 0)
+
+
+def _block_qr(gpu, A, torch):
+    m, s = A.shape[1], gpu.s
+    R = np.zeros((m, m))
+    for j in range(m // s):
+        Hd, Rd, _ = gpu.step(to_dev(A[:, j * s:(j + 1) * s]))
+        R[:j * s, j * s:(j + 1) * s] = to_host(Hd)
+        R[j * s:(j + 1) * s, j * s:(j + 1) * s] = to_host(Rd)
+    st, info = gpu.status()
+    assert st == 0, info
+    Q = to_host(gpu.apply_Q(torch.eye(m, dtype=torch.float64, device="cuda")))
+    return Q, R
+
+
+@pytest.mark.parametrize("p", [8, 64, 256])
+def test_subproblems_table_householder_column(torch_cuda, stewart_1e4, p):
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("subproblems householder", p)
+    A = stewart_1e4
+    n = A.shape[0]
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_stability_tables.json")))
+    gpu = Orthogonalizer(n, 4, 32, n // p, precision=orth.ORTH_FP64_HOUSEHOLDER,
+                         reduction_variant=orth.ORTH_HOUSEHOLDER)
+    Q, R = _block_qr(gpu, A, torch)
+    e = metrics.e_perp(Q)
+    res = np.linalg.norm(A - Q @ R, "fro")
+    vals = [row[2] for row in gold["subproblems"].values()]
+    rvals = [row[5] for row in gold["subproblems"].values()]
+    assert min(vals) / 10 <= e <= max(vals) * 10, (p, e)
+    assert min(rvals) / 10 <= res <= max(rvals) * 10, (p, res)
+    print(f"[subproblems] {p} householder/householder: e_perp {e:.2e} ||A-QR|| {res:.2e}", flush=True)
+    gpu.close()
+
+
+def test_householder_both_levels_past_the_cholesky_bound(torch_cuda):
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    A = stewart(2 ** 16, 32, 1e12, 1)
+    gpu = Orthogonalizer(A.shape[0], 4, 32, 256, precision=orth.ORTH_FP64_HOUSEHOLDER,
+                         reduction_variant=orth.ORTH_HOUSEHOLDER)
+    Q, R = _block_qr(gpu, A, torch)
+    assert metrics.e_perp(Q) <= 1e-13
+    assert metrics.qr_residual(A, Q, R) <= 1e-13
+    gpu.close()
+
+
+def test_householder_reduction_over_a_dirty_workspace(torch_cuda):
+    """The reduction's compact-WY factor and reflector top rows start at zero
+    whatever the workspace held (the kernels rely on the stored zeros below
+    T's diagonal and above the pivots): a handle created over a NaN-filled
+    workspace gives the same bits as one over a zeroed workspace."""
+    torch = torch_cuda
+    from paper_2204_13393_amd import orth
+    n, s, kmax, lr = 3000, 8, 48, 1000
+    nbytes = orth.orth_workspace_bytes(n, s, kmax, lr, orth.ORTH_FP64)
+    rng = np.random.default_rng(17)
+    W = [to_dev(rng.standard_normal((n, s))) for _ in range(kmax // s)]
+    outs = []
+    for fill in (0.0, float("nan")):
+        ws = torch.full((nbytes // 8 + 32,), fill, dtype=torch.float64, device="cuda")
+        base = (ws.data_ptr() + 255) // 256 * 256
+        code, h = orth.orth_create(n, s, kmax, lr, orth.ORTH_FP64, base, nbytes, None)
+        assert code == 0
+        assert orth.orth_set_level_variants(h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == 0
+        res = []
+        for j, Wd in enumerate(W):
+            k = j * s
+            H = torch.zeros((s, max(k, 1)), dtype=torch.float64, device="cuda")
+            R = torch.zeros((s, s), dtype=torch.float64, device="cuda")
+            U = torch.zeros((s, n), dtype=torch.float64, device="cuda")
+            assert orth.orth_step(h, Wd.data_ptr(), n, H.data_ptr(), max(k, 1), R.data_ptr(), s, U.data_ptr(), n) == 0
+            res += [to_host(H), to_host(R), to_host(U)]
+        code, st, info = orth.orth_status(h)
+        assert code == 0 and st == 0, info
+        orth.orth_destroy(h)
+        outs.append(res)
+        del ws
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+        assert np.all(np.isfinite(a))
+

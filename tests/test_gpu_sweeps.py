@@ -49,6 +49,8 @@ EPS = 2.0 ** -52
 N, M, S, LEAF = 2 ** 16, 32, 4, 256
 COMBOS = [("pip+", "pip+"), ("pip+", "pip"), ("pip", "pip+"), ("pip", "pip")]
 HH = [("hh", "pip+"), ("hh", "pip")]
+# Householder at the reduction (the third row of the local x reduction map)
+HHRED = [("pip+", "hh"), ("pip", "hh"), ("hh", "hh")]
 
 
 def _say(*a):
@@ -69,7 +71,7 @@ def torch_cuda():
 def _gpu_e_perp(A, local, reduction):
     """(status, e_perp or None, breakdown level) of the GPU QR of A in blocks of S."""
     from paper_2204_13393_amd import Orthogonalizer, orth
-    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP}
+    v = {"pip+": orth.ORTH_PIP_PLUS, "pip": orth.ORTH_PIP, "hh": orth.ORTH_HOUSEHOLDER}
     if local == "hh":
         g = Orthogonalizer(N, S, M, LEAF, precision=orth.ORTH_FP64_HOUSEHOLDER, reduction_variant=v[reduction])
     else:
@@ -99,7 +101,7 @@ def sweep(torch_cuda):
     out = {}
     for kappa in (1e0, 1e3, 1e6, 1e8, 1e9, 1e10):
         A = stewart(N, M, kappa, 11)
-        for local, red in COMBOS + HH:
+        for local, red in COMBOS + HH + HHRED:
             _say("sweep", kappa, local, red)
             st, eg, level = _gpu_e_perp(A, local, red)
             eo = _oracle_e_perp(A, local, red)
@@ -161,6 +163,26 @@ def test_householder_leaves_never_break_down(sweep):
     # the BCGS-PIP reduction shows its O(eps kappa^2) error with any leaves
     st, eg, eo = sweep[(1e6, "hh", "pip")]
     assert st == 0 and eg >= 1e-10 and eo is not None and eo >= 1e-10, (eg, eo)
+
+
+def test_householder_reduction_map(sweep):
+    """The reduction row of the local x reduction map (Sec. 6.1): Householder
+    at both levels is O(eps) at every kappa of the sweep, the paper's
+    kappa = 1e8 included; with CholeskyQR leaves the leaves decide: BCGS-PIP+
+    O(eps) and BCGS-PIP O(eps kappa^2) while the leaves hold, and a
+    breakdown at the leaves past u kappa^2 = 1/2."""
+    for kappa in (1e0, 1e3, 1e6, 1e8, 1e9, 1e10):
+        st, eg, eo = sweep[(kappa, "hh", "hh")]
+        assert st == 0 and eg <= 1e-13, (kappa, st, eg)
+        assert eo is not None and eo <= 1e-13, (kappa, eo)
+    for kappa in (1e0, 1e3, 1e6):
+        st, eg, eo = sweep[(kappa, "pip+", "hh")]
+        assert st == 0 and eg <= 1e-13, (kappa, st, eg)
+    st, eg, eo = sweep[(1e6, "pip", "hh")]
+    assert st == 0 and eg >= 1e-10 and eg <= 100 * EPS * 1e12, eg
+    for local in ("pip+", "pip"):
+        st, eg, eo = sweep[(1e9, local, "hh")]
+        assert st != 0 and sweep[("level", 1e9, local, "hh")] == 0, (local, st)
 
 
 def test_gpu_matches_oracle(sweep):
