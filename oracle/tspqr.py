@@ -36,12 +36,12 @@ Readings adopted where the paper is silent:
 * the first step (k = 0) is the same procedure with an empty basis: it is the
   TSQR of the start block (Sec. 4.1, tree TSQR);
 * Householder as the reduction subalgorithm (the stability table of Sec. 6.1
-  uses one method at both levels): the single reduction node holds its basis
-  as unit reflectors over the stacked rows (Algorithm "HH", Sec. 2.2); every
+  uses one method at every level): every reduction node holds its basis as
+  unit reflectors over its stacked rows (Algorithm "HH", Sec. 2.2); every
   step inserts s zero rows into them after each child's k rows, the rows of
   that child's new coordinates, as the stacked factors are extended with
-  zero rows; the pivots are the node's leading rows (child 1's).  The
-  diagonal of N then carries the Householder signs and the new basis
+  zero rows; the pivots are the node's leading rows (its first child's).
+  The diagonal of N then carries the Householder signs and the new basis
   columns the same signs, as with Householder leaves.
 """
 
@@ -84,8 +84,8 @@ class TreeTSPQR:
                 reference solution); ``local`` may also be "hh": the
                 Householder method (Sec. 2.2), each leaf basis then held as
                 reflectors (``oracle.hhpqr.HouseholderBasis``);
-                ``reduction`` may be "hh" for the single-level tree (the
-                reduction node's basis held as reflectors).
+                ``reduction`` may be "hh" (every reduction node's basis held
+                as reflectors).
     fan_in      None for the single-level tree, else the tree fan-in.
     deflate     None, or the relative tolerance delta of the deflating
                 reduction (``oracle.deflate``, Sec. 3.1): the single
@@ -125,9 +125,10 @@ class TreeTSPQR:
                 break
         if deflate is not None and len(self.levels) != 1:
             raise ValueError("deflation is defined for the single-level tree")
-        if self.hh_reduction and len(self.levels) != 1:
-            raise ValueError("the Householder reduction is defined for the single-level tree")
-        self.root_hh = None      # the reduction node's reflectors (reduction "hh")
+        if self.hh_reduction:
+            for nodes in self.levels:
+                for node in nodes:
+                    node["H"] = None      # the node's reflectors (reduction "hh")
 
     @property
     def p(self):
@@ -164,7 +165,7 @@ class TreeTSPQR:
                 B = np.vstack([np.vstack([Sc, np.zeros((s, k))]) for Sc in node["S"]])
                 Yv = np.vstack(Y[c0:c1])
                 if self.hh_reduction:
-                    Pv, Nv, Uv = self._hh_reduce(c1 - c0, Yv)
+                    Pv, Nv, Uv = self._hh_reduce(node, c1 - c0, Yv)
                 elif self.deflate is None:
                     Pv, Nv, Uv = self.reduction(B, Yv)
                 else:
@@ -192,16 +193,21 @@ class TreeTSPQR:
         U = self.apply_Q(np.vstack([np.zeros((k, s)), np.eye(s)]))
         return P, N, U
 
-    def _hh_reduce(self, children, Yv):
-        """The reduction problem by Algorithm "HH" on the node's reflectors:
+    def _hh_reduce(self, node, children, Yv):
+        """A node's reduction problem by Algorithm "HH" on its reflectors:
         s zero rows inserted after every child's k rows, then one pqr."""
         k, s = self.k, self.s
-        if self.root_hh is None:
-            self.root_hh = HouseholderBasis(children * s)
+        if node["H"] is None:
+            node["H"] = HouseholderBasis(children * s)
         else:
             for c in range(children - 1, -1, -1):
-                self.root_hh = hh_with_zero_rows(self.root_hh, c * k + k, s)
-        return self.root_hh.pqr(Yv)
+                node["H"] = hh_with_zero_rows(node["H"], c * k + k, s)
+        return node["H"].pqr(Yv)
+
+    @property
+    def root_hh(self):
+        """The single root's reflectors (reduction "hh")."""
+        return self.levels[-1][0]["H"]
 
     def apply_Q(self, C):
         """Y = Q C for C ((current k) x m): down-sweep of C, then leaf products.

@@ -170,9 +170,46 @@ def test_householder_reduction_inserted_rows_are_zero():
 
 def test_householder_reduction_refusals():
     with pytest.raises(ValueError):
-        TreeTSPQR(1000, 4, 100, "pip+", "hh", fan_in=2)
-    with pytest.raises(ValueError):
         TreeTSPQR(1000, 4, 100, "hh", "hh", deflate=1e-6)
+
+
+@pytest.mark.parametrize("n,s,leaf_rows,fan_in,local", [(2000, 4, 100, 2, "hh"), (3000, 3, 150, 3, "pip+"),
+                                                          (1037, 2, 64, 4, "hh"), (4096, 8, 256, 2, "ref")])
+def test_householder_tree_equals_unique_reference(n, s, leaf_rows, fan_in, local):
+    """Householder at every node of a reduction tree (fan-in 2..4, ragged
+    groups): (P, N D, U D) equals the unique solution; every node's stacked
+    factor stays orthonormal."""
+    rng = np.random.default_rng(n + fan_in)
+    tree = TreeTSPQR(n, s, leaf_rows, local, "hh", fan_in)
+    assert len(tree.levels) > 1
+    Q = np.zeros((n, 0))
+    for step in range(5):
+        X = rng.standard_normal((n, s)) * np.geomspace(1, 1e-2, s)
+        if step:
+            X += Q @ rng.standard_normal((Q.shape[1], s))
+        P, N, Uraw = tree.step(X)
+        P, N, U = _signfix(P, N, Uraw)
+        Pr, Nr, Ur = pqr_reference(Q, X)
+        assert np.linalg.norm(P - Pr) / np.linalg.norm(X) < 1e-13
+        assert np.linalg.norm(N - Nr) / np.linalg.norm(X) < 1e-13
+        assert np.max(np.abs(U - Ur)) < 1e-11
+        Q = np.hstack([Q, Uraw])
+    for level in range(len(tree.levels)):
+        for node in tree.levels[level]:
+            assert metrics.e_perp(np.vstack(node["S"])) < 1e-13
+    C = rng.standard_normal((tree.k, 3))
+    assert np.allclose(tree.apply_Q(C), tree.explicit_Q() @ C, atol=1e-12)
+
+
+@pytest.mark.parametrize("level", [1, 3, 8])
+def test_recursion_levels_householder_column(golden, stewart_1e4, level):
+    """The Householder column of the recursion-levels table (Sec. 6.1):
+    Householder at the leaves and at every node of the fan-in-2 tree."""
+    e, res_abs, res_rel = _run(stewart_1e4, 2 ** level, 2, "hh")
+    lo, hi = _band(golden, "recursion_levels", 2)
+    assert lo <= e <= hi, (level, e, lo, hi)
+    rlo, rhi = _band(golden, "recursion_levels", 5)
+    assert rlo <= res_abs <= rhi and rlo <= res_rel <= rhi
 
 
 @pytest.mark.parametrize("p", [8, 64, 256])
