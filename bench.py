@@ -827,6 +827,9 @@ def main():
     ap.add_argument("--flat-blocks", default="",
                     help="default workload: also time the FP64 sequence with FlatTSPQR over this many "
                          "row blocks (comma-separated counts)")
+    ap.add_argument("--householder-tree", type=int, default=0,
+                    help="default workload: also time Householder at every level (Householder leaves and a "
+                         "Householder reduction tree of this fan-in)")
     ap.add_argument("--workload", default="lap2d-4096x4096-s8",
                     choices=["lap2d-4096x4096-s8", "batched", "lap3d-256-s32", "stewart", "kappa-sweep",
                              "lap2d-100x100-s4"],
@@ -1056,7 +1059,7 @@ def main():
     # over P row blocks (Sec. 4.2)
     fan_ins = [int(g) for g in args.tree_fan_ins.split(",") if g] if args.tree_fan_ins else []
     flat_ps = [int(q) for q in args.flat_blocks.split(",") if q] if args.flat_blocks else []
-    if fan_ins or flat_ps:
+    if fan_ins or flat_ps or args.householder_tree:
         del ws
         torch.cuda.empty_cache()
 
@@ -1104,6 +1107,21 @@ def main():
         trees[str(g)] = {"levels": levels, "ms_per_step": ms, "e_perp": ep, "vs_single_level": ms / ms_per_step}
         print(f"[bench] tree fan-in {g}: {levels} levels, {ms:.2f} ms per sequence, e_perp {ep:.2e}",
               file=sys.stderr, flush=True)
+    hh_tree = None
+    if args.householder_tree:
+        g = args.householder_tree
+
+        def create_hh_tree(ptr, nb):
+            code, th = orth.orth_create_tree(n, s, kmax, leaf, orth.ORTH_FP64_HOUSEHOLDER, g, ptr, nb, sptr)
+            if code == 0:
+                code = orth.orth_set_level_variants(th, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER)
+            return code, th
+        levels, ms, ep = time_arrangement(
+            orth.orth_tree_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64_HOUSEHOLDER, g), create_hh_tree,
+            f"householder tree fan-in {g}")
+        hh_tree = {"fan_in": g, "levels": levels, "ms_per_step": ms, "e_perp": ep, "vs_fp64": ms / ms_per_step}
+        print(f"[bench] householder leaves and householder tree, fan-in {g}: {levels} levels, {ms:.2f} ms per "
+              f"sequence, e_perp {ep:.2e}", file=sys.stderr, flush=True)
     flats = {}
     for q in flat_ps:
         rows = n // q
@@ -1191,6 +1209,8 @@ def main():
         out["reduction_trees"] = trees
     if flats:
         out["flat_tspqr"] = flats
+    if hh_tree:
+        out["householder_every_level"] = hh_tree
     print(json.dumps(out), flush=True)
 
 

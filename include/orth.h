@@ -188,9 +188,10 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
  *   fan_in   0 (or >= the number of leaves): the single reduction level of
  *            orth_create; otherwise >= 2
  * The workspace grows by the upper levels' factors (about 1 / (fan_in - 1)
- * of the level over the leaves).  Not with ORTH_FP64_HOUSEHOLDER (returns 0
- * / UNSUPPORTED) and not with deflation.  Errors as orth_workspace_bytes
- * and orth_create (fan_in < 0 or = 1: ARG).
+ * of the level over the leaves).  Any leaf form; the nodes' subalgorithm is
+ * the reduction variant (orth_set_level_variants, ORTH_HOUSEHOLDER
+ * included).  Not with deflation (orth_set_deflation: UNSUPPORTED).  Errors
+ * as orth_workspace_bytes and orth_create (fan_in < 0 or = 1: ARG).
  */
 size_t orth_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
                                  int32_t precision, int32_t fan_in);
@@ -260,15 +261,18 @@ int orth_set_variant(orth_t *h, int32_t variant);
  * leaves of an ORTH_FP64_HOUSEHOLDER handle run the Householder method:
  * their variant must stay ORTH_PIP_PLUS (else UNSUPPORTED), the reduction's
  * may be any.
- * reduction_variant = ORTH_HOUSEHOLDER: the reduction problem by Algorithm
- * HH (the stability table of Sec. 6.1 runs one method at both levels).  The
- * reduction's basis is then held as unit reflectors over the stacked rows
- * (p segments of k_max rows; each call's s new coordinates of a segment are
- * zero rows of the older reflectors) with its compact-WY factor, and one
- * workgroup factors the stacked panel: offered on single-level handles
- * with s <= 16, p k_max <= 8192 rows (s <= 4), 4096 (s = 8), 1024 (s = 16)
- * and k_max s <= 4096, without deflation, chosen before the first step or
- * kept (a switch to or from it once k > 0 is UNSUPPORTED).  R's diagonal
+ * reduction_variant = ORTH_HOUSEHOLDER: every reduction problem by
+ * Algorithm HH (the stability table of Sec. 6.1 runs one method at every
+ * level).  Each reduction node's basis is then held as unit reflectors over
+ * its stacked rows (its children's segments of k_max rows; each call's s new
+ * coordinates of a segment are zero rows of the older reflectors) with its
+ * compact-WY factor, and one workgroup factors each node's panel: offered
+ * when every node's rows (children x k_max; all p leaves for the single
+ * level, fan_in leaves or nodes on an orth_create_tree handle) are at most
+ * 8192 (s <= 4), 4096 (s = 8), 1024 (s = 16), with k_max s <= 4096, without
+ * deflation, chosen before the first step or kept (a switch to or from it
+ * once k > 0 is UNSUPPORTED).  The workspace of such handles holds 3 k_max^2
+ * doubles per node for the factors.  R's diagonal
  * then carries the Householder signs and U's columns the same signs: (H,
  * R D, U D) with D = diag(sign R_jj) is the unique solution.
  * orth_export_local's d_T and orth_export_tree_level are UNSUPPORTED then

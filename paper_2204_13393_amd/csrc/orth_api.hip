@@ -117,11 +117,12 @@ struct Plan {
     int32_t nchunkL, nchunkR;
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
-    // Householder reduction (single level, the stacked problem within one
-    // workgroup's panel): the root's compact-WY factor, its coefficient
-    // record, its [P; N], its explicit new columns and a third apply scratch
-    bool hhroot;
-    int64_t oTHR, oCR, oHR, oUR, oCA3;
+    // Householder reduction (every node's stacked problem within one
+    // workgroup's panel): per level the nodes' compact-WY factors and the
+    // explicit new columns; the root's coefficient record and [P; N]; a
+    // third apply scratch
+    bool hhtree;
+    int64_t oTHl[kMaxLevels], oURl[kMaxLevels], oCR, oHR, oCA3;
     int64_t slot_cap, red_cap;   // doubles of each partial-slot region and of the pre-sum region
 };
 
@@ -129,6 +130,18 @@ int32_t default_leaf_rows(int64_t n, int32_t kmax) {
     int64_t lr = n < 4096 ? n : 4096;
     if (lr < kmax) lr = kmax;
     return (int32_t)lr;
+}
+
+// children of the widest node of tree level l
+int32_t hh_node_children(const Plan &pl, int l) {
+    return pl.fan_in == 0 ? pl.nchild[l] : std::min(pl.fan_in, pl.nchild[l]);
+}
+
+// tree level l for the Householder reduction: its children's k_max physical
+// rows each, its nodes as the kernels' leaves
+LevelGeom hh_level_geom(const Plan &pl, int l, int chunk) {
+    const int64_t rows = (int64_t)pl.nchild[l] * pl.kmax;
+    return make_leaf_geom(rows, (int32_t)((int64_t)hh_node_children(pl, l) * pl.kmax), pl.nnode[l], chunk);
 }
 
 bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t precision, Plan &pl,
@@ -182,10 +195,6 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         if (nodes == 1) break;
         count = nodes;
     }
-    if (pl.nlev > 1 && precision == ORTH_FP64_HOUSEHOLDER) {
-        *why = ORTH_ERR_UNSUPPORTED;      // Householder leaves keep the single level
-        return false;
-    }
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
     const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
@@ -209,9 +218,12 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         const int32_t ncol = k + s;
         const int64_t per = (int64_t)gram_row_groups(ncol) * ncol * s;
         int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
-        for (int l = 0; l < pl.nlev; ++l)
+        for (int l = 0; l < pl.nlev; ++l) {
             nR = std::max(nR, (int64_t)make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in,
                                                       kmax, ncol, kRootChunk).nchunks());
+            // the Householder reduction's levels run over the physical rows
+            nR = std::max(nR, (int64_t)hh_level_geom(pl, l, kRootChunk).nchunks());
+        }
         slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
         // pre-summed slot groups of a level with a single local problem: the
         // reduction level, and the leaf level when there is one leaf
@@ -234,18 +246,23 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
-    // the Householder reduction is offered when the stacked problem (p k_max
-    // physical rows) fits the panel kernel
-    pl.hhroot = pl.nlev == 1 && s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)pl.p * kmax <= hh_max_leaf_rows(s) &&
-                (int64_t)kmax * s <= kHhMaxCoef;
+    // the Householder reduction is offered when every node's stacked problem
+    // (its children's k_max physical rows each) fits the panel kernel
+    pl.hhtree = s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)kmax * s <= kHhMaxCoef;
+    for (int l = 0; l < pl.nlev && pl.hhtree; ++l)
+        pl.hhtree = (int64_t)hh_node_children(pl, l) * kmax <= hh_max_leaf_rows(s);
     // and orth_apply_Q's second coefficient scratch (-Z_i, or the tree's
     // down-sweep in turn with CA), like CA
-    pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhroot) ? take(pl.ldt * kApplyMB) : 0;
-    pl.oTHR = pl.hhroot ? take((int64_t)3 * kmax * kmax) : 0;
-    pl.oCR = pl.hhroot ? take((int64_t)kmax * 2 * s) : 0;
-    pl.oHR = pl.hhroot ? take((int64_t)kmax * s) : 0;
-    pl.oUR = pl.hhroot ? take(pl.ldt * s) : 0;
-    pl.oCA3 = pl.hhroot ? take(pl.ldt * kApplyMB) : 0;
+    pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhtree) ? take(pl.ldt * kApplyMB) : 0;
+    for (int l = 0; l < pl.nlev; ++l) {
+        pl.oTHl[l] = pl.hhtree ? take((int64_t)3 * pl.nnode[l] * kmax * kmax) : 0;
+        pl.oURl[l] = pl.hhtree ? take(pl.ldtl[l] * s) : 0;
+    }
+    pl.oCR = pl.hhtree ? take((int64_t)kmax * 2 * s) : 0;
+    pl.oHR = pl.hhtree ? take((int64_t)kmax * s) : 0;
+    // a third region: the Householder reduction's apply, and Householder
+    // leaves under a tree (their -Z_i beside the down-sweep's two regions)
+    pl.oCA3 = (pl.hhtree || (precision == ORTH_FP64_HOUSEHOLDER && pl.nlev > 1)) ? take(pl.ldt * kApplyMB) : 0;
     // deflation state (counters and the first sweep's s x s W), Householder leaves only
     pl.oDF = precision == ORTH_FP64_HOUSEHOLDER ? take(defl_state_doubles(s)) : 0;
     // the tree's levels: level 0 stacks the leaves' factors in T, Y, U1R;
@@ -427,15 +444,17 @@ struct orth_ctx {
     // second apply scratch: Householder leaves (-Z_i) and reduction trees (the
     // down-sweep alternates between CA and CA2)
     double *CA2() const {
-        return (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhroot) ? ws + pl.oCA2 : nullptr;
+        return (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhtree) ? ws + pl.oCA2 : nullptr;
     }
     // Householder reduction regions (null unless the plan offers it)
     bool hh_red() const { return variant_red == ORTH_HOUSEHOLDER; }
-    double *THR() const { return pl.hhroot ? ws + pl.oTHR : nullptr; }
-    double *CR() const { return pl.hhroot ? ws + pl.oCR : nullptr; }
-    double *HR() const { return pl.hhroot ? ws + pl.oHR : nullptr; }
-    double *UR() const { return pl.hhroot ? ws + pl.oUR : nullptr; }
-    double *CA3() const { return pl.hhroot ? ws + pl.oCA3 : nullptr; }
+    double *THl(int l) const { return pl.hhtree ? ws + pl.oTHl[l] : nullptr; }
+    double *URl(int l) const { return pl.hhtree ? ws + pl.oURl[l] : nullptr; }
+    double *CR() const { return pl.hhtree ? ws + pl.oCR : nullptr; }
+    double *HR() const { return pl.hhtree ? ws + pl.oHR : nullptr; }
+    double *CA3() const {
+        return (pl.hhtree || (pl.precision == ORTH_FP64_HOUSEHOLDER && pl.nlev > 1)) ? ws + pl.oCA3 : nullptr;
+    }
     DeflState *DF() const {
         return pl.precision == ORTH_FP64_HOUSEHOLDER ? reinterpret_cast<DeflState *>(ws + pl.oDF) : nullptr;
     }
@@ -502,9 +521,9 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
     // Householder leaves: the compact-WY factors grow into zeros below their diagonal
     if (e == hipSuccess && h->TH())
         e = launch_fill(h->TH(), (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, h->stream);
-    // and so does the Householder reduction's (with the reflectors' top rows)
-    if (e == hipSuccess && h->THR())
-        e = launch_fill(h->THR(), (int64_t)3 * pl.kmax * pl.kmax, 0.0, h->stream);
+    // and so do the Householder reduction's (with the reflectors' top rows)
+    for (int l = 0; l < pl.nlev && e == hipSuccess && pl.hhtree; ++l)
+        e = launch_fill(h->THl(l), (int64_t)3 * pl.nnode[l] * pl.kmax * pl.kmax, 0.0, h->stream);
     if (e == hipSuccess && h->DF())
         e = launch_fill_i32(reinterpret_cast<int32_t *>(h->DF()), (int64_t)(sizeof(DeflState) / sizeof(int32_t)), 0,
                             h->stream);
@@ -582,7 +601,7 @@ int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_v
     if (h->poisoned) return ORTH_ERR_POISONED;
     // Householder at the reduction: single-level handles whose stacked
     // problem fits the panel kernel, not with deflation, not mid-basis
-    if (reduction_variant == ORTH_HOUSEHOLDER && (h->flat || !h->pl.hhroot || h->defl_delta > 0.0))
+    if (reduction_variant == ORTH_HOUSEHOLDER && (h->flat || !h->pl.hhtree || h->defl_delta > 0.0))
         return ORTH_ERR_UNSUPPORTED;
     if ((reduction_variant == ORTH_HOUSEHOLDER) != (h->variant_red == ORTH_HOUSEHOLDER) && h->k > 0)
         return ORTH_ERR_UNSUPPORTED;
@@ -849,59 +868,64 @@ int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
     return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
 }
 
-// Householder reduction (Sec. 2.2 on the reduction problem of Sec. 4.1):
-// the stacked [P_i; N_i] (p segments of k_max physical rows, zero past each
-// segment's k+s rows) against the root's reflectors V (the level's factor
-// storage), one "leaf" of p k_max rows for the leaf-level kernels:
-// M = V^T Y, Y~ = T^T M, w~ = Y - V Y~, the panel (pivots: segment 0's rows
-// k .. k+s-1; [P; N] to the root scratch, then to H and R), [V v]^T v and T's
-// growth.  Zero rows stay zero through every product, so each segment's
-// rows k+s .. k+2s-1 are the zero rows the next call's new coordinates take.
-LevelGeom root_hh_geom(const Plan &pl, int chunk) {
-    const int64_t rows = (int64_t)pl.p * pl.kmax;
-    return make_leaf_geom(rows, (int32_t)rows, 1, chunk);
-}
-
-int run_root_hh(orth_ctx *h, int k, double *d_H, int64_t ldh, double *d_R, int64_t ldr) {
+// Householder reduction (Sec. 2.2 on the reduction problems of Sec. 4.1):
+// at tree level l every node's stacked [P_c; N_c] (its children's segments
+// of k_max physical rows, zero past each segment's k+s rows) against the
+// node's reflectors V (the level's factor storage), the nodes as the
+// leaf-level kernels' leaves: M = V^T Y, Y~ = T^T M, w~ = Y - V Y~, the panel
+// in one workgroup per node (pivots: the rows k .. k+s-1 of the node's first
+// segment; [P_v; N_v] to the next level's X, the root's to a small scratch
+// and then to H and R), [V v]^T v and the growth of each node's T.  Zero
+// rows stay zero through every product, so each segment's rows
+// k+s .. k+2s-1 are the zero rows the next call's new coordinates take.  The
+// leaf instantiations are used: the reflectors have none of the stacked
+// factor's zero structure that the reduction kernels skip.
+int run_level_hh(orth_ctx *h, int l, int k, double *d_H, int64_t ldh, double *d_R, int64_t ldr) {
     const Plan &pl = h->pl;
     const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
+    const bool root = l == pl.nlev - 1;
     hipStream_t st = h->stream;
     const int64_t pstride = (int64_t)ncol * s;
-    const LevelGeom gg = root_hh_geom(pl, kRootChunk);
+    const LevelGeom gg = hh_level_geom(pl, l, kRootChunk);
     const int rg = gram_row_groups(ncol);
-    if (!pl.hhroot || (int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
+    if (!pl.hhtree || (int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
+    const int64_t ld = pl.ldtl[l];
     hipError_t e;
     HhArgs ha{};
     ha.geom = gg;
     ha.k = k;
     ha.kmax = kmax;
-    ha.Q = h->T();
-    ha.ldq = pl.ldt;
-    ha.T = h->THR();
+    ha.Q = h->Tl(l);
+    ha.ldq = ld;
+    ha.T = h->THl(l);
     ha.partials = h->PR();
     ha.part_stride = pstride;
     ha.slots_per_leaf = gg.cpl * rg;
     ha.slots_last = gg.cpl_last * rg;
-    ha.small = h->SR();
+    ha.small = h->Sl(l);
     ha.small_stride = small_stride(kmax, s);
-    ha.Yout = h->HR();
-    ha.ldy = kmax;
-    ha.yseg = 0;
+    if (root) {
+        ha.Yout = h->HR();
+        ha.ldy = kmax;
+        ha.yseg = 0;
+    } else {
+        ha.Yout = h->Yl(l + 1);
+        ha.ldy = pl.ldtl[l + 1];
+        ha.yseg = kmax;
+    }
     ha.status = h->status();
-    ha.X = h->Y();
-    ha.ldx = pl.ldt;
+    ha.X = h->Yl(l);
+    ha.ldx = ld;
     GramArgs ga{};
-    ga.Q = Operand{h->T(), pl.ldt};
+    ga.Q = Operand{h->Tl(l), ld};
     ga.k = k;
     ga.tile_groups = gram_tile_groups(ncol);
     ga.geom = gg;
     ga.partials = h->PR();
     ga.part_stride = pstride;
     ga.status = h->status();
-    // the leaf-level instantiations (identity rows): the reflectors have no
-    // zero structure for the reduction kernels' skipping
     if (k > 0) {
-        ga.X = Operand{h->Y(), pl.ldt};
+        ga.X = Operand{h->Yl(l), ld};
         int pm = h->begin(ORTH_K_ROOT_GRAM);
         e = launch_gram(s, ga, ORTH_K_LEAF_GRAM, st);
         h->end(pm);
@@ -911,13 +935,13 @@ int run_root_hh(orth_ctx *h, int k, double *d_H, int64_t ldh, double *d_R, int64
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
         FinalizeArgs f{};
-        f.Q = Operand{h->T(), pl.ldt};
-        f.Qnew = OutOperand{h->U1R(), pl.ldt};
-        f.U1 = Operand{h->Y(), pl.ldt};
+        f.Q = Operand{h->Tl(l), ld};
+        f.Qnew = OutOperand{h->U1l(l), ld};
+        f.U1 = Operand{h->Yl(l), ld};
         f.sweep = 1;
         f.k = k;
-        f.geom = root_hh_geom(pl, kRootRowChunk);
-        f.small = h->SR();
+        f.geom = hh_level_geom(pl, l, kRootRowChunk);
+        f.small = h->Sl(l);
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
         f.status = h->status();
@@ -925,13 +949,13 @@ int run_root_hh(orth_ctx *h, int k, double *d_H, int64_t ldh, double *d_R, int64
         e = launch_finalize(s, f, ORTH_K_LEAF_CORRECT, st);
         h->end(pm);
         if (e != hipSuccess) return ORTH_ERR_HIP;
-        ha.X = h->U1R();
+        ha.X = h->U1l(l);
     }
     int pm = h->begin(ORTH_K_ROOT_CHOL);
     e = launch_hh(s, HH_PANEL, ha, st);
     h->end(pm);
     if (e != hipSuccess) return ORTH_ERR_HIP;
-    ga.X = Operand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
+    ga.X = Operand{h->Tl(l) + (int64_t)k * ld, ld};
     pm = h->begin(ORTH_K_ROOT_GRAM2);
     e = launch_gram(s, ga, ORTH_K_LEAF_GRAM2, st);
     h->end(pm);
@@ -940,55 +964,65 @@ int run_root_hh(orth_ctx *h, int k, double *d_H, int64_t ldh, double *d_R, int64
     e = launch_hh(s, HH_TUPD, ha, st);
     h->end(pm);
     if (e != hipSuccess) return ORTH_ERR_HIP;
-    // [P; N] -> H (k x s) and R (s x s)
-    if (k > 0) e = launch_copy_cols(h->HR(), kmax, RowMap{0, 0}, d_H, ldh, k, s, st);
-    if (e == hipSuccess) e = launch_copy_cols(h->HR() + k, kmax, RowMap{0, 0}, d_R, ldr, s, s, st);
+    if (root) {
+        // [P; N] -> H (k x s) and R (s x s)
+        if (k > 0) e = launch_copy_cols(h->HR(), kmax, RowMap{0, 0}, d_H, ldh, k, s, st);
+        if (e == hipSuccess) e = launch_copy_cols(h->HR() + k, kmax, RowMap{0, 0}, d_R, ldr, s, s, st);
+    }
     return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
 }
 
-// The root's new columns U_R = Q_{k+s} [0; I_s] = -V (T V[0:k+s]^T E) + E
-// over the stacked rows, then each segment's k+s rows -> the right half of
-// that leaf's record (its C_i = [P~_i; N~_i])
-int finalize_root_hh(orth_ctx *h, int k) {
+// Down the tree: every node's new columns U_v = Q_{v,k+s} [C_v; 0] =
+// -V (T V[0:k+s]^T C_v) + E C_v over its rows (C_v = [0; I_s] at the root,
+// else the node's block from its parent, in the right half of its record),
+// then each child segment's k+s rows -> the right half of that child's
+// record (the leaves' C_i at level 0)
+int finalize_level_hh(orth_ctx *h, int l, int k) {
     const Plan &pl = h->pl;
     const int32_t s = pl.s, kmax = pl.kmax, K = k + s;
+    const bool root = l == pl.nlev - 1;
     hipStream_t st = h->stream;
     const int64_t cseg = (int64_t)kmax * 2 * s;
-    // E = [0; I_s] in the right half of the root's record
-    hipError_t e = launch_fill(h->CR(), cseg, 0.0, st);
-    for (int32_t j = 0; j < s && e == hipSuccess; ++j)
-        e = launch_fill(h->CR() + (int64_t)(k + j) * 2 * s + s + j, 1, 1.0, st);
-    if (e != hipSuccess) return ORTH_ERR_HIP;
+    const int64_t ld = pl.ldtl[l];
+    double *rec = root ? h->CR() : h->Cl(l);
+    hipError_t e = hipSuccess;
+    if (root) {
+        // E = [0; I_s] in the right half of the root's record
+        e = launch_fill(rec, cseg, 0.0, st);
+        for (int32_t j = 0; j < s && e == hipSuccess; ++j)
+            e = launch_fill(rec + (int64_t)(k + j) * 2 * s + s + j, 1, 1.0, st);
+        if (e != hipSuccess) return ORTH_ERR_HIP;
+    }
     HhArgs ha{};
-    ha.geom = root_hh_geom(pl, kRootRowChunk);
+    ha.geom = hh_level_geom(pl, l, kRootRowChunk);
     ha.k = k;
     ha.kmax = kmax;
-    ha.Q = h->T();
-    ha.ldq = pl.ldt;
-    ha.T = h->THR();
-    ha.crec = h->CR();
+    ha.Q = h->Tl(l);
+    ha.ldq = ld;
+    ha.T = h->THl(l);
+    ha.crec = rec;
     ha.cseg = cseg;
-    ha.U = h->UR();
-    ha.ldu = pl.ldt;
+    ha.U = h->URl(l);
+    ha.ldu = ld;
     ha.status = h->status();
     int pm = h->begin(ORTH_K_ROOT_CHOL);
     e = launch_hh(s, HH_COEF, ha, st);
     h->end(pm);
     if (e != hipSuccess) return ORTH_ERR_HIP;
     FinalizeArgs f{};
-    f.Q = Operand{h->T(), pl.ldt};
-    f.Qnew = OutOperand{h->U1R(), pl.ldt};
-    f.U1 = Operand{h->T() + (int64_t)k * pl.ldt, pl.ldt};
+    f.Q = Operand{h->Tl(l), ld};
+    f.Qnew = OutOperand{h->U1l(l), ld};
+    f.U1 = Operand{h->Tl(l) + (int64_t)k * ld, ld};
     f.sweep = 2;
     f.k = k;
     f.geom = ha.geom;
-    f.small = h->SR();
+    f.small = h->Sl(l);
     f.small_stride = small_stride(kmax, s);
     f.kmax = kmax;
     f.single_sweep = 1;
-    f.Cptr = h->CR();
+    f.Cptr = rec;
     f.cseg = cseg;
-    f.Uout = OutOperand{h->UR(), pl.ldt};
+    f.Uout = OutOperand{h->URl(l), ld};
     f.status = h->status();
     pm = h->begin(ORTH_K_ROOT_FINALIZE);
     e = launch_finalize(s, f, ORTH_K_LEAF_FINALIZE, st);
@@ -999,7 +1033,7 @@ int finalize_root_hh(orth_ctx *h, int k) {
     h->end(pm);
     if (e != hipSuccess) return ORTH_ERR_HIP;
     pm = h->begin(ORTH_K_ROOT_FINALIZE);
-    e = launch_rows_to_records(h->UR(), pl.ldt, pl.p, kmax, K, s, h->CL(), cseg, st);
+    e = launch_rows_to_records(h->URl(l), ld, pl.nchild[l], kmax, K, s, l == 0 ? h->CL() : h->Cl(l - 1), cseg, st);
     h->end(pm);
     return e == hipSuccess ? ORTH_OK : ORTH_ERR_HIP;
 }
@@ -1227,8 +1261,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     // children (segments of k+s rows), level by level up to the root
     for (int l = 0; l < pl.nlev; ++l) {
         const bool root = l == pl.nlev - 1;
-        if (h->hh_red()) {                       // Householder reduction (single level)
-            if ((rc = run_root_hh(h, k, k > 0 ? d_H : nullptr, ldh, d_R, ldr))) goto fail;
+        if (h->hh_red()) {                       // Householder reduction
+            if ((rc = run_level_hh(h, l, k, k > 0 ? d_H : nullptr, ldh, d_R, ldr))) goto fail;
             continue;
         }
         LevelRun L{};
@@ -1265,7 +1299,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
     for (int l = pl.nlev - 1; l >= 0; --l) {
         const bool root = l == pl.nlev - 1;
         if (h->hh_red()) {
-            if ((rc = finalize_root_hh(h, k))) goto fail;
+            if ((rc = finalize_level_hh(h, l, k))) goto fail;
             continue;
         }
         double *below = l == 0 ? h->CL() : h->Cl(l - 1);
@@ -1346,7 +1380,8 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
     auto end = [&](int idx) { if (prof) h->end(idx); };
     // host check: the tree's down-sweep and the Householder products need
     // the second scratch region
-    if (!ca || ((hh || pl.nlev > 1) && !ca2) || (h->hh_red() && (!ca2 || !ca3)) || mb_max < 1) return ORTH_ERR_HIP;
+    if (!ca || ((hh || pl.nlev > 1) && !ca2) || ((h->hh_red() || (hh && pl.nlev > 1)) && !ca3) || mb_max < 1)
+        return ORTH_ERR_HIP;
     for (int32_t j0 = 0; j0 < m; j0 += mb_max) {
         const int32_t mb = (m - j0) < mb_max ? (m - j0) : mb_max;
         // down the reduction tree: a node's children get C_c = S_v,c C_v
@@ -1355,40 +1390,49 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         // scratch regions in turn, so level 0 leaves C_i in `cur`
         hipError_t e = hipSuccess;
         double *cur = nullptr;
+        double *zleaf = ca2;                     // Householder leaves' -Z_i scratch
         if (h->hh_red()) {
-            // Householder reduction: Y_R = Q_k [C; 0] = -V Z + E C over the
-            // stacked rows (Z = T V[0:k]^T C), i.e. every leaf's C_i at its
-            // segment of ca3
-            e = launch_copy_cols(d_C + (int64_t)j0 * ldc, ldc, RowMap{0, 0}, ca, pl.ldt, k, mb, st);
-            HhArgs hr{};
-            hr.geom = root_hh_geom(pl, kRootRowChunk);
-            hr.k = k;
-            hr.kmax = pl.kmax;
-            hr.T = h->THR();
-            hr.ca = ca;
-            hr.ca_out = ca2;
-            hr.ldca = pl.ldt;
-            hr.m = mb;
-            hr.U = ca3;
-            hr.ldu = pl.ldt;
-            int pm = begin(ORTH_K_APPLY);
-            if (e == hipSuccess) e = launch_hh_apply(HH_APPLY_COEF, hr, st);
-            if (e == hipSuccess) {
-                ApplyArgs r{};
-                r.Q = Operand{h->T(), pl.ldt};
-                r.k = k;
-                r.geom = hr.geom;
-                r.Cptr = ca2;
-                r.ldc = pl.ldt;
-                r.cseg = 0;
-                r.m = mb;
-                r.Y = OutOperand{ca3, pl.ldt};
-                e = launch_apply(r, st);
+            // Householder reduction, level by level from the root: a node's
+            // children get [C_c] = Q_{v,k} [C_v; 0] = -V Z + E C_v over its
+            // rows (Z = T V[0:k]^T C_v); three regions in turn hold C, -Z and
+            // the children's blocks
+            double *buf[3] = {ca, ca2, ca3};
+            int ci = 0;
+            e = launch_copy_cols(d_C + (int64_t)j0 * ldc, ldc, RowMap{0, 0}, buf[0], pl.ldt, k, mb, st);
+            for (int l = pl.nlev - 1; l >= 0 && e == hipSuccess; --l) {
+                const int zi = (ci + 1) % 3, yi = (ci + 2) % 3;
+                HhArgs hr{};
+                hr.geom = hh_level_geom(pl, l, kRootRowChunk);
+                hr.k = k;
+                hr.kmax = pl.kmax;
+                hr.T = h->THl(l);
+                hr.ca = buf[ci];
+                hr.ca_out = buf[zi];
+                hr.ldca = pl.ldt;
+                hr.m = mb;
+                hr.U = buf[yi];
+                hr.ldu = pl.ldt;
+                const int pm = begin(ORTH_K_APPLY);
+                e = launch_hh_apply(HH_APPLY_COEF, hr, st);
+                if (e == hipSuccess) {
+                    ApplyArgs r{};
+                    r.Q = Operand{h->Tl(l), pl.ldtl[l]};
+                    r.k = k;
+                    r.geom = hr.geom;
+                    r.Cptr = buf[zi];
+                    r.ldc = pl.ldt;
+                    r.cseg = pl.kmax;
+                    r.m = mb;
+                    r.Y = OutOperand{buf[yi], pl.ldt};
+                    e = launch_apply(r, st);
+                }
+                if (e == hipSuccess) e = launch_hh_apply(HH_APPLY_ADD, hr, st);
+                end(pm);
+                ci = yi;
             }
-            if (e == hipSuccess) e = launch_hh_apply(HH_APPLY_ADD, hr, st);
-            end(pm);
             if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
-            cur = ca3;
+            cur = buf[ci];
+            zleaf = buf[(ci + 1) % 3];            // free now
         }
         for (int l = h->hh_red() ? -1 : pl.nlev - 1; l >= 0; --l) {
             double *out = (cur == ca) ? ca2 : ca;
@@ -1413,6 +1457,9 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             if (e != hipSuccess) { (void)hipGetLastError(); return ORTH_ERR_HIP; }
             cur = out;
         }
+        // under a tree the down-sweep may end in ca2: the leaves' -Z_i then
+        // goes to the third region
+        if (hh && !h->hh_red() && cur == ca2) zleaf = ca3;
         // leaves: Y_i = Q_i C_i; with Householder leaves Y_i = -V Z_i + E C_i,
         // Z_i = T (V[0:k]^T C_i)
         HhArgs ha{};
@@ -1422,7 +1469,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             ha.kmax = pl.kmax;
             ha.T = h->TH();
             ha.ca = cur;            // (one level: cur == ca)
-            ha.ca_out = ca2;
+            ha.ca_out = zleaf;
             ha.ldca = pl.ldt;
             ha.m = mb;
             ha.U = d_Y + (int64_t)j0 * ldy;
@@ -1436,7 +1483,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         a.Q = h->Qop();
         a.k = k;
         a.geom = leaf_geom(pl, kFinalChunk);
-        a.Cptr = hh ? ca2 : cur;
+        a.Cptr = hh ? zleaf : cur;
         a.ldc = pl.ldt;
         a.cseg = pl.kmax;
         a.m = mb;
@@ -1477,8 +1524,9 @@ int orth_apply_Q_noalloc(orth_t *h, const double *d_C, int64_t ldc, int32_t m, d
     // one column of coefficient blocks per region (two regions with
     // Householder leaves or a reduction tree, three with the Householder
     // reduction) must fit the static scratch
+    const bool hh_leaves = h->pl.precision == ORTH_FP64_HOUSEHOLDER;
     const int64_t regions =
-        h->hh_red() ? 3 : ((h->pl.precision == ORTH_FP64_HOUSEHOLDER || h->pl.nlev > 1) ? 2 : 1);
+        (h->hh_red() || (hh_leaves && h->pl.nlev > 1)) ? 3 : ((hh_leaves || h->pl.nlev > 1) ? 2 : 1);
     const int64_t cols = kStaticScratchDoubles / (regions * h->pl.ldt);
     if (cols < 1) return ORTH_ERR_SCRATCH;
     if (h->k < 1 || m < 1 || !d_C || !d_Y || ldc < h->k || ldy < h->pl.n) return ORTH_ERR_ARG;
@@ -1516,7 +1564,8 @@ int orth_set_deflation(orth_t *h, double delta) {
     if (!h) return ORTH_ERR_ARG;
     if (h->poisoned) return ORTH_ERR_POISONED;
     if (!(delta >= 0.0 && delta < 1.0)) return ORTH_ERR_ARG;      // NaN fails too
-    if (delta > 0.0 && (!h->DF() || h->hh_red())) return ORTH_ERR_UNSUPPORTED;
+    // deflation is defined for the single reduction level
+    if (delta > 0.0 && (!h->DF() || h->hh_red() || h->pl.nlev > 1)) return ORTH_ERR_UNSUPPORTED;
     h->defl_delta = delta;
     return ORTH_OK;
 }

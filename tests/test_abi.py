@@ -207,13 +207,16 @@ def test_autotune_batch_buckets(monkeypatch, tmp_path):
 
 def test_tree_workspace_arguments():
     """Reduction trees: fan-in 1 and negative fan-ins are refused, Householder
-    leaves keep the single level, a fan-in at or above the leaf count is the
+    leaves take trees too, a fan-in at or above the leaf count is the
     single level, and the upper levels add storage (host arithmetic only)."""
     one = orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 0)
     assert one == orth.orth_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64) > 0
     assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 1) == 0
     assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, -2) == 0
-    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64_HOUSEHOLDER, 2) == 0
+    # Householder leaves under a tree (their compact-WY factors and a third
+    # apply region on top)
+    assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64_HOUSEHOLDER, 2) > \
+        orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 2) > 0
     assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 20) == one
     assert orth.orth_tree_workspace_bytes(10000, 4, 16, 500, orth.ORTH_FP64, 2) > one
     assert orth.orth_tree_levels(None)[0] == orth.ORTH_ERR_ARG

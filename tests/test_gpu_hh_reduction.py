@@ -129,14 +129,75 @@ def test_householder_reduction_parity(torch_cuda, n, s, kmax, leaf_rows, leaves)
     gpu.close()
 
 
+TREE_CASES = [
+    # n, s, kmax, leaf_rows, fan_in, leaves
+    (20000, 4, 40, 500, 2, "hh"),        # 40 leaves, 6 levels, a node with one child
+    (30000, 8, 64, 1000, 4, "pip+"),     # ragged groups
+    (25000, 16, 48, 1000, 3, "hh"),      # s = 16: 25 -> 9 -> 3 -> 1
+    (2 ** 20, 8, 64, 4096, 16, "hh"),    # 256 leaves -> 16 -> 1
+    (24000, 8, 48, 1000, 5, "mixed"),    # the mixed form's leaves
+]
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf_rows,fan_in,leaves", TREE_CASES)
+def test_householder_tree_parity(torch_cuda, n, s, kmax, leaf_rows, fan_in, leaves):
+    """Householder at every node of a reduction tree against the oracle's
+    tree with the same leaves, fan-in and subalgorithms (after the sign
+    fix), the apply and the allocation-free apply."""
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("hh tree", n, s, kmax, leaf_rows, fan_in, leaves)
+    rng = np.random.default_rng(n + 3 * fan_in)
+    prec = {"hh": orth.ORTH_FP64_HOUSEHOLDER, "mixed": orth.ORTH_MIXED_SPLIT32}.get(leaves, orth.ORTH_FP64)
+    gpu = Orthogonalizer(n, s, kmax, leaf_rows, precision=prec, fan_in=fan_in,
+                         reduction_variant=orth.ORTH_HOUSEHOLDER)
+    tree = TreeTSPQR(n, s, leaf_rows, {"mixed": "pip+"}.get(leaves, leaves), "hh", fan_in)
+    assert gpu.levels == len(tree.levels) > 1
+    Q = np.zeros((n, 0))
+    Ugpu = []
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        Hd, Rd, Ud = gpu.step(to_dev(X))
+        Hraw, Rraw, Uraw = to_host(Hd), to_host(Rd), to_host(Ud)
+        H, R, U = _signfix(Hraw, Rraw, Uraw)
+        P, N, Ur = pqr_reference(Q, X)
+        Pt, Nt, Ut = _signfix(*tree.step(X))
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if step:
+            assert np.linalg.norm(H - P) / xn <= 1e-12, step
+            assert np.linalg.norm(H - Pt) / xn <= 1e-12 * kap, step
+        assert np.linalg.norm(R - N) / xn <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-12 * kap, step
+        assert np.linalg.norm(R - Nt) / xn <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ut)) <= 1e-12 * kap, step
+        Ugpu.append(Uraw)
+        Q = np.hstack([Q, Uraw])
+    st, info = gpu.status()
+    assert st == 0, info
+    V = np.hstack(Ugpu)
+    assert metrics.e_perp(V) <= 1e-12
+    C = rng.standard_normal((gpu.k, 19))
+    Cd = to_dev(C)
+    Y = to_host(gpu.apply_Q(Cd))
+    assert np.max(np.abs(Y - V @ C)) <= 1e-12 * np.abs(C).sum(0).max()
+    Y2 = torch.empty((19, n), dtype=torch.float64, device="cuda")
+    assert orth.orth_apply_Q_noalloc(gpu.h, Cd.data_ptr(), gpu.k, 19, Y2.data_ptr(), n) == 0
+    assert np.array_equal(to_host(Y2), Y)
+    gpu.close()
+
+
 def test_householder_reduction_refusals(torch_cuda):
     from paper_2204_13393_amd import Orthogonalizer, orth
     # the stacked problem past the panel kernel: 300 leaves x 32 rows > 8192 at s = 4
     g = Orthogonalizer(300 * 256, 4, 32, 256)
     assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
     g.close()
-    # a reduction tree
-    g = Orthogonalizer(8000, 4, 32, 500, fan_in=4)
+    # a reduction tree whose nodes are past the panel kernel (300 children x 32 rows)
+    g = Orthogonalizer(600 * 256, 4, 32, 256, fan_in=300)
+    assert g.levels == 2
     assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
     g.close()
     # s = 32, and the leaf variant may not be Householder
@@ -236,4 +297,29 @@ def test_householder_reduction_over_a_dirty_workspace(torch_cuda):
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
         assert np.all(np.isfinite(a))
+
+
+@pytest.mark.parametrize("level", [3, 5, 8])      # Householder leaves hold at most 8192 rows at s = 4
+def test_recursion_levels_table_householder_column(torch_cuda, stewart_1e4, level):
+    """The Householder column of the recursion-levels table (Sec. 6.1) on
+    the GPU: 2^level leaves, fan-in 2, Householder at the leaves and at every
+    node; e_perp and ||A - QR|| in [min / 10, 10 max] of the printed column."""
+    torch = torch_cuda
+    from paper_2204_13393_amd import Orthogonalizer, orth
+    _say("recursion householder", level)
+    A = stewart_1e4
+    n = A.shape[0]
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_stability_tables.json")))
+    gpu = Orthogonalizer(n, 4, 32, n // 2 ** level, precision=orth.ORTH_FP64_HOUSEHOLDER, fan_in=2,
+                         reduction_variant=orth.ORTH_HOUSEHOLDER)
+    assert gpu.levels == level
+    Q, R = _block_qr(gpu, A, torch)
+    e = metrics.e_perp(Q)
+    res = np.linalg.norm(A - Q @ R, "fro")
+    vals = [row[2] for row in gold["recursion_levels"].values()]
+    rvals = [row[5] for row in gold["recursion_levels"].values()]
+    assert min(vals) / 10 <= e <= max(vals) * 10, (level, e)
+    assert min(rvals) / 10 <= res <= max(rvals) * 10, (level, res)
+    print(f"[recursion] level {level} householder/householder: e_perp {e:.2e} ||A-QR|| {res:.2e}", flush=True)
+    gpu.close()
 

@@ -55,6 +55,7 @@ CASES = [
     (8192, 32, 96, 1024, 2, 0, "pip+"),     # s = 32, 8 -> 4 -> 2 -> 1
     (20000, 8, 48, 1000, 4, 1, "pip+"),     # mixed form under a tree
     (12000, 4, 32, 600, 3, 0, "pip"),       # BCGS-PIP at every reduction level
+    (24000, 8, 48, 1000, 3, 2, "pip+"),     # Householder leaves under a BCGS-PIP+ tree
 ]
 
 
@@ -80,7 +81,7 @@ def test_tree_parity(torch_cuda, n, s, kmax, leaf_rows, fan_in, precision, red):
     p = n // leaf_rows
     children = _levels_children(p, fan_in)
     assert gpu.levels == len(children) > 1 and gpu.fan_in == fan_in
-    tree = TreeTSPQR(n, s, leaf_rows, "pip+", red, fan_in)
+    tree = TreeTSPQR(n, s, leaf_rows, "hh" if precision == 2 else "pip+", red, fan_in)
     assert len(tree.levels) == gpu.levels
     tol = 1e-12 if (precision == 0 and red == "pip+") else 1e-10
     Q = np.zeros((n, 0))
