@@ -38,6 +38,7 @@ using namespace orth;
 namespace {
 
 constexpr int64_t kAlign = 32;        // doubles (256 bytes)
+constexpr int64_t kWideGrid = 256;    // workgroups per launch below which chunks shrink (one per CU)
 constexpr int kApplyMB = 16;
 
 // Scratch of orth_apply_Q_noalloc: the per-leaf coefficient blocks of one
@@ -115,6 +116,9 @@ struct Plan {
     bool qblk;                   // leaf bases stored leaf by leaf (ldl, ld_last)
     int64_t ldl, ld_last, qcount;
     int32_t nchunkL, nchunkR;
+    // chunk heights (rows per workgroup): leaf Gram, leaf row updates,
+    // reduction Gram, reduction row updates
+    int32_t cL, cF, cR, cRR;
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
     // Householder reduction (every node's stacked problem within one
@@ -195,10 +199,28 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         if (nodes == 1) break;
         count = nodes;
     }
+    // chunk heights: the defaults, halved (down to 128 rows for the Grams and
+    // 64 for the row updates) while a launch would have fewer workgroups than
+    // the chip has compute units -- a small problem is bound by each
+    // workgroup's serial walk over its rows, not by its bytes
+    {
+        auto shrink = [](int32_t c, int32_t cmin, auto count) {
+            while (c > cmin && count(c) < kWideGrid) c /= 2;
+            return c;
+        };
+        auto leaf_chunks = [&](int32_t c) { return (int64_t)make_leaf_geom(n, leaf_rows, pl.p, c).nchunks(); };
+        auto root_chunks = [&](int32_t c) { return ceil_div((int64_t)pl.p * kmax, c); };
+        // (a single leaf keeps its chunks: its many slots would go through
+        // the grouped pre-sums, which the batched form does not take)
+        pl.cL = pl.p > 1 ? shrink(kLeafChunk, 128, leaf_chunks) : kLeafChunk;
+        pl.cF = shrink(kFinalChunk, 64, leaf_chunks);
+        pl.cR = shrink(kRootChunk, 128, root_chunks);
+        pl.cRR = shrink(kRootRowChunk, 64, root_chunks);
+    }
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
-    const int64_t cpl = ceil_div(leaf_rows, kLeafChunk), cpl_last = ceil_div(last, kLeafChunk);
+    const int64_t cpl = ceil_div(leaf_rows, pl.cL), cpl_last = ceil_div(last, pl.cL);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
-    pl.nchunkR = (int32_t)ceil_div((int64_t)pl.p * kmax, kRootChunk);
+    pl.nchunkR = (int32_t)ceil_div((int64_t)pl.p * kmax, pl.cR);
     int64_t off = 0;
     auto take = [&](int64_t count) {
         const int64_t o = off;
@@ -217,17 +239,17 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     for (int32_t k = 0; k + s <= kmax; k += s) {
         const int32_t ncol = k + s;
         const int64_t per = (int64_t)gram_row_groups(ncol) * ncol * s;
-        int64_t nR = ceil_div((int64_t)pl.p * ncol, kRootChunk);
+        int64_t nR = ceil_div((int64_t)pl.p * ncol, pl.cR);
         for (int l = 0; l < pl.nlev; ++l) {
             nR = std::max(nR, (int64_t)make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in,
-                                                      kmax, ncol, kRootChunk).nchunks());
+                                                      kmax, ncol, pl.cR).nchunks());
             // the Householder reduction's levels run over the physical rows
-            nR = std::max(nR, (int64_t)hh_level_geom(pl, l, kRootChunk).nchunks());
+            nR = std::max(nR, (int64_t)hh_level_geom(pl, l, pl.cR).nchunks());
         }
         slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
         // pre-summed slot groups of a level with a single local problem: the
         // reduction level, and the leaf level when there is one leaf
-        const int64_t nroot = ceil_div((int64_t)pl.nchild[pl.nlev - 1] * ncol, kRootChunk);
+        const int64_t nroot = ceil_div((int64_t)pl.nchild[pl.nlev - 1] * ncol, pl.cR);
         const int64_t single = pl.p == 1 ? std::max((int64_t)pl.nchunkL, nroot) : nroot;
         red_max = std::max(red_max, ceil_div(single * gram_row_groups(ncol), kReduceGroup) * ncol * s);
     }
@@ -792,7 +814,7 @@ int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
     const int32_t s = pl.s, kmax = pl.kmax, ncol = k + s;
     hipStream_t st = h->stream;
     const int64_t pstride = (int64_t)ncol * s;
-    const LevelGeom gg = leaf_geom(pl, kLeafChunk);
+    const LevelGeom gg = leaf_geom(pl, pl.cL);
     const int rg = gram_row_groups(ncol);
     if ((int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
     hipError_t e;
@@ -840,7 +862,7 @@ int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
         f.U1 = Operand{d_W, ldw};
         f.sweep = 1;
         f.k = k;
-        f.geom = leaf_geom(pl, kFinalChunk);
+        f.geom = leaf_geom(pl, pl.cF);
         f.small = h->SL();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -886,7 +908,7 @@ int run_level_hh(orth_ctx *h, int l, int k, double *d_H, int64_t ldh, double *d_
     const bool root = l == pl.nlev - 1;
     hipStream_t st = h->stream;
     const int64_t pstride = (int64_t)ncol * s;
-    const LevelGeom gg = hh_level_geom(pl, l, kRootChunk);
+    const LevelGeom gg = hh_level_geom(pl, l, pl.cR);
     const int rg = gram_row_groups(ncol);
     if (!pl.hhtree || (int64_t)gg.nchunks() * rg * pstride > pl.slot_cap) return ORTH_ERR_HIP;
     const int64_t ld = pl.ldtl[l];
@@ -940,7 +962,7 @@ int run_level_hh(orth_ctx *h, int l, int k, double *d_H, int64_t ldh, double *d_
         f.U1 = Operand{h->Yl(l), ld};
         f.sweep = 1;
         f.k = k;
-        f.geom = hh_level_geom(pl, l, kRootRowChunk);
+        f.geom = hh_level_geom(pl, l, pl.cRR);
         f.small = h->Sl(l);
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -994,7 +1016,7 @@ int finalize_level_hh(orth_ctx *h, int l, int k) {
         if (e != hipSuccess) return ORTH_ERR_HIP;
     }
     HhArgs ha{};
-    ha.geom = hh_level_geom(pl, l, kRootRowChunk);
+    ha.geom = hh_level_geom(pl, l, pl.cRR);
     ha.k = k;
     ha.kmax = kmax;
     ha.Q = h->Tl(l);
@@ -1045,7 +1067,7 @@ int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
     const int32_t s = pl.s, kmax = pl.kmax;
     hipStream_t st = h->stream;
     HhArgs ha{};
-    ha.geom = leaf_geom(pl, kFinalChunk);
+    ha.geom = leaf_geom(pl, pl.cF);
     ha.k = k;
     ha.kmax = kmax;
     ha.Q = h->Q();
@@ -1068,7 +1090,7 @@ int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
     f.U1 = Operand{h->Q() + (int64_t)k * pl.ldq, pl.ldq};
     f.sweep = 2;
     f.k = k;
-    f.geom = leaf_geom(pl, kFinalChunk);
+    f.geom = leaf_geom(pl, pl.cF);
     f.small = h->SL();
     f.small_stride = small_stride(kmax, s);
     f.kmax = kmax;
@@ -1242,8 +1264,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.Q = h->Qop();
         L.X = Operand{d_W, ldw};
         L.U1 = OutOperand{h->U1L(), pl.ldq};
-        L.geom = leaf_geom(pl, kLeafChunk);
-        L.rgeom = leaf_geom(pl, kFinalChunk);
+        L.geom = leaf_geom(pl, pl.cL);
+        L.rgeom = leaf_geom(pl, pl.cF);
         L.Qhi = h->Qhi();
         L.pc = h->CL();
         L.part = h->PL();
@@ -1269,8 +1291,8 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         L.Q = Operand{h->Tl(l), pl.ldtl[l]};
         L.X = Operand{h->Yl(l), pl.ldtl[l]};
         L.U1 = OutOperand{h->U1l(l), pl.ldtl[l]};
-        L.geom = tree_geom(pl, l, ncol, kRootChunk);
-        L.rgeom = tree_geom(pl, l, ncol, kRootRowChunk);
+        L.geom = tree_geom(pl, l, ncol, pl.cR);
+        L.rgeom = tree_geom(pl, l, ncol, pl.cRR);
         L.part = h->PR();
         L.part2 = h->PR2();
         L.part_cap = pl.slot_cap;
@@ -1309,7 +1331,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.U1 = Operand{h->U1l(l), pl.ldtl[l]};
         f.sweep = 2;
         f.k = k;
-        f.geom = tree_geom(pl, l, ncol, kRootRowChunk);
+        f.geom = tree_geom(pl, l, ncol, pl.cRR);
         f.small = h->Sl(l);
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -1341,7 +1363,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.U1 = Operand{h->U1L(), pl.ldq};
         f.sweep = 2;
         f.k = k;
-        f.geom = leaf_geom(pl, kFinalChunk);
+        f.geom = leaf_geom(pl, pl.cF);
         f.small = h->SL();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -1402,7 +1424,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             for (int l = pl.nlev - 1; l >= 0 && e == hipSuccess; --l) {
                 const int zi = (ci + 1) % 3, yi = (ci + 2) % 3;
                 HhArgs hr{};
-                hr.geom = hh_level_geom(pl, l, kRootRowChunk);
+                hr.geom = hh_level_geom(pl, l, pl.cRR);
                 hr.k = k;
                 hr.kmax = pl.kmax;
                 hr.T = h->THl(l);
@@ -1439,7 +1461,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
             ApplyArgs r{};
             r.Q = Operand{h->Tl(l), pl.ldtl[l]};
             r.k = k;
-            r.geom = tree_geom(pl, l, k, kRootRowChunk);
+            r.geom = tree_geom(pl, l, k, pl.cRR);
             if (l == pl.nlev - 1) {
                 r.Cptr = d_C + (int64_t)j0 * ldc;
                 r.ldc = ldc;
@@ -1464,7 +1486,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         // Z_i = T (V[0:k]^T C_i)
         HhArgs ha{};
         if (hh) {
-            ha.geom = leaf_geom(pl, kFinalChunk);
+            ha.geom = leaf_geom(pl, pl.cF);
             ha.k = k;
             ha.kmax = pl.kmax;
             ha.T = h->TH();
@@ -1482,7 +1504,7 @@ int apply_q_impl(orth_ctx *h, const double *d_C, int64_t ldc, int32_t m, double 
         ApplyArgs a{};
         a.Q = h->Qop();
         a.k = k;
-        a.geom = leaf_geom(pl, kFinalChunk);
+        a.geom = leaf_geom(pl, pl.cF);
         a.Cptr = hh ? zleaf : cur;
         a.ldc = pl.ldt;
         a.cseg = pl.kmax;
@@ -1648,7 +1670,7 @@ int orth_export_local(orth_t *h, double *d_Qloc, int64_t ldq, double *d_T, int64
     if (d_T && ldt < (int64_t)pl.p * k) return ORTH_ERR_ARG;
     hipError_t e = hipSuccess;
     if (d_Qloc)
-        e = pl.qblk ? launch_copy_leafblk(h->Qop(), leaf_geom(pl, kLeafChunk), d_Qloc, ldq, k, h->stream)
+        e = pl.qblk ? launch_copy_leafblk(h->Qop(), leaf_geom(pl, pl.cL), d_Qloc, ldq, k, h->stream)
                     : launch_copy_cols(h->Q(), pl.ldq, RowMap{0, 0}, d_Qloc, ldq, pl.n, k, h->stream);
     if (e == hipSuccess && d_T)
         e = launch_copy_cols(h->T(), pl.ldt, RowMap{k, pl.kmax}, d_T, ldt, (int64_t)pl.p * k, k,
@@ -1860,6 +1882,8 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         d.kmax = pl.kmax;
         d.leaf_rows = pl.leaf_rows;
         d.p = pl.p;
+        d.cL = pl.cL;
+        d.cR = pl.cR;
         d.Q = base + pl.oQ;
         d.T = base + pl.oT;
         d.Y = base + pl.oY;

@@ -66,8 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.geom.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < k * S; e += kThreads) {
-        double v = 0.0;
-        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        const double v = slot_sum(a.partials + (int64_t)first * a.part_stride + e, a.part_stride, cnt);
         lds[e] = v;
     }
     __syncthreads();
@@ -241,8 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.geom.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < K * S; e += kThreads) {
-        double v = 0.0;
-        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        const double v = slot_sum(a.partials + (int64_t)first * a.part_stride + e, a.part_stride, cnt);
         W[e] = v;
     }
     for (int e = tid; e < S * S; e += kThreads) Ts[e] = (e / S == e % S) ? 2.0 : 0.0;

@@ -95,6 +95,23 @@ constexpr int kReduceGroup = 16;      // slots pre-summed per group at a single-
 
 __host__ __device__ inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Fixed-order sum p[0] + p[stride] + ... + p[(cnt-1) stride], added in slot
+// order; the loads are issued eight at a time so they are in flight
+// together (the additions, and so the bits, are those of the plain loop).
+__device__ __forceinline__ double slot_sum(const double *p, int64_t stride, int cnt) {
+    double v = 0.0;
+    int q = 0;
+    for (; q + 8 <= cnt; q += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; q < cnt; ++q) v += p[(int64_t)q * stride];
+    return v;
+}
+
 // leaves of leaf_rows rows (the last takes the remainder), identity rows
 __host__ __device__ inline LevelGeom make_leaf_geom(int64_t n, int32_t leaf_rows, int32_t p, int chunk) {
     LevelGeom g{};
@@ -380,6 +397,7 @@ hipError_t launch_hh_apply(HhKernel which, const HhArgs &a, hipStream_t st);
 struct BatchInst {
     int64_t n, ldq, ldt;
     int32_t s, kmax, leaf_rows, p;
+    int32_t cL, cR;           // Gram chunk heights of the leaves and the reduction (the plan's)
     double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR, *CL;
 };
 
@@ -412,7 +430,7 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
     switch (phase) {
         case BP_LGRAM:
         case BP_LGRAM2:
-            return make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk).nchunks() * gram_col_groups(ncol);
+            return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol);
         case BP_LCHOL1:
         case BP_LCHOL2:
             return d.p;
@@ -421,10 +439,10 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
             return make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk).nchunks();
         case BP_RGRAM:
         case BP_RGRAM2:
-            return make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_col_groups(ncol);
+            return make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_col_groups(ncol);
         case BP_RRED1:
         case BP_RRED2: {
-            const int32_t slots = make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_row_groups(ncol);
+            const int32_t slots = make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_row_groups(ncol);
             if (slots <= kReduceGroup) return 0;
             return (int32_t)(ceil_div64((int64_t)ncol * d.s, kThreads) * ceil_div64(slots, kReduceGroup));
         }

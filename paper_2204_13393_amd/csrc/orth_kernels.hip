@@ -415,8 +415,7 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int bx, int by)
     const int grp = by;
     const int s0 = grp * a.group;
     const int s1 = s0 + a.group < a.nslots ? s0 + a.group : a.nslots;
-    double v = 0.0;
-    for (int sl = s0; sl < s1; ++sl) v += a.in[(int64_t)sl * a.stride + e];
+    const double v = slot_sum(a.in + (int64_t)s0 * a.stride + e, a.stride, s1 - s0);
     a.out[(int64_t)grp * a.stride + e] = v;
 }
 
@@ -495,8 +494,7 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < ncol * S; e += kThreads) {
-        double v = 0.0;
-        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        const double v = slot_sum(a.partials + (int64_t)first * a.part_stride + e, a.part_stride, cnt);
         if (e < k * S) {
             recP[e] = v;
             if (a.pc && a.sweep == 2) a.pc[(int64_t)leaf * a.pc_stride + (int64_t)(e / S) * 2 * S + e % S] = v;
@@ -663,8 +661,7 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < ncol * S; e += kThreads) {
-        double v = 0.0;
-        for (int q = 0; q < cnt; ++q) v += a.partials[(int64_t)(first + q) * a.part_stride + e];
+        const double v = slot_sum(a.partials + (int64_t)first * a.part_stride + e, a.part_stride, cnt);
         if (e < k * S) {
             recP[e] = v;
             if (a.pc && a.sweep == 2) a.pc[(int64_t)leaf * a.pc_stride + (int64_t)(e / S) * 2 * S + e % S] = v;
@@ -1538,12 +1535,12 @@ __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int
     if (leaf) {
         g.Q = Operand{d.Q, d.ldq};
         g.X = a.phase == BP_LGRAM ? Operand{a.W[inst], d.n} : Operand{d.U1L, d.ldq};
-        g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk);
+        g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
         g.partials = d.PL;
     } else {
         g.Q = Operand{d.T, d.ldt};
         g.X = a.phase == BP_RGRAM ? Operand{d.Y, d.ldt} : Operand{d.U1R, d.ldt};
-        g.geom = make_root_geom(d.p, d.kmax, ncol, kRootChunk);
+        g.geom = make_root_geom(d.p, d.kmax, ncol, d.cR);
         g.partials = d.PR;
     }
     const int cg = gram_col_groups(ncol);
@@ -1567,7 +1564,7 @@ __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int
     c.status = a.status;
     const int rg = gram_row_groups(ncol);
     if (leaf) {
-        const LevelGeom gl = make_leaf_geom(d.n, d.leaf_rows, d.p, kLeafChunk);
+        const LevelGeom gl = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
         c.partials = d.PL;
         c.nleaf = d.p;
         c.slots_per_leaf = gl.cpl * rg;
@@ -1579,7 +1576,7 @@ __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int
         c.pc = d.CL;
         c.pc_stride = (int64_t)d.kmax * 2 * S;
     } else {
-        const LevelGeom gr = make_root_geom(d.p, d.kmax, ncol, kRootChunk);
+        const LevelGeom gr = make_root_geom(d.p, d.kmax, ncol, d.cR);
         const int slots = gr.nchunks() * rg;
         c.partials = slots > kReduceGroup ? d.PR2 : d.PR;
         c.nleaf = 1;
@@ -1596,7 +1593,7 @@ __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int
 
 __device__ void batch_reduce(const BatchArgs &a, const BatchInst &d, int local) {
     const int k = a.step * d.s, ncol = k + d.s;
-    const int slots = make_root_geom(d.p, d.kmax, ncol, kRootChunk).nchunks() * gram_row_groups(ncol);
+    const int slots = make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_row_groups(ncol);
     ReduceArgs r{};
     r.in = d.PR;
     r.stride = (int64_t)ncol * d.s;
