@@ -545,6 +545,23 @@ int orth_tune_leaf_rows(int64_t n, int32_t s, int32_t k_max, int32_t steps,
                         void *stream, int32_t *best_leaf_rows, int32_t *cand_rows,
                         double *cand_ms, int32_t max_cand, int32_t *ncand);
 
+/*
+ * orth_tune_tree_workspace_bytes / orth_tune_tree -- the reduction tree's
+ * fan-in for single handles (the recursion of Sec. 4.1; the tree fan-in
+ * entry of the tuner's search space).  For the given leaf height it times
+ * `steps` calls (the synthetic blocks of orth_tune_leaf_rows) through
+ * orth_create_tree handles of every candidate fan-in: 0 (the single
+ * reduction level), then 2, 4, 8, ... below the leaf count, and writes the
+ * fastest to *best_fan_in (the single level when it is within 2% of the
+ * fastest).  Synchronous.  Workspace, steps, cand_fan_in / cand_ms / ncand
+ * and errors as orth_tune_leaf_rows (ARG also for leaf_rows outside
+ * [k_max, n]); orth_tune_tree_workspace_bytes returns 0 for invalid sizes.
+ */
+size_t orth_tune_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows);
+int orth_tune_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t steps, void *d_workspace,
+                   size_t workspace_bytes, void *stream, int32_t *best_fan_in, int32_t *cand_fan_in,
+                   double *cand_ms, int32_t max_cand, int32_t *ncand);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,24 @@ def measure_leaf_rows(n, s, k_max, steps=None, copies=1, stream=None):
     return best, cand
 
 
+def measure_fan_in(n, s, k_max, leaf_rows, steps=None, stream=None):
+    """Run the library's fan-in tuner for single handles once:
+    (best fan-in, [(candidate, ms), ...]); 0 is the single reduction level."""
+    import torch
+    steps = steps or min(k_max // s, 32)
+    nbytes = orth.orth_tune_tree_workspace_bytes(n, s, k_max, leaf_rows)
+    if nbytes == 0:
+        raise orth.OrthError("orth_tune_tree_workspace_bytes", orth.ORTH_ERR_ARG)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    sp = (stream or torch.cuda.current_stream()).cuda_stream
+    code, best, cand = orth.orth_tune_tree(n, s, k_max, leaf_rows, steps, base, nbytes, sp)
+    del ws
+    if code != orth.ORTH_OK:
+        raise orth.OrthError("orth_tune_tree", code)
+    return best, cand
+
+
 def tune_leaf_rows(n, s, k_max, steps=None, copies=1, cache=None, stream=None):
     """Measured leaf height for one shape, cached per device and shape."""
     import torch

@@ -2145,9 +2145,112 @@ int tune_one(int64_t n, int32_t s, int32_t kmax, int32_t lr, int32_t steps, int3
     return status == ORTH_OK ? ORTH_OK : ORTH_ERR_BREAKDOWN;
 }
 
+// fan-in candidates for a handle of p leaves: the single level (0), then
+// 2, 4, 8, ... below p
+std::vector<int32_t> tune_fan_ins(int32_t p) {
+    std::vector<int32_t> c{0};
+    for (int32_t g = 2; g < p; g *= 2) c.push_back(g);
+    return c;
+}
+
+// regions of the fan-in search: [handle workspace][W][U][H][R] (doubles)
+bool tune_tree_layout(int64_t n, int32_t s, int32_t kmax, int32_t lr, TuneLayout &L) {
+    Plan pl;
+    int why;
+    if (!make_plan(n, s, kmax, lr, ORTH_FP64, pl, &why, 0, true)) return false;
+    for (int32_t g : tune_fan_ins(pl.p)) {
+        Plan pg;
+        if (!make_plan(n, s, kmax, lr, ORTH_FP64, pg, &why, g, true)) return false;
+        L.head = std::max(L.head, round_up(pg.total, kAlign));
+    }
+    L.oW = L.head;
+    L.oU = L.oW + round_up(n * s, kAlign);
+    L.oH = L.oU + round_up(n * s, kAlign);
+    L.oR = L.oH + round_up((int64_t)kmax * s, kAlign);
+    L.total = L.oR + round_up((int64_t)s * s, kAlign);
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t orth_tune_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows) {
+    TuneLayout L;
+    if (leaf_rows < 1 || !tune_tree_layout(n, s, k_max, leaf_rows, L)) return 0;
+    return (size_t)L.total * sizeof(double);
+}
+
+int orth_tune_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t steps, void *d_workspace,
+                   size_t workspace_bytes, void *stream, int32_t *best_fan_in, int32_t *cand_fan_in,
+                   double *cand_ms, int32_t max_cand, int32_t *ncand) {
+    if (!best_fan_in || (max_cand > 0 && (!cand_fan_in || !cand_ms))) return ORTH_ERR_ARG;
+    TuneLayout L;
+    if (leaf_rows < 1 || !tune_tree_layout(n, s, k_max, leaf_rows, L)) return ORTH_ERR_ARG;
+    if (steps < 1 || steps > k_max / s) return ORTH_ERR_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 || workspace_bytes < (size_t)L.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    const int32_t p = (int32_t)std::max<int64_t>(1, n / leaf_rows);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *ws = static_cast<double *>(d_workspace);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    const std::vector<int32_t> cand = tune_fan_ins(p);
+    std::vector<double> times(cand.size(), -1.0);
+    double *W = ws + L.oW, *U = ws + L.oU, *H = ws + L.oH, *R = ws + L.oR;
+    int rc = ORTH_OK;
+    for (size_t c = 0; c < cand.size() && rc == ORTH_OK; ++c) {
+        orth_t *h = nullptr;
+        rc = orth_create_tree(n, s, k_max, leaf_rows, ORTH_FP64, cand[c], ws, (size_t)L.head * sizeof(double), st,
+                              &h);
+        if (rc != ORTH_OK) break;
+        double total = 0.0;
+        for (int32_t j = 0; j < steps && rc == ORTH_OK; ++j) {
+            float ms = 0.0f;
+            if (launch_synth(W, n, n, s, (uint64_t)j + 1, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                rc = ORTH_ERR_HIP;
+                break;
+            }
+            rc = orth_step(h, W, n, H, k_max, R, s, U, n);
+            if (rc == ORTH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = ORTH_ERR_HIP;
+            total += ms;
+        }
+        int32_t status = ORTH_OK;
+        if (rc == ORTH_OK) rc = orth_status(h, &status, nullptr);
+        (void)orth_destroy(h);
+        if (rc == ORTH_OK && status == ORTH_OK) times[c] = total;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ORTH_OK) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    // the fastest; the single level (the simplest) wins ties within 2%
+    double fastest = -1.0;
+    size_t best = 0;
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (times[c] >= 0.0 && (fastest < 0.0 || times[c] < fastest)) {
+            fastest = times[c];
+            best = c;
+        }
+    if (fastest < 0.0) return ORTH_ERR_BREAKDOWN;
+    if (times[0] >= 0.0 && times[0] <= 1.02 * fastest) best = 0;
+    *best_fan_in = cand[best];
+    for (size_t c = 0; c < cand.size() && (int32_t)c < max_cand; ++c) {
+        cand_fan_in[c] = cand[c];
+        cand_ms[c] = times[c];
+    }
+    if (ncand) *ncand = (int32_t)cand.size();
+    return ORTH_OK;
+}
 
 size_t orth_tune_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t copies) {
     TuneLayout L;

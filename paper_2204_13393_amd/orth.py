@@ -45,6 +45,10 @@ SIGNATURES = [
     ("orth_tree_levels", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_export_tree_level", ctypes.c_int, [_vp, _i32, _dp, _i64]),
     ("orth_flat_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_tune_tree_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_tune_tree", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double), _i32,
+                                      ctypes.POINTER(_i32)]),
     ("orth_create_flat", ctypes.c_int, [_i64, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     ("orth_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_set_level_variants", ctypes.c_int, [_vp, _i32, _i32]),
@@ -154,6 +158,21 @@ def orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stre
     code = load().orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stream,
                                    ctypes.byref(h))
     return code, h
+
+
+def orth_tune_tree_workspace_bytes(n, s, k_max, leaf_rows):
+    return load().orth_tune_tree_workspace_bytes(n, s, k_max, leaf_rows)
+
+
+def orth_tune_tree(n, s, k_max, leaf_rows, steps, d_workspace, workspace_bytes, stream, max_cand=16):
+    """(code, best fan-in, [(fan_in, ms), ...])"""
+    best = ctypes.c_int32()
+    fans = (ctypes.c_int32 * max(max_cand, 1))()
+    ms = (ctypes.c_double * max(max_cand, 1))()
+    nc = ctypes.c_int32()
+    code = load().orth_tune_tree(n, s, k_max, leaf_rows, steps, d_workspace, workspace_bytes, stream,
+                                 ctypes.byref(best), fans, ms, max_cand, ctypes.byref(nc))
+    return code, best.value, [(fans[i], ms[i]) for i in range(min(nc.value, max_cand))]
 
 
 def orth_set_variant(h, variant):

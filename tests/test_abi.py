@@ -261,3 +261,18 @@ def test_variant_constants_match_the_header():
         assert m and int(m.group(1)) == getattr(orth, name), name
     assert orth.orth_set_level_variants(None, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_ARG
     assert orth.orth_set_level_variants(None, orth.ORTH_HOUSEHOLDER, orth.ORTH_PIP_PLUS) == orth.ORTH_ERR_ARG
+
+
+def test_tune_tree_workspace_arguments():
+    """The fan-in tuner's workspace holds the largest candidate handle plus
+    one block of W, U, H, R; invalid sizes give 0 and ARG (host only)."""
+    n, s, kmax, lr = 1 << 16, 8, 64, 1024
+    ws = orth.orth_tune_tree_workspace_bytes(n, s, kmax, lr)
+    assert ws >= orth.orth_tree_workspace_bytes(n, s, kmax, lr, orth.ORTH_FP64, 2) + 2 * 8 * n * s
+    assert orth.orth_tune_tree_workspace_bytes(n, s, kmax, 0) == 0
+    assert orth.orth_tune_tree_workspace_bytes(n, s, kmax, kmax - 1) == 0
+    assert orth.orth_tune_tree_workspace_bytes(n, 3, kmax, lr) == 0
+    code, best, cand = orth.orth_tune_tree(n, s, kmax, lr, 2, 0, 0, None)
+    assert code == orth.ORTH_ERR_WORKSPACE
+    code, best, cand = orth.orth_tune_tree(n, s, kmax, lr, 0, 256, ws, None)
+    assert code == orth.ORTH_ERR_ARG

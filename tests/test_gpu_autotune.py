@@ -82,3 +82,25 @@ def test_tuner_cache_and_tuned_handle(torch_cuda, tmp_path):
         Q = np.hstack([Q, Ur])
     assert g.status()[0] == 0
     g.close()
+
+
+def test_fan_in_tuner(torch_cuda):
+    """The fan-in tuner times the single level and every power-of-two fan-in
+    below the leaf count, returns the fastest (the single level within 2%),
+    and a handle with the chosen tree solves the problem."""
+    from paper_2204_13393_amd import Orthogonalizer, autotune
+    _say("tune fan-in")
+    n, s, k_max, lr = 1 << 20, 8, 64, 4096
+    best, cand = autotune.measure_fan_in(n, s, k_max, lr, steps=4)
+    assert [g for g, _ in cand] == [0, 2, 4, 8, 16, 32, 64, 128]
+    assert all(ms > 0 for _, ms in cand)
+    times = dict(cand)
+    fastest = min(times.values())
+    assert times[best] == fastest or (best == 0 and times[0] <= 1.02 * fastest)
+    print(f"[fan-in] {cand} -> {best}", flush=True)
+    g = Orthogonalizer(n, s, k_max, lr, fan_in=best)
+    X = np.random.default_rng(3).standard_normal((n, s))
+    H, R, U = g.step(to_dev(X))
+    P, N, Ur = pqr_reference(np.zeros((n, 0)), X)
+    assert np.linalg.norm(to_host(R) - N) / np.linalg.norm(X) <= 1e-12
+    g.close()
