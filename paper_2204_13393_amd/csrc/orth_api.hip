@@ -217,6 +217,11 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         pl.cR = shrink(kRootChunk, 128, root_chunks);
         pl.cRR = shrink(kRootRowChunk, 64, root_chunks);
     }
+    // the Householder reduction is offered when every node's stacked problem
+    // (its children's k_max physical rows each) fits the panel kernel
+    pl.hhtree = s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)kmax * s <= kHhMaxCoef;
+    for (int l = 0; l < pl.nlev && pl.hhtree; ++l)
+        pl.hhtree = (int64_t)hh_node_children(pl, l) * kmax <= hh_max_leaf_rows(s);
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
     const int64_t cpl = ceil_div(leaf_rows, pl.cL), cpl_last = ceil_div(last, pl.cL);
     pl.nchunkL = (int32_t)((pl.p - 1) * cpl + cpl_last);
@@ -244,7 +249,7 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
             nR = std::max(nR, (int64_t)make_tree_geom(pl.nchild[l], pl.fan_in == 0 ? pl.nchild[l] : pl.fan_in,
                                                       kmax, ncol, pl.cR).nchunks());
             // the Householder reduction's levels run over the physical rows
-            nR = std::max(nR, (int64_t)hh_level_geom(pl, l, pl.cR).nchunks());
+            if (pl.hhtree) nR = std::max(nR, (int64_t)hh_level_geom(pl, l, pl.cR).nchunks());
         }
         slot_max = std::max(slot_max, std::max((int64_t)pl.nchunkL, nR) * per);
         // pre-summed slot groups of a level with a single local problem: the
@@ -268,11 +273,6 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     // Householder leaves: per leaf the compact-WY factor (column- and
     // row-major) and the reflectors' top rows (row-major), k_max x k_max each
     pl.oTH = precision == ORTH_FP64_HOUSEHOLDER ? take((int64_t)3 * pl.p * kmax * kmax) : 0;
-    // the Householder reduction is offered when every node's stacked problem
-    // (its children's k_max physical rows each) fits the panel kernel
-    pl.hhtree = s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)kmax * s <= kHhMaxCoef;
-    for (int l = 0; l < pl.nlev && pl.hhtree; ++l)
-        pl.hhtree = (int64_t)hh_node_children(pl, l) * kmax <= hh_max_leaf_rows(s);
     // and orth_apply_Q's second coefficient scratch (-Z_i, or the tree's
     // down-sweep in turn with CA), like CA
     pl.oCA2 = (precision == ORTH_FP64_HOUSEHOLDER || pl.nlev > 1 || pl.hhtree) ? take(pl.ldt * kApplyMB) : 0;
