@@ -276,3 +276,15 @@ def test_tune_tree_workspace_arguments():
     assert code == orth.ORTH_ERR_WORKSPACE
     code, best, cand = orth.orth_tune_tree(n, s, kmax, lr, 0, 256, ws, None)
     assert code == orth.ORTH_ERR_ARG
+
+
+def test_large_plan_sizes_are_sane():
+    """Plans far past one GPU's memory still size consistently (64-bit row
+    counts throughout): the workspace holds at least the leaf bases and stays
+    within a small multiple of them (host arithmetic only)."""
+    n, s, kmax = 1 << 34, 8, 248
+    for lr in (kmax, 4096, 1 << 16):
+        b = orth.orth_workspace_bytes(n, s, kmax, lr, orth.ORTH_FP64)
+        assert 8 * n * kmax <= b <= 4 * 8 * n * kmax, (lr, b)
+        t = orth.orth_tree_workspace_bytes(n, s, kmax, lr, orth.ORTH_FP64, 16)
+        assert b <= t <= 4 * 8 * n * kmax, (lr, t)
