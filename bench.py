@@ -185,8 +185,9 @@ def bench_batched(args):
     """Batched form: all instances advance together, one grouped launch per
     phase; closed-loop Arnoldi with the stencil between steps.  Reports the
     orthogonalisation time (HIP events around every batch step, stencils
-    excluded), the same run replayed from one captured hipGraph, and the
-    same instances run one after another through single handles."""
+    excluded), the same run in the mixed form, the same run replayed from
+    one captured hipGraph, and the same instances run one after another
+    through single handles."""
     import torch
     from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, autotune, orth
     inst = batched_workload()
@@ -238,15 +239,16 @@ def bench_batched(args):
                 evs.append((e0, e1))
         return evs
 
-    def eager_runs(leaf_rows):
+    def eager_runs(leaf_rows, precision=orth.ORTH_FP64):
+        falls = 0
         with torch.cuda.stream(stream):
-            bb = BatchOrthogonalizer(ns, ss, ks, leaf_rows, stream=stream)
+            bb = BatchOrthogonalizer(ns, ss, ks, leaf_rows, stream=stream, precision=precision)
             bptrs = (bb.pointer_array(W), bb.pointer_array(U), bb.pointer_array(H))
             base, nbytes = (bb.workspace.data_ptr() + 255) // 256 * 256, bb.workspace.numel() * 8 - 256
             bb.close()
             times = []
             for rep in range(args.warmup + args.steps):
-                code, h = orth.orth_batch_create(ns, ss, ks, leaf_rows, orth.ORTH_FP64, base, nbytes, sp)
+                code, h = orth.orth_batch_create(ns, ss, ks, leaf_rows, precision, base, nbytes, sp)
                 if code:
                     raise orth.OrthError("orth_batch_create", code)
                 bb.h = h
@@ -255,10 +257,12 @@ def bench_batched(args):
                 st, info = bb.status()
                 if st:
                     raise RuntimeError(f"batched breakdown {info}")
+                falls = max(falls, bb.mixed_fallbacks())
                 if evs:
                     times.append(sum(e0.elapsed_time(e1) for e0, e1 in evs))
                 orth.orth_batch_destroy(h)
                 bb.h = None
+        bb.fallbacks = falls
         return bb, bptrs, base, nbytes, times
 
     b, _, _, _, default_runs = eager_runs(None)
@@ -306,6 +310,14 @@ def bench_batched(args):
     del b, g, gs
     torch.cuda.empty_cache()
 
+    # the mixed form (FP32 copies of the leaf bases read by the first leaf
+    # Gram) on the same instances and leaf heights
+    print("[bench] batched mixed form", file=sys.stderr, flush=True)
+    bm, _, _, _, mixed_runs = eager_runs(tuned, orth.ORTH_MIXED_SPLIT32)
+    mixed_falls = bm.fallbacks
+    del bm
+    torch.cuda.empty_cache()
+
     # the same instances through single handles, one after another
     print("[bench] single handles, sequential", file=sys.stderr, flush=True)
     single = []
@@ -347,6 +359,9 @@ def bench_batched(args):
         "ms_per_run_batched_default_leaf": min(default_runs),
         "leaf_rows": {"source": "autotuned", "tuning_s": tune_s, "buckets": buckets, "histogram": hist,
                       "default_histogram": {str(v): default_leaf.count(v) for v in sorted(set(default_leaf))}},
+        "ms_per_run_batched_mixed": min(mixed_runs),
+        "mixed_speedup": best / min(mixed_runs),
+        "mixed_fallbacks": mixed_falls,
         "ms_per_run_graph": min(graph_ms),
         "graph_note": "one hipGraph of the whole run minus a graph of its stencils alone",
         "ms_per_run_single_sequential": t_single,

@@ -92,9 +92,10 @@ enum orth_code {
  *                       the step redoes its first sweep in FP64 from the
  *                       FP64 bases on the device (no host synchronisation;
  *                       counted by orth_mixed_fallbacks), so the mixed form
- *                       breaks down only where the FP64 form does.  Single
- *                       handles only: orth_batch_create returns
- *                       UNSUPPORTED.
+ *                       breaks down only where the FP64 form does.  Also
+ *                       for batches: each instance keeps its own copy and
+ *                       redoes only its own first sweep (counted by
+ *                       orth_batch_mixed_fallbacks).
  *   ORTH_FP64_HOUSEHOLDER  the leaves run the Householder method (Sec. 2.2,
  *                       Algorithm "HH") instead of BCGS-PIP+: each leaf basis
  *                       is held as unit reflectors (column c zero above leaf
@@ -446,7 +447,8 @@ typedef struct orth_batch_ctx orth_batch_t;
  * of `count` entries: n[i], s[i], k_max[i] as for orth_workspace_bytes;
  * leaf_rows may be NULL (default height for every instance) or hold 0 for
  * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  precision
- * must be ORTH_FP64.  Returns 0 for invalid arguments.
+ * ORTH_FP64 or ORTH_MIXED_SPLIT32, for every instance (Householder leaves
+ * are single-handle only).  Returns 0 for invalid or unsupported arguments.
  */
 size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t *s,
                                   const int32_t *k_max, const int32_t *leaf_rows,
@@ -494,6 +496,15 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
  * breakdown.  After a breakdown the batch is poisoned.  Errors: ARG, HIP.
  */
 int orth_batch_status(orth_batch_t *b, int32_t *status, int32_t *info);
+
+/*
+ * orth_batch_mixed_fallbacks -- (the mixed form; the reiteration of Sec. 3.1
+ * restores accuracy only where the first sweep did not break down)
+ * synchronise the batch's stream and read how many (instance, step) pairs
+ * redid their first CholeskyQR sweep from the FP64 bases (0 for an FP64
+ * batch).  Errors: ARG, HIP.
+ */
+int orth_batch_mixed_fallbacks(orth_batch_t *b, int64_t *count);
 
 /* orth_batch_progress -- steps taken and the number of steps the batch
  * allows (host state; resource management, no passage). */

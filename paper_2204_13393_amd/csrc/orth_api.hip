@@ -684,6 +684,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     ga.part_stride = pstride;
     ga.status = h->status();
     ga.clear_retry = L.Qhi ? 1 : 0;
+    ga.retry = &h->status()->retry;
     {
         const int pm = h->begin(cls0 + 0);
         e = launch_gram(s, ga, cls0 + 0, st);
@@ -710,6 +711,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     c.pc = L.pc;
     c.pc_stride = (int64_t)kmax * 2 * s;
     c.status = h->status();
+    c.retry = &h->status()->retry;
 
     // sum the slots of each leaf; pre-reduce when a single leaf owns many
     auto chol = [&](int sweep, int ppc, int cls, bool soft, bool cond) -> int {
@@ -731,6 +733,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
             r.out = L.part2;
             r.status = h->status();
             r.cond = cond ? 1 : 0;
+            r.retry = &h->status()->retry;
             const int pm = h->begin(cls);
             e = launch_reduce(r, st);
             h->end(pm);
@@ -1783,17 +1786,20 @@ struct BatchLayout {
     std::vector<int32_t> widths;        // distinct block widths, ascending
     std::vector<Plan> plans;
     std::vector<int64_t> inst_off;      // doubles, per instance region
-    int64_t o_desc = 0, o_prefix = 0, o_status = 0, total = 0;   // doubles
+    int32_t precision = ORTH_FP64;
+    int64_t o_desc = 0, o_prefix = 0, o_status = 0, o_retry = 0, total = 0;   // doubles
 };
 
 bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const int32_t *k_max,
                        const int32_t *leaf_rows, int32_t precision, BatchLayout &L, int *why) {
     *why = ORTH_ERR_ARG;
     if (count < 1 || count > (1 << 20) || !n || !s || !k_max) return false;
-    if (precision != ORTH_FP64) {
-        *why = ORTH_ERR_UNSUPPORTED;   // the batched kernels keep FP64 bases only
+    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32) {
+        // Householder leaves are single-handle only
+        *why = precision == ORTH_FP64_HOUSEHOLDER ? ORTH_ERR_UNSUPPORTED : ORTH_ERR_ARG;
         return false;
     }
+    L.precision = precision;
     L.count = count;
     L.plans.resize(count);
     L.inst_off.resize(count);
@@ -1814,6 +1820,7 @@ bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const 
     L.o_desc = take(ceil_div((int64_t)count * sizeof(BatchInst), 8));
     L.o_prefix = take(ceil_div((int64_t)L.steps_max * BP_COUNT * (int64_t)L.widths.size() * (count + 1) * 4, 8));
     L.o_status = take(ceil_div(sizeof(DevStatus), 8));
+    L.o_retry = take(ceil_div((int64_t)count * 4, 8));      // per-instance retry flags (mixed form)
     for (int32_t i = 0; i < count; ++i) L.inst_off[i] = take(L.plans[i].total);
     L.total = off;
     return true;
@@ -1895,6 +1902,8 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         d.SL = base + pl.oSL;
         d.SR = base + pl.oSR;
         d.CL = base + pl.oCL;
+        d.Qhi = pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(base + pl.oQH) : nullptr;
+        d.retry = reinterpret_cast<int32_t *>(b->ws + L.o_retry) + i;
     }
     // block prefix tables of every (step, phase, width)
     const size_t nw = L.widths.size();
@@ -1929,6 +1938,7 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(b->status()),
                             (int64_t)(sizeof(DevStatus) / sizeof(int32_t)), 0, b->stream);
+    if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(b->ws + L.o_retry), count, 0, b->stream);
     // the host copies above read b->desc / b->prefix; finish before returning
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
@@ -1958,6 +1968,7 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
     a.count = count;
     a.step = b->step;
     a.two = b->variant == ORTH_PIP_PLUS ? 1 : 0;
+    a.mixed = b->L.precision == ORTH_MIXED_SPLIT32 ? 1 : 0;
     a.W = d_W;
     a.U = d_U;
     a.Hess = d_Hess;
@@ -2001,6 +2012,18 @@ int orth_batch_status(orth_batch_t *b, int32_t *status, int32_t *info) {
         info[3] = ds.sweep;
         info[4] = ds.column;
     }
+    return ORTH_OK;
+}
+
+int orth_batch_mixed_fallbacks(orth_batch_t *b, int64_t *count) {
+    if (!b || !count) return ORTH_ERR_ARG;
+    DevStatus ds{};
+    if (hipStreamSynchronize(b->stream) != hipSuccess ||
+        hipMemcpy(&ds, b->status(), sizeof(ds), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    *count = ds.fallbacks;
     return ORTH_OK;
 }
 

@@ -253,8 +253,9 @@ struct GramArgs {
     double *partials;     // slot (chunk * row_groups + rg): [k + s][s]
     int64_t part_stride;  // doubles per slot
     DevStatus *status;
-    int32_t cond;         // 1: run only when status->retry is set (the mixed form's fallback)
-    int32_t clear_retry;  // 1: the first thread clears status->retry (the step's first Gram)
+    int32_t cond;         // 1: run only when *retry is set (the mixed form's fallback)
+    int32_t clear_retry;  // 1: the first thread clears *retry (the step's first Gram)
+    int32_t *retry;       // mixed form's retry flag: &status->retry, or a batch instance's own
 };
 
 // fixed-order pre-reduction of many partial slots of one leaf:
@@ -267,7 +268,8 @@ struct ReduceArgs {
     int32_t nentries;
     double *out;
     const DevStatus *status;
-    int32_t cond;         // 1: run only when status->retry is set
+    int32_t cond;         // 1: run only when *retry is set
+    const int32_t *retry;
 };
 
 // per-leaf Cholesky of one sweep (and the combination after sweep 2)
@@ -299,8 +301,9 @@ struct CholArgs {
     // the per-leaf coefficient record [c][2s] (nullptr: not needed)
     double *pc;
     int64_t pc_stride;        // doubles per leaf record
-    int32_t soft;             // 1: a failed pivot sets status->retry instead of the breakdown
-    int32_t cond;             // 1: run only when status->retry is set
+    int32_t soft;             // 1: a failed pivot sets *retry instead of the breakdown
+    int32_t cond;             // 1: run only when *retry is set
+    int32_t *retry;           // as GramArgs::retry
 };
 
 // row update: sweep 1: u1 = (x - q P1) N1^{-1} (U1 = x in, Qnew = u1 out);
@@ -399,11 +402,15 @@ struct BatchInst {
     int32_t s, kmax, leaf_rows, p;
     int32_t cL, cR;           // Gram chunk heights of the leaves and the reduction (the plan's)
     double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR, *CL;
+    float *Qhi;               // mixed form: FP32 copy of Q (same layout, floats); nullptr for FP64
+    int32_t *retry;           // mixed form: this instance's retry flag
 };
 
 // phases of one orth_batch_step, in stream order
 enum BatchPhase {
-    BP_LGRAM = 0, BP_LCHOL1, BP_LCORR, BP_LGRAM2, BP_LCHOL2,
+    BP_LGRAM = 0, BP_LCHOL1,
+    BP_LGRAMF, BP_LCHOLF,     // mixed form: the first sweep redone from the FP64 basis when flagged
+    BP_LCORR, BP_LGRAM2, BP_LCHOL2,
     BP_RGRAM, BP_RRED1, BP_RCHOL1, BP_RCORR, BP_RGRAM2, BP_RRED2, BP_RCHOL2,
     BP_RFIN, BP_LFIN, BP_COUNT
 };
@@ -415,6 +422,7 @@ struct BatchArgs {
     int32_t step;             // call index: instance i works at k = step * s_i
     int32_t phase;
     int32_t two;              // 1: BCGS-PIP+ (two sweeps), 0: BCGS-PIP
+    int32_t mixed;            // 1: the instances keep FP32 copies (the first leaf Gram reads them)
     const double *const *W;   // device array: instance i's W (n_i x s_i, ld n_i)
     double *const *U;         // device array: explicit new blocks
     double *const *Hess;      // device array: K_i x K_i column-major, block `step` gets [H; R]
@@ -428,9 +436,15 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
                         phase == BP_RRED2 || phase == BP_RCHOL2;
     if (second && !two) return 0;
     switch (phase) {
+        case BP_LGRAMF:
+            if (!d.Qhi) return 0;
+            [[fallthrough]];
         case BP_LGRAM:
         case BP_LGRAM2:
             return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol);
+        case BP_LCHOLF:
+            if (!d.Qhi) return 0;
+            [[fallthrough]];
         case BP_LCHOL1:
         case BP_LCHOL2:
             return d.p;

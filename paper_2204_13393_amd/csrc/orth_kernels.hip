@@ -127,7 +127,7 @@ __host__ __device__ constexpr int gram_rpl() { return 8; }
 // Those entries are taken as zeros without being read.
 template <int S, bool TZ = false>
 __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
-    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
+    if (failed(a.status) || (a.cond && *a.retry == 0)) return;
     constexpr int NT = (S + 15) / 16;
     constexpr int RPL = gram_rpl<S>();
     constexpr int MS = 4 * RPL;                 // rows per macro-step
@@ -292,7 +292,7 @@ __device__ __forceinline__ void load_run_f(const double *p, float (&v)[R]) {
 
 template <int S>
 __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by) {
-    if (a.clear_retry && bx == 0 && by == 0 && threadIdx.x == 0) a.status->retry = 0;
+    if (a.clear_retry && bx == 0 && by == 0 && threadIdx.x == 0) *a.retry = 0;
     if (failed(a.status)) return;
     constexpr int NT = (S + 15) / 16;
     constexpr int RPL = 16;                    // 64 contiguous bytes of the copy per lane and column
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_hi(GramArgs a) {
 // ---------------------------------------------------------------- reduce
 // Fixed-order pre-sum of groups of partial slots (one thread per entry).
 __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int bx, int by) {
-    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
+    if (failed(a.status) || (a.cond && *a.retry == 0)) return;
     const int e = bx * kThreads + threadIdx.x;
     if (e >= a.nentries) return;
     const int grp = by;
@@ -434,7 +434,7 @@ constexpr int kCholCB = 64;   // P rows per LDS chunk
 // flagged for the FP64 redo of that sweep instead.
 __device__ __forceinline__ void chol_fail(const CholArgs &a, int leaf, int column) {
     if (a.soft) {
-        a.status->retry = 1;
+        *a.retry = 1;
         return;
     }
     if (atomicCAS(&a.status->code, 0, 3) == 0) {
@@ -471,7 +471,7 @@ template <int S>
 __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
     static_assert(S == 16 || S == 32, "wide blocks only");
     constexpr int NT = S / 16;
-    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
+    if (failed(a.status) || (a.cond && *a.retry == 0)) return;
     extern __shared__ double lds[];
     double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
     double *part = n1 + S * S;                                // 4 x S x S partial sums of P^T P
@@ -572,7 +572,7 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
         if (tid == 0) chol_fail(a, leaf, bad - 1);
         return;
     }
-    if (a.cond && leaf == 0 && tid == 0) a.status->fallbacks += 1;
+    if (a.cond && leaf == 0 && tid == 0) atomicAdd(&a.status->fallbacks, 1);
     if (wave == 0 && lane < S) {
         // back substitution N x = e_j, x[l] = 0 past j; the rows of N are read
         // by every lane at once (LDS broadcast)
@@ -639,7 +639,7 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
 
 template <int S>
 __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
-    if (failed(a.status) || (a.cond && a.status->retry == 0)) return;
+    if (failed(a.status) || (a.cond && *a.retry == 0)) return;
     constexpr int EPT = (S * S + kThreads - 1) / kThreads;   // S x S entries per thread
     extern __shared__ double lds[];
     double *gs = lds, *sm = gs + S * S, *nm = sm + S * S, *ni = nm + S * S, *n1 = ni + S * S;
@@ -721,7 +721,7 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
         if (tid == 0) chol_fail(a, leaf, bad - 1);
         return;
     }
-    if (a.cond && leaf == 0 && tid == 0) a.status->fallbacks += 1;
+    if (a.cond && leaf == 0 && tid == 0) atomicAdd(&a.status->fallbacks, 1);
     // 4. N^{-1}, lane j owns column j
     if (tid < S) {
         const int j = tid;
@@ -1526,7 +1526,7 @@ __device__ __forceinline__ int64_t hess_offset(const BatchInst &d, int step) {
 template <int S>
 __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int local) {
     const int k = a.step * S, ncol = k + S;
-    const bool leaf = a.phase == BP_LGRAM || a.phase == BP_LGRAM2;
+    const bool leaf = a.phase == BP_LGRAM || a.phase == BP_LGRAMF || a.phase == BP_LGRAM2;
     GramArgs g{};
     g.k = k;
     g.tile_groups = gram_tile_groups(ncol);
@@ -1534,9 +1534,11 @@ __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int
     g.status = a.status;
     if (leaf) {
         g.Q = Operand{d.Q, d.ldq};
-        g.X = a.phase == BP_LGRAM ? Operand{a.W[inst], d.n} : Operand{d.U1L, d.ldq};
+        g.X = a.phase == BP_LGRAM2 ? Operand{d.U1L, d.ldq} : Operand{a.W[inst], d.n};
         g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
         g.partials = d.PL;
+        g.retry = d.retry;
+        g.cond = a.phase == BP_LGRAMF ? 1 : 0;   // the mixed form's FP64 redo, when flagged
     } else {
         g.Q = Operand{d.T, d.ldt};
         g.X = a.phase == BP_RGRAM ? Operand{d.Y, d.ldt} : Operand{d.U1R, d.ldt};
@@ -1547,11 +1549,32 @@ __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int
     gram_body<S>(g, local / cg, local % cg);
 }
 
+// the mixed form's first leaf Gram, on the FP32 copy of the instance's basis;
+// it clears the instance's retry flag for this step
+template <int S>
+__device__ void batch_gram_hi(const BatchArgs &a, const BatchInst &d, int inst, int local) {
+    const int k = a.step * S, ncol = k + S;
+    GramArgs g{};
+    g.k = k;
+    g.tile_groups = gram_tile_groups(ncol);
+    g.part_stride = (int64_t)ncol * S;
+    g.status = a.status;
+    g.Q = Operand{d.Q, d.ldq};
+    g.Qhi = d.Qhi;
+    g.X = Operand{a.W[inst], d.n};
+    g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
+    g.partials = d.PL;
+    g.clear_retry = 1;
+    g.retry = d.retry;
+    const int cg = gram_col_groups(ncol);
+    gram_f32_body<S>(g, local / cg, local % cg);
+}
+
 template <int S>
 __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int local) {
     const int k = a.step * S, ncol = k + S;
-    const bool leaf = a.phase == BP_LCHOL1 || a.phase == BP_LCHOL2;
-    const int sweep = (a.phase == BP_LCHOL1 || a.phase == BP_RCHOL1) ? 1 : 2;
+    const bool leaf = a.phase == BP_LCHOL1 || a.phase == BP_LCHOLF || a.phase == BP_LCHOL2;
+    const int sweep = (a.phase == BP_LCHOL2 || a.phase == BP_RCHOL2) ? 2 : 1;
     CholArgs c{};
     c.part_stride = (int64_t)ncol * S;
     c.k = k;
@@ -1575,6 +1598,11 @@ __device__ void batch_chol(const BatchArgs &a, const BatchInst &d, int inst, int
         c.yseg = d.kmax;
         c.pc = d.CL;
         c.pc_stride = (int64_t)d.kmax * 2 * S;
+        // mixed form: a failed pivot on the FP32 copy flags the instance's
+        // FP64 redo (BP_LGRAMF, BP_LCHOLF), which runs only when flagged
+        c.retry = d.retry;
+        c.soft = (a.phase == BP_LCHOL1 && d.Qhi) ? 1 : 0;
+        c.cond = a.phase == BP_LCHOLF ? 1 : 0;
     } else {
         const LevelGeom gr = make_root_geom(d.p, d.kmax, ncol, d.cR);
         const int slots = gr.nchunks() * rg;
@@ -1626,6 +1654,7 @@ __device__ __forceinline__ FinalizeArgs batch_leaf_rowupdate_args(const BatchArg
     } else {
         f.Q = Operand{d.Q, d.ldq};
         f.Qnew = OutOperand{d.Q + (int64_t)k * d.ldq, d.ldq};
+        f.Qnew_hi = d.Qhi ? d.Qhi + (int64_t)k * d.ldq : nullptr;   // mixed form: FP32 copy
         f.U1 = Operand{d.U1L, d.ldq};
         f.sweep = 2;
         f.single_sweep = a.two ? 0 : 1;
@@ -1678,6 +1707,7 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
         default:   // BP_LFIN
             f.Q = Operand{d.Q, d.ldq};
             f.Qnew = OutOperand{d.Q + (int64_t)k * d.ldq, d.ldq};
+            f.Qnew_hi = d.Qhi ? d.Qhi + (int64_t)k * d.ldq : nullptr;
             f.U1 = Operand{d.U1L, d.ldq};
             f.sweep = 2;
             f.single_sweep = a.two ? 0 : 1;
@@ -1701,6 +1731,14 @@ __global__ __launch_bounds__(kThreads) void kb_gram(BatchArgs a) {
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
     batch_gram<S>(a, d, inst, local);
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void kb_gram_hi(BatchArgs a) {
+    int inst, local;
+    batch_locate(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    batch_gram_hi<S>(a, d, inst, local);
 }
 
 template <int S>
@@ -1995,7 +2033,7 @@ static size_t rowlds_lds_bytes() {
 size_t batch_phase_lds(int phase, int s, bool rowlds) {
     auto chol = [](int s) -> size_t { return chol_lds_bytes_s(s); };
     switch (phase) {
-        case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
+        case BP_LCHOL1: case BP_LCHOLF: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
             return chol(s);
         case BP_LCORR: case BP_LFIN:
             if (!rowlds || s < 16) return 0;
@@ -2008,10 +2046,16 @@ size_t batch_phase_lds(int phase, int s, bool rowlds) {
 template <int S>
 static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st) {
     switch (a.phase) {
-        case BP_LGRAM: case BP_LGRAM2: case BP_RGRAM: case BP_RGRAM2:
+        case BP_LGRAM:
+            if (a.mixed) {       // its own kernel: the FP64 Grams keep their register budget
+                hipLaunchKernelGGL((kb_gram_hi<S>), dim3(blocks), dim3(kThreads), lds, st, a);
+                break;
+            }
+            [[fallthrough]];
+        case BP_LGRAMF: case BP_LGRAM2: case BP_RGRAM: case BP_RGRAM2:
             hipLaunchKernelGGL((kb_gram<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
-        case BP_LCHOL1: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
+        case BP_LCHOL1: case BP_LCHOLF: case BP_LCHOL2: case BP_RCHOL1: case BP_RCHOL2:
             hipLaunchKernelGGL((kb_chol<S>), dim3(blocks), dim3(kThreads), lds, st, a);
             break;
         case BP_RRED1: case BP_RRED2:

@@ -73,6 +73,7 @@ SIGNATURES = [
     ("orth_batch_set_variant", ctypes.c_int, [_vp, _i32]),
     ("orth_batch_step", ctypes.c_int, [_vp, _dp, _dp, _dp]),
     ("orth_batch_status", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("orth_batch_mixed_fallbacks", ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
     ("orth_batch_progress", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_batch_leaf_rows", ctypes.c_int, [_vp, _vp]),
     ("orth_batch_destroy", ctypes.c_int, [_vp]),
@@ -328,6 +329,12 @@ def orth_batch_status(b):
     return code, st.value, list(info)
 
 
+def orth_batch_mixed_fallbacks(b):
+    n = _i64(0)
+    code = load().orth_batch_mixed_fallbacks(b, ctypes.byref(n))
+    return code, n.value
+
+
 def orth_batch_progress(b):
     done, mx = ctypes.c_int32(), ctypes.c_int32()
     code = load().orth_batch_progress(b, ctypes.byref(done), ctypes.byref(mx))
@@ -491,21 +498,24 @@ class BatchOrthogonalizer:
     default height).  Tensors are column-major as in ``Orthogonalizer``:
     instance i's block is a (s_i, n_i) float64 tensor, its Hessenberg buffer a
     (K_i, K_i) tensor (column j of the K_i x K_i matrix is row j of the tensor).
+    precision: ORTH_FP64 or ORTH_MIXED_SPLIT32 (every instance).
     """
 
-    def __init__(self, n, s, k_max, leaf_rows=None, device="cuda", stream=None, variant=ORTH_PIP_PLUS):
+    def __init__(self, n, s, k_max, leaf_rows=None, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
+                 precision=ORTH_FP64):
         import torch
         load()
         self.n, self.s, self.k_max = list(map(int, n)), list(map(int, s)), list(map(int, k_max))
         self.count = len(self.n)
         self.device = torch.device(device)
-        nbytes = orth_batch_workspace_bytes(self.n, self.s, self.k_max, leaf_rows)
+        self.precision = precision
+        nbytes = orth_batch_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision)
         if nbytes == 0:
             raise OrthError("orth_batch_workspace_bytes", ORTH_ERR_ARG)
         self.workspace = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
         aligned = (self.workspace.data_ptr() + 255) // 256 * 256
         self.stream = stream
-        code, h = orth_batch_create(self.n, self.s, self.k_max, leaf_rows, ORTH_FP64, aligned, nbytes,
+        code, h = orth_batch_create(self.n, self.s, self.k_max, leaf_rows, precision, aligned, nbytes,
                                     _stream_ptr(stream))
         _check("orth_batch_create", code)
         self.h = h
@@ -532,6 +542,11 @@ class BatchOrthogonalizer:
 
     def progress(self):
         return orth_batch_progress(self.h)[1:]
+
+    def mixed_fallbacks(self):
+        code, n = orth_batch_mixed_fallbacks(self.h)
+        _check("orth_batch_mixed_fallbacks", code)
+        return n
 
     def status(self):
         code, st, info = orth_batch_status(self.h)

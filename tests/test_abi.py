@@ -107,12 +107,24 @@ def test_mixed_form_workspace_adds_the_fp32_copy():
         assert stored * 4 <= mixed - f64 <= stored * 4 + 256
 
 
-@pytest.mark.parametrize("form", ["mixed", "householder"])
-def test_other_forms_are_single_handle_only(form):
-    f = orth.ORTH_MIXED_SPLIT32 if form == "mixed" else orth.ORTH_FP64_HOUSEHOLDER
+def test_householder_leaves_are_single_handle_only():
+    f = orth.ORTH_FP64_HOUSEHOLDER
     assert orth.orth_batch_workspace_bytes([5000, 3000], [4, 8], [16, 32], None, f) == 0
     code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, f, 4096, 1 << 30, None)
     assert code == orth.ORTH_ERR_UNSUPPORTED
+    code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, 7, 4096, 1 << 30, None)
+    assert code == orth.ORTH_ERR_ARG
+
+
+def test_mixed_batch_workspace():
+    # the mixed batch adds each instance's FP32 copy of its leaf bases (a
+    # single column-major n x k_max matrix per instance, padded ld)
+    ns, ss, ks, lrs = [5000, 3000, 777], [4, 8, 1], [16, 32, 12], [1000, 0, 100]
+    f64 = orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, orth.ORTH_FP64)
+    mixed = orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, orth.ORTH_MIXED_SPLIT32)
+    assert f64 > 0 and mixed % 8 == 0
+    copy = sum(n * k * 4 for n, k in zip(ns, ks))
+    assert copy <= mixed - f64 <= copy + sum(ks) * 256 * 4 + 3 * 512
 
 
 def test_wide_blocks_are_planned():

@@ -8,7 +8,12 @@
 * a captured hipGraph of a closed-loop Arnoldi run (operator + batch step)
   replayed several times from a freshly created batch, eager work and
   synchronisation in between, equals the eager run bitwise every time;
-* breakdown in one instance is reported with its index.
+* breakdown in one instance is reported with its index;
+* the mixed form (ORTH_MIXED_SPLIT32): every instance equals a mixed single
+  handle bitwise and the FP64 oracle at the mixed form's tolerances
+  (||dP||_F / ||X||_F <= 1e-10, ||dN||_F / ||X||_F and max |dU| <= 1e-10
+  kappa_j); a first-sweep pivot that fails on the FP32 copy of one
+  instance redoes that instance's sweep only, in a graph replay too.
 """
 
 import sys
@@ -59,16 +64,18 @@ def _inputs(seed):
     return out
 
 
-def test_batch_equals_single_handles_bitwise(torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_equals_single_handles_bitwise(torch_cuda, precision):
     import torch
     from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer
-    _say("batch vs single", len(INSTANCES))
+    _say("batch vs single", len(INSTANCES), "precision", precision)
     X = _inputs(3)
     ns = [i[0] for i in INSTANCES]
     ss = [i[1] for i in INSTANCES]
     ks = [i[2] for i in INSTANCES]
     lrs = [i[3] for i in INSTANCES]
-    b = BatchOrthogonalizer(ns, ss, ks, lrs)
+    tol = 1e-12 if precision == 0 else 1e-10
+    b = BatchOrthogonalizer(ns, ss, ks, lrs, precision=precision)
     assert tuple(b.progress()) == (0, STEPS)
     W = [torch.empty((s, n), dtype=torch.float64, device="cuda") for (n, s, _, _) in INSTANCES]
     U = [torch.empty_like(w) for w in W]
@@ -82,8 +89,9 @@ def test_batch_equals_single_handles_bitwise(torch_cuda):
             Ub[i].append(to_host(u))
     st, info = b.status()
     assert st == 0, info
+    assert b.mixed_fallbacks() == 0
     for i, (n, s, km, lr) in enumerate(INSTANCES):
-        g = Orthogonalizer(n, s, km, lr)
+        g = Orthogonalizer(n, s, km, lr, precision=precision)
         assert g.leaf_rows == b.leaf_rows[i]
         Hb = to_host(Hess[i])
         Q = np.zeros((n, 0))
@@ -98,9 +106,9 @@ def test_batch_equals_single_handles_bitwise(torch_cuda):
             kap = kappa_after_projection(N, X[i][j])
             xn = np.linalg.norm(X[i][j])
             if k:
-                assert np.linalg.norm(Hb[:k, j * s:(j + 1) * s] - P) / xn <= 1e-12
-            assert np.linalg.norm(Hb[k:k + s, j * s:(j + 1) * s] - N) / xn <= 1e-12 * kap
-            assert np.max(np.abs(Ub[i][j] - Ur)) <= 1e-12 * kap
+                assert np.linalg.norm(Hb[:k, j * s:(j + 1) * s] - P) / xn <= tol
+            assert np.linalg.norm(Hb[k:k + s, j * s:(j + 1) * s] - N) / xn <= tol * kap
+            assert np.max(np.abs(Ub[i][j] - Ur)) <= tol * kap
             Q = np.hstack([Q, Ur])
         g.close()
     b.close()
@@ -110,11 +118,12 @@ def _grids():
     return [(50, 60), (101, 37), (64, 64)]
 
 
-def test_batch_graph_replay_arnoldi(torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_graph_replay_arnoldi(torch_cuda, precision):
     """Capture start block + 4 Arnoldi steps (operator and batch step) and replay."""
     import torch
     from paper_2204_13393_amd import BatchOrthogonalizer, orth
-    _say("graph replay")
+    _say("graph replay", precision)
     grids = _grids()
     ss = [4, 8, 2]
     steps = 5
@@ -146,7 +155,7 @@ def test_batch_graph_replay_arnoldi(torch_cuda):
     # eager reference
     We, Ue, He = buffers()
     with torch.cuda.stream(side):
-        ref = BatchOrthogonalizer(ns, ss, ks, lrs, stream=side)
+        ref = BatchOrthogonalizer(ns, ss, ks, lrs, stream=side, precision=precision)
         run(ref, We, Ue, He, side)
     side.synchronize()
     st, info = ref.status()
@@ -158,7 +167,7 @@ def test_batch_graph_replay_arnoldi(torch_cuda):
     # captured run on its own workspace
     Wg, Ug, Hg = buffers()
     with torch.cuda.stream(side):
-        cap = BatchOrthogonalizer(ns, ss, ks, lrs, stream=side)
+        cap = BatchOrthogonalizer(ns, ss, ks, lrs, stream=side, precision=precision)
         ptrs = (cap.pointer_array(Wg), cap.pointer_array(Ug), cap.pointer_array(Hg))
     side.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -175,9 +184,9 @@ def test_batch_graph_replay_arnoldi(torch_cuda):
     cap.close()
     for rep in range(3):
         # fresh basis state on the same workspace, eager and synchronised
-        code, h = orth.orth_batch_create(ns, ss, ks, lrs, orth.ORTH_FP64,
+        code, h = orth.orth_batch_create(ns, ss, ks, lrs, precision,
                                          (ws.data_ptr() + 255) // 256 * 256,
-                                         orth.orth_batch_workspace_bytes(ns, ss, ks, lrs),
+                                         orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, precision),
                                          side.cuda_stream)
         assert code == 0
         for t in Ug + Hg:
@@ -239,3 +248,91 @@ def test_batch_pip_variant_equals_single(torch_cuda):
     for g in singles:
         g.close()
     b.close()
+
+
+def test_batch_mixed_fallback_is_per_instance(torch_cuda):
+    """Instance 1 gets a block that lies in its basis up to 1e-5 (its first
+    sweep on the FP32 copy fails a pivot, as in the single-handle fallback
+    test); instances 0 and 2 get well-conditioned blocks.  Exactly one redo
+    is counted, and every instance equals a mixed single handle bitwise, so
+    the others did not take the redo; a graph replay of the same three steps
+    counts one redo per replay and equals the eager run bitwise."""
+    import torch
+    from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, orth
+    _say("batch mixed fallback")
+    MIX = orth.ORTH_MIXED_SPLIT32
+    ns, ss, ks, lrs = [6000, 8192, 3000], [4, 8, 2], [12, 24, 6], [1500, 2048, 1000]
+    rng = np.random.default_rng(21)
+    n1, s1 = ns[1], ss[1]
+    W0, _ = np.linalg.qr(rng.standard_normal((n1, s1)))
+    X1 = W0 @ rng.standard_normal((s1, s1)) + 1e-5 * rng.standard_normal((n1, s1)) / np.sqrt(n1)
+    blocks = [[normal_block(ns[0], ss[0], 50 + j) for j in range(3)],
+              [W0, X1, normal_block(n1, s1, 22)],
+              [normal_block(ns[2], ss[2], 60 + j) for j in range(3)]]
+    Wd = [[to_dev(x) for x in bl] for bl in blocks]
+
+    def buffers():
+        U = [torch.empty((s, n), dtype=torch.float64, device="cuda") for n, s in zip(ns, ss)]
+        H = [torch.zeros((k, k), dtype=torch.float64, device="cuda") for k in ks]
+        return U, H
+
+    b = BatchOrthogonalizer(ns, ss, ks, lrs, precision=MIX)
+    U, H = buffers()
+    Ue, falls = [], []
+    for j in range(3):
+        b.step([Wd[i][j] for i in range(3)], U, H)
+        Ue.append([to_host(u) for u in U])
+        falls.append(b.mixed_fallbacks())
+    st, info = b.status()
+    assert st == 0, info
+    assert falls == [0, 1, 1], falls
+    He = [to_host(h) for h in H]
+    for i in range(3):
+        g = Orthogonalizer(ns[i], ss[i], ks[i], lrs[i], precision=MIX)
+        s = ss[i]
+        for j in range(3):
+            Hs, Rs, Us = g.step(Wd[i][j])
+            k = j * s
+            assert np.array_equal(Ue[j][i], to_host(Us)), (i, j)
+            assert np.array_equal(He[i][k:k + s, j * s:(j + 1) * s], to_host(Rs)), (i, j)
+            if k:
+                assert np.array_equal(He[i][:k, j * s:(j + 1) * s], to_host(Hs)), (i, j)
+        assert orth.orth_mixed_fallbacks(g.h)[1] == (1 if i == 1 else 0)
+        g.close()
+    ws = b.workspace
+    b.close()
+
+    # the same three steps captured once and replayed on fresh batch state
+    side = torch.cuda.Stream()
+    nbytes = orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, MIX)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    Ug, Hg = buffers()
+    with torch.cuda.stream(side):
+        code, h = orth.orth_batch_create(ns, ss, ks, lrs, MIX, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        parr = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device="cuda")
+        ptrs = [(parr([Wd[i][j] for i in range(3)]), parr(Ug), parr(Hg)) for j in range(3)]
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for j in range(3):
+            assert orth.orth_batch_step(h, *(p.data_ptr() for p in ptrs[j])) == 0
+    orth.orth_batch_destroy(h)
+    for rep in range(3):
+        code, h = orth.orth_batch_create(ns, ss, ks, lrs, MIX, wp, nbytes, side.cuda_stream)
+        assert code == 0
+        for t in Ug + Hg:
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        code, st, info = orth.orth_batch_status(h)
+        assert code == 0 and st == 0, info
+        assert orth.orth_batch_mixed_fallbacks(h) == (0, 1), rep
+        for i in range(3):
+            assert np.array_equal(to_host(Ug[i]), Ue[2][i]), (rep, i)
+            assert np.array_equal(to_host(Hg[i]), He[i]), (rep, i)
+        orth.orth_batch_destroy(h)
+        x = torch.randn(1000, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
