@@ -511,12 +511,13 @@ def bench_lap3d(args):
     start block is W0 = G M with singular values sigma_j = 10^(-8 j / 31)
     (G Gaussian from default_rng(5), M = R_G^{-1} diag(sigma) V^T, V the QR
     factor of a Gaussian from default_rng(6); kappa = 1e8, eps kappa^2 ~ 1.1).
-    FP64 and mixed forms on that block (the timed line), then FP64 from an
-    N(0,1) start block (default_rng(5)) as a second, labelled line.  Closed
+    FP64 and mixed forms on that block (the timed line), FP64 from an N(0,1)
+    start block (default_rng(5)) as a second, labelled line, and the
+    Householder leaves on the configured block.  Closed
     loop; HIP events around every orth_step (stencils excluded)."""
     import numpy as np
     import torch
-    from paper_2204_13393_amd import Orthogonalizer, orth
+    from paper_2204_13393_amd import orth
     from synth import normal_block
     nx = ny = nz = 256
     n, s, steps, leaf = nx * ny * nz, 32, 16, 4096
@@ -540,11 +541,12 @@ def bench_lap3d(args):
     V = torch.empty((kmax, n), dtype=torch.float64, device=dev)
     W = torch.empty((s, n), dtype=torch.float64, device=dev)
     H = torch.zeros((kmax, kmax), dtype=torch.float64, device=dev)
-    # one workspace for both forms (the mixed form adds the FP32 copy)
-    o = Orthogonalizer(n, s, kmax, leaf, precision=orth.ORTH_MIXED_SPLIT32)
-    ws_ptr = (o.workspace.data_ptr() + 255) // 256 * 256
-    nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, orth.ORTH_MIXED_SPLIT32)
-    o.close()
+    # one workspace for every form (the mixed form adds the FP32 copy, the
+    # Householder form the per-leaf compact-WY factors)
+    nbytes = max(orth.orth_workspace_bytes(n, s, kmax, leaf, p_)
+                 for p_ in (orth.ORTH_MIXED_SPLIT32, orth.ORTH_FP64_HOUSEHOLDER))
+    ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
 
     fallbacks = {}      # steps whose first sweep was redone in FP64, per form
 
@@ -599,6 +601,8 @@ def bench_lap3d(args):
     best, prof, e_perp = timed(orth.ORTH_FP64)
     best_mixed, prof_mixed, e_perp_mixed = timed(orth.ORTH_MIXED_SPLIT32)
     best_normal, _, e_perp_normal = timed(orth.ORTH_FP64, "normal", profile=False)
+    print("[bench] lap3d: householder leaves", file=sys.stderr, flush=True)
+    best_hh, prof_hh, e_perp_hh = timed(orth.ORTH_FP64_HOUSEHOLDER)
     p = n // leaf
     widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
@@ -624,6 +628,15 @@ def bench_lap3d(args):
             "fp64_redo_steps": fallbacks[orth.ORTH_MIXED_SPLIT32],
             "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
                         for name, (ms, cnt) in prof_mixed.items() if cnt},
+        },
+        "householder": {
+            "precision": "fp64_householder: Algorithm HH at the leaves (s = 32 in 8-column sub-panels), "
+                         "BCGS-PIP+ reduction",
+            "ms_per_sequence": best_hh,
+            "speedup_vs_fp64": best / best_hh,
+            "e_perp": e_perp_hh,
+            "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
+                        for name, (ms, cnt) in prof_hh.items() if cnt},
         },
         "normal_start_block": {
             "start": "N(0,1), default_rng(5)",

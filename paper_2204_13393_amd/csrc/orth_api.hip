@@ -161,11 +161,11 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     if (n > ((int64_t)1 << 40)) return false;
     if (precision == ORTH_FP64_HOUSEHOLDER) {
         // the panel kernel holds a whole leaf in registers, the per-leaf
-        // small products stage (k_max) s doubles in LDS
+        // small products stage k_max x s blocks in LDS
         const int32_t p = std::max<int32_t>(1, (int32_t)(n / leaf_rows));
         const int64_t last = n - (int64_t)(p - 1) * leaf_rows;
         const int64_t rows_max = std::max<int64_t>(last, p > 1 ? leaf_rows : last);
-        if (hh_max_leaf_rows(s) == 0 || rows_max > hh_max_leaf_rows(s) || (int64_t)kmax * s > kHhMaxCoef) {
+        if (hh_max_leaf_rows(s) == 0 || rows_max > hh_max_leaf_rows(s) || !hh_small_fits(s, kmax)) {
             *why = ORTH_ERR_UNSUPPORTED;
             return false;
         }
@@ -219,7 +219,7 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
     }
     // the Householder reduction is offered when every node's stacked problem
     // (its children's k_max physical rows each) fits the panel kernel
-    pl.hhtree = s <= 16 && hh_max_leaf_rows(s) > 0 && (int64_t)kmax * s <= kHhMaxCoef;
+    pl.hhtree = hh_max_leaf_rows(s) > 0 && hh_small_fits(s, kmax);
     for (int l = 0; l < pl.nlev && pl.hhtree; ++l)
         pl.hhtree = (int64_t)hh_node_children(pl, l) * kmax <= hh_max_leaf_rows(s);
     const int64_t last = n - (int64_t)(pl.p - 1) * leaf_rows;
@@ -536,6 +536,7 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
     // tree factors must start at zero: the reduction level relies on the
     // zero rows below every T_i's current k x k block
     hipError_t e = prepare_kernels(pl.s);
+    if (e == hipSuccess && (pl.precision == ORTH_FP64_HOUSEHOLDER || pl.hhtree)) e = prepare_hh_kernels(pl.s);
     for (int l = 0; l < pl.nlev && e == hipSuccess; ++l) {
         e = launch_fill(h->Tl(l), pl.ldtl[l] * (int64_t)pl.kmax, 0.0, h->stream);
         if (e == hipSuccess) e = launch_fill(h->Yl(l), pl.ldtl[l] * (int64_t)pl.s, 0.0, h->stream);
@@ -1590,7 +1591,8 @@ int orth_set_deflation(orth_t *h, double delta) {
     if (h->poisoned) return ORTH_ERR_POISONED;
     if (!(delta >= 0.0 && delta < 1.0)) return ORTH_ERR_ARG;      // NaN fails too
     // deflation is defined for the single reduction level
-    if (delta > 0.0 && (!h->DF() || h->hh_red() || h->pl.nlev > 1)) return ORTH_ERR_UNSUPPORTED;
+    // (the eigen solver of the reduction-level factorisation stops at s = 16)
+    if (delta > 0.0 && (!h->DF() || h->hh_red() || h->pl.nlev > 1 || h->pl.s > 16)) return ORTH_ERR_UNSUPPORTED;
     h->defl_delta = delta;
     return ORTH_OK;
 }

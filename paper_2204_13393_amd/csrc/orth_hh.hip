@@ -109,6 +109,10 @@ constexpr int kHhWaves = kHhThreads / 64;
 
 template <int S>
 __host__ __device__ constexpr int hh_rpt() { return S <= 4 ? 16 : (S == 8 ? 8 : 2); }
+// sub-panel width: blocks wider than 16 columns are factored 8 columns at a
+// time (k_hh_panel_sub)
+template <int S>
+__host__ __device__ constexpr int hh_sub() { return S <= 16 ? S : 8; }
 
 template <int S>
 __global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
@@ -224,6 +228,219 @@ __global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
     }
 }
 
+// Blocks wider than the register budget (s = 32): the same factorisation in
+// sub-panels of SB columns, in a kernel of 1024 threads holding 4 rows each
+// (4096 rows; an 8-column sub-panel takes 64 registers per thread).  A
+// sub-panel is loaded, the reflectors of the earlier sub-panels are applied
+// to it one at a time, H_0 first (x -= 2 v (v^T x) with the stored unit
+// reflector, whose rows a thread reads back from the ones it stored
+// itself), so its rows k .. k + cb - 1 hold N's rows above it; it is then
+// factored from row k + cb down as in k_hh_panel.  Each reduction takes two
+// barriers: after the waves' partial sums, one wave forms the column's
+// scalars and coefficients in LDS, which every thread then reads.
+constexpr int kHhSubThreads = 1024;
+constexpr int kHhSubWaves = kHhSubThreads / 64;
+constexpr int kHhSubRows = 4;
+
+template <int SB>
+struct HhSubShared {
+    double red[2][kHhSubWaves][SB];   // the waves' partial sums
+    double rowv[2][SB];               // the pivot row
+    double cf[2][SB];                 // per-column coefficients of the update
+    double v0[2], vn[2];              // pivot entry of v~ and ||v~||
+};
+
+template <int SB>
+struct HhSubCtx {
+    const HhArgs &a;
+    double *Yl;
+    HhSubShared<SB> &sh;
+    int k, cb, nl, it, tid, lane, wave;
+};
+
+// the waves' partial sums part[c], c >= J0, into sh.red[b] (then a barrier)
+template <int SB, int J0>
+__device__ __forceinline__ void hh_sub_partials(double (&part)[SB], HhSubShared<SB> &sh, int b, int lane, int wave) {
+#pragma unroll
+    for (int c = J0; c < SB; ++c) {
+        const double w = wave_sum(part[c]);
+        if (lane == 0) sh.red[b][wave][c] = w;
+    }
+}
+
+// One column J of a sub-panel (the steps of k_hh_panel's column loop), as a
+// template so that every index into the register block is a constant.
+template <int SB, int RPT, int J>
+__device__ __forceinline__ void hh_sub_column(double (&x)[RPT][SB], const HhSubCtx<SB> &g) {
+    const HhArgs &a = g.a;
+    HhSubShared<SB> &sh = g.sh;
+    const int k = g.k, cb = g.cb, nl = g.nl, tid = g.tid, lane = g.lane, wave = g.wave;
+    const int pj = k + cb + J, b = (g.it + J) & 1;
+    {
+        double part[SB];
+#pragma unroll
+        for (int c = J; c < SB; ++c) part[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhSubThreads * q;
+            if (row >= pj && row < nl) {
+#pragma unroll
+                for (int c = J; c < SB; ++c) part[c] = fma(x[q][J], x[q][c], part[c]);
+            }
+        }
+        hh_sub_partials<SB, J>(part, sh, b, lane, wave);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            if (tid + kHhSubThreads * q == pj) {
+#pragma unroll
+                for (int c = J; c < SB; ++c) sh.rowv[b][c] = x[q][c];
+            }
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // lane c < SB: column c's dot product with column J (fixed wave order)
+        // and its pivot-row entry
+        const int c = lane < SB ? lane : SB - 1;
+        double d = 0.0;
+#pragma unroll
+        for (int w = 0; w < kHhSubWaves; ++w) d += sh.red[b][w][c < J ? J : c];
+        const double av = sh.rowv[b][c < J ? J : c];
+        const double dj = __shfl(d, J, 64), u0 = __shfl(av, J, 64);
+        const double lam = sqrt(dj);
+        const bool zero = lam == 0.0;
+        const double njj = zero ? 0.0 : (u0 >= 0.0 ? -lam : lam);
+        const double v0 = zero ? 1.0 : u0 - njj;
+        const double nv2 = zero ? 1.0 : 2.0 * lam * (lam + fabs(u0));
+        const double cf = 2.0 * (zero ? av : d - njj * av) / nv2;
+        if (lane > J && lane < SB) sh.cf[b][lane] = cf;
+        if (lane == 0) {
+            sh.v0[b] = v0;
+            sh.vn[b] = sqrt(nv2);
+        }
+        // row pj of N: zero left of the diagonal, this sub-panel's entries
+        // (the later sub-panels write theirs when loaded)
+        double *yr = g.Yl + pj;
+        if (lane < cb + J) yr[(int64_t)lane * a.ldy] = 0.0;
+        if (lane >= J && lane < SB) yr[(int64_t)(cb + lane) * a.ldy] = lane == J ? njj : av - v0 * cf;
+    }
+    __syncthreads();
+    const double v0 = sh.v0[b], vn = sh.vn[b];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = tid + kHhSubThreads * q;
+        if (row >= pj && row < nl) {
+            const double vi = row == pj ? v0 : x[q][J];
+#pragma unroll
+            for (int c = J + 1; c < SB; ++c) x[q][c] = fma(-vi, sh.cf[b][c], x[q][c]);
+            x[q][J] = vi / vn;
+        }
+    }
+}
+
+template <int SB, int RPT, int J>
+struct HhSubCols {
+    static __device__ __forceinline__ void run(double (&x)[RPT][SB], const HhSubCtx<SB> &g) {
+        hh_sub_column<SB, RPT, J>(x, g);
+        HhSubCols<SB, RPT, J + 1>::run(x, g);
+    }
+};
+template <int SB, int RPT>
+struct HhSubCols<SB, RPT, SB> {
+    static __device__ __forceinline__ void run(double (&)[RPT][SB], const HhSubCtx<SB> &) {}
+};
+
+template <int S, int SB>
+__global__ __launch_bounds__(kHhSubThreads) void k_hh_panel_sub(HhArgs a) {
+    static_assert(S % SB == 0 && SB <= 64, "whole sub-panels, a column per lane");
+    if (hh_failed(a.status)) return;
+    constexpr int RPT = kHhSubRows;
+    __shared__ HhSubShared<SB> sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int leaf = blockIdx.x;
+    const int64_t r0 = a.geom.leaf_begin(leaf);
+    const int nl = (int)(a.geom.leaf_end(leaf) - r0);
+    const int k = a.k;
+    double *Yl = a.Yout + (int64_t)leaf * a.yseg;   // [P; N] of this leaf, column c at Yl + c ldy
+    int it = 0;                                      // reductions so far (LDS buffer it & 1)
+
+    for (int cb = 0; cb < S; cb += SB) {
+        double x[RPT][SB];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhSubThreads * q;
+#pragma unroll
+            for (int c = 0; c < SB; ++c)
+                x[q][c] = row < nl ? a.X[(r0 + row) + (int64_t)(cb + c) * a.ldx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhSubThreads * q;
+            if (row < k) {
+#pragma unroll
+                for (int c = 0; c < SB; ++c) Yl[row + (int64_t)(cb + c) * a.ldy] = x[q][c];
+            }
+        }
+        // the earlier sub-panels' reflectors, H_0 first
+#pragma unroll 1
+        for (int j = 0; j < cb; ++j, ++it) {
+            const int b = it & 1;
+            double v[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int row = tid + kHhSubThreads * q;
+                v[q] = row < nl ? a.Q[(r0 + row) + (int64_t)(k + j) * a.ldq] : 0.0;
+            }
+            {
+                double part[SB];
+#pragma unroll
+                for (int c = 0; c < SB; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) t = fma(v[q], x[q][c], t);
+                    part[c] = t;
+                }
+                hh_sub_partials<SB, 0>(part, sh, b, lane, wave);
+            }
+            __syncthreads();
+            if (wave == 0 && lane < SB) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < kHhSubWaves; ++w) t += sh.red[b][w][lane];
+                sh.cf[b][lane] = 2.0 * t;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < SB; ++c) {
+                const double tw = sh.cf[b][c];
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) x[q][c] = fma(-v[q], tw, x[q][c]);
+            }
+        }
+        // rows k .. k + cb - 1: N's entries above this sub-panel
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhSubThreads * q;
+            if (row >= k && row < k + cb) {
+#pragma unroll
+                for (int c = 0; c < SB; ++c) Yl[row + (int64_t)(cb + c) * a.ldy] = x[q][c];
+            }
+        }
+        HhSubCols<SB, RPT, 0>::run(x, HhSubCtx<SB>{a, Yl, sh, k, cb, nl, it, tid, lane, wave});
+        it += SB;
+        // this sub-panel's reflectors, zero above their pivot rows
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = tid + kHhSubThreads * q;
+            if (row < nl) {
+#pragma unroll
+                for (int c = 0; c < SB; ++c)
+                    a.Q[(r0 + row) + (int64_t)(k + cb + c) * a.ldq] = row >= k + cb + c ? x[q][c] : 0.0;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ T update
 // From the slots of [V v_new]^T v_new: W = V^T v_new (k x s) and
 // G = v_new^T v_new.  T_s (s x s, upper): diagonal 2, column j above the
@@ -310,58 +527,64 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
 // record) -> Z = T (V[0:k+s]^T C_i); the record's right half becomes -Z (the
 // row-update kernel then forms -V Z) and its left half keeps C_i for the
 // final E C_i term.
-template <int S>
+// CB columns of C_i at a time (CB = S, or S / 2 when two K x S blocks do
+// not fit the LDS); every output column is the same sum either way.
+template <int S, int CB>
 __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
+    static_assert(S % CB == 0, "whole column blocks");
     if (hh_failed(a.status)) return;
     extern __shared__ double lds[];
     const int leaf = blockIdx.x, tid = threadIdx.x, K = a.k + S;
-    double *C = lds, *B = lds + K * S;             // K x S row-major each
+    double *C = lds, *B = lds + K * CB;            // K x CB row-major each
     double *rec = a.crec + (int64_t)leaf * a.cseg;  // row c: [left S | right S]
-    for (int e = tid; e < K * S; e += kThreads) {
-        const int r = e / S, j = e - (e / S) * S;
-        const double v = rec[(int64_t)r * 2 * S + S + j];
-        C[e] = v;
-        rec[(int64_t)r * 2 * S + j] = v;
-    }
-    __syncthreads();
     const int64_t km = a.kmax;
     const double *Tc = hh_tc(a, leaf), *Vr = Tc + 2 * km * km;
-    for (int cb = 0; cb < K; cb += kThreads) {
-        const int c = cb + tid;
-        // B[c] = sum over r >= c of V(r, c) C[r]: V row r, lanes along c
-        const int wmin = cb + (tid & ~63);
-        double acc[S];
-#pragma unroll
-        for (int j = 0; j < S; ++j) acc[j] = 0.0;
-        #pragma unroll 4      // four loads in flight per lane
-        for (int r = wmin; r < K; ++r) {
-            const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
-#pragma unroll
-            for (int j = 0; j < S; ++j) acc[j] = fma(v, C[r * S + j], acc[j]);
+    for (int j0 = 0; j0 < S; j0 += CB) {
+        for (int e = tid; e < K * CB; e += kThreads) {
+            const int r = e / CB, j = e - (e / CB) * CB;
+            const double v = rec[(int64_t)r * 2 * S + S + j0 + j];
+            C[e] = v;
+            rec[(int64_t)r * 2 * S + j0 + j] = v;
         }
-        if (c < K) {
+        __syncthreads();
+        for (int cb = 0; cb < K; cb += kThreads) {
+            const int c = cb + tid;
+            // B[c] = sum over r >= c of V(r, c) C[r]: V row r, lanes along c
+            const int wmin = cb + (tid & ~63);
+            double acc[CB];
 #pragma unroll
-            for (int j = 0; j < S; ++j) B[c * S + j] = acc[j];
+            for (int j = 0; j < CB; ++j) acc[j] = 0.0;
+            #pragma unroll 4      // four loads in flight per lane
+            for (int r = wmin; r < K; ++r) {
+                const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
+#pragma unroll
+                for (int j = 0; j < CB; ++j) acc[j] = fma(v, C[r * CB + j], acc[j]);
+            }
+            if (c < K) {
+#pragma unroll
+                for (int j = 0; j < CB; ++j) B[c * CB + j] = acc[j];
+            }
         }
-    }
-    __syncthreads();
-    for (int rb = 0; rb < K; rb += kThreads) {
-        const int r = rb + tid;
-        // Z[r] = sum over c >= r of T(r, c) B[c]: T column c, lanes along r
-        const int wmin = rb + (tid & ~63);
-        double acc[S];
+        __syncthreads();
+        for (int rb = 0; rb < K; rb += kThreads) {
+            const int r = rb + tid;
+            // Z[r] = sum over c >= r of T(r, c) B[c]: T column c, lanes along r
+            const int wmin = rb + (tid & ~63);
+            double acc[CB];
 #pragma unroll
-        for (int j = 0; j < S; ++j) acc[j] = 0.0;
-        #pragma unroll 4      // four loads in flight per lane
-        for (int c = wmin; c < K; ++c) {
-            const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
+            for (int j = 0; j < CB; ++j) acc[j] = 0.0;
+            #pragma unroll 4      // four loads in flight per lane
+            for (int c = wmin; c < K; ++c) {
+                const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
-            for (int j = 0; j < S; ++j) acc[j] = fma(t, B[c * S + j], acc[j]);
+                for (int j = 0; j < CB; ++j) acc[j] = fma(t, B[c * CB + j], acc[j]);
+            }
+            if (r < K) {
+#pragma unroll
+                for (int j = 0; j < CB; ++j) rec[(int64_t)r * 2 * S + S + j0 + j] = -acc[j];
+            }
         }
-        if (r < K) {
-#pragma unroll
-            for (int j = 0; j < S; ++j) rec[(int64_t)r * 2 * S + S + j] = -acc[j];
-        }
+        __syncthreads();      // the next block overwrites C and B
     }
 }
 
@@ -449,6 +672,17 @@ __global__ __launch_bounds__(kThreads) void k_hh_apply_add(HhArgs a) {
     }
 }
 
+// dynamic LDS of the per-leaf small products for block width s at K = k + s
+// columns (0: the K x s staging does not fit); coef_cb: the coefficient
+// kernel's column block
+size_t hh_prep_lds(int s, int64_t K) { return (size_t)(K - s) * s * 8; }
+size_t hh_tupd_lds(int s, int64_t K) { return (size_t)(K * s + (int64_t)s * s) * 8; }
+int hh_coef_cb(int s, int64_t K) {
+    if ((size_t)2 * K * s * 8 <= kHhLdsMax) return s;
+    if (s > 1 && (size_t)2 * K * (s / 2) * 8 <= kHhLdsMax) return s / 2;
+    return 0;
+}
+
 template <int S>
 hipError_t hh_launch(HhKernel which, const HhArgs &a, hipStream_t st) {
     const int nleaf = a.geom.nleaf;
@@ -456,16 +690,24 @@ hipError_t hh_launch(HhKernel which, const HhArgs &a, hipStream_t st) {
     switch (which) {
         case HH_PREP:
             if (a.k < 1) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_hh_prep<S>), dim3(nleaf), dim3(kThreads), (size_t)a.k * S * 8, st, a);
+            hipLaunchKernelGGL((k_hh_prep<S>), dim3(nleaf), dim3(kThreads), hh_prep_lds(S, K), st, a);
             break;
         case HH_PANEL:
-            hipLaunchKernelGGL((k_hh_panel<S>), dim3(nleaf), dim3(kHhThreads), 0, st, a);
+            if constexpr (S > 16) {
+                hipLaunchKernelGGL((k_hh_panel_sub<S, hh_sub<S>()>), dim3(nleaf), dim3(kHhSubThreads), 0, st, a);
+            } else {
+                hipLaunchKernelGGL((k_hh_panel<S>), dim3(nleaf), dim3(kHhThreads), 0, st, a);
+            }
             break;
         case HH_TUPD:
-            hipLaunchKernelGGL((k_hh_tupd<S>), dim3(nleaf), dim3(kThreads), (size_t)(K * S + S * S) * 8, st, a);
+            hipLaunchKernelGGL((k_hh_tupd<S>), dim3(nleaf), dim3(kThreads), hh_tupd_lds(S, K), st, a);
             break;
         case HH_COEF:
-            hipLaunchKernelGGL((k_hh_coef<S>), dim3(nleaf), dim3(kThreads), (size_t)2 * K * S * 8, st, a);
+            if (hh_coef_cb(S, K) == S) {
+                hipLaunchKernelGGL((k_hh_coef<S, S>), dim3(nleaf), dim3(kThreads), (size_t)2 * K * S * 8, st, a);
+            } else if constexpr (S > 1) {
+                hipLaunchKernelGGL((k_hh_coef<S, S / 2>), dim3(nleaf), dim3(kThreads), (size_t)K * S * 8, st, a);
+            }
             break;
         case HH_ADDEC:
             hipLaunchKernelGGL((k_hh_addec<S>), dim3(nleaf), dim3(kThreads), 0, st, a);
@@ -511,13 +753,49 @@ int64_t hh_max_leaf_rows(int s) {
         case 4: return (int64_t)kHhThreads * hh_rpt<4>();
         case 8: return (int64_t)kHhThreads * hh_rpt<8>();
         case 16: return (int64_t)kHhThreads * hh_rpt<16>();
+        case 32: return (int64_t)kHhSubThreads * kHhSubRows;
     }
     return 0;
 }
 
+bool hh_small_fits(int s, int64_t kmax) {
+    return hh_prep_lds(s, kmax) <= kHhLdsMax && hh_tupd_lds(s, kmax) <= kHhLdsMax && hh_coef_cb(s, kmax) > 0;
+}
+
+template <int S>
+static hipError_t raise_hh_lds() {
+    const int lim = (int)kHhLdsMax;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hh_prep<S>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hh_tupd<S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hh_coef<S, S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if constexpr (S > 1) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hh_coef<S, S / 2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
+    return e;
+}
+
+hipError_t prepare_hh_kernels(int s) {
+    switch (s) {
+        case 1: return raise_hh_lds<1>();
+        case 2: return raise_hh_lds<2>();
+        case 4: return raise_hh_lds<4>();
+        case 8: return raise_hh_lds<8>();
+        case 16: return raise_hh_lds<16>();
+        case 32: return raise_hh_lds<32>();
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st) {
     // host checks of the launch against what the kernels assume
-    if (a.geom.nleaf < 1 || a.k < 0 || (int64_t)(a.k + s) * s > kHhMaxCoef) return hipErrorInvalidValue;
+    if (a.geom.nleaf < 1 || a.k < 0 || !hh_small_fits(s, (int64_t)a.k + s)) return hipErrorInvalidValue;
     if (which == HH_PANEL) {
         const int64_t last = a.geom.leaf_end(a.geom.nleaf - 1) - a.geom.leaf_begin(a.geom.nleaf - 1);
         const int64_t full = a.geom.nleaf > 1 ? a.geom.leaf_rows : last;
@@ -529,6 +807,7 @@ hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st) {
         case 4: return hh_launch<4>(which, a, st);
         case 8: return hh_launch<8>(which, a, st);
         case 16: return hh_launch<16>(which, a, st);
+        case 32: return hh_launch<32>(which, a, st);
     }
     return hipErrorInvalidValue;
 }

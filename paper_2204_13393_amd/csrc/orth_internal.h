@@ -386,10 +386,19 @@ struct HhArgs {
     int32_t m;
 };
 enum HhKernel { HH_PREP = 0, HH_PANEL, HH_TUPD, HH_COEF, HH_ADDEC, HH_APPLY_COEF, HH_APPLY_ADD };
-// (k + s) s bound of the per-leaf small products (their LDS staging)
+// (k + s) x 16 bound of orth_apply_Q's per-leaf coefficient blocks at full
+// width (two of them within 64 KB of LDS; narrower blocks above it)
 constexpr int64_t kHhMaxCoef = 4096;
+// dynamic LDS a workgroup may hold (the per-leaf small products stage
+// (k + s) x s blocks in it)
+constexpr size_t kHhLdsMax = 160 * 1024;
 // largest leaf the panel kernel holds in registers for block width s (0: unsupported s)
 int64_t hh_max_leaf_rows(int s);
+// the per-leaf small products' LDS staging fits for block width s at k_max columns
+bool hh_small_fits(int s, int64_t kmax);
+// once per handle, on its device: raise the dynamic-LDS limit of the
+// Householder kernels of block width s
+hipError_t prepare_hh_kernels(int s);
 hipError_t launch_hh(int s, HhKernel which, const HhArgs &a, hipStream_t st);
 // orth_apply_Q with Householder leaves: HH_APPLY_COEF (Z_i = T V_top^T C_i, -Z_i
 // to ca_out), then the apply kernel, then HH_APPLY_ADD (Y_i[0:k] += C_i)

@@ -82,15 +82,21 @@ def test_householder_form_workspace_and_limits():
         qdiff = (_basis_ld(n) - (p - 1) * _basis_ld(lr) - _basis_ld(last)) * k * 8
         extra = 3 * p * k * k * 8 + (p * k + 64) * 16 * 8 + 64 + s * s * 8 + 256
         assert 3 * p * k * k * 8 - 512 <= hh - f64 - qdiff <= extra + 512
-    # limits: the panel kernel's register capacity and k_max s <= 4096
+    # limits: the panel kernel's register capacity (s = 32 in 8-column
+    # sub-panels, 4096 rows) and the small products' LDS staging, at most
+    # 160 KB: ((k_max) s + s^2) doubles for the T update
     assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 4096, H) > 0
     assert orth.orth_workspace_bytes(2 ** 20, 8, 64, 8192, H) == 0        # leaf rows > 4096 at s = 8
     assert orth.orth_workspace_bytes(4096 + 4095, 8, 64, 4096, H) == 0    # the last leaf takes 8191 rows
     assert orth.orth_workspace_bytes(2 ** 20, 4, 64, 8192, H) > 0
     assert orth.orth_workspace_bytes(2 ** 20, 16, 64, 1024, H) > 0
     assert orth.orth_workspace_bytes(2 ** 20, 16, 64, 2048, H) == 0
-    assert orth.orth_workspace_bytes(2 ** 20, 32, 64, 512, H) == 0        # s = 32 not supported
-    assert orth.orth_workspace_bytes(2 ** 20, 8, 1024, 4096, H) == 0      # k_max s > 4096
+    assert orth.orth_workspace_bytes(2 ** 20, 32, 64, 512, H) > 0
+    assert orth.orth_workspace_bytes(2 ** 20, 32, 64, 8192, H) == 0       # leaf rows > 4096 at s = 32
+    assert orth.orth_workspace_bytes(2 ** 24, 32, 544, 4096, H) > 0       # the 3D large-block shape
+    assert orth.orth_workspace_bytes(2 ** 20, 32, 608, 4096, H) > 0       # (608 * 32 + 1024) * 8 <= 160 KB
+    assert orth.orth_workspace_bytes(2 ** 20, 32, 640, 4096, H) == 0      # (640 * 32 + 1024) * 8 > 160 KB
+    assert orth.orth_workspace_bytes(2 ** 20, 8, 1024, 4096, H) > 0       # past the former k_max s <= 4096
     code, h = orth.orth_create(2 ** 20, 8, 64, 8192, H, 4096, 1 << 40, 0)
     assert code == orth.ORTH_ERR_UNSUPPORTED
 

@@ -252,6 +252,11 @@ def test_deflation_arguments(torch_cuda):
         assert orth.orth_set_deflation(g.h, 0.0) == 0
         assert g.deflation_info() == (4, 0, 0)
         g.close()
+    # Householder leaves at s = 32: the reduction level's eigen solver stops at s = 16
+    g = Orthogonalizer(8192, 32, 64, 4096, precision=orth.ORTH_FP64_HOUSEHOLDER)
+    assert orth.orth_set_deflation(g.h, 1e-6) == orth.ORTH_ERR_UNSUPPORTED
+    assert orth.orth_set_deflation(g.h, 0.0) == 0
+    g.close()
 
 
 def test_deflation_graph_replay(torch_cuda):

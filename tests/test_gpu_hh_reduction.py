@@ -7,7 +7,8 @@ reduction "hh".
   (1.1)) after the sign fix D = diag(sign R_jj) (R's diagonal carries the
   Householder signs, U's columns the same signs), and against the oracle
   tree with the same leaves and subalgorithms, at the FP64 tolerances of
-  the tree tests; BCGS-PIP leaves against the oracle only (1e-10);
+  the tree tests; BCGS-PIP leaves against the oracle only (1e-10); s from
+  1 to 32 (s = 32 through the sub-panel factorisation);
 * Y = Q C through the representation, the allocation-free form bit for bit;
 * the refusals: exports of the reduction factors, deflation, a switch once
   the basis is non-empty, shapes past the panel kernel;
@@ -65,6 +66,8 @@ CASES = [
     (6000, 4, 32, 500, "pip"),       # BCGS-PIP leaves
     (8000, 8, 40, 1000, "mixed"),    # the mixed form's leaves
     (65536, 4, 32, 256, "hh"),       # 256 leaves: 8192 stacked rows, the panel's limit at s = 4
+    (9000, 32, 96, 1500, "hh"),      # s = 32 (sub-panel factorisation): 6 leaves, 576 stacked rows
+    (20000, 32, 64, 1000, "pip+"),   # s = 32 reduction under BCGS-PIP+ leaves: 1280 stacked rows
 ]
 
 
@@ -136,6 +139,7 @@ TREE_CASES = [
     (25000, 16, 48, 1000, 3, "hh"),      # s = 16: 25 -> 9 -> 3 -> 1
     (2 ** 20, 8, 64, 4096, 16, "hh"),    # 256 leaves -> 16 -> 1
     (24000, 8, 48, 1000, 5, "mixed"),    # the mixed form's leaves
+    (30000, 32, 96, 2000, 4, "hh"),      # s = 32: 15 -> 4 -> 1
 ]
 
 
@@ -200,8 +204,9 @@ def test_householder_reduction_refusals(torch_cuda):
     assert g.levels == 2
     assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
     g.close()
-    # s = 32, and the leaf variant may not be Householder
-    g = Orthogonalizer(8000, 32, 64, 1000)
+    # s = 32 past the sub-panel kernel (80 leaves x 64 rows > 4096), and the
+    # leaf variant may not be Householder
+    g = Orthogonalizer(80 * 1000, 32, 64, 1000)
     assert orth.orth_set_level_variants(g.h, orth.ORTH_PIP_PLUS, orth.ORTH_HOUSEHOLDER) == orth.ORTH_ERR_UNSUPPORTED
     assert orth.orth_set_level_variants(g.h, orth.ORTH_HOUSEHOLDER, orth.ORTH_PIP_PLUS) == orth.ORTH_ERR_ARG
     g.close()

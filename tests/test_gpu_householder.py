@@ -5,8 +5,10 @@ at the reduction level.
 * parity with the oracle's TreeTSPQR with Householder leaves on the same
   partition, step by step: H, R, U and the stored reflectors, at the
   tolerances of test_gpu_parity.py (ragged last leaves, one leaf, the
-  register capacity of the panel kernel, s from 1 to 16), and Y = Q C
-  through orth_apply_Q;
+  register capacity of the panel kernel, s from 1 to 32 (s = 32 factored
+  in 8-column sub-panels), bases past 256 columns whose per-leaf small
+  products stage more than 64 KB of LDS), and Y = Q C through
+  orth_apply_Q;
 * the FP64 (BCGS-PIP+) form gives the same H, R, U where both succeed;
 * a leaf whose local block is nearly dependent on its basis: the BCGS-PIP+
   leaves break down, the Householder leaves match the unique solution;
@@ -54,6 +56,10 @@ CASES = [
     (16384, 8, 64, 4096),     # s = 8 at its capacity (4096 rows), 2 chunks per leaf
     (8192, 4, 40, 8192),      # one leaf of 8192 rows (s = 4 capacity), 4 chunks
     (5000, 8, 248, 2500),     # the headline basis width (k + s = 256)
+    (6000, 32, 128, 2000),    # s = 32: the panel in 8-column sub-panels
+    (12288, 32, 96, 4096),    # s = 32 at its capacity (4096 rows)
+    (13000, 32, 352, 3000),   # s = 32, ragged (4000 rows); coefficients in two 16-column blocks
+    (8000, 16, 512, 1000),    # s = 16 past 256 columns (small products' LDS above 64 KB)
 ]
 
 
