@@ -111,9 +111,12 @@ enum orth_code {
  *                       reduction still needs u kappa^2 <= 1/2 for the
  *                       global block.  Results equal the FP64 form's to
  *                       rounding where both succeed.  Limits (else
- *                       UNSUPPORTED): s <= 16, every leaf at most 8192 rows
- *                       for s <= 4, 4096 for s = 8, 1024 for s = 16 (the
- *                       panel is held in registers), and k_max s <= 4096.
+ *                       UNSUPPORTED): every leaf at most 8192 rows for
+ *                       s <= 4, 4096 for s = 8 and s = 32 (s = 32 in
+ *                       8-column sub-panels), 1024 for s = 16 (the panel
+ *                       is held in registers), and (k_max s + s^2) doubles
+ *                       within 160 KB (the per-leaf products' LDS staging:
+ *                       k_max <= 608 at s = 32).
  *                       orth_apply_Q forms Q_k [C_i; 0] per leaf through
  *                       the same compact-WY products; orth_export_local
  *                       exports the reflectors as d_Qloc.  Single handles
@@ -304,8 +307,10 @@ int orth_set_level_variants(orth_t *h, int32_t leaf_variant, int32_t reduction_v
  * The rank of the latest step is on the device; orth_deflation_info reads
  * it.  Only ORTH_FP64_HOUSEHOLDER handles deflate: BCGS-PIP leaves break
  * down on a block that is rank deficient as a whole, since every leaf's
- * part of it is rank deficient too.  Host-side only.
- * Errors: ARG (delta < 0, >= 1 or NaN), POISONED, UNSUPPORTED (other forms).
+ * part of it is rank deficient too; and only for s <= 16 (the eigen
+ * solver's width).  Host-side only.
+ * Errors: ARG (delta < 0, >= 1 or NaN), POISONED, UNSUPPORTED (other forms,
+ * s = 32).
  */
 int orth_set_deflation(orth_t *h, double delta);
 
