@@ -376,7 +376,7 @@ hipError_t launch_defl(int s, const CholArgs &a, const DeflArgs &d, hipStream_t 
         case 8: return defl_s<8>(a, d, st);
         case 16: return defl_s<16>(a, d, st);
     }
-    // s = 32: only Householder-leaf handles deflate and those stop at s = 16
+    // s = 32: orth_set_deflation refuses it (the eigen solver holds s <= 16 columns)
     return hipErrorInvalidValue;
 }
 
