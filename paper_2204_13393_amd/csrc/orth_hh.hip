@@ -40,6 +40,58 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// acc[j] += sum over c in [c0, c1) of t(c) L[c ls + j], c in order: the
+// contraction loop of the per-leaf products for blocks of 32 columns.
+// These kernels run one wave per SIMD (their LDS staging takes up to
+// 160 KB), so the loads of t (T or V, from global memory) are issued
+// kHhRing columns ahead; the scheduling barrier keeps each column's LDS
+// reads next to its products (hoisted, they would take the registers of
+// all the columns in flight).
+// t(c) = valid ? p[c stride] : 0; every load is unconditional (p is a valid
+// row for every lane, c is clamped into [c0, c1)) so that no value is
+// needed before its use.
+constexpr int kHhRing = 8;
+template <int NJ>
+__device__ __forceinline__ void hh_ring_contract(double (&acc)[NJ], int c0, int c1, const double *p, int64_t stride,
+                                                 bool valid, const double *L, int ls) {
+    // the range is the same for the whole wave: scalar loop control
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c1 = __builtin_amdgcn_readfirstlane(c1);
+    if (c0 >= c1) return;
+    double ring[kHhRing];
+    // (issued in ring order, as in the loop, so that the waits before each
+    // use count the loads still in flight)
+#pragma unroll
+    for (int u = 0; u < kHhRing; ++u) {
+        ring[u] = p[(int64_t)min(c0 + u, c1 - 1) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // whole groups of kHhRing columns, no branch inside a group: a column
+    // past c1 adds t = 0 times a finite entry of row c1 - 1, which leaves
+    // every sum as it is.  The LDS row of the next column is read while the
+    // current one is multiplied.
+    double cur[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) cur[j] = L[c0 * ls + j];
+    for (int c = c0; c < c1; c += kHhRing) {
+#pragma unroll
+        for (int u = 0; u < kHhRing; ++u) {
+            const int cc = c + u;
+            const double t = (valid && cc < c1) ? ring[u] : 0.0;
+            ring[u] = p[(int64_t)min(cc + kHhRing, c1 - 1) * stride];
+            const double *Ln = L + min(cc + 1, c1 - 1) * ls;
+            double nx[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) nx[j] = Ln[j];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[j] = fma(t, cur[j], acc[j]);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) cur[j] = nx[j];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 // Per-leaf small matrices, k_max x k_max doubles each, at T + leaf 3 k_max^2:
 //   Tc  the compact-WY factor T, column-major (element (r, c) at c k_max + r)
 //   Tr  the same factor row-major (element (r, c) at r k_max + c)
@@ -77,15 +129,20 @@ __global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
         const int r = rb + tid;
         // Y[r] = sum over c <= r of T(c, r) M[c]: T row c, lanes along r
         const int wmax = rb + (tid & ~63) + 63;
-        const int cend = wmax + 1 < k ? wmax + 1 : k;
+        // (a wave whose rows all lie past k has nothing to form)
+        const int cend = rb + (tid & ~63) >= k ? 0 : (wmax + 1 < k ? wmax + 1 : k);
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
-        #pragma unroll 4      // four loads in flight per lane
-        for (int c = 0; c < cend; ++c) {
-            const double t = r < k ? Tr[(int64_t)c * km + r] : 0.0;
+        if constexpr (S >= 32) {
+            hh_ring_contract(acc, 0, cend, Tr + (r < k ? r : k - 1), km, r < k, lds, S);
+        } else {
+            #pragma unroll 4      // four loads in flight per lane
+            for (int c = 0; c < cend; ++c) {
+                const double t = r < k ? Tr[(int64_t)c * km + r] : 0.0;
 #pragma unroll
-            for (int j = 0; j < S; ++j) acc[j] = fma(t, lds[c * S + j], acc[j]);
+                for (int j = 0; j < S; ++j) acc[j] = fma(t, lds[c * S + j], acc[j]);
+            }
         }
         if (r < k) {
 #pragma unroll
@@ -258,14 +315,41 @@ struct HhSubCtx {
     int k, cb, nl, it, tid, lane, wave;
 };
 
-// the waves' partial sums part[c], c >= J0, into sh.red[b] (then a barrier)
+// The wave sums of eight values per lane with ten exchanges instead of
+// eight butterflies of six: at each of the first three steps a lane keeps
+// half of its values and adds its partner's matching half, so afterwards
+// lane l holds value (l >> 3) & 7 summed over the eight lanes that differ in
+// bits 3..5; three more steps add over bits 0..2.  Lanes with l & 7 == 0
+// end with the sum of value l >> 3 over the wave.
+__device__ __forceinline__ double wave_sum8_transposed(const double (&v)[8], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    double w[4], x[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = b5 ? v[4 + i] : v[i], give = b5 ? v[i] : v[4 + i];
+        w[i] = keep + __shfl_xor(give, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = b4 ? w[2 + i] : w[i], give = b4 ? w[i] : w[2 + i];
+        x[i] = keep + __shfl_xor(give, 16, 64);
+    }
+    double y = (b3 ? x[1] : x[0]) + __shfl_xor(b3 ? x[0] : x[1], 8, 64);
+    y += __shfl_xor(y, 4, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
+// the waves' partial sums part[c] (c >= J0; the others are not used) into
+// sh.red[b] (then a barrier)
 template <int SB, int J0>
 __device__ __forceinline__ void hh_sub_partials(double (&part)[SB], HhSubShared<SB> &sh, int b, int lane, int wave) {
+    static_assert(SB == 8, "eight values per lane");
 #pragma unroll
-    for (int c = J0; c < SB; ++c) {
-        const double w = wave_sum(part[c]);
-        if (lane == 0) sh.red[b][wave][c] = w;
-    }
+    for (int c = 0; c < J0; ++c) part[c] = 0.0;
+    const double y = wave_sum8_transposed(part, lane);
+    if ((lane & 7) == 0) sh.red[b][wave][lane >> 3] = y;
 }
 
 // One column J of a sub-panel (the steps of k_hh_panel's column loop), as a
@@ -495,11 +579,15 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
         double acc[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) acc[j] = 0.0;
-        #pragma unroll 4      // four loads in flight per lane
-        for (int c = wmin; c < k; ++c) {
-            const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
+        if constexpr (S >= 32) {
+            hh_ring_contract(acc, wmin, k, Tc + (r < k ? r : k - 1), km, r < k, W, S);
+        } else {
+            #pragma unroll 4      // four loads in flight per lane
+            for (int c = wmin; c < k; ++c) {
+                const double t = r < k ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
-            for (int j = 0; j < S; ++j) acc[j] = fma(t, W[c * S + j], acc[j]);
+                for (int j = 0; j < S; ++j) acc[j] = fma(t, W[c * S + j], acc[j]);
+            }
         }
         if (r < k) {
 #pragma unroll
@@ -554,11 +642,15 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
             double acc[CB];
 #pragma unroll
             for (int j = 0; j < CB; ++j) acc[j] = 0.0;
-            #pragma unroll 4      // four loads in flight per lane
-            for (int r = wmin; r < K; ++r) {
-                const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
+            if constexpr (S >= 32) {
+                hh_ring_contract(acc, wmin, K, Vr + (c < K ? c : K - 1), km, c < K, C, CB);
+            } else {
+                #pragma unroll 4      // four loads in flight per lane
+                for (int r = wmin; r < K; ++r) {
+                    const double v = c < K ? Vr[(int64_t)r * km + c] : 0.0;
 #pragma unroll
-                for (int j = 0; j < CB; ++j) acc[j] = fma(v, C[r * CB + j], acc[j]);
+                    for (int j = 0; j < CB; ++j) acc[j] = fma(v, C[r * CB + j], acc[j]);
+                }
             }
             if (c < K) {
 #pragma unroll
@@ -573,11 +665,15 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
             double acc[CB];
 #pragma unroll
             for (int j = 0; j < CB; ++j) acc[j] = 0.0;
-            #pragma unroll 4      // four loads in flight per lane
-            for (int c = wmin; c < K; ++c) {
-                const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
+            if constexpr (S >= 32) {
+                hh_ring_contract(acc, wmin, K, Tc + (r < K ? r : K - 1), km, r < K, B, CB);
+            } else {
+                #pragma unroll 4      // four loads in flight per lane
+                for (int c = wmin; c < K; ++c) {
+                    const double t = r < K ? Tc[(int64_t)c * km + r] : 0.0;
 #pragma unroll
-                for (int j = 0; j < CB; ++j) acc[j] = fma(t, B[c * CB + j], acc[j]);
+                    for (int j = 0; j < CB; ++j) acc[j] = fma(t, B[c * CB + j], acc[j]);
+                }
             }
             if (r < K) {
 #pragma unroll
