@@ -96,18 +96,26 @@ constexpr int kReduceGroup = 16;      // slots pre-summed per group at a single-
 __host__ __device__ inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Fixed-order sum p[0] + p[stride] + ... + p[(cnt-1) stride], added in slot
-// order; the loads are issued eight at a time so they are in flight
-// together (the additions, and so the bits, are those of the plain loop).
+// order; the loads are issued sixteen (then eight, then four) at a time so
+// they are in flight together (the additions, and so the bits, are those of
+// the plain loop).  A small problem's leaf sums 32 slots: two rounds of
+// load latency instead of four.
+template <int B>
+__device__ __forceinline__ void slot_sum_batches(const double *p, int64_t stride, int cnt, int &q, double &v) {
+    for (; q + B <= cnt; q += B) {
+        double t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v += t[u];
+    }
+}
 __device__ __forceinline__ double slot_sum(const double *p, int64_t stride, int cnt) {
     double v = 0.0;
     int q = 0;
-    for (; q + 8 <= cnt; q += 8) {
-        double t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(q + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v += t[u];
-    }
+    slot_sum_batches<16>(p, stride, cnt, q, v);
+    slot_sum_batches<8>(p, stride, cnt, q, v);
+    slot_sum_batches<4>(p, stride, cnt, q, v);
     for (; q < cnt; ++q) v += p[(int64_t)q * stride];
     return v;
 }

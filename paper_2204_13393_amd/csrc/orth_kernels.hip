@@ -461,6 +461,68 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Steps 3-4 of the per-leaf Cholesky: N^T N = sm (upper, right-looking) and
+// N^{-1}, in one wave: lane j < S owns column j in registers and the pivot
+// row is broadcast with readlane, so no step needs a workgroup barrier.
+// Returns false after recording a failed pivot (then nm and ni are not set).
+template <int S>
+__device__ __forceinline__ bool chol_factor_one_wave(const CholArgs &a, int leaf, const double *sm, double *nm,
+                                                     double *ni, int &bad, int wave, int lane, int tid) {
+    if (wave == 0) {
+        const int j = lane;
+        const bool own = j < S;
+        double col[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) col[i] = own ? sm[i * S + j] : 0.0;
+        int fail = 0;
+#pragma unroll
+        for (int kk = 0; kk < S; ++kk) {
+            const double piv = readlane_d(col[kk], kk);
+            if (!(piv > 0.0) || !isfinite(piv)) { fail = kk + 1; break; }
+            const double nkk = sqrt(piv);
+            const double r = j == kk ? nkk : (j > kk && own ? col[kk] / nkk : 0.0);   // N[kk][j]
+            col[kk] = r;
+#pragma unroll
+            for (int i = kk + 1; i < S; ++i) {
+                const double ri = readlane_d(r, i);                                   // N[kk][i]
+                if (j >= i && own) col[i] -= ri * r;
+            }
+        }
+        if (fail) {
+            if (lane == 0) bad = fail;
+        } else if (own) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                if (i > j) col[i] = 0.0;
+                nm[i * S + j] = col[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) chol_fail(a, leaf, bad - 1);
+        return false;
+    }
+    if (a.cond && leaf == 0 && tid == 0) atomicAdd(&a.status->fallbacks, 1);
+    if (wave == 0 && lane < S) {
+        // back substitution N x = e_j, x[l] = 0 past j; the rows of N are read
+        // by every lane at once (LDS broadcast)
+        const int j = lane;
+        double x[S];
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = i + 1; l < S; ++l) t = fma(nm[i * S + l], x[l], t);
+            x[i] = i > j ? 0.0 : (i == j ? 1.0 / nm[i * S + i] : -t / nm[i * S + i]);
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) ni[i * S + j] = x[i];
+    }
+    __syncthreads();
+    return true;
+}
+
 // The same steps for s = 16, 32 with the two products whose length grows with
 // k on the matrix cores: P^T P (the four waves take interleaved 4-row steps
 // and their partial sums are added in wave order) and, after the second
@@ -537,58 +599,7 @@ __device__ __forceinline__ void chol_wide_body(const CholArgs &a, int bx) {
     __syncthreads();
 
     // 3-4. N^T N = sm (upper) and N^{-1}, one wave, lane j < S owns column j
-    if (wave == 0) {
-        const int j = lane;
-        const bool own = j < S;
-        double col[S];
-#pragma unroll
-        for (int i = 0; i < S; ++i) col[i] = own ? sm[i * S + j] : 0.0;
-        int fail = 0;
-#pragma unroll
-        for (int kk = 0; kk < S; ++kk) {
-            const double piv = readlane_d(col[kk], kk);
-            if (!(piv > 0.0) || !isfinite(piv)) { fail = kk + 1; break; }
-            const double nkk = sqrt(piv);
-            const double r = j == kk ? nkk : (j > kk && own ? col[kk] / nkk : 0.0);   // N[kk][j]
-            col[kk] = r;
-#pragma unroll
-            for (int i = kk + 1; i < S; ++i) {
-                const double ri = readlane_d(r, i);                                   // N[kk][i]
-                if (j >= i && own) col[i] -= ri * r;
-            }
-        }
-        if (fail) {
-            if (lane == 0) bad = fail;
-        } else if (own) {
-#pragma unroll
-            for (int i = 0; i < S; ++i) {
-                if (i > j) col[i] = 0.0;
-                nm[i * S + j] = col[i];
-            }
-        }
-    }
-    __syncthreads();
-    if (bad) {
-        if (tid == 0) chol_fail(a, leaf, bad - 1);
-        return;
-    }
-    if (a.cond && leaf == 0 && tid == 0) atomicAdd(&a.status->fallbacks, 1);
-    if (wave == 0 && lane < S) {
-        // back substitution N x = e_j, x[l] = 0 past j; the rows of N are read
-        // by every lane at once (LDS broadcast)
-        const int j = lane;
-        double x[S];
-#pragma unroll
-        for (int i = S - 1; i >= 0; --i) {
-            double t = 0.0;
-#pragma unroll
-            for (int l = i + 1; l < S; ++l) t = fma(nm[i * S + l], x[l], t);
-            x[i] = i > j ? 0.0 : (i == j ? 1.0 / nm[i * S + i] : -t / nm[i * S + i]);
-        }
-#pragma unroll
-        for (int i = 0; i < S; ++i) ni[i * S + j] = x[i];
-    }
-    __syncthreads();
+    if (!chol_factor_one_wave<S>(a, leaf, sm, nm, ni, bad, wave, lane, tid)) return;
     if (a.sweep == 1) {
         for (int e = tid; e < S * S; e += kThreads) { recN1[e] = nm[e]; recN1i[e] = ni[e]; }
     } else {
@@ -657,13 +668,16 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
     double *recN2i = recP2 + (int64_t)a.kmax * S;
     double *recP = a.sweep == 1 ? recP1 : recP2;
 
-    // 1. fixed-order slot sum: P -> leaf record, G -> LDS
+    // 1. fixed-order slot sum: P -> leaf record, G -> LDS (and P too when it
+    //    fits one LDS chunk: step 2 then reads no global memory)
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
+    const bool p_in_lds = k <= kCholCB;
     for (int e = tid; e < ncol * S; e += kThreads) {
         const double v = slot_sum(a.partials + (int64_t)first * a.part_stride + e, a.part_stride, cnt);
         if (e < k * S) {
             recP[e] = v;
+            if (p_in_lds) pc[e] = v;
             if (a.pc && a.sweep == 2) a.pc[(int64_t)leaf * a.pc_stride + (int64_t)(e / S) * 2 * S + e % S] = v;
         }
         else gs[e - k * S] = v;
@@ -677,8 +691,10 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
     for (int m = 0; m < EPT; ++m) d[m] = 0.0;
     for (int c0 = 0; c0 < k; c0 += kCholCB) {
         const int cb = (k - c0) < kCholCB ? (k - c0) : kCholCB;
-        for (int e = tid; e < cb * S; e += kThreads) pc[e] = recP[(int64_t)c0 * S + e];
-        __syncthreads();
+        if (!p_in_lds) {
+            for (int e = tid; e < cb * S; e += kThreads) pc[e] = recP[(int64_t)c0 * S + e];
+            __syncthreads();
+        }
 #pragma unroll
         for (int m = 0; m < EPT; ++m) {
             const int e = tid + kThreads * m;
@@ -699,40 +715,11 @@ __device__ __forceinline__ void chol_narrow_body(const CholArgs &a, int bx) {
         }
     }
     __syncthreads();
-    // 3. right-looking upper Cholesky: N^T N = sm
-    for (int kk = 0; kk < S; ++kk) {
-        if (tid == kk) {
-            const double piv = sm[kk * S + kk];
-            if (!(piv > 0.0) || !isfinite(piv)) bad = kk + 1;
-            else nm[kk * S + kk] = sqrt(piv);
-        }
-        __syncthreads();
-        if (bad) break;
-        if (tid > kk && tid < S) nm[kk * S + tid] = sm[kk * S + tid] / nm[kk * S + kk];
-        __syncthreads();
-        if (tid > kk && tid < S) {
-            const int j = tid;
-            const double nkj = nm[kk * S + j];
-            for (int i = kk + 1; i <= j; ++i) sm[i * S + j] -= nm[kk * S + i] * nkj;
-        }
-        __syncthreads();
+    // 3-4. N^T N = sm and N^{-1} in one wave (as for the wide blocks)
+    {
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        if (!chol_factor_one_wave<S>(a, leaf, sm, nm, ni, bad, wave, lane, tid)) return;
     }
-    if (bad) {
-        if (tid == 0) chol_fail(a, leaf, bad - 1);
-        return;
-    }
-    if (a.cond && leaf == 0 && tid == 0) atomicAdd(&a.status->fallbacks, 1);
-    // 4. N^{-1}, lane j owns column j
-    if (tid < S) {
-        const int j = tid;
-        ni[j * S + j] = 1.0 / nm[j * S + j];
-        for (int i = j - 1; i >= 0; --i) {
-            double t = 0.0;
-            for (int l = i + 1; l <= j; ++l) t = fma(nm[i * S + l], ni[l * S + j], t);
-            ni[i * S + j] = -t / nm[i * S + i];
-        }
-    }
-    __syncthreads();
     if (a.sweep == 1) {
         for (int e = tid; e < S * S; e += kThreads) { recN1[e] = nm[e]; recN1i[e] = ni[e]; }
     } else {
