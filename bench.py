@@ -526,6 +526,14 @@ def bench_lap3d(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+    if args.tune_tiles:
+        # (before the bench's own buffers: the tuner holds a workspace of its own)
+        from paper_2204_13393_amd import autotune
+        t0 = time.perf_counter()
+        best_t, cand_t = autotune.measure_tiles(n, s, kmax, leaf, steps=kmax // s)
+        tune_s = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+        print(f"[bench] lap3d: tile tuner picked {best_t} in {tune_s:.1f} s", file=sys.stderr, flush=True)
     print("[bench] lap3d: generating the start blocks", file=sys.stderr, flush=True)
     R0_normal = torch.from_numpy(np.ascontiguousarray(normal_block(n, s, 5).T)).to(dev)
     # the configured start block: sigma_j = 10^(-8 j / 31)
@@ -550,9 +558,9 @@ def bench_lap3d(args):
 
     fallbacks = {}      # steps whose first sweep was redone in FP64, per form
 
-    def run(profiled, precision=orth.ORTH_FP64, block="sigma"):
+    def run(profiled, precision=orth.ORTH_FP64, block="sigma", tiles=None):
         R0 = start[block]
-        code, h = orth.orth_create(n, s, kmax, leaf, precision, ws_ptr, nbytes, sp)
+        code, h = orth.orth_create_tiles(n, s, kmax, leaf, precision, 0, tiles, ws_ptr, nbytes, sp)
         if code:
             raise orth.OrthError("orth_create", code)
         if profiled:
@@ -582,14 +590,14 @@ def bench_lap3d(args):
             raise RuntimeError(f"breakdown {info}")
         return ms, prof
 
-    def timed(precision, block="sigma", profile=True):
+    def timed(precision, block="sigma", profile=True, tiles=None):
         """Warmup, args.steps unprofiled runs (the time), then one run with
         every launch bracketed by events (the per-class breakdown)."""
         for _ in range(args.warmup):
-            run(False, precision, block)
+            run(False, precision, block, tiles)
         times = []
         for _ in range(args.steps):
-            ms, _ = run(False, precision, block)
+            ms, _ = run(False, precision, block, tiles)
             times.append(ms)
         G = torch.mm(V, V.t())
         G -= torch.eye(kmax, dtype=torch.float64, device=dev)
@@ -603,6 +611,16 @@ def bench_lap3d(args):
     best_normal, _, e_perp_normal = timed(orth.ORTH_FP64, "normal", profile=False)
     print("[bench] lap3d: householder leaves", file=sys.stderr, flush=True)
     best_hh, prof_hh, e_perp_hh = timed(orth.ORTH_FP64_HOUSEHOLDER)
+    tiles = None
+    if args.tune_tiles:
+        if orth.orth_tiles_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, 0, best_t) > nbytes:
+            raise RuntimeError("the pick needs a larger workspace than the bench holds")
+        ms_t, _, ep_t = timed(orth.ORTH_FP64, profile=False, tiles=best_t)
+        tiles = {"pick": list(best_t), "tuning_s": tune_s,
+                 "candidates_ms": {str(tuple(c)): m for c, m in cand_t},
+                 "ms_per_sequence_pick": ms_t, "pick_vs_plan": ms_t / best, "e_perp": ep_t}
+        print(f"[bench] lap3d tiles {best_t}: {ms_t:.2f} ms against {best:.2f} ms (tuned in {tune_s:.1f} s)",
+              file=sys.stderr, flush=True)
     p = n // leaf
     widths = [j * s for j in range(steps + 1)]
     total_bytes = sum(step_bytes(n, s, p, k) for k in widths)
@@ -638,6 +656,7 @@ def bench_lap3d(args):
             "kernels": {name: {"ms_total": ms, "launches": cnt, "avg_us": ms / cnt * 1e3}
                         for name, (ms, cnt) in prof_hh.items() if cnt},
         },
+        "tile_tuner": tiles,
         "normal_start_block": {
             "start": "N(0,1), default_rng(5)",
             "ms_per_sequence": best_normal,
@@ -855,6 +874,9 @@ def main():
     ap.add_argument("--flat-blocks", default="",
                     help="default workload: also time the FP64 sequence with FlatTSPQR over this many "
                          "row blocks (comma-separated counts)")
+    ap.add_argument("--tune-tiles", action="store_true",
+                    help="default and lap3d workloads: run the tile tuner (orth_tune_tiles) at the shape and "
+                         "time the FP64 sequence with its pick")
     ap.add_argument("--householder-tree", type=int, default=0,
                     help="default workload: also time Householder at every level (Householder leaves and a "
                          "Householder reduction tree of this fan-in)")
@@ -1087,7 +1109,7 @@ def main():
     # over P row blocks (Sec. 4.2)
     fan_ins = [int(g) for g in args.tree_fan_ins.split(",") if g] if args.tree_fan_ins else []
     flat_ps = [int(q) for q in args.flat_blocks.split(",") if q] if args.flat_blocks else []
-    if fan_ins or flat_ps or args.householder_tree:
+    if fan_ins or flat_ps or args.householder_tree or args.tune_tiles:
         del ws
         torch.cuda.empty_cache()
 
@@ -1150,6 +1172,28 @@ def main():
         hh_tree = {"fan_in": g, "levels": levels, "ms_per_step": ms, "e_perp": ep, "vs_fp64": ms / ms_per_step}
         print(f"[bench] householder leaves and householder tree, fan-in {g}: {levels} levels, {ms:.2f} ms per "
               f"sequence, e_perp {ep:.2e}", file=sys.stderr, flush=True)
+    tiles = None
+    if args.tune_tiles:
+        from paper_2204_13393_amd import autotune
+        t0 = time.perf_counter()
+        best_t, cand_t = autotune.measure_tiles(n, s, kmax, leaf, steps=kmax // s)
+        tune_s = time.perf_counter() - t0
+        print(f"[bench] tile tuner: {len(cand_t)} candidates in {tune_s:.1f} s, pick {best_t}",
+              file=sys.stderr, flush=True)
+        _, ms_def, _ = time_arrangement(
+            orth.orth_tiles_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, 0, None),
+            lambda ptr, nb: orth.orth_create_tiles(n, s, kmax, leaf, orth.ORTH_FP64, 0, None, ptr, nb, sptr),
+            "plan's own tiles")
+        _, ms_t, ep_t = time_arrangement(
+            orth.orth_tiles_workspace_bytes(n, s, kmax, leaf, orth.ORTH_FP64, 0, best_t),
+            lambda ptr, nb: orth.orth_create_tiles(n, s, kmax, leaf, orth.ORTH_FP64, 0, best_t, ptr, nb, sptr),
+            f"tiles {best_t}")
+        tiles = {"pick": list(best_t), "tuning_s": tune_s,
+                 "candidates_ms": {str(tuple(c)): m for c, m in cand_t},
+                 "ms_per_step_plan_tiles": ms_def, "ms_per_step_pick": ms_t, "pick_vs_plan": ms_t / ms_def,
+                 "e_perp": ep_t}
+        print(f"[bench] tiles {best_t}: {ms_t:.2f} ms per sequence against {ms_def:.2f} ms with the plan's own",
+              file=sys.stderr, flush=True)
     flats = {}
     for q in flat_ps:
         rows = n // q
@@ -1239,6 +1283,8 @@ def main():
         out["flat_tspqr"] = flats
     if hh_tree:
         out["householder_every_level"] = hh_tree
+    if tiles:
+        out["tile_tuner"] = tiles
     print(json.dumps(out), flush=True)
 
 

@@ -203,6 +203,52 @@ int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int
                      int32_t fan_in, void *d_workspace, size_t workspace_bytes, void *stream,
                      orth_t **out);
 
+/*
+ * Tile shapes of the leaf passes (resource management; the launch-shape
+ * entries of the local-problem-size study, Sec. 6.2): how many rows of a
+ * leaf one workgroup takes in the leaf Grams and in the leaf row updates,
+ * and which row-update kernel runs for s >= 16.
+ *   gram_rows      0 (the plan's own: 2048, halved for small problems down
+ *                  to 128 while a launch has fewer workgroups than the GPU
+ *                  has compute units) or a power of two in [128, 8192].
+ *                  Other heights change the order in which the leaf Grams'
+ *                  partial sums are added (results to rounding).
+ *   update_rows    0 (the plan's own: 512, halved the same way down to 64)
+ *                  or a power of two in [64, 8192]; results unchanged.
+ *   update_kernel  ORTH_TILE_AUTO: LDS-staged row updates for s >= 16 where
+ *                  their layout conditions hold (even leaf heights or one
+ *                  leaf), register-streamed otherwise; ORTH_TILE_REGISTER:
+ *                  the register-streamed kernel at every width (results
+ *                  unchanged: the two kernels form the same products).
+ */
+typedef struct orth_tiles {
+    int32_t gram_rows;
+    int32_t update_rows;
+    int32_t update_kernel;
+} orth_tiles;
+
+enum orth_tile_kernel {
+    ORTH_TILE_AUTO = 0,
+    ORTH_TILE_REGISTER = 1
+};
+
+/*
+ * orth_tiles_workspace_bytes / orth_create_tiles -- as
+ * orth_tree_workspace_bytes and orth_create_tree with the given tile shapes
+ * (tiles may be NULL: the plan's own).  Smaller Gram tiles mean more partial
+ * sums, so the workspace depends on gram_rows.  Errors as orth_create_tree;
+ * invalid tile values: ARG (orth_tiles_workspace_bytes returns 0).
+ */
+size_t orth_tiles_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows,
+                                  int32_t precision, int32_t fan_in, const orth_tiles *tiles);
+int orth_create_tiles(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                      int32_t fan_in, const orth_tiles *tiles, void *d_workspace,
+                      size_t workspace_bytes, void *stream, orth_t **out);
+
+/* orth_tiles_in_use -- the tile shapes the handle's plan resolved (heights
+ * in rows, never 0).  Host state only.  Errors: ARG. */
+int orth_tiles_in_use(const orth_t *h, orth_tiles *tiles);
+
 /* orth_tree_levels -- number of reduction levels (1 for a single level) and
  * the fan-in in use (0 for a single level).  Host state only.  Resource
  * management of the Sec. 4.1 recursion, no further passage. */
@@ -577,6 +623,25 @@ size_t orth_tune_tree_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32
 int orth_tune_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t steps, void *d_workspace,
                    size_t workspace_bytes, void *stream, int32_t *best_fan_in, int32_t *cand_fan_in,
                    double *cand_ms, int32_t max_cand, int32_t *ncand);
+
+/*
+ * orth_tune_tiles_workspace_bytes / orth_tune_tiles -- the tile shapes of
+ * the leaf passes (orth_tiles; the rows-per-tile and kernel-variant entries
+ * of the tuner's search space) for single handles of the given leaf height,
+ * single reduction level.  It times `steps` calls (the synthetic blocks of
+ * orth_tune_leaf_rows) through orth_create_tiles handles of every candidate:
+ * the plan's own choice {0, 0, ORTH_TILE_AUTO} first, then gram_rows in
+ * {1024, 2048, 4096} x update_rows in {256, 512, 1024, 2048}, each with
+ * ORTH_TILE_AUTO and, for s >= 16, ORTH_TILE_REGISTER; and writes the fastest
+ * to *best (the plan's own when it is within 2% of the fastest).
+ * Synchronous.  Workspace, steps, cand / cand_ms / ncand and errors as
+ * orth_tune_tree; orth_tune_tiles_workspace_bytes returns 0 for invalid
+ * sizes.
+ */
+size_t orth_tune_tiles_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows);
+int orth_tune_tiles(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t steps, void *d_workspace,
+                    size_t workspace_bytes, void *stream, orth_tiles *best, orth_tiles *cand, double *cand_ms,
+                    int32_t max_cand, int32_t *ncand);
 
 #ifdef __cplusplus
 }

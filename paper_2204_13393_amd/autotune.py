@@ -77,6 +77,24 @@ def measure_fan_in(n, s, k_max, leaf_rows, steps=None, stream=None):
     return best, cand
 
 
+def measure_tiles(n, s, k_max, leaf_rows, steps=None, stream=None):
+    """Run the library's tile tuner once: (best (gram_rows, update_rows,
+    update_kernel), [(candidate, ms), ...]); (0, 0, 0) is the plan's own."""
+    import torch
+    steps = steps or min(k_max // s, 32)
+    nbytes = orth.orth_tune_tiles_workspace_bytes(n, s, k_max, leaf_rows)
+    if nbytes == 0:
+        raise orth.OrthError("orth_tune_tiles_workspace_bytes", orth.ORTH_ERR_ARG)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    sp = (stream or torch.cuda.current_stream()).cuda_stream
+    code, best, cand = orth.orth_tune_tiles(n, s, k_max, leaf_rows, steps, base, nbytes, sp)
+    del ws
+    if code != orth.ORTH_OK:
+        raise orth.OrthError("orth_tune_tiles", code)
+    return best, cand
+
+
 def tune_leaf_rows(n, s, k_max, steps=None, copies=1, cache=None, stream=None):
     """Measured leaf height for one shape, cached per device and shape."""
     import torch

@@ -119,6 +119,7 @@ struct Plan {
     // chunk heights (rows per workgroup): leaf Gram, leaf row updates,
     // reduction Gram, reduction row updates
     int32_t cL, cF, cR, cRR;
+    bool rowreg = false;         // leaf row updates on the register-streamed kernel at every width
     // region offsets in doubles
     int64_t oQ, oT, oY, oU1L, oU1R, oCA, oPL, oPR, oPR2, oSL, oSR, oST, oQH, oCL, oTH, oCA2, oDF, total;
     // Householder reduction (every node's stacked problem within one
@@ -148,10 +149,21 @@ LevelGeom hh_level_geom(const Plan &pl, int l, int chunk) {
     return make_leaf_geom(rows, (int32_t)((int64_t)hh_node_children(pl, l) * pl.kmax), pl.nnode[l], chunk);
 }
 
+bool is_pow2_in(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+// tile heights a caller may ask for (0: the plan's own choice)
+bool valid_tiles(const orth_tiles *t) {
+    if (!t) return true;
+    if (t->gram_rows != 0 && !is_pow2_in(t->gram_rows, 128, 8192)) return false;
+    if (t->update_rows != 0 && !is_pow2_in(t->update_rows, 64, 8192)) return false;
+    return t->update_kernel == ORTH_TILE_AUTO || t->update_kernel == ORTH_TILE_REGISTER;
+}
+
 bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t precision, Plan &pl,
-               int *why, int32_t fan_in = 0, bool blocked = false) {
+               int *why, int32_t fan_in = 0, bool blocked = false, const orth_tiles *tiles = nullptr) {
     *why = ORTH_ERR_ARG;
     if (fan_in < 0 || fan_in == 1) return false;
+    if (!valid_tiles(tiles)) return false;
     if (n < 1 || !valid_s(s) || kmax < s || kmax % s != 0) return false;
     if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32 && precision != ORTH_FP64_HOUSEHOLDER)
         return false;
@@ -216,6 +228,10 @@ bool make_plan(int64_t n, int32_t s, int32_t kmax, int32_t leaf_rows, int32_t pr
         pl.cF = shrink(kFinalChunk, 64, leaf_chunks);
         pl.cR = shrink(kRootChunk, 128, root_chunks);
         pl.cRR = shrink(kRootRowChunk, 64, root_chunks);
+        // the caller's tile heights for the leaf passes
+        if (tiles && tiles->gram_rows) pl.cL = tiles->gram_rows;
+        if (tiles && tiles->update_rows) pl.cF = tiles->update_rows;
+        pl.rowreg = tiles && tiles->update_kernel == ORTH_TILE_REGISTER;
     }
     // the Householder reduction is offered when every node's stacked problem
     // (its children's k_max physical rows each) fits the panel kernel
@@ -515,11 +531,34 @@ int orth_create(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t 
 
 int orth_create_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
                      int32_t fan_in, void *d_workspace, size_t workspace_bytes, void *stream, orth_t **out) {
+    return orth_create_tiles(n, s, k_max, leaf_rows, precision, fan_in, nullptr, d_workspace, workspace_bytes,
+                             stream, out);
+}
+
+size_t orth_tiles_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                                  int32_t fan_in, const orth_tiles *tiles) {
+    Plan pl;
+    int why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in, true, tiles)) return 0;
+    return (size_t)pl.total * sizeof(double);
+}
+
+int orth_tiles_in_use(const orth_t *h, orth_tiles *tiles) {
+    if (!h || !tiles) return ORTH_ERR_ARG;
+    tiles->gram_rows = h->pl.cL;
+    tiles->update_rows = h->pl.cF;
+    tiles->update_kernel = h->pl.rowreg ? ORTH_TILE_REGISTER : ORTH_TILE_AUTO;
+    return ORTH_OK;
+}
+
+int orth_create_tiles(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t precision,
+                      int32_t fan_in, const orth_tiles *tiles, void *d_workspace, size_t workspace_bytes,
+                      void *stream, orth_t **out) {
     if (!out) return ORTH_ERR_ARG;
     *out = nullptr;
     Plan pl;
     int why;
-    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in, true)) return why;
+    if (!make_plan(n, s, k_max, leaf_rows, precision, pl, &why, fan_in, true, tiles)) return why;
     if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 ||
         workspace_bytes < (size_t)pl.total * sizeof(double))
         return ORTH_ERR_WORKSPACE;
@@ -772,6 +811,7 @@ int run_level(orth_ctx *h, const LevelRun &L, int k, bool two) {
     f.sweep = 1;
     f.k = k;
     f.geom = L.rgeom;
+    f.reg_only = (L.level == 0 && pl.rowreg) ? 1 : 0;
     f.small = L.small;
     f.small_stride = small_stride(kmax, s);
     f.kmax = kmax;
@@ -867,6 +907,7 @@ int run_leaves_hh(orth_ctx *h, const double *d_W, int64_t ldw, int k) {
         f.sweep = 1;
         f.k = k;
         f.geom = leaf_geom(pl, pl.cF);
+        f.reg_only = pl.rowreg ? 1 : 0;
         f.small = h->SL();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -1095,6 +1136,7 @@ int finalize_leaves_hh(orth_ctx *h, double *d_U, int64_t ldu, int k) {
     f.sweep = 2;
     f.k = k;
     f.geom = leaf_geom(pl, pl.cF);
+    f.reg_only = pl.rowreg ? 1 : 0;
     f.small = h->SL();
     f.small_stride = small_stride(kmax, s);
     f.kmax = kmax;
@@ -1368,6 +1410,7 @@ int orth_step(orth_t *h, const double *d_W, int64_t ldw, double *d_H, int64_t ld
         f.sweep = 2;
         f.k = k;
         f.geom = leaf_geom(pl, pl.cF);
+        f.reg_only = pl.rowreg ? 1 : 0;
         f.small = h->SL();
         f.small_stride = small_stride(kmax, s);
         f.kmax = kmax;
@@ -2274,6 +2317,118 @@ int orth_tune_tree(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32
         cand_ms[c] = times[c];
     }
     if (ncand) *ncand = (int32_t)cand.size();
+    return ORTH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// tile candidates: the plan's own choice first, then leaf Gram rows x leaf
+// row-update rows per workgroup (and, from s = 16, the register-streamed
+// row updates against the LDS-staged ones)
+std::vector<orth_tiles> tune_tile_candidates(int32_t s) {
+    std::vector<orth_tiles> c{orth_tiles{0, 0, ORTH_TILE_AUTO}};
+    for (int32_t g : {1024, 2048, 4096})
+        for (int32_t u : {256, 512, 1024, 2048})
+            for (int32_t kern = ORTH_TILE_AUTO; kern <= (s >= 16 ? ORTH_TILE_REGISTER : ORTH_TILE_AUTO); ++kern)
+                c.push_back(orth_tiles{g, u, kern});
+    return c;
+}
+
+// [handle workspace (the largest candidate's)][W][U][H][R] (doubles)
+bool tune_tiles_layout(int64_t n, int32_t s, int32_t kmax, int32_t lr, TuneLayout &L) {
+    for (const orth_tiles &t : tune_tile_candidates(s)) {
+        Plan pl;
+        int why;
+        if (!make_plan(n, s, kmax, lr, ORTH_FP64, pl, &why, 0, true, &t)) return false;
+        L.head = std::max(L.head, round_up(pl.total, kAlign));
+    }
+    L.oW = L.head;
+    L.oU = L.oW + round_up(n * s, kAlign);
+    L.oH = L.oU + round_up(n * s, kAlign);
+    L.oR = L.oH + round_up((int64_t)kmax * s, kAlign);
+    L.total = L.oR + round_up((int64_t)s * s, kAlign);
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t orth_tune_tiles_workspace_bytes(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows) {
+    TuneLayout L;
+    if (leaf_rows < 1 || !tune_tiles_layout(n, s, k_max, leaf_rows, L)) return 0;
+    return (size_t)L.total * sizeof(double);
+}
+
+int orth_tune_tiles(int64_t n, int32_t s, int32_t k_max, int32_t leaf_rows, int32_t steps, void *d_workspace,
+                    size_t workspace_bytes, void *stream, orth_tiles *best, orth_tiles *cand, double *cand_ms,
+                    int32_t max_cand, int32_t *ncand) {
+    if (!best || (max_cand > 0 && (!cand || !cand_ms))) return ORTH_ERR_ARG;
+    TuneLayout L;
+    if (leaf_rows < 1 || !tune_tiles_layout(n, s, k_max, leaf_rows, L)) return ORTH_ERR_ARG;
+    if (steps < 1 || steps > k_max / s) return ORTH_ERR_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 || workspace_bytes < (size_t)L.total * sizeof(double))
+        return ORTH_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *ws = static_cast<double *>(d_workspace);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return ORTH_ERR_HIP;
+    }
+    const std::vector<orth_tiles> tc = tune_tile_candidates(s);
+    std::vector<double> times(tc.size(), -1.0);
+    double *W = ws + L.oW, *U = ws + L.oU, *H = ws + L.oH, *R = ws + L.oR;
+    int rc = ORTH_OK;
+    for (size_t c = 0; c < tc.size() && rc == ORTH_OK; ++c) {
+        orth_t *h = nullptr;
+        rc = orth_create_tiles(n, s, k_max, leaf_rows, ORTH_FP64, 0, &tc[c], ws, (size_t)L.head * sizeof(double),
+                               st, &h);
+        if (rc != ORTH_OK) break;
+        double total = 0.0;
+        for (int32_t j = 0; j < steps && rc == ORTH_OK; ++j) {
+            float ms = 0.0f;
+            if (launch_synth(W, n, n, s, (uint64_t)j + 1, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                rc = ORTH_ERR_HIP;
+                break;
+            }
+            rc = orth_step(h, W, n, H, k_max, R, s, U, n);
+            if (rc == ORTH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = ORTH_ERR_HIP;
+            total += ms;
+        }
+        int32_t status = ORTH_OK;
+        if (rc == ORTH_OK) rc = orth_status(h, &status, nullptr);
+        (void)orth_destroy(h);
+        if (rc == ORTH_OK && status == ORTH_OK) times[c] = total;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ORTH_OK) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    // the fastest; the plan's own choice wins ties within 2%
+    double fastest = -1.0;
+    size_t pick = 0;
+    for (size_t c = 0; c < tc.size(); ++c)
+        if (times[c] >= 0.0 && (fastest < 0.0 || times[c] < fastest)) {
+            fastest = times[c];
+            pick = c;
+        }
+    if (fastest < 0.0) return ORTH_ERR_BREAKDOWN;
+    if (times[0] >= 0.0 && times[0] <= 1.02 * fastest) pick = 0;
+    *best = tc[pick];
+    for (size_t c = 0; c < tc.size() && (int32_t)c < max_cand; ++c) {
+        cand[c] = tc[c];
+        cand_ms[c] = times[c];
+    }
+    if (ncand) *ncand = (int32_t)tc.size();
     return ORTH_OK;
 }
 

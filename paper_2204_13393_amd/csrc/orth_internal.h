@@ -347,6 +347,7 @@ struct FinalizeArgs {
     double *Cout;
     int64_t cout_seg;
     const DevStatus *status;
+    int32_t reg_only;     // host-side choice: 1 keeps the register-streamed kernel for s >= 16
 };
 
 // Y = Q C_leaf for a column block of C

@@ -1870,7 +1870,7 @@ template <int S>
 static hipError_t rowupdate_s(const FinalizeArgs &a, int cls, hipStream_t st) {
     const dim3 grid(a.geom.nchunks());
     if constexpr (S >= 16) {
-        if (rowlds_eligible(a, S)) {
+        if (!a.reg_only && rowlds_eligible(a, S)) {
             if (a.Cptr != nullptr) return launch_rowlds<S, true, 7>(a, st);
             return launch_rowlds<S, false, 2>(a, st);   // the leaf correction is the only leaf-level one
         }

@@ -31,6 +31,18 @@ ORTH_FP64_HOUSEHOLDER = 2
 ORTH_PIP_PLUS = 0
 ORTH_PIP = 1
 ORTH_HOUSEHOLDER = 2      # reduction variant only
+ORTH_TILE_AUTO = 0
+ORTH_TILE_REGISTER = 1
+
+
+class OrthTiles(ctypes.Structure):
+    """orth_tiles: rows per workgroup of the leaf Grams and row updates, row-update kernel."""
+    _fields_ = [("gram_rows", ctypes.c_int32), ("update_rows", ctypes.c_int32), ("update_kernel", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.gram_rows, self.update_rows, self.update_kernel)
+
+
 
 CODE_NAMES = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "BREAKDOWN", 4: "HIP", 5: "POISONED",
               6: "WORKSPACE", 7: "UNSUPPORTED", 8: "SCRATCH"}
@@ -45,6 +57,13 @@ SIGNATURES = [
     ("orth_tree_levels", ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("orth_export_tree_level", ctypes.c_int, [_vp, _i32, _dp, _i64]),
     ("orth_flat_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_tiles_workspace_bytes", _sz, [_i64, _i32, _i32, _i32, _i32, _i32, _vp]),
+    ("orth_create_tiles", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _sz, _vp,
+                                         ctypes.POINTER(_vp)]),
+    ("orth_tiles_in_use", ctypes.c_int, [_vp, _vp]),
+    ("orth_tune_tiles_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
+    ("orth_tune_tiles", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp,
+                                       ctypes.POINTER(ctypes.c_double), _i32, ctypes.POINTER(_i32)]),
     ("orth_tune_tree_workspace_bytes", _sz, [_i64, _i32, _i32, _i32]),
     ("orth_tune_tree", ctypes.c_int, [_i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double), _i32,
@@ -159,6 +178,48 @@ def orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stre
     code = load().orth_create_flat(n, s, k_max, block_rows, d_workspace, workspace_bytes, stream,
                                    ctypes.byref(h))
     return code, h
+
+
+def _tiles_arg(tiles):
+    if tiles is None:
+        return None, None
+    t = tiles if isinstance(tiles, OrthTiles) else OrthTiles(*tiles)
+    return t, ctypes.cast(ctypes.byref(t), _vp)
+
+
+def orth_tiles_workspace_bytes(n, s, k_max, leaf_rows, precision, fan_in, tiles):
+    t, ptr = _tiles_arg(tiles)
+    return load().orth_tiles_workspace_bytes(n, s, k_max, leaf_rows, precision, fan_in, ptr)
+
+
+def orth_create_tiles(n, s, k_max, leaf_rows, precision, fan_in, tiles, d_workspace, workspace_bytes, stream):
+    h = ctypes.c_void_p()
+    t, ptr = _tiles_arg(tiles)
+    code = load().orth_create_tiles(n, s, k_max, leaf_rows, precision, fan_in, ptr, d_workspace,
+                                    workspace_bytes, stream, ctypes.byref(h))
+    return code, h
+
+
+def orth_tiles_in_use(h):
+    t = OrthTiles()
+    code = load().orth_tiles_in_use(h, ctypes.cast(ctypes.byref(t), _vp))
+    return code, t.as_tuple()
+
+
+def orth_tune_tiles_workspace_bytes(n, s, k_max, leaf_rows):
+    return load().orth_tune_tiles_workspace_bytes(n, s, k_max, leaf_rows)
+
+
+def orth_tune_tiles(n, s, k_max, leaf_rows, steps, d_workspace, workspace_bytes, stream, max_cand=32):
+    """(code, best (gram_rows, update_rows, update_kernel), [(tiles, ms), ...])"""
+    best = OrthTiles()
+    cand = (OrthTiles * max(max_cand, 1))()
+    ms = (ctypes.c_double * max(max_cand, 1))()
+    nc = ctypes.c_int32()
+    code = load().orth_tune_tiles(n, s, k_max, leaf_rows, steps, d_workspace, workspace_bytes, stream,
+                                  ctypes.cast(ctypes.byref(best), _vp), ctypes.cast(cand, _vp), ms, max_cand,
+                                  ctypes.byref(nc))
+    return code, best.as_tuple(), [(cand[i].as_tuple(), ms[i]) for i in range(min(nc.value, max_cand))]
 
 
 def orth_tune_tree_workspace_bytes(n, s, k_max, leaf_rows):
@@ -366,10 +427,11 @@ class Orthogonalizer:
     Tensors are column-major: an n x s matrix is a contiguous float64 tensor
     of shape (s, n) on the device.  flat=True: FlatTSPQR over blocks of
     leaf_rows rows instead (orth_create_flat; FP64, no reduction tree).
+    tiles: None or (gram_rows, update_rows, update_kernel) for orth_create_tiles.
     """
 
     def __init__(self, n, s, k_max, leaf_rows=0, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
-                 precision=ORTH_FP64, reduction_variant=None, fan_in=0, flat=False):
+                 precision=ORTH_FP64, reduction_variant=None, fan_in=0, flat=False, tiles=None):
         import torch
         load()
         self.n, self.s, self.k_max = int(n), int(s), int(k_max)
@@ -377,11 +439,11 @@ class Orthogonalizer:
         self.device = torch.device(device)
         self.flat = bool(flat)
         if self.flat:
-            if precision != ORTH_FP64 or fan_in:
+            if precision != ORTH_FP64 or fan_in or tiles is not None:
                 raise OrthError("orth_create_flat", ORTH_ERR_UNSUPPORTED)
             nbytes = orth_flat_workspace_bytes(self.n, self.s, self.k_max, leaf_rows)
         else:
-            nbytes = orth_tree_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision, fan_in)
+            nbytes = orth_tiles_workspace_bytes(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, tiles)
         if nbytes == 0:
             raise OrthError("orth_workspace_bytes", ORTH_ERR_ARG)
         self.stream = stream
@@ -391,8 +453,8 @@ class Orthogonalizer:
         if self.flat:
             code, h = orth_create_flat(self.n, self.s, self.k_max, leaf_rows, aligned, nbytes, _stream_ptr(stream))
         else:
-            code, h = orth_create_tree(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, aligned, nbytes,
-                                       _stream_ptr(stream))
+            code, h = orth_create_tiles(self.n, self.s, self.k_max, leaf_rows, precision, fan_in, tiles, aligned,
+                                        nbytes, _stream_ptr(stream))
         _check("orth_create", code)
         self.h = h
         red = variant if reduction_variant is None else reduction_variant
@@ -403,6 +465,13 @@ class Orthogonalizer:
     @property
     def k(self):
         return orth_basis_width(self.h)[1]
+
+    @property
+    def tiles(self):
+        """(gram_rows, update_rows, update_kernel) the plan resolved."""
+        code, t = orth_tiles_in_use(self.h)
+        _check("orth_tiles_in_use", code)
+        return t
 
     def step(self, W, H=None, R=None, U=None):
         """Solve eq. (1.1) for W ((s, n) tensor); returns (H (s,k), R (s,s), U (s,n))."""

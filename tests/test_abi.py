@@ -296,6 +296,43 @@ def test_tune_tree_workspace_arguments():
     assert code == orth.ORTH_ERR_ARG
 
 
+def test_tile_shapes_workspace_and_arguments():
+    """orth_tiles: the plan's own tiles size the workspace like
+    orth_tree_workspace_bytes; smaller leaf-Gram tiles mean more partial-sum
+    slots and never a smaller workspace; row-update heights and the kernel
+    choice do not change it; values off the power-of-two ranges are refused
+    (host only)."""
+    n, s, kmax, lr = 1 << 20, 8, 64, 4096
+    F = orth.ORTH_FP64
+    base = orth.orth_tree_workspace_bytes(n, s, kmax, lr, F, 0)
+    assert orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, None) == base
+    assert orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, (0, 0, 0)) == base
+    small = orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, (128, 0, 0))
+    big = orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, (8192, 0, 0))
+    assert small > base >= big > 0
+    for upd, kern in ((64, 0), (8192, 1), (512, 1)):
+        assert orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, (0, upd, kern)) == base
+    for bad in ((100, 0, 0), (64, 0, 0), (16384, 0, 0), (0, 32, 0), (0, 16384, 0), (0, 100, 0), (0, 0, 2),
+                (0, 0, -1)):
+        assert orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, bad) == 0, bad
+        code, h = orth.orth_create_tiles(n, s, kmax, lr, F, 0, bad, 4096, 1 << 40, None)
+        assert code == orth.ORTH_ERR_ARG, bad
+    # the tuner's workspace holds its largest candidate handle plus W, U, H, R
+    ws = orth.orth_tune_tiles_workspace_bytes(n, s, kmax, lr)
+    assert ws >= orth.orth_tiles_workspace_bytes(n, s, kmax, lr, F, 0, (1024, 0, 0)) + 2 * 8 * n * s
+    assert orth.orth_tune_tiles_workspace_bytes(n, s, kmax, 0) == 0
+    code, best, cand = orth.orth_tune_tiles(n, s, kmax, lr, 2, 0, 0, None)
+    assert code == orth.ORTH_ERR_WORKSPACE
+    code, best, cand = orth.orth_tune_tiles(n, s, kmax, lr, 0, 256, ws, None)
+    assert code == orth.ORTH_ERR_ARG
+    assert orth.orth_tiles_in_use(None)[0] == orth.ORTH_ERR_ARG
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "orth.h")).read()
+    import re
+    for name in ("ORTH_TILE_AUTO", "ORTH_TILE_REGISTER"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, hdr)
+        assert m and int(m.group(1)) == getattr(orth, name), name
+
+
 def test_large_plan_sizes_are_sane():
     """Plans far past one GPU's memory still size consistently (64-bit row
     counts throughout): the workspace holds at least the leaf bases and stays

@@ -104,3 +104,91 @@ def test_fan_in_tuner(torch_cuda):
     P, N, Ur = pqr_reference(np.zeros((n, 0)), X)
     assert np.linalg.norm(to_host(R) - N) / np.linalg.norm(X) <= 1e-12
     g.close()
+
+
+# ---- tile shapes of the leaf passes (orth_tiles, orth_tune_tiles)
+
+@pytest.mark.parametrize("n,s,kmax,leaf,tiles", [
+    (65536, 16, 96, 4096, (0, 256, 1)),     # register row updates at s = 16, 256-row tiles
+    (20000, 32, 128, 2500, (0, 128, 1)),    # s = 32, ragged last leaf
+    (65536, 8, 64, 8192, (0, 2048, 0)),     # taller row-update tiles at s = 8
+])
+def test_row_update_tiles_keep_the_bits(torch_cuda, n, s, kmax, leaf, tiles):
+    """Row-update tile height and kernel do not change a bit: each row's
+    products are the same whichever workgroup forms them, and the
+    register-streamed and LDS-staged kernels form the same products."""
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("row-update tiles", n, s, kmax, leaf, tiles)
+    rng = np.random.default_rng(n + s)
+    a = Orthogonalizer(n, s, kmax, leaf)
+    b = Orthogonalizer(n, s, kmax, leaf, tiles=tiles)
+    assert b.tiles[1:] == tiles[1:] and b.tiles[0] == a.tiles[0]
+    Q = np.zeros((n, 0))
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s))
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        ra = [to_host(t) for t in a.step(to_dev(X))]
+        rb = [to_host(t) for t in b.step(to_dev(X))]
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y), step
+        Q = np.hstack([Q, ra[2]])
+    assert a.status()[0] == 0 and b.status()[0] == 0
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("n,s,kmax,leaf,tiles", [
+    (65536, 8, 64, 8192, (4096, 1024, 0)),
+    (30000, 4, 40, 3000, (1024, 64, 0)),
+    (40000, 16, 80, 5000, (8192, 512, 1)),
+])
+def test_gram_tiles_parity(torch_cuda, n, s, kmax, leaf, tiles):
+    """Other leaf-Gram tile heights add the partial sums in another order:
+    every call against the unique PQR solution at the FP64 tolerances."""
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("gram tiles", n, s, kmax, leaf, tiles)
+    rng = np.random.default_rng(3 * n + s)
+    g = Orthogonalizer(n, s, kmax, leaf, tiles=tiles)
+    assert g.tiles == tiles
+    Q = np.zeros((n, 0))
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        H, R, U = (to_host(t) for t in g.step(to_dev(X)))
+        P, N, Ur = pqr_reference(Q, X)
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if step:
+            assert np.linalg.norm(H - P) / xn <= 1e-12, step
+        assert np.linalg.norm(R - N) / xn <= 1e-12 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-12 * kap, step
+        Q = np.hstack([Q, Ur])
+    assert g.status()[0] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("s", [8, 16])
+def test_tile_tuner(torch_cuda, s):
+    """Every candidate is timed (no breakdown on the synthetic blocks), the
+    plan's own comes first and wins ties within 2%, and the pick makes a
+    working handle."""
+    from paper_2204_13393_amd import Orthogonalizer, autotune
+    n, kmax, leaf = 1 << 18, 8 * s, 4096
+    _say("tile tuner", n, s, kmax, leaf)
+    best, cand = autotune.measure_tiles(n, s, kmax, leaf, steps=4)
+    assert len(cand) == 1 + 12 * (2 if s >= 16 else 1)
+    assert cand[0][0] == (0, 0, 0)
+    ms = [m for _, m in cand]
+    assert all(m > 0 for m in ms)
+    fastest = min(ms)
+    if ms[0] <= 1.02 * fastest:
+        assert best == (0, 0, 0)
+    else:
+        assert best in [c for c, m in cand if m == fastest]
+    print(f"[tiles] s={s} best {best}: {fastest:.3f} ms, plan's own {ms[0]:.3f} ms", flush=True)
+    g = Orthogonalizer(n, s, kmax, leaf, tiles=best)
+    H, R, U = g.step(to_dev(normal_block(n, s, 7)))
+    assert g.status()[0] == 0
+    g.close()
