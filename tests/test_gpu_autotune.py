@@ -1,11 +1,17 @@
-"""GPU tests of the leaf-height autotuner (orth_tune_leaf_rows and its cache).
+"""GPU tests of the autotuner: leaf heights (orth_tune_leaf_rows and its cache),
+the reduction fan-in (orth_tune_tree) and the leaf passes' tile shapes
+(orth_tiles, orth_tune_tiles).
 
 * every admissible candidate {256, ..., 65536} within [k_max, n] (and n itself
   when n <= 65536) is timed, through one handle and through batches of
   identical copies, with a positive time (no breakdown on the synthetic
   blocks), and the reported best is the tallest within 2% of the fastest;
 * the Python cache returns the measured value without measuring again;
-* a handle built with the tuned height reproduces the oracle's unique PQR.
+* a handle built with the tuned height reproduces the oracle's unique PQR;
+* tile shapes: row-update heights and the register-streamed row update leave
+  every bit unchanged (FP64, mixed and Householder forms); other leaf-Gram
+  heights reproduce the unique PQR at the form's tolerances; the tile tuner
+  times every candidate and keeps the plan's own within 2%.
 """
 
 import json
@@ -190,5 +196,55 @@ def test_tile_tuner(torch_cuda, s):
     print(f"[tiles] s={s} best {best}: {fastest:.3f} ms, plan's own {ms[0]:.3f} ms", flush=True)
     g = Orthogonalizer(n, s, kmax, leaf, tiles=best)
     H, R, U = g.step(to_dev(normal_block(n, s, 7)))
+    assert g.status()[0] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("precision,n,s,kmax,leaf,tiles", [
+    (1, 65536, 16, 64, 4096, (0, 256, 1)),      # mixed form: register row updates, 256-row tiles
+    (2, 32768, 32, 96, 4096, (0, 128, 1)),      # Householder leaves, s = 32
+    (2, 40000, 8, 48, 4000, (0, 2048, 0)),      # Householder leaves, s = 8
+])
+def test_row_update_tiles_other_forms(torch_cuda, precision, n, s, kmax, leaf, tiles):
+    """The mixed form and the Householder leaves take the same tile choices:
+    row-update heights and the register kernel leave their bits unchanged."""
+    from paper_2204_13393_amd import Orthogonalizer
+    _say("row-update tiles, precision", precision, n, s, kmax, leaf, tiles)
+    rng = np.random.default_rng(n + 7 * s)
+    a = Orthogonalizer(n, s, kmax, leaf, precision=precision)
+    b = Orthogonalizer(n, s, kmax, leaf, precision=precision, tiles=tiles)
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s))
+        ra = [to_host(t) for t in a.step(to_dev(X))]
+        rb = [to_host(t) for t in b.step(to_dev(X))]
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y), step
+    assert a.status()[0] == 0 and b.status()[0] == 0
+    a.close()
+    b.close()
+
+
+def test_mixed_form_gram_tiles_parity(torch_cuda):
+    """The mixed form's first Gram (FP32 copy) on 1024-row tiles: every call
+    against the unique PQR solution at the mixed form's tolerances."""
+    from paper_2204_13393_amd import Orthogonalizer
+    n, s, kmax, leaf = 65536, 8, 48, 8192
+    _say("mixed gram tiles", n, s, kmax, leaf)
+    rng = np.random.default_rng(29)
+    g = Orthogonalizer(n, s, kmax, leaf, precision=1, tiles=(1024, 512, 0))
+    Q = np.zeros((n, 0))
+    for step in range(kmax // s):
+        X = rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s)
+        if step:
+            X = X + Q @ rng.standard_normal((Q.shape[1], s))
+        H, R, U = (to_host(t) for t in g.step(to_dev(X)))
+        P, N, Ur = pqr_reference(Q, X)
+        kap = kappa_after_projection(N, X)
+        xn = np.linalg.norm(X)
+        if step:
+            assert np.linalg.norm(H - P) / xn <= 1e-10, step
+        assert np.linalg.norm(R - N) / xn <= 1e-10 * kap, step
+        assert np.max(np.abs(U - Ur)) <= 1e-10 * kap, step
+        Q = np.hstack([Q, Ur])
     assert g.status()[0] == 0
     g.close()
