@@ -232,17 +232,18 @@ def test_householder_pip_reduction_and_determinism(torch_cuda):
             assert np.array_equal(x, y)
 
 
-def test_householder_graph_replay(torch_cuda):
-    """Four steps with Householder leaves captured in a hipGraph and replayed
+@pytest.mark.parametrize("n,s,kmax,leaf", [(16384, 8, 32, 4096), (12288, 32, 320, 4096)])
+def test_householder_graph_replay(torch_cuda, n, s, kmax, leaf):
+    """k_max / s steps with Householder leaves captured in a hipGraph and replayed
     from freshly created handles on the same workspace, eager work and
     synchronisation between replays: every replay equals the eager run
-    bitwise (the step makes no host call and allocates nothing)."""
+    bitwise (the step makes no host call and allocates nothing); s = 32
+    runs the sub-panel kernel and the small products above 64 KB of LDS."""
     import torch
     from paper_2204_13393_amd import orth
-    _say("householder graph")
-    n, s, kmax, leaf = 16384, 8, 32, 4096
+    _say("householder graph", n, s, kmax, leaf)
     H_ = orth.ORTH_FP64_HOUSEHOLDER
-    X = [to_dev(normal_block(n, s, 80 + j)) for j in range(4)]
+    X = [to_dev(normal_block(n, s, 80 + j)) for j in range(kmax // s)]
     nbytes = orth.orth_workspace_bytes(n, s, kmax, leaf, H_)
     side = torch.cuda.Stream()
 
@@ -251,7 +252,7 @@ def test_householder_graph_replay(torch_cuda):
                 torch.empty((kmax, n), dtype=torch.float64, device="cuda"))
 
     def run(h, H, U):
-        for j in range(4):
+        for j in range(kmax // s):
             k = j * s
             col = H[j * s:(j + 1) * s]
             hp = col.data_ptr() if k else 0
