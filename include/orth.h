@@ -119,8 +119,8 @@ enum orth_code {
  *                       k_max <= 608 at s = 32).
  *                       orth_apply_Q forms Q_k [C_i; 0] per leaf through
  *                       the same compact-WY products; orth_export_local
- *                       exports the reflectors as d_Qloc.  Single handles
- *                       only.
+ *                       exports the reflectors as d_Qloc.  Also for
+ *                       batches (orth_batch_create).
  */
 enum orth_precision {
     ORTH_FP64 = 0,
@@ -498,8 +498,9 @@ typedef struct orth_batch_ctx orth_batch_t;
  * of `count` entries: n[i], s[i], k_max[i] as for orth_workspace_bytes;
  * leaf_rows may be NULL (default height for every instance) or hold 0 for
  * the default.  The batch runs min_i(k_max[i] / s[i]) steps.  precision
- * ORTH_FP64 or ORTH_MIXED_SPLIT32, for every instance (Householder leaves
- * are single-handle only).  Returns 0 for invalid or unsupported arguments.
+ * ORTH_FP64, ORTH_MIXED_SPLIT32 or ORTH_FP64_HOUSEHOLDER, for every instance
+ * (each instance within that form's limits, as for orth_workspace_bytes).
+ * Returns 0 for invalid or unsupported arguments.
  */
 size_t orth_batch_workspace_bytes(int32_t count, const int64_t *n, const int32_t *s,
                                   const int32_t *k_max, const int32_t *leaf_rows,
@@ -517,7 +518,8 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
                       size_t workspace_bytes, void *stream, orth_batch_t **out);
 
 /* orth_batch_set_variant -- ORTH_PIP_PLUS (default, Sec. 3.1) or ORTH_PIP
- * (Sec. 3) for all instances. */
+ * (Sec. 3) for all instances, at both levels; a batch of Householder leaves
+ * takes ORTH_PIP_PLUS only (UNSUPPORTED otherwise). */
 int orth_batch_set_variant(orth_batch_t *b, int32_t variant);
 
 /*

@@ -1839,11 +1839,8 @@ bool make_batch_layout(int32_t count, const int64_t *n, const int32_t *s, const 
                        const int32_t *leaf_rows, int32_t precision, BatchLayout &L, int *why) {
     *why = ORTH_ERR_ARG;
     if (count < 1 || count > (1 << 20) || !n || !s || !k_max) return false;
-    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32) {
-        // Householder leaves are single-handle only
-        *why = precision == ORTH_FP64_HOUSEHOLDER ? ORTH_ERR_UNSUPPORTED : ORTH_ERR_ARG;
+    if (precision != ORTH_FP64 && precision != ORTH_MIXED_SPLIT32 && precision != ORTH_FP64_HOUSEHOLDER)
         return false;
-    }
     L.precision = precision;
     L.count = count;
     L.plans.resize(count);
@@ -1916,7 +1913,8 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
     b->stream = static_cast<hipStream_t>(stream);
     b->ws = static_cast<double *>(d_workspace);
     for (int32_t w : L.widths) {
-        if (prepare_kernels(w) != hipSuccess) {
+        if (prepare_kernels(w) != hipSuccess ||
+            (precision == ORTH_FP64_HOUSEHOLDER && prepare_hh_kernels(w) != hipSuccess)) {
             (void)hipGetLastError();
             delete b;
             return ORTH_ERR_HIP;
@@ -1949,6 +1947,7 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         d.CL = base + pl.oCL;
         d.Qhi = pl.precision == ORTH_MIXED_SPLIT32 ? reinterpret_cast<float *>(base + pl.oQH) : nullptr;
         d.retry = reinterpret_cast<int32_t *>(b->ws + L.o_retry) + i;
+        d.TH = pl.precision == ORTH_FP64_HOUSEHOLDER ? base + pl.oTH : nullptr;
     }
     // block prefix tables of every (step, phase, width)
     const size_t nw = L.widths.size();
@@ -1979,6 +1978,9 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
         const Plan &pl = L.plans[i];
         e = launch_fill(b->desc[i].T, pl.ldt * (int64_t)pl.kmax, 0.0, b->stream);
         if (e == hipSuccess) e = launch_fill(b->desc[i].Y, pl.ldt * (int64_t)pl.s, 0.0, b->stream);
+        // Householder leaves: the compact-WY factors grow into zeros below their diagonal
+        if (e == hipSuccess && b->desc[i].TH)
+            e = launch_fill(b->desc[i].TH, (int64_t)3 * pl.p * pl.kmax * pl.kmax, 0.0, b->stream);
     }
     if (e == hipSuccess)
         e = launch_fill_i32(reinterpret_cast<int32_t *>(b->status()),
@@ -1998,6 +2000,8 @@ int orth_batch_create(int32_t count, const int64_t *n, const int32_t *s, const i
 int orth_batch_set_variant(orth_batch_t *b, int32_t variant) {
     if (!b || (variant != ORTH_PIP_PLUS && variant != ORTH_PIP)) return ORTH_ERR_ARG;
     if (b->poisoned) return ORTH_ERR_POISONED;
+    // (the variant names both levels; Householder leaves take no CholeskyQR variant)
+    if (b->L.precision == ORTH_FP64_HOUSEHOLDER && variant != ORTH_PIP_PLUS) return ORTH_ERR_UNSUPPORTED;
     b->variant = variant;
     return ORTH_OK;
 }
@@ -2014,6 +2018,7 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
     a.step = b->step;
     a.two = b->variant == ORTH_PIP_PLUS ? 1 : 0;
     a.mixed = b->L.precision == ORTH_MIXED_SPLIT32 ? 1 : 0;
+    a.hh = b->L.precision == ORTH_FP64_HOUSEHOLDER ? 1 : 0;
     a.W = d_W;
     a.U = d_U;
     a.Hess = d_Hess;
@@ -2030,7 +2035,10 @@ int orth_batch_step(orth_batch_t *b, const double *const *d_W, double *const *d_
             const int32_t blocks = b->prefix[row + count];
             if (blocks == 0) continue;
             a.prefix = dprefix + row;
-            if (launch_batch_phase(a, b->L.widths[w], blocks, b->lds[ph * nw + w], b->stream) != hipSuccess) {
+            const hipError_t e = batch_hh_phase(ph) ? launch_batch_hh_phase(a, b->L.widths[w], blocks, b->stream)
+                                                    : launch_batch_phase(a, b->L.widths[w], blocks, b->lds[ph * nw + w],
+                                                                         b->stream);
+            if (e != hipSuccess) {
                 (void)hipGetLastError();
                 return ORTH_ERR_HIP;
             }

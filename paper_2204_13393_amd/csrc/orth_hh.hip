@@ -111,10 +111,10 @@ __device__ __forceinline__ double *hh_tc(const HhArgs &a, int leaf) {
 // record's first-sweep inverse normalizer is set to I, so the row-update
 // kernel's sweep-1 pass computes w - V Y.
 template <int S>
-__global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
+__device__ __forceinline__ void hh_prep_body(const HhArgs &a, int leaf) {
     if (hh_failed(a.status)) return;
     extern __shared__ double lds[];                 // M, k x S row-major
-    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k;
+    const int tid = threadIdx.x, k = a.k;
     const int first = leaf * a.slots_per_leaf;
     const int cnt = leaf == a.geom.nleaf - 1 ? a.slots_last : a.slots_per_leaf;
     for (int e = tid; e < k * S; e += kThreads) {
@@ -153,6 +153,9 @@ __global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) {
     for (int e = tid; e < S * S; e += kThreads) n1i[e] = (e / S == e % S) ? 1.0 : 0.0;
 }
 
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_prep(HhArgs a) { hh_prep_body<S>(a, blockIdx.x); }
+
 // ------------------------------------------------------------ panel
 // One workgroup factors leaf i's block w~ (n_i x s) held in registers: rows
 // below k form the projection P, rows k.. the panel, triangularised column by
@@ -172,13 +175,12 @@ template <int S>
 __host__ __device__ constexpr int hh_sub() { return S <= 16 ? S : 8; }
 
 template <int S>
-__global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
+__device__ __forceinline__ void hh_panel_body(const HhArgs &a, int leaf) {
     if (hh_failed(a.status)) return;
     constexpr int RPT = hh_rpt<S>();
     __shared__ double red[2][kHhWaves][S];
     __shared__ double rowv[2][S];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int leaf = blockIdx.x;
     const int64_t r0 = a.geom.leaf_begin(leaf);
     const int nl = (int)(a.geom.leaf_end(leaf) - r0);
     const int k = a.k;
@@ -284,6 +286,9 @@ __global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) {
         }
     }
 }
+
+template <int S>
+__global__ __launch_bounds__(kHhThreads) void k_hh_panel(HhArgs a) { hh_panel_body<S>(a, blockIdx.x); }
 
 // Blocks wider than the register budget (s = 32): the same factorisation in
 // sub-panels of SB columns, in a kernel of 1024 threads holding 4 rows each
@@ -435,13 +440,12 @@ struct HhSubCols<SB, RPT, SB> {
 };
 
 template <int S, int SB>
-__global__ __launch_bounds__(kHhSubThreads) void k_hh_panel_sub(HhArgs a) {
+__device__ __forceinline__ void hh_panel_sub_body(const HhArgs &a, int leaf) {
     static_assert(S % SB == 0 && SB <= 64, "whole sub-panels, a column per lane");
     if (hh_failed(a.status)) return;
     constexpr int RPT = kHhSubRows;
     __shared__ HhSubShared<SB> sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int leaf = blockIdx.x;
     const int64_t r0 = a.geom.leaf_begin(leaf);
     const int nl = (int)(a.geom.leaf_end(leaf) - r0);
     const int k = a.k;
@@ -525,6 +529,9 @@ __global__ __launch_bounds__(kHhSubThreads) void k_hh_panel_sub(HhArgs a) {
     }
 }
 
+template <int S, int SB>
+__global__ __launch_bounds__(kHhSubThreads) void k_hh_panel_sub(HhArgs a) { hh_panel_sub_body<S, SB>(a, blockIdx.x); }
+
 // ------------------------------------------------------------ T update
 // From the slots of [V v_new]^T v_new: W = V^T v_new (k x s) and
 // G = v_new^T v_new.  T_s (s x s, upper): diagonal 2, column j above the
@@ -532,10 +539,10 @@ __global__ __launch_bounds__(kHhSubThreads) void k_hh_panel_sub(HhArgs a) {
 // both copies of T.  Also copies the reflectors' new top rows k..k+s-1 to
 // the row-major Vr.
 template <int S>
-__global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
+__device__ __forceinline__ void hh_tupd_body(const HhArgs &a, int leaf) {
     if (hh_failed(a.status)) return;
     extern __shared__ double lds[];
-    const int leaf = blockIdx.x, tid = threadIdx.x, k = a.k, K = k + S;
+    const int tid = threadIdx.x, k = a.k, K = k + S;
     double *W = lds;                    // K x S row-major: W (rows < k), G (rows k..)
     double *Ts = W + K * S;             // S x S row-major
     const int first = leaf * a.slots_per_leaf;
@@ -610,6 +617,9 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) { hh_tupd_body<S>(a, blockIdx.x); }
+
 // ------------------------------------------------------------ coefficients
 // C_i (the leaf's (k+s) x s block from the reduction, right half of its
 // record) -> Z = T (V[0:k+s]^T C_i); the record's right half becomes -Z (the
@@ -618,11 +628,11 @@ __global__ __launch_bounds__(kThreads) void k_hh_tupd(HhArgs a) {
 // CB columns of C_i at a time (CB = S, or S / 2 when two K x S blocks do
 // not fit the LDS); every output column is the same sum either way.
 template <int S, int CB>
-__global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
+__device__ __forceinline__ void hh_coef_body(const HhArgs &a, int leaf) {
     static_assert(S % CB == 0, "whole column blocks");
     if (hh_failed(a.status)) return;
     extern __shared__ double lds[];
-    const int leaf = blockIdx.x, tid = threadIdx.x, K = a.k + S;
+    const int tid = threadIdx.x, K = a.k + S;
     double *C = lds, *B = lds + K * CB;            // K x CB row-major each
     double *rec = a.crec + (int64_t)leaf * a.cseg;  // row c: [left S | right S]
     const int64_t km = a.kmax;
@@ -684,11 +694,14 @@ __global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) {
     }
 }
 
+template <int S, int CB>
+__global__ __launch_bounds__(kThreads) void k_hh_coef(HhArgs a) { hh_coef_body<S, CB>(a, blockIdx.x); }
+
 // U|_i[0:k+s] += C_i (left half of the leaf's record)
 template <int S>
-__global__ __launch_bounds__(kThreads) void k_hh_addec(HhArgs a) {
+__device__ __forceinline__ void hh_addec_body(const HhArgs &a, int leaf) {
     if (hh_failed(a.status)) return;
-    const int leaf = blockIdx.x, tid = threadIdx.x, K = a.k + S;
+    const int tid = threadIdx.x, K = a.k + S;
     const double *rec = a.crec + (int64_t)leaf * a.cseg;
     const int64_t r0 = a.geom.leaf_begin(leaf);
     for (int e = tid; e < K * S; e += kThreads) {
@@ -696,6 +709,9 @@ __global__ __launch_bounds__(kThreads) void k_hh_addec(HhArgs a) {
         a.U[(r0 + r) + (int64_t)j * a.ldu] += rec[(int64_t)r * 2 * S + j];
     }
 }
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_hh_addec(HhArgs a) { hh_addec_body<S>(a, blockIdx.x); }
 
 // ------------------------------------------------------------ apply
 // orth_apply_Q: Y_i = Q_k [C_i; 0] = -V Z_i + E C_i with Z_i = T (V[0:k]^T C_i),
@@ -777,6 +793,140 @@ int hh_coef_cb(int s, int64_t K) {
     if ((size_t)2 * K * s * 8 <= kHhLdsMax) return s;
     if (s > 1 && (size_t)2 * K * (s / 2) * 8 <= kHhLdsMax) return s / 2;
     return 0;
+}
+
+// ------------------------------------------------------------ batched form
+// The per-leaf Householder kernels for a batch: workgroup b is leaf `local`
+// of the instance batch_locate finds, with the arguments a single handle of
+// that instance's plan would pass (its leaf Gram geometry for the partial
+// slots; the leaf bounds are those of every geometry).
+// The instance of workgroup b without shared memory (these kernels keep the
+// whole 160 KB of LDS for their staging): the last i with prefix[i] <= b,
+// which is the i with prefix[i] <= b < prefix[i + 1] (instances with no
+// blocks repeat their neighbour's entry).  Every lane takes the same path.
+__device__ __forceinline__ void batch_locate_nolds(const BatchArgs &a, int &inst, int &local) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = a.count - 1;          // prefix[0] = 0 <= b, prefix[count] > b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    inst = lo;
+    local = b - a.prefix[lo];
+}
+
+template <int S>
+__device__ __forceinline__ HhArgs batch_hh_args(const BatchArgs &a, const BatchInst &d, int inst) {
+    const int k = a.step * S, ncol = k + S;
+    const LevelGeom gg = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
+    const int rg = gram_row_groups(ncol);
+    HhArgs h{};
+    h.geom = gg;
+    h.k = k;
+    h.kmax = d.kmax;
+    h.Q = d.Q;
+    h.ldq = d.ldq;
+    h.T = d.TH;
+    h.partials = d.PL;
+    h.part_stride = (int64_t)ncol * S;
+    h.slots_per_leaf = gg.cpl * rg;
+    h.slots_last = gg.cpl_last * rg;
+    h.small = d.SL;
+    h.small_stride = small_stride(d.kmax, S);
+    h.X = k > 0 ? d.U1L : a.W[inst];        // Q_k^T w (or w at k = 0)
+    h.ldx = k > 0 ? d.ldq : d.n;
+    h.Yout = d.Y;
+    h.ldy = d.ldt;
+    h.yseg = d.kmax;
+    h.crec = d.CL;
+    h.cseg = (int64_t)d.kmax * 2 * S;
+    h.U = a.U[inst];
+    h.ldu = d.n;
+    h.status = a.status;
+    return h;
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void kb_hh_prep(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_prep_body<S>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S>
+__global__ __launch_bounds__(kHhThreads) void kb_hh_panel(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_panel_body<S>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S, int SB>
+__global__ __launch_bounds__(kHhSubThreads) void kb_hh_panel_sub(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_panel_sub_body<S, SB>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void kb_hh_tupd(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_tupd_body<S>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S, int CB>
+__global__ __launch_bounds__(kThreads) void kb_hh_coef(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_coef_body<S, CB>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void kb_hh_addec(BatchArgs a) {
+    int inst, local;
+    batch_locate_nolds(a, inst, local);
+    const BatchInst d = a.inst[inst];
+    hh_addec_body<S>(batch_hh_args<S>(a, d, inst), local);
+}
+
+template <int S>
+hipError_t batch_hh_s(const BatchArgs &a, int32_t blocks, hipStream_t st) {
+    const int K = a.step * S + S;
+    if (!hh_small_fits(S, K)) return hipErrorInvalidValue;
+    switch (a.phase) {
+        case BP_HPREP:
+            hipLaunchKernelGGL((kb_hh_prep<S>), dim3(blocks), dim3(kThreads), hh_prep_lds(S, K), st, a);
+            break;
+        case BP_HPANEL:
+            if constexpr (S > 16) {
+                hipLaunchKernelGGL((kb_hh_panel_sub<S, hh_sub<S>()>), dim3(blocks), dim3(kHhSubThreads), 0, st, a);
+            } else {
+                hipLaunchKernelGGL((kb_hh_panel<S>), dim3(blocks), dim3(kHhThreads), 0, st, a);
+            }
+            break;
+        case BP_HTUPD:
+            hipLaunchKernelGGL((kb_hh_tupd<S>), dim3(blocks), dim3(kThreads), hh_tupd_lds(S, K), st, a);
+            break;
+        case BP_HCOEF:
+            if (hh_coef_cb(S, K) == S) {
+                hipLaunchKernelGGL((kb_hh_coef<S, S>), dim3(blocks), dim3(kThreads), (size_t)2 * K * S * 8, st, a);
+            } else if constexpr (S > 1) {
+                hipLaunchKernelGGL((kb_hh_coef<S, S / 2>), dim3(blocks), dim3(kThreads), (size_t)K * S * 8, st, a);
+            }
+            break;
+        case BP_HADDEC:
+            hipLaunchKernelGGL((kb_hh_addec<S>), dim3(blocks), dim3(kThreads), 0, st, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <int S>
@@ -874,7 +1024,35 @@ static hipError_t raise_hh_lds() {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hh_coef<S, S / 2>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
+    // and the batched forms of the same kernels
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_hh_prep<S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_hh_tupd<S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_hh_coef<S, S>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if constexpr (S > 1) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_hh_coef<S, S / 2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
     return e;
+}
+
+hipError_t launch_batch_hh_phase(const BatchArgs &a, int s, int32_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    switch (s) {
+        case 1: return batch_hh_s<1>(a, blocks, st);
+        case 2: return batch_hh_s<2>(a, blocks, st);
+        case 4: return batch_hh_s<4>(a, blocks, st);
+        case 8: return batch_hh_s<8>(a, blocks, st);
+        case 16: return batch_hh_s<16>(a, blocks, st);
+        case 32: return batch_hh_s<32>(a, blocks, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t prepare_hh_kernels(int s) {

@@ -422,16 +422,25 @@ struct BatchInst {
     double *Q, *T, *Y, *U1L, *U1R, *PL, *PR, *PR2, *SL, *SR, *CL;
     float *Qhi;               // mixed form: FP32 copy of Q (same layout, floats); nullptr for FP64
     int32_t *retry;           // mixed form: this instance's retry flag
+    double *TH;               // Householder leaves: per-leaf compact-WY factors (nullptr otherwise)
 };
 
 // phases of one orth_batch_step, in stream order
+// (Householder leaves: the leaf Gram and correction form Q_k^T w through the
+// compact-WY factor, BP_HPREP between them forms T^T M; the panel, the Gram
+// of the new reflectors and the T update follow; BP_HCOEF and BP_HADDEC
+// frame the finalize.  The FP64 and mixed leaves' Cholesky phases have no
+// blocks there, and the H phases none for the other forms.)
 enum BatchPhase {
-    BP_LGRAM = 0, BP_LCHOL1,
+    BP_LGRAM = 0, BP_HPREP, BP_LCHOL1,
     BP_LGRAMF, BP_LCHOLF,     // mixed form: the first sweep redone from the FP64 basis when flagged
-    BP_LCORR, BP_LGRAM2, BP_LCHOL2,
+    BP_LCORR, BP_HPANEL, BP_LGRAM2, BP_LCHOL2, BP_HTUPD,
     BP_RGRAM, BP_RRED1, BP_RCHOL1, BP_RCORR, BP_RGRAM2, BP_RRED2, BP_RCHOL2,
-    BP_RFIN, BP_LFIN, BP_COUNT
+    BP_RFIN, BP_HCOEF, BP_LFIN, BP_HADDEC, BP_COUNT
 };
+__host__ __device__ inline bool batch_hh_phase(int phase) {
+    return phase == BP_HPREP || phase == BP_HPANEL || phase == BP_HTUPD || phase == BP_HCOEF || phase == BP_HADDEC;
+}
 
 struct BatchArgs {
     const BatchInst *inst;
@@ -441,6 +450,7 @@ struct BatchArgs {
     int32_t phase;
     int32_t two;              // 1: BCGS-PIP+ (two sweeps), 0: BCGS-PIP
     int32_t mixed;            // 1: the instances keep FP32 copies (the first leaf Gram reads them)
+    int32_t hh;               // 1: Householder leaves (the instances' TH)
     const double *const *W;   // device array: instance i's W (n_i x s_i, ld n_i)
     double *const *U;         // device array: explicit new blocks
     double *const *Hess;      // device array: K_i x K_i column-major, block `step` gets [H; R]
@@ -450,6 +460,34 @@ struct BatchArgs {
 // workgroups instance d needs in a phase of a given step (0: phase skipped)
 __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int phase, int step, int two) {
     const int32_t k = step * d.s, ncol = k + d.s;
+    if (d.TH) {
+        // Householder leaves: Q_k^T w only past the first call; the panel,
+        // the new reflectors' Gram and the T update every call
+        switch (phase) {
+            case BP_LGRAM:
+                return k > 0 ? make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol) : 0;
+            case BP_LGRAM2:
+                return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol);
+            case BP_HPREP:
+                return k > 0 ? d.p : 0;
+            case BP_LCORR:
+                return k > 0 ? make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk).nchunks() : 0;
+            case BP_HPANEL:
+            case BP_HTUPD:
+            case BP_HCOEF:
+            case BP_HADDEC:
+                return d.p;
+            case BP_LCHOL1:
+            case BP_LCHOL2:
+            case BP_LGRAMF:
+            case BP_LCHOLF:
+                return 0;
+            default:
+                break;            // the reduction level and the finalize as below
+        }
+    } else if (batch_hh_phase(phase)) {
+        return 0;
+    }
     const bool second = phase == BP_LGRAM2 || phase == BP_LCHOL2 || phase == BP_RGRAM2 ||
                         phase == BP_RRED2 || phase == BP_RCHOL2;
     if (second && !two) return 0;
@@ -488,6 +526,24 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
     return 0;
 }
 
+#if defined(__HIPCC__)
+// The batched kernels: workgroup b belongs to the instance whose block range
+// [prefix[i], prefix[i+1]) holds b; its index within that range is `local`.
+__device__ __forceinline__ void batch_locate(const BatchArgs &a, int &inst, int &local) {
+    __shared__ int32_t found[2];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    for (int i = tid; i < a.count; i += (int)blockDim.x)
+        if (a.prefix[i] <= b && b < a.prefix[i + 1]) {
+            found[0] = i;
+            found[1] = b - a.prefix[i];
+        }
+    __syncthreads();
+    inst = found[0];
+    local = found[1];
+}
+#endif
+
 // launchers (orth_kernels.hip)
 hipError_t launch_gram(int s, const GramArgs &a, int cls, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
@@ -519,6 +575,9 @@ hipError_t launch_batch_phase(const BatchArgs &a, int s, int32_t blocks, size_t 
 // updates of s >= 16 run LDS-staged (every instance of the width has even
 // leaf heights)
 size_t batch_phase_lds(int phase, int s, bool rowlds);
+// the Householder phases (orth_hh.hip): one launch for the instances of
+// width s (all at k = step * s, which sizes the LDS staging)
+hipError_t launch_batch_hh_phase(const BatchArgs &a, int s, int32_t blocks, hipStream_t st);
 
 
 }  // namespace orth

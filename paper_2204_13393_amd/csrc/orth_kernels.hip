@@ -1492,19 +1492,6 @@ __global__ __launch_bounds__(256) void k_copy(const double *__restrict__ src, do
 // belongs to the instance whose block range [prefix[i], prefix[i+1]) holds b.
 // The per-instance work is the same device code as the single-handle
 // kernels, selected by the instance's block width.
-__device__ __forceinline__ void batch_locate(const BatchArgs &a, int &inst, int &local) {
-    __shared__ int32_t found[2];
-    const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    for (int i = tid; i < a.count; i += kThreads)
-        if (a.prefix[i] <= b && b < a.prefix[i + 1]) {
-            found[0] = i;
-            found[1] = b - a.prefix[i];
-        }
-    __syncthreads();
-    inst = found[0];
-    local = found[1];
-}
 
 __device__ __forceinline__ int64_t hess_offset(const BatchInst &d, int step) {
     return (int64_t)step * d.s * d.kmax;      // column block `step` of the K x K buffer
@@ -1522,6 +1509,9 @@ __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int
     if (leaf) {
         g.Q = Operand{d.Q, d.ldq};
         g.X = a.phase == BP_LGRAM2 ? Operand{d.U1L, d.ldq} : Operand{a.W[inst], d.n};
+        // Householder leaves: the second leaf Gram is [V v_new]^T v_new, the
+        // new reflectors just stored after the basis
+        if (a.hh && a.phase == BP_LGRAM2) g.X = Operand{d.Q + (int64_t)k * d.ldq, d.ldq};
         g.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL);
         g.partials = d.PL;
         g.retry = d.retry;
@@ -1648,6 +1638,14 @@ __device__ __forceinline__ FinalizeArgs batch_leaf_rowupdate_args(const BatchArg
         f.Cptr = d.CL;
         f.cseg = (int64_t)d.kmax * 2 * S;
         f.Uout = OutOperand{a.U[inst], d.n};
+        if (a.hh) {
+            // Householder leaves: -V Z over the k + s reflectors (the new
+            // ones as the "u1" block, copied to the scratch unchanged)
+            f.Qnew = OutOperand{d.U1L, d.ldq};
+            f.Qnew_hi = nullptr;
+            f.U1 = Operand{d.Q + (int64_t)k * d.ldq, d.ldq};
+            f.single_sweep = 1;
+        }
     }
     return f;
 }
@@ -1698,6 +1696,12 @@ __device__ void batch_rowupdate(const BatchArgs &a, const BatchInst &d, int inst
             f.U1 = Operand{d.U1L, d.ldq};
             f.sweep = 2;
             f.single_sweep = a.two ? 0 : 1;
+            if (a.hh) {      // Householder leaves, as in batch_leaf_rowupdate_args
+                f.Qnew = OutOperand{d.U1L, d.ldq};
+                f.Qnew_hi = nullptr;
+                f.U1 = Operand{d.Q + (int64_t)k * d.ldq, d.ldq};
+                f.single_sweep = 1;
+            }
             f.geom = make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk);
             f.small = d.SL;
             f.Cptr = d.CL;
@@ -2032,6 +2036,7 @@ size_t batch_phase_lds(int phase, int s, bool rowlds) {
 
 template <int S>
 static hipError_t batch_phase_s(const BatchArgs &a, int32_t blocks, size_t lds, hipStream_t st) {
+    if (batch_hh_phase(a.phase)) return hipErrorInvalidValue;   // launch_batch_hh_phase
     switch (a.phase) {
         case BP_LGRAM:
             if (a.mixed) {       // its own kernel: the FP64 Grams keep their register budget

@@ -113,10 +113,18 @@ def test_mixed_form_workspace_adds_the_fp32_copy():
         assert stored * 4 <= mixed - f64 <= stored * 4 + 256
 
 
-def test_householder_leaves_are_single_handle_only():
+def test_householder_batch_workspace_and_limits():
+    # a Householder batch adds each instance's compact-WY factors (three
+    # k_max x k_max blocks per leaf) and its apply scratch; an instance past
+    # the panel's limits (s = 16, 2048-row leaves) makes the batch invalid
     f = orth.ORTH_FP64_HOUSEHOLDER
-    assert orth.orth_batch_workspace_bytes([5000, 3000], [4, 8], [16, 32], None, f) == 0
-    code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, f, 4096, 1 << 30, None)
+    ns, ss, ks, lrs = [5000, 3000], [4, 8], [16, 32], [1000, 1000]
+    f64 = orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, orth.ORTH_FP64)
+    hh = orth.orth_batch_workspace_bytes(ns, ss, ks, lrs, f)
+    factors = sum(3 * (n // lr) * k * k * 8 for n, k, lr in zip(ns, ks, lrs))
+    assert f64 > 0 and hh >= f64 + factors
+    assert orth.orth_batch_workspace_bytes([8192, 3000], [16, 8], [32, 32], [2048, 1000], f) == 0
+    code, h = orth.orth_batch_create([8192, 3000], [16, 8], [32, 32], [2048, 1000], f, 4096, 1 << 30, None)
     assert code == orth.ORTH_ERR_UNSUPPORTED
     code, h = orth.orth_batch_create([5000, 3000], [4, 8], [16, 32], None, 7, 4096, 1 << 30, None)
     assert code == orth.ORTH_ERR_ARG

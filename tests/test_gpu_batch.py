@@ -13,7 +13,10 @@
   handle bitwise and the FP64 oracle at the mixed form's tolerances
   (||dP||_F / ||X||_F <= 1e-10, ||dN||_F / ||X||_F and max |dU| <= 1e-10
   kappa_j); a first-sweep pivot that fails on the FP32 copy of one
-  instance redoes that instance's sweep only, in a graph replay too.
+  instance redoes that instance's sweep only, in a graph replay too;
+* Householder leaves (ORTH_FP64_HOUSEHOLDER, s from 1 to 32): every instance
+  equals a Householder single handle bitwise and the unique PQR solution at
+  the FP64 tolerances; the BCGS-PIP variant is refused.
 """
 
 import sys
@@ -118,7 +121,7 @@ def _grids():
     return [(50, 60), (101, 37), (64, 64)]
 
 
-@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp64", "mixed", "householder"])
 def test_batch_graph_replay_arnoldi(torch_cuda, precision):
     """Capture start block + 4 Arnoldi steps (operator and batch step) and replay."""
     import torch
@@ -336,3 +339,63 @@ def test_batch_mixed_fallback_is_per_instance(torch_cuda):
         x = torch.randn(1000, device="cuda", dtype=torch.float64)
         torch.cuda.synchronize()
         assert torch.isfinite(x.sum())
+
+
+HH_INSTANCES = [  # n, s, k_max, leaf_rows (0: default): within the panel's limits
+    (5000, 4, 24, 1000),
+    (3001, 8, 48, 700),        # ragged last leaf
+    (777, 1, 6, 100),
+    (6000, 16, 96, 1000),
+    (8192, 32, 192, 4096),     # s = 32: the sub-panel kernel
+    (2600, 2, 12, 0),
+]
+
+
+def test_batch_householder_equals_single_handles_bitwise(torch_cuda):
+    import torch
+    from paper_2204_13393_amd import BatchOrthogonalizer, Orthogonalizer, orth
+    HH = orth.ORTH_FP64_HOUSEHOLDER
+    _say("batch householder vs single", len(HH_INSTANCES))
+    rng = np.random.default_rng(11)
+    steps = min(k // s for _, s, k, _ in HH_INSTANCES)
+    X = [[rng.standard_normal((n, s)) * np.geomspace(1.0, 0.25, s) for _ in range(steps)]
+         for (n, s, _, _) in HH_INSTANCES]
+    ns = [i[0] for i in HH_INSTANCES]
+    ss = [i[1] for i in HH_INSTANCES]
+    ks = [i[2] for i in HH_INSTANCES]
+    lrs = [i[3] for i in HH_INSTANCES]
+    b = BatchOrthogonalizer(ns, ss, ks, lrs, precision=HH)
+    assert orth.orth_batch_set_variant(b.h, orth.ORTH_PIP) == orth.ORTH_ERR_UNSUPPORTED
+    W = [torch.empty((s, n), dtype=torch.float64, device="cuda") for (n, s, _, _) in HH_INSTANCES]
+    U = [torch.empty_like(w) for w in W]
+    Hess = [torch.zeros((k, k), dtype=torch.float64, device="cuda") for k in ks]
+    Ub = [[] for _ in HH_INSTANCES]
+    for j in range(steps):
+        for i, w in enumerate(W):
+            w.copy_(to_dev(X[i][j]))
+        b.step(W, U, Hess)
+        for i, u in enumerate(U):
+            Ub[i].append(to_host(u))
+    st, info = b.status()
+    assert st == 0, info
+    for i, (n, s, km, lr) in enumerate(HH_INSTANCES):
+        g = Orthogonalizer(n, s, km, lr, precision=HH)
+        assert g.leaf_rows == b.leaf_rows[i]
+        Hb = to_host(Hess[i])
+        Q = np.zeros((n, 0))
+        for j in range(steps):
+            H, R, Uo = g.step(to_dev(X[i][j]))
+            k = j * s
+            assert np.array_equal(Hb[:k, j * s:(j + 1) * s], to_host(H)), (i, j)
+            assert np.array_equal(Hb[k:k + s, j * s:(j + 1) * s], to_host(R)), (i, j)
+            assert np.array_equal(Ub[i][j], to_host(Uo)), (i, j)
+            P, N, Ur = pqr_reference(Q, X[i][j])
+            kap = kappa_after_projection(N, X[i][j])
+            xn = np.linalg.norm(X[i][j])
+            if k:
+                assert np.linalg.norm(Hb[:k, j * s:(j + 1) * s] - P) / xn <= 1e-12
+            assert np.linalg.norm(Hb[k:k + s, j * s:(j + 1) * s] - N) / xn <= 1e-12 * kap
+            assert np.max(np.abs(Ub[i][j] - Ur)) <= 1e-12 * kap
+            Q = np.hstack([Q, Ur])
+        g.close()
+    b.close()
