@@ -567,7 +567,7 @@ class BatchOrthogonalizer:
     default height).  Tensors are column-major as in ``Orthogonalizer``:
     instance i's block is a (s_i, n_i) float64 tensor, its Hessenberg buffer a
     (K_i, K_i) tensor (column j of the K_i x K_i matrix is row j of the tensor).
-    precision: ORTH_FP64 or ORTH_MIXED_SPLIT32 (every instance).
+    precision: ORTH_FP64, ORTH_MIXED_SPLIT32 or ORTH_FP64_HOUSEHOLDER (every instance).
     """
 
     def __init__(self, n, s, k_max, leaf_rows=None, device="cuda", stream=None, variant=ORTH_PIP_PLUS,
