@@ -71,10 +71,30 @@ __host__ __device__ inline int gram_tile_groups(int ncol) {
     const int groups = (nmt + kGramTPW - 1) / kGramTPW;
     return groups <= 1 ? 1 : (groups <= 2 ? 2 : 4);
 }
-__host__ __device__ inline int gram_col_groups(int ncol) {
+// At s = 32 the products outweigh the loads, so the tiles are spread evenly
+// over the waves of a chunk's workgroups (at most gram_tpw of them per wave)
+// rather than packed kGramTPW to a wave: packing left whole workgroups with
+// one busy wave.  Each output entry still comes from one wave, summed over
+// the rows in the same order, so the split does not change the bits.
+__host__ __device__ constexpr int gram_tpw(int s) { return s >= 32 ? 5 : kGramTPW; }
+__host__ __device__ inline int gram_col_groups(int ncol, int s) {
     const int nmt = (ncol + 15) / 16;
+    if (s >= 32 && gram_tile_groups(ncol) == kWaves) return (nmt + kWaves * gram_tpw(s) - 1) / (kWaves * gram_tpw(s));
     const int groups = (nmt + kGramTPW - 1) / kGramTPW;
     return groups <= 4 ? 1 : (groups + 3) / 4;
+}
+// first tile and number of tiles (<= gram_tpw(s); none when <= 0) of tile
+// group tg (workgroup column by, wave w: tg = by * tile_groups + w % tile_groups)
+__host__ __device__ inline void gram_wave_tiles(int ncol, int s, int tg, int &tile0, int &ntl) {
+    const int nmt = (ncol + 15) / 16;
+    if (s >= 32 && gram_tile_groups(ncol) == kWaves) {
+        const int w = kWaves * gram_col_groups(ncol, s);
+        tile0 = tg * nmt / w;
+        ntl = (tg + 1) * nmt / w - tile0;
+    } else {
+        tile0 = tg * kGramTPW;
+        ntl = nmt - tile0 < kGramTPW ? nmt - tile0 : kGramTPW;
+    }
 }
 __host__ __device__ inline int gram_row_groups(int ncol) { return kWaves / gram_tile_groups(ncol); }
 constexpr int kLeafChunk = 2048;      // rows per workgroup at the leaf level
@@ -465,9 +485,9 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
         // the new reflectors' Gram and the T update every call
         switch (phase) {
             case BP_LGRAM:
-                return k > 0 ? make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol) : 0;
+                return k > 0 ? make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol, d.s) : 0;
             case BP_LGRAM2:
-                return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol);
+                return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol, d.s);
             case BP_HPREP:
                 return k > 0 ? d.p : 0;
             case BP_LCORR:
@@ -497,7 +517,7 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
             [[fallthrough]];
         case BP_LGRAM:
         case BP_LGRAM2:
-            return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol);
+            return make_leaf_geom(d.n, d.leaf_rows, d.p, d.cL).nchunks() * gram_col_groups(ncol, d.s);
         case BP_LCHOLF:
             if (!d.Qhi) return 0;
             [[fallthrough]];
@@ -509,7 +529,7 @@ __host__ __device__ inline int32_t batch_phase_blocks(const BatchInst &d, int ph
             return make_leaf_geom(d.n, d.leaf_rows, d.p, kBatchFinalChunk).nchunks();
         case BP_RGRAM:
         case BP_RGRAM2:
-            return make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_col_groups(ncol);
+            return make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_col_groups(ncol, d.s);
         case BP_RRED1:
         case BP_RRED2: {
             const int32_t slots = make_root_geom(d.p, d.kmax, ncol, d.cR).nchunks() * gram_row_groups(ncol);

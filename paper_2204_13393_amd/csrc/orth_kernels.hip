@@ -106,7 +106,7 @@ typedef double dbl2v __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- sweep 1
 // Partial [Q X]^T X of one row chunk on the matrix cores.  The columns of
-// Z = [Q X] are cut into 16-column tiles; a wave owns up to kGramTPW tiles
+// Z = [Q X] are cut into 16-column tiles; a wave owns up to gram_tpw(s) tiles
 // and one N tile per 16 columns of X.  The contraction runs over rows: in a
 // macro-step of 32 rows, lane group kk = lane/16 feeds rows r + 8 kk + t to
 // the t-th of 8 back-to-back products, so every lane streams 8 consecutive
@@ -138,20 +138,23 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     const int TG = a.tile_groups, RG = kWaves / TG;
     const int tg = by * TG + wave % TG;
     const int rg = wave / TG;
-    const int tile0 = tg * kGramTPW;
-    if (tile0 >= nmt) return;  // no columns for this wave (no barrier in this kernel)
+    constexpr int TPW = gram_tpw(S);
+    int tile0, ntl;
+    gram_wave_tiles(ncol, S, tg, tile0, ntl);
+    if (ntl <= 0) return;  // no columns for this wave (no barrier in this kernel)
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(bx, leaf, r0, r1);
     const Operand Qv = leaf_view(a.Q, a.geom, leaf);    // the leaf's block of a blocked basis
 
-    const double *colp[kGramTPW];
-    int cz[kGramTPW];                           // TZ: segment rows of column c that can be nonzero
+    const double *colp[TPW];
+    int cz[TPW];                                // TZ: segment rows of column c that can be nonzero
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t) {
+    for (int t = 0; t < TPW; ++t) {
         const int c = (tile0 + t) * 16 + il;
-        colp[t] = c < k ? Qv.ptr + (int64_t)c * Qv.ld
-                        : (c < ncol ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr);
+        colp[t] = t >= ntl ? nullptr
+                           : (c < k ? Qv.ptr + (int64_t)c * Qv.ld
+                                    : (c < ncol ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr));
         cz[t] = c < k ? (c / S + 1) * S : ncol;
     }
     const double *xcol[NT];
@@ -160,15 +163,15 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
         const int j = 16 * nt + il;
         xcol[nt] = j < S ? a.X.ptr + (int64_t)j * a.X.ld : nullptr;
     }
-    dbl4 acc[kGramTPW][NT];
+    dbl4 acc[TPW][NT];
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t)
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[t][nt] = zero4();
 
     const bool ident = a.geom.map.seg_len == 0;
     for (int64_t rm = r0 + MS * rg; rm < r1; rm += MS * RG) {
-        double av[kGramTPW][RPL], bv[NT][RPL];
+        double av[TPW][RPL], bv[NT][RPL];
         const int64_t rb = rm + RPL * g;
         // this lane's RPL rows are contiguous in memory: always at the leaf
         // level, and at the reduction level when they sit in one segment
@@ -182,7 +185,7 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
         }
         if (contig) {
 #pragma unroll
-            for (int t = 0; t < kGramTPW; ++t) {
+            for (int t = 0; t < TPW; ++t) {
                 if (colp[t] && (!TZ || rs + RPL <= cz[t])) {
                     load_run<RPL>(colp[t] + pb, av[t]);
                 } else if (TZ && S % RPL != 0 && colp[t] && rs < cz[t]) {
@@ -212,7 +215,7 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
                 const int64_t prow = a.geom.map.phys(ok ? row : r0);
                 const int64_t srow = TZ ? row % a.geom.map.seg_len : 0;
 #pragma unroll
-                for (int t = 0; t < kGramTPW; ++t)
+                for (int t = 0; t < TPW; ++t)
                     av[t][u] = (ok && colp[t] && (!TZ || srow < cz[t])) ? colp[t][prow] : 0.0;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? xcol[nt][prow] : 0.0;
@@ -221,15 +224,15 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
 #pragma unroll
         for (int u = 0; u < RPL; ++u)
 #pragma unroll
-            for (int t = 0; t < kGramTPW; ++t)
-                if (tile0 + t < nmt)
+            for (int t = 0; t < TPW; ++t)
+                if (t < ntl)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[t][nt] = mfma16(av[t][u], bv[nt][u], acc[t][nt]);
     }
     double *out = a.partials + ((int64_t)bx * RG + rg) * a.part_stride;
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t) {
-        if (tile0 + t >= nmt) break;
+    for (int t = 0; t < TPW; ++t) {
+        if (t >= ntl) break;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int j = 16 * nt + il;
@@ -304,21 +307,23 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
     const int TG = a.tile_groups, RG = kWaves / TG;
     const int tg = by * TG + wave % TG;
     const int rg = wave / TG;
-    const int tile0 = tg * kGramTPW;
-    if (tile0 >= nmt) return;
+    constexpr int TPW = gram_tpw(S);
+    int tile0, ntl;
+    gram_wave_tiles(ncol, S, tg, tile0, ntl);
+    if (ntl <= 0) return;
     int leaf;
     int64_t r0, r1;
     a.geom.chunk(bx, leaf, r0, r1);
     const float *qhi = leaf_view_hi(a.Qhi, a.Q, a.geom, leaf);   // the leaf's block of the copy
     const int64_t qld = leaf_view(a.Q, a.geom, leaf).ld;
 
-    const float *colh[kGramTPW];
-    const double *colp[kGramTPW];
+    const float *colh[TPW];
+    const double *colp[TPW];
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t) {
+    for (int t = 0; t < TPW; ++t) {
         const int c = (tile0 + t) * 16 + il;
-        colh[t] = c < k ? qhi + (int64_t)c * qld : nullptr;
-        colp[t] = (c >= k && c < ncol) ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr;
+        colh[t] = (t < ntl && c < k) ? qhi + (int64_t)c * qld : nullptr;
+        colp[t] = (t < ntl && c >= k && c < ncol) ? a.X.ptr + (int64_t)(c - k) * a.X.ld : nullptr;
     }
     const double *xcol[NT];
 #pragma unroll
@@ -326,9 +331,9 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
         const int j = 16 * nt + il;
         xcol[nt] = j < S ? a.X.ptr + (int64_t)j * a.X.ld : nullptr;
     }
-    double acc[kGramTPW][NT][4];
+    double acc[TPW][NT][4];
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t)
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -336,11 +341,11 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
 
     const bool ident = a.geom.map.seg_len == 0;
     for (int64_t rm = r0 + MS * rg; rm < r1; rm += MS * RG) {
-        float av[kGramTPW][RPL], bv[NT][RPL];
+        float av[TPW][RPL], bv[NT][RPL];
         const int64_t rb = rm + RPL * g;
         if (ident && rm + MS <= r1) {
 #pragma unroll
-            for (int t = 0; t < kGramTPW; ++t) {
+            for (int t = 0; t < TPW; ++t) {
                 if (colh[t]) {
                     load_run_f<RPL>(colh[t] + rb, av[t]);
                 } else if (colp[t]) {
@@ -366,15 +371,15 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
                 const bool ok = row < r1;
                 const int64_t prow = a.geom.map.phys(ok ? row : r0);
 #pragma unroll
-                for (int t = 0; t < kGramTPW; ++t)
+                for (int t = 0; t < TPW; ++t)
                     av[t][u] = !ok ? 0.0f : (colh[t] ? colh[t][prow] : (colp[t] ? (float)colp[t][prow] : 0.0f));
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) bv[nt][u] = (ok && xcol[nt]) ? (float)xcol[nt][prow] : 0.0f;
             }
         }
 #pragma unroll
-        for (int t = 0; t < kGramTPW; ++t) {
-            if (tile0 + t >= nmt) continue;
+        for (int t = 0; t < TPW; ++t) {
+            if (t >= ntl) continue;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 flt4 d = flt4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -387,8 +392,8 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
     }
     double *out = a.partials + ((int64_t)bx * RG + rg) * a.part_stride;
 #pragma unroll
-    for (int t = 0; t < kGramTPW; ++t) {
-        if (tile0 + t >= nmt) break;
+    for (int t = 0; t < TPW; ++t) {
+        if (t >= ntl) break;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int j = 16 * nt + il;
@@ -402,7 +407,7 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
 }
 
 template <int S>
-__global__ __launch_bounds__(kThreads) void k_gram_hi(GramArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_gram_hi(GramArgs a) {
     gram_f32_body<S>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -1522,7 +1527,7 @@ __device__ void batch_gram(const BatchArgs &a, const BatchInst &d, int inst, int
         g.geom = make_root_geom(d.p, d.kmax, ncol, d.cR);
         g.partials = d.PR;
     }
-    const int cg = gram_col_groups(ncol);
+    const int cg = gram_col_groups(ncol, S);
     gram_body<S>(g, local / cg, local % cg);
 }
 
@@ -1543,7 +1548,7 @@ __device__ void batch_gram_hi(const BatchArgs &a, const BatchInst &d, int inst, 
     g.partials = d.PL;
     g.clear_retry = 1;
     g.retry = d.retry;
-    const int cg = gram_col_groups(ncol);
+    const int cg = gram_col_groups(ncol, S);
     gram_f32_body<S>(g, local / cg, local % cg);
 }
 
@@ -1725,7 +1730,7 @@ __global__ __launch_bounds__(kThreads) void kb_gram(BatchArgs a) {
 }
 
 template <int S>
-__global__ __launch_bounds__(kThreads) void kb_gram_hi(BatchArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_gram_hi(BatchArgs a) {
     int inst, local;
     batch_locate(a, inst, local);
     const BatchInst d = a.inst[inst];
@@ -1781,7 +1786,7 @@ static int grid_for(int64_t count, int threads) {
 template <int S>
 static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
     const int ncol = a.k + S;
-    const dim3 grid(a.geom.nchunks(), gram_col_groups(ncol));
+    const dim3 grid(a.geom.nchunks(), gram_col_groups(ncol, S));
     switch (cls) {
         case 0: hipLaunchKernelGGL((k_gram<S, 0>), grid, dim3(kThreads), 0, st, a); break;
         case 3: hipLaunchKernelGGL((k_gram<S, 3>), grid, dim3(kThreads), 0, st, a); break;
@@ -1794,7 +1799,7 @@ static hipError_t gram_s(const GramArgs &a, int cls, hipStream_t st) {
 
 template <int S>
 static hipError_t gram_hi_s(const GramArgs &a, hipStream_t st) {
-    const dim3 grid(a.geom.nchunks(), gram_col_groups(a.k + S));
+    const dim3 grid(a.geom.nchunks(), gram_col_groups(a.k + S, S));
     hipLaunchKernelGGL((k_gram_hi<S>), grid, dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
