@@ -134,7 +134,6 @@ __device__ __forceinline__ void gram_body(const GramArgs &a, int bx, int by) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
     const int k = a.k, ncol = k + S;
-    const int nmt = (ncol + 15) >> 4;
     const int TG = a.tile_groups, RG = kWaves / TG;
     const int tg = by * TG + wave % TG;
     const int rg = wave / TG;
@@ -303,7 +302,6 @@ __device__ __forceinline__ void gram_f32_body(const GramArgs &a, int bx, int by)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int il = lane & 15, g = lane >> 4;
     const int k = a.k, ncol = k + S;
-    const int nmt = (ncol + 15) >> 4;
     const int TG = a.tile_groups, RG = kWaves / TG;
     const int tg = by * TG + wave % TG;
     const int rg = wave / TG;
