@@ -54,6 +54,9 @@ def torch_cuda():
     (777, 1, 12, 100),
     (6000, 32, 160, 2000),
     (5000, 16, 256, 2500),
+    # s = 32 up to k + s = 672 (42 column tiles): the first Gram's tiles
+    # spread over one, two and three workgroups per chunk
+    (7001, 32, 672, 3500),
 ])
 def test_mixed_open_loop_parity(torch_cuda, n, s, kmax, leaf_rows):
     from paper_2204_13393_amd import Orthogonalizer
