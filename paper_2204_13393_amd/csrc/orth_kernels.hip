@@ -1012,6 +1012,10 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a_in, int bx) {
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
     const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
     const bool ident_only = a.single_sweep != 0;   // u = u1 (one-sweep variant)
+    // the explicit form's first S coefficient columns are zero then: at
+    // s >= 16 they fill whole tiles, whose products are skipped (they would
+    // add exact zeros)
+    const bool skip_p = EXPL && S % 16 == 0 && ident_only;
     const double *cbase = EXPL ? a.Cptr + (int64_t)leaf * a.cseg : nullptr;
     const bool ident = a.geom.map.seg_len == 0;
 
@@ -1073,7 +1077,8 @@ __device__ __forceinline__ void rowmfma_body(const FinalizeArgs &a_in, int bx) {
 #pragma unroll
             for (int t = 0; t < TR; ++t)
 #pragma unroll
-                for (int T = 0; T < NTM; ++T) acc[t][T] = mfma16(cs[0][T], qs[0][t], acc[t][T]);
+                for (int T = 0; T < NTM; ++T)
+                    if (!skip_p || T >= S / 16) acc[t][T] = mfma16(cs[0][T], qs[0][t], acc[t][T]);
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
 #pragma unroll
@@ -1231,6 +1236,7 @@ __device__ __forceinline__ void rowlds_body(const FinalizeArgs &a_in, int bx, do
     const double *recP = a.sweep == 1 ? rec : rec + (int64_t)a.kmax * S + 2 * S * S;
     const double *recNi = a.sweep == 1 ? rec + (int64_t)a.kmax * S + S * S : recP + (int64_t)a.kmax * S;
     const bool ident_only = a.single_sweep != 0;
+    const bool skip_p = EXPL && S % 16 == 0 && ident_only;   // zero tiles, as in rowmfma_body
     const double *cbase = EXPL ? a.Cptr + (int64_t)leaf * a.cseg : nullptr;
     const double *coef = EXPL ? cbase : recP;           // rows c of [P2 | C] or of P
 
@@ -1311,7 +1317,8 @@ __device__ __forceinline__ void rowlds_body(const FinalizeArgs &a_in, int bx, do
 #pragma unroll
                     for (int t = 0; t < TR; ++t)
 #pragma unroll
-                        for (int T = 0; T < NTM; ++T) acc[t][T] = mfma16(cv[T], qv[t], acc[t][T]);
+                        for (int T = 0; T < NTM; ++T)
+                            if (!skip_p || T >= S / 16) acc[t][T] = mfma16(cv[T], qv[t], acc[t][T]);
                 }
             }
         }
