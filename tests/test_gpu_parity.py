@@ -422,11 +422,17 @@ def test_probe_copy(torch_cuda):
     assert torch.equal(src, dst)
 
 
-def test_pip_variant_matches_oracle_tree(torch_cuda):
+@pytest.mark.parametrize("n,s,kmax,leaf", [
+    (6000, 4, 24, 1000),
+    # s >= 16: the one-sweep finalize skips the products of its zero
+    # coefficient tiles
+    (6000, 16, 64, 1000),
+    (8192, 32, 128, 2048),
+])
+def test_pip_variant_matches_oracle_tree(torch_cuda, n, s, kmax, leaf):
     """BCGS-PIP leaves and reduction (one CholQR sweep) on a well-conditioned input."""
     from paper_2204_13393_amd import Orthogonalizer, orth
-    _say("pip variant")
-    n, s, kmax, leaf = 6000, 4, 24, 1000
+    _say("pip variant", n, s, kmax, leaf)
     gpu = Orthogonalizer(n, s, kmax, leaf, variant=orth.ORTH_PIP)
     tree = TreeTSPQR(n, s, leaf, "pip", "pip")
     rng = np.random.default_rng(8)
